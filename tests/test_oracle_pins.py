@@ -1,0 +1,423 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+closed forms, library routines, brute force, hand-worked fixtures and invariants.
+CPU only."""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize_scalar
+from scipy.spatial.transform import Rotation
+from scipy.special import sph_harm_y
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _sigma_from_params(g, i):
+    """Covariance from scipy's quaternion->rotation (scalar-last order)."""
+    w, x, y, z = g["quat"][:, i].astype(np.float64)
+    R = Rotation.from_quat([x, y, z, w]).as_matrix()
+    s = np.exp(g["log_scale"][:, i].astype(np.float64))
+    return R @ np.diag(s * s) @ R.T
+
+
+def _one(g, i):
+    return synth.subset(g, [i])
+
+
+# ------------------------------------------------------------------ unscented transform
+@pytest.mark.parametrize("abk", [(1.0, 2.0, 0.0), (0.5, 2.0, 1.0), (1.3, 0.0, 2.0)])
+def test_ut_exact_for_linear_projection(abk):
+    """Sec. 3.2 UT: for an affine sensor map the 7-point UT reproduces A mu + b and A Sigma A^T."""
+    rng = np.random.default_rng(11)
+    yaw = 0.7
+    R_sw = synth.yaw_camera_pose(yaw)
+    origin = np.array([0.3, -0.2, 0.5], np.float32)
+    s = synth.pinhole(64, 48, 3.0, 2.5, cx=31.0, cy=22.0, R_sw=R_sw, origin=origin, kind=synth.ORTHO)
+    n = 200
+    mean = np.stack([rng.uniform(-5, 5, n), rng.uniform(-5, 5, n), rng.uniform(-1, 1, n)])
+    fwd = R_sw[2].astype(np.float64)
+    mean = mean + 20.0 * fwd[:, None]            # in front of the sensor
+    g = synth.particles(rng, mean, 0.05, 2.0, 0, synth.FEAT_CAMERA)
+    proj = oracle.project(g, s, abk)
+    assert proj["valid"].all()
+    A = np.diag([3.0, 2.5]) @ R_sw[:2].astype(np.float64)
+    for i in range(n):
+        mu = g["mean"][:, i].astype(np.float64)
+        m_ref = A @ (mu - origin.astype(np.float64)) + np.array([31.0, 22.0])
+        S = A @ _sigma_from_params(g, i) @ A.T
+        np.testing.assert_allclose(proj["mean2"][:, i], m_ref, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(proj["cov2"][:, i], [S[0, 0], S[0, 1], S[1, 1]], rtol=1e-11, atol=1e-12)
+
+
+def test_ut_close_to_monte_carlo_pinhole():
+    """App. (LiDAR projection, Table 8): UT moments are close to Monte Carlo moments for
+    small particles (statistical; 4x10^5 samples)."""
+    rng = np.random.default_rng(3)
+    g, s = synth.scene_pinhole_small(5, n=20)
+    proj = oracle.project(g, s)
+    for i in range(5):
+        S = _sigma_from_params(g, i)
+        x = rng.multivariate_normal(g["mean"][:, i].astype(np.float64), S, 400000)
+        u = 100.0 * x[:, 0] / x[:, 2] + 64.0
+        v = 100.0 * x[:, 1] / x[:, 2] + 48.0
+        mc_m = np.array([u.mean(), v.mean()])
+        mc_c = np.cov(np.stack([u, v]))
+        scale = np.sqrt(mc_c[0, 0] + mc_c[1, 1])
+        assert np.all(np.abs(proj["mean2"][:, i] - mc_m) < 0.05 * scale)
+        np.testing.assert_allclose([proj["cov2"][0, i], proj["cov2"][2, i]], [mc_c[0, 0], mc_c[1, 1]], rtol=0.05)
+
+
+# ------------------------------------------------------------------ projections
+def test_projection_round_trip_of_ray_tables():
+    """Every camera ray of the generator's table, pushed out to 7 m, projects back to its
+    pixel centre (fisheye: Newton-inverted distortion vs the oracle's forward model)."""
+    rng = np.random.default_rng(0)
+    k = synth.fisheye_distortion(rng, np.deg2rad(95))
+    for s in (synth.fisheye(96, 64, k, R_sw=synth.yaw_camera_pose(0.4), origin=[1, 2, 0.5]),
+              synth.pinhole(40, 30, 35.0, 33.0, cx=19.5, cy=14.0, R_sw=synth.yaw_camera_pose(2.0), origin=[0, 1, 0])):
+        d = s["ray_dir"].astype(np.float64)
+        valid = np.any(d != 0, axis=0)
+        pts = s["origin"].astype(np.float64)[None] + 7.0 * d.T
+        uv, ok = oracle.project_points(s, pts)
+        W = s["width"]
+        idx = np.arange(d.shape[1])
+        centre = np.stack([idx % W + 0.5, idx // W + 0.5], 1)
+        assert ok[valid].all()
+        assert np.abs(uv[valid] - centre[valid]).max() < 2e-3   # float32 ray rounding
+        if s["kind"] == synth.FISHEYE:
+            assert (~valid).sum() > 0                            # corners beyond theta_max
+
+
+def test_lidar_projection_eq3():
+    """Eq. 3: ray (b, a) at range 30 m maps to (2 pi a / A, elevation_b)."""
+    s = synth.lidar(np.deg2rad([-20.0, -3.0, 0.0, 7.5, 14.0]), 64, R_sw=synth.yaw_lidar_pose(1.1), origin=[3, -2, 1])
+    d = s["ray_dir"].astype(np.float64)
+    pts = s["origin"].astype(np.float64)[None] + 30.0 * d.T
+    uv, ok = oracle.project_points(s, pts)
+    assert ok.all()
+    a = np.arange(d.shape[1]) % 64
+    b = np.arange(d.shape[1]) // 64
+    dphi = (uv[:, 0] - 2 * np.pi * a / 64 + np.pi) % (2 * np.pi) - np.pi
+    assert np.abs(dphi).max() < 1e-6
+    assert np.abs(uv[:, 1] - s["beam_elev"].astype(np.float64)[b]).max() < 1e-6
+    # axis points in the sensor frame
+    s0 = synth.lidar([0.0, 0.1], 8)
+    uv, ok = oracle.project_points(s0, [[5, 0, 0], [0, 5, 0], [-5, 0, 0], [0, -5, 0], [3, 0, 4]])
+    np.testing.assert_allclose(uv[:, 0], [0, np.pi / 2, np.pi, 3 * np.pi / 2, 0], atol=1e-15)
+    np.testing.assert_allclose(uv[:, 1], [0, 0, 0, 0, np.arcsin(0.8)], atol=1e-15)
+
+
+# ------------------------------------------------------------------ spherical harmonics
+def test_sh_matches_scipy_and_is_orthonormal():
+    rng = np.random.default_rng(1)
+    d = rng.standard_normal((500, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y = oracle.sh_eval(3, d)
+    theta = np.arccos(np.clip(d[:, 2], -1, 1))
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    for l in range(4):
+        for m in range(-l, l + 1):
+            c = sph_harm_y(l, abs(m), theta, phi)      # complex, Condon-Shortley phase
+            ref = c.real if m == 0 else (np.sqrt(2) * c.real if m > 0 else np.sqrt(2) * c.imag)
+            np.testing.assert_allclose(Y[:, l * l + l + m], ref, atol=1e-12)
+    # Gauss-Legendre x uniform-azimuth quadrature: exact for these polynomial degrees
+    zt, zw = np.polynomial.legendre.leggauss(12)
+    ph = np.arange(24) * 2 * np.pi / 24
+    Z, P = np.meshgrid(zt, ph, indexing="ij")
+    W = np.repeat(zw, 24) * (2 * np.pi / 24)
+    r = np.sqrt(1 - Z.ravel() ** 2)
+    dirs = np.stack([r * np.cos(P.ravel()), r * np.sin(P.ravel()), Z.ravel()], 1)
+    Yq = oracle.sh_eval(3, dirs)
+    G = (Yq * W[:, None]).T @ Yq
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+# ------------------------------------------------------------------ response and compositing
+def test_single_isotropic_gaussian_closed_form():
+    """Eq. 1 with one particle: C = c alpha, depth = tau* alpha, omega = alpha, with
+    tau* = mu.d and D^2 = |mu x d|^2 / s^2 for an isotropic particle and a camera at 0."""
+    s = synth.pinhole(64, 64, 60.0, 60.0)
+    mu = np.array([[0.15], [-0.1], [3.0]])
+    g = synth.particles(np.random.default_rng(0), mu, 0.2, 0.2, 0, synth.FEAT_CAMERA,
+                        dc=synth.camera_rgb_dc(np.array([[0.9], [0.4], [0.2]])))
+    g["log_scale"][:] = np.float32(np.log(0.2))
+    g["opacity_logit"][:] = np.float32(np.log(0.3 / 0.7))
+    sigma = 1.0 / (1.0 + np.exp(-np.float64(g["opacity_logit"][0])))
+    sc = np.exp(np.float64(g["log_scale"][0, 0]))
+    proj, lists, out = oracle.render(g, s)
+    d = s["ray_dir"].astype(np.float64).T
+    m = mu.ravel().astype(np.float32).astype(np.float64)
+    dd = np.sum(d * d, axis=1)                  # float32 rays are unit only to ~1e-7
+    tau = d @ m / dd
+    D2 = np.sum(np.cross(m, d) ** 2, axis=1) / (sc**2 * dd)
+    alpha = np.minimum(sigma * np.exp(-0.5 * D2), 0.99)
+    alpha = np.where(alpha < 1 / 255, 0.0, alpha)
+    col = g["feat"][0, :, 0].astype(np.float64) / synth.DC_SCALE + 0.5
+    assert (alpha > 0).sum() > 100
+    np.testing.assert_allclose(out["alpha"], alpha, atol=1e-13)
+    np.testing.assert_allclose(out["depth"], tau * alpha, atol=1e-12)
+    np.testing.assert_allclose(out["feat"], col[:, None] * alpha[None], atol=1e-13)
+
+
+def test_two_gaussians_closed_form():
+    """C = c1 a1 + c2 a2 (1 - a1), nearer particle first."""
+    s = synth.pinhole(32, 32, 30.0, 30.0)
+    mu = np.array([[0.05, -0.04], [0.02, 0.03], [2.0, 3.5]])
+    g = synth.particles(np.random.default_rng(0), mu, 0.3, 0.3, 0, synth.FEAT_CAMERA,
+                        dc=synth.camera_rgb_dc(np.array([[0.9, 0.1], [0.2, 0.8], [0.5, 0.5]])))
+    g["log_scale"][:] = np.float32(np.log(0.3))
+    g["opacity_logit"][:] = np.float32(np.log(0.25 / 0.75))
+    proj, lists, out = oracle.render(g, s)
+    d = s["ray_dir"].astype(np.float64).T
+    sc = np.exp(np.float64(g["log_scale"][0, 0]))
+    sig = 1.0 / (1.0 + np.exp(-np.float64(g["opacity_logit"][0])))
+    a, t, c = [], [], []
+    dd = np.sum(d * d, axis=1)
+    for i in range(2):
+        m = g["mean"][:, i].astype(np.float64)
+        al = np.minimum(sig * np.exp(-0.5 * np.sum(np.cross(m, d) ** 2, 1) / (sc**2 * dd)), 0.99)
+        a.append(np.where(al < 1 / 255, 0, al))
+        t.append(d @ m / dd)
+        c.append(g["feat"][0, :, i].astype(np.float64) / synth.DC_SCALE + 0.5)
+    Cref = c[0][:, None] * a[0] + c[1][:, None] * a[1] * (1 - a[0])
+    np.testing.assert_allclose(out["feat"], Cref, atol=1e-13)
+    np.testing.assert_allclose(out["depth"], t[0] * a[0] + t[1] * a[1] * (1 - a[0]), atol=1e-12)
+    np.testing.assert_allclose(out["t_final"], (1 - a[0]) * (1 - a[1]), atol=1e-14)
+
+
+def test_response_is_numeric_maximum_along_ray():
+    """Sec. 3.2 (3DGRT response): tau* maximises rho along the ray; checked against a 1D
+    numeric minimiser of the Mahalanobis distance with scipy's rotation matrices."""
+    rng = np.random.default_rng(4)
+    s = synth.pinhole(16, 16, 12.0, 12.0, R_sw=synth.yaw_camera_pose(0.3), origin=[0.5, -0.5, 0.2])
+    mean = (s["origin"].astype(np.float64)[:, None] + 4.0 * s["R_sw"][2].astype(np.float64)[:, None]
+            + rng.uniform(-0.5, 0.5, (3, 6)))
+    for i in range(6):
+        g = synth.particles(rng, mean[:, i:i + 1], 0.1, 1.2, 0, synth.FEAT_CAMERA,
+                            dc=synth.camera_rgb_dc(np.full((3, 1), 0.75)))
+        g["opacity_logit"][:] = np.float32(np.log(0.6 / 0.4))
+        proj, lists, out = oracle.render(g, s)
+        B = np.linalg.inv(_sigma_from_params(g, 0))
+        mu = g["mean"][:, 0].astype(np.float64)
+        o = s["origin"].astype(np.float64)
+        sig = 1.0 / (1.0 + np.exp(-np.float64(g["opacity_logit"][0])))
+        for r in rng.choice(256, 40, replace=False):
+            if proj["count"][0] == 0:
+                break
+            d = s["ray_dir"][:, r].astype(np.float64)
+            f = lambda t: (o + t * d - mu) @ B @ (o + t * d - mu)
+            res = minimize_scalar(f, bounds=(-50.0, 50.0), method="bounded", options={"xatol": 1e-11})
+            al = min(sig * np.exp(-0.5 * res.fun), 0.99)
+            tx, ty = (r % 16) // 16, (r // 16) // 16
+            if al < 1 / 255:
+                assert out["alpha"][r] == 0
+                continue
+            np.testing.assert_allclose(out["alpha"][r], al, rtol=1e-9)
+            np.testing.assert_allclose(out["depth"][r] / out["alpha"][r], res.x, rtol=1e-6)
+
+
+@pytest.mark.parametrize("which", ["pinhole", "fisheye", "lidar"])
+def test_tiled_equals_brute_force(which):
+    """Tile lists change nothing: tiled compositing == all particles in (key, index) order
+    gated by rect membership, bit for bit in FP64."""
+    if which == "pinhole":
+        g, s = synth.scene_pinhole_small(2)
+    elif which == "fisheye":
+        g, s = synth.scene_fisheye(1, n=3000, width=160, height=112)
+        g["mean"] *= np.float32(0.2)
+    else:
+        g, s = synth.scene_lidar(1, n=4000, n_beams=32, n_az=256, n_phi=4, max_per_tile=32)
+        g["mean"] *= np.float32(0.1)
+    proj, lists, out = oracle.render(g, s)
+    assert lists["n_pairs"] > 100
+    out_b = oracle.composite(g, s, lists, proj, mode=1)
+    for k in out:
+        assert np.array_equal(out[k], out_b[k]), k
+
+
+def test_invariants_and_monotone_transmittance():
+    g, s = synth.scene_pinhole_small(3)
+    proj, lists, out = oracle.render(g, s)
+    assert np.all((out["t_final"] >= 0) & (out["t_final"] <= 1))
+    assert np.all((out["alpha"] >= 0) & (out["alpha"] <= 1))
+    np.testing.assert_allclose(out["alpha"], 1 - out["t_final"], atol=1e-13)
+    cmax = oracle.project(g, s)["feat"].max()
+    assert np.all(out["feat"] <= cmax * out["alpha"] + 1e-12)
+    # T over list prefixes is non-increasing (no early stop so prefixes are comparable)
+    prev = np.ones(s["width"] * s["height"])
+    r = lists["ranges"].copy()
+    length = (r[1] - r[0]).max()
+    for k in range(0, int(length) + 1, 4):
+        lk = dict(lists)
+        lk["ranges"] = np.stack([r[0], np.minimum(r[1], r[0] + k)])
+        o = oracle.composite(g, s, lk, proj, t_min=0.0)
+        assert np.all(o["t_final"] <= prev + 1e-15)
+        prev = o["t_final"]
+
+
+def test_permutation_invariance():
+    g, s = synth.scene_pinhole_small(4)
+    _, _, out = oracle.render(g, s)
+    perm = np.random.default_rng(0).permutation(g["mean"].shape[1])
+    _, _, out_p = oracle.render(synth.permute(g, perm), s)
+    for k in out:
+        assert np.array_equal(out[k], out_p[k]), k
+
+
+def test_sort_order_and_ranges():
+    g, s = synth.scene_pinhole_small(5)
+    proj = oracle.project(g, s)
+    lists = oracle.bin_pairs(s, proj["rect"], proj["count"], proj["key"])
+    pairs = []
+    TX = (s["width"] + 15) // 16
+    for i in np.nonzero(proj["count"])[0]:
+        x0, y0, x1, y1 = proj["rect"][:, i]
+        for y in range(y0, y1 + 1):
+            for x in range(x0, x1 + 1):
+                pairs.append((y * TX + x, int(proj["key"][i]), int(i)))
+    pairs.sort()
+    assert [p[0] for p in pairs] == list(lists["pair_tile"])
+    assert [p[2] for p in pairs] == list(lists["pair_gauss"])
+    for t in range(lists["ranges"].shape[1]):
+        a, b = lists["ranges"][:, t]
+        assert all(p[0] == t for p in pairs[a:b])
+        assert sum(p[0] == t for p in pairs) == b - a
+
+
+def test_depth_key_is_float32_squared_distance():
+    g, s = synth.scene_pinhole_small(6)
+    s["origin"] = np.array([0.1, -0.2, 0.3], np.float32)
+    proj = oracle.project(g, s)
+    d = g["mean"] - s["origin"][:, None]
+    key = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+    assert np.array_equal(proj["key"], key.astype(np.float32).view(np.uint32))
+
+
+def test_camera_rect_matches_brute_force_overlap():
+    """Rect = the set of tiles whose pixel range meets [m - 3 sd, m + 3 sd]."""
+    g, s = synth.scene_pinhole_small(7)
+    proj = oracle.project(g, s)
+    TX, TY = 8, 6
+    for i in range(g["mean"].shape[1]):
+        m, c = proj["mean2"][:, i], proj["cov2"][:, i]
+        e = 3 * np.sqrt([c[0], c[2]])
+        tiles = [(x, y) for y in range(TY) for x in range(TX)
+                 if 16 * x <= m[0] + e[0] and 16 * (x + 1) > m[0] - e[0]
+                 and 16 * y <= m[1] + e[1] and 16 * (y + 1) > m[1] - e[1]]
+        x0, y0, x1, y1 = proj["rect"][:, i]
+        got = [(x, y) for y in range(y0, y1 + 1) for x in range(x0, x1 + 1)] if proj["count"][i] else []
+        assert sorted(got) == sorted(tiles)
+
+
+# ------------------------------------------------------------------ LiDAR tiling and culling
+@pytest.mark.parametrize("name", ["alg1_8beam.json", "alg1_multicross.json"])
+def test_alg1_hand_worked(name):
+    fx = json.load(open(os.path.join(GOLDEN, name)))
+    be = np.deg2rad(np.array(fx["beam_elev_deg"])).astype(np.float32)
+    bounds, bstart, nth = oracle.lidar_tiling(be, fx["n_az"], fx["n_phi"], fx["M"])
+    np.testing.assert_allclose(np.rad2deg(bounds), fx["bounds_deg"], atol=1e-5)
+    assert list(bstart) == fx["beam_start"]
+    assert nth == fx["n_theta"]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_alg1_invariants(seed):
+    rng = np.random.default_rng(seed)
+    be = synth.beams_uniform(rng, 128)
+    A, NP, M = 2048, 16, 32
+    bounds, bstart, nth = oracle.lidar_tiling(be, A, NP, M)
+    assert bounds[0] == np.float64(be.min()) and abs(bounds[-1] - be.max()) < 1e-12
+    assert np.all(np.diff(bounds) >= 0)
+    counts = np.diff(bstart)
+    assert counts.sum() == 128 and bstart[0] == 0
+    # per-tile beam counts deviate from B/N_phi by at most the beams of one histogram bin
+    w = (be.max() - be.min()) / 400
+    bins = np.minimum(((be.astype(np.float64) - be.min()) / w).astype(int), 399)
+    biggest_bin = np.bincount(bins).max()
+    assert np.all(np.abs(counts - 128 / NP) <= biggest_bin + 1)
+    assert nth == int(np.ceil(counts.max() * A / M))
+    # every ray tile holds at most M (1 + 1/N_theta) rays
+    per_az = [len([a for a in range(A) if a * nth // A == j]) for j in range(nth)]
+    assert counts.max() * max(per_az) <= M * (1 + 1 / nth) + counts.max()
+
+
+def test_sat_query_matches_mask_sum():
+    rng = np.random.default_rng(8)
+    be = synth.beams_uniform(rng, 24)
+    mask, sat = oracle.ray_sat(be, 300, float(be.min()), float(be.max()), 160, 40)
+    assert mask.sum() > 0
+    for _ in range(500):
+        x0, x1 = sorted(rng.integers(0, 160, 2))
+        y0, y1 = sorted(rng.integers(0, 40, 2))
+        n = sat[x1 + 1, y1 + 1] - sat[x0, y1 + 1] - sat[x1 + 1, y0] + sat[x0, y0]
+        assert n == mask[x0:x1 + 1, y0:y1 + 1].sum()
+
+
+def test_ray_culling_between_beams():
+    """Alg. 2 / Alg. 3: a small particle that falls between two distant beams is culled;
+    one on a beam is kept; culling never drops a particle some ray passes through."""
+    be = np.deg2rad([-10.0, -9.9, 9.9, 10.0]).astype(np.float32)
+    s = synth.lidar(be, 512, n_phi=2, max_per_tile=64, cull=True, cull_az=1600, cull_el_per_tile=8)
+    mean = np.array([[50.0, 50.0 * np.cos(np.deg2rad(10.0))], [0.0, 0.0], [0.0, 50.0 * np.sin(np.deg2rad(10.0))]])
+    g = synth.particles(np.random.default_rng(0), mean, 0.05, 0.05, 0, synth.FEAT_LIDAR)
+    proj = oracle.project(g, s)
+    assert proj["count"][0] == 0 and proj["n_culled_rays"] == 1
+    assert proj["count"][1] > 0
+    s_off = dict(s)
+    s_off["cull"] = False
+    assert oracle.project(g, s_off)["count"][0] > 0
+
+
+def test_lidar_drop_probability_is_softmax():
+    g, s = synth.scene_lidar(0, n=3000, n_beams=16, n_az=128, n_phi=4, max_per_tile=32)
+    g["mean"] *= np.float32(0.05)
+    proj, lists, out = oracle.render(g, s)
+    z = out["feat"]
+    ref = 1.0 / (1.0 + np.exp(-(z[2] - z[1])))
+    np.testing.assert_allclose(out["drop"], ref, atol=1e-15)
+    assert (out["alpha"] > 0).sum() > 50
+
+
+# ------------------------------------------------------------------ gradients
+def _small_diff_scene(seed, n=300, size=32, f=20.0):
+    rng = np.random.default_rng(seed)
+    mean = np.stack([rng.uniform(-3, 3, n), rng.uniform(-3, 3, n), rng.uniform(3, 9, n)])
+    g = synth.particles(rng, mean, 0.05, 0.6, 3, synth.FEAT_CAMERA)
+    return g, synth.pinhole(size, size, f, f, R_sw=synth.yaw_camera_pose(0.0) @ synth.yaw_camera_pose(0.0).T,
+                            origin=[0.05, -0.02, 0.01])
+
+
+def test_adjoint_matches_finite_differences_camera():
+    g, s = _small_diff_scene(0)
+    proj, lists, out = oracle.render(g, s)
+    rng = np.random.default_rng(1)
+    R = s["width"] * s["height"]
+    up = dict(feat=rng.standard_normal((3, R)), depth=0.1 * rng.standard_normal(R),
+              alpha=rng.standard_normal(R))
+    gr = oracle.backward(g, s, lists, up)
+    sel = np.nonzero(proj["count"])[0][:40]
+    fd = oracle.fd_grad(g, s, lists, up, sel, h=1e-5)
+    an = oracle.grads_as_rows(gr, sel)
+    scale = np.abs(fd).max(axis=0, keepdims=True) + 1e-12
+    assert np.abs(an).max() > 0
+    np.testing.assert_allclose(an, fd, atol=1e-6 * scale.max(), rtol=1e-5)
+
+
+def test_adjoint_matches_finite_differences_lidar():
+    g, s = synth.scene_lidar(2, n=2000, n_beams=16, n_az=128, n_phi=4, max_per_tile=32)
+    g["mean"] *= np.float32(0.05)
+    proj, lists, out = oracle.render(g, s)
+    rng = np.random.default_rng(2)
+    R = out["alpha"].shape[0]
+    up = dict(feat=rng.standard_normal((3, R)), depth=0.1 * rng.standard_normal(R),
+              alpha=rng.standard_normal(R), drop=rng.standard_normal(R))
+    gr = oracle.backward(g, s, lists, up)
+    sel = np.nonzero(proj["count"])[0][:40]
+    fd = oracle.fd_grad(g, s, lists, up, sel, h=1e-5)
+    an = oracle.grads_as_rows(gr, sel)
+    assert np.abs(an).max() > 0
+    np.testing.assert_allclose(an, fd, atol=1e-6 * np.abs(fd).max(), rtol=1e-5)
