@@ -1,0 +1,285 @@
+/*
+ * utrast.h -- C-ABI of the MI355X (gfx950) unscented-transform Gaussian rasterizer for
+ * arbitrary cameras and spinning LiDAR (SimULi, arXiv 2510.12901).
+ *
+ * The library renders a set of 3D Gaussian particles (Sec. 3.1) seen by a sensor
+ * (Sec. 3.2 camera models; Sec. 3.3 spinning LiDAR, Eq. 3) along given rays
+ * r(t) = o + t d (Sec. 3.2, "Volume Rendering").  The hot path is five calls:
+ *
+ *   ut_project            sigma-point projection, tile rect, LiDAR ray-based culling
+ *   ut_bin_and_sort       (tile, depth, index)-ordered tile lists
+ *   ut_composite_camera   front-to-back compositing of the 3D response (Eq. 1)
+ *   ut_composite_lidar    the same over azimuth-elevation tiles, plus LiDAR outputs
+ *   ut_composite_backward adjoint of the above with respect to every particle parameter
+ *
+ * plus host set-up (ut_lidar_tiling = Alg. 1, ut_sensor_build = ray mask / summed-area
+ * table of Appendix B) and a batched, persistent composite for serving.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers marked "device" are HIP device pointers (hipMalloc or torch CUDA tensors);
+ *   "host" pointers are ordinary CPU memory.  The caller owns every buffer; the library
+ *   never allocates or frees device memory and keeps no mutable global state, so calls on
+ *   different streams with disjoint buffers are independent.
+ * - All work is enqueued on the given stream (ut_stream = hipStream_t, NULL = the null
+ *   stream).  Only ut_bin_and_sort with a non-NULL n_pairs pointer synchronises that stream.
+ * - Errors: host-side argument checks return UT_ERR_ARG before anything is enqueued;
+ *   HIP launch or copy failures return UT_ERR_DEVICE; a tile-list capacity overflow returns
+ *   UT_ERR_CAPACITY.  Non-finite or degenerate particles are not errors: they are culled
+ *   (tile count 0) and counted.  No C++ exception crosses this ABI.
+ * - Particle arrays are float32 structure-of-arrays, component-major: mean[3][n] means
+ *   mean[c * n + i].
+ */
+#ifndef UTRAST_H
+#define UTRAST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int ut_status;
+enum { UT_OK = 0, UT_ERR_ARG = -1, UT_ERR_CAPACITY = -2, UT_ERR_DEVICE = -3, UT_ERR_UNSUPPORTED = -4 };
+
+/* Sensor kinds and feature kinds. */
+enum { UT_PINHOLE = 0, UT_FISHEYE = 1, UT_LIDAR = 2, UT_ORTHO = 3 };
+enum { UT_FEAT_CAMERA = 0, UT_FEAT_LIDAR = 1 };
+
+#define UT_RECORD_BYTES 96      /* per-particle compositing record written by ut_project */
+#define UT_MAX_ELEV_TILES 256   /* largest N_phi accepted */
+#define UT_CAMERA_TILE 16       /* camera tiles are 16 x 16 pixels */
+#define UT_MAX_LIDAR_TILE_RAYS 256
+#define UT_ACC_FLOATS 13        /* per-particle adjoint accumulator width (doubles) */
+
+typedef void* ut_stream; /* hipStream_t */
+
+/* Particles (Sec. 3.1): mean mu, rotation quaternion q = (w,x,y,z) (any non-zero norm; the
+ * library normalises), log_scale (S = diag(exp(log_scale)), Sigma = R S S^T R^T),
+ * opacity_logit (sigma = sigmoid), feat = SH coefficients feat[K][3][n] with
+ * K = (sh_degree+1)^2, coefficient k of channel c of particle i at feat[(k*3+c)*n + i],
+ * real SH with the Condon-Shortley phase ordered by l then m = -l..l.
+ * feat_kind UT_FEAT_CAMERA: colour = max(0, SH(dir) + 0.5); UT_FEAT_LIDAR: the three
+ * features (intensity, hit logit, drop logit) of Sec. 3.2 are SH(dir) raw.  dir is the
+ * unit vector from the sensor origin to the particle mean.  All device, read-only. */
+typedef struct {
+  const float* mean;
+  const float* quat;
+  const float* log_scale;
+  const float* opacity_logit;
+  const float* feat;
+  int32_t n;
+  int32_t sh_degree;   /* 0..3 */
+  int32_t feat_kind;
+} ut_gaussians;
+
+/* Sensor.  R_sw (row-major) maps world axes to sensor axes, origin is the sensor position
+ * in the world (both float32, host fields).  Camera axes x right, y down, z forward;
+ * LiDAR axes x forward, y left, z up.
+ *   UT_PINHOLE : (u,v) = (fx x/z + cx, fy y/z + cy), valid iff z > near
+ *   UT_FISHEYE : equidistant, theta = atan2(|xy|, z), theta_d = theta(1 + k1 t^2 + k2 t^4
+ *                + k3 t^6 + k4 t^8), (u,v) = (cx,cy) + (fx,fy) theta_d xy/|xy|,
+ *                valid iff |x| > near and theta <= theta_max
+ *   UT_LIDAR   : Eq. 3, azimuth atan2(y,x) in [0, 2pi), elevation asin(z/r), valid iff r > near
+ *   UT_ORTHO   : (fx x + cx, fy y + cy), valid iff z > near (affine; used to test the UT)
+ * ray_dir: device float32 [3][R] world-frame directions.  Camera ray y*width + x goes
+ * through the pixel centre (x+0.5, y+0.5); LiDAR ray b*n_az + a is beam b (elevations
+ * sorted ascending) at azimuth 2 pi a / n_az.  An all-zero direction marks "no ray"
+ * (its outputs are zero).  tables: device buffer of ut_sensor_table_bytes() bytes filled
+ * by ut_sensor_build (LiDAR only; may be NULL for cameras). */
+typedef struct {
+  int32_t kind;
+  float R_sw[9];
+  float origin[3];
+  double near_;
+  /* cameras */
+  int32_t width, height;
+  double fx, fy, cx, cy, k[4], theta_max;
+  /* spinning LiDAR */
+  int32_t n_beams, n_az;
+  int32_t n_phi;          /* elevation tiles N_phi */
+  int32_t max_per_tile;   /* M of Alg. 1 */
+  int32_t cull;           /* ray-based culling on/off */
+  int32_t cull_az, cull_el; /* culling grid: azimuth cells over 360 deg, elevation cells */
+  int32_t n_theta;        /* azimuth tiles, set by ut_sensor_build */
+  int32_t max_tile_rays;  /* largest ray count of one tile, set by ut_sensor_build */
+  const float* beam_elev_host; /* host [n_beams] radians, sorted ascending (LiDAR set-up only) */
+  const float* ray_dir;   /* device [3][R] */
+  void* tables;           /* device, LiDAR tiling + summed-area table */
+} ut_sensor;
+
+/* Compositing cut-offs (Eq. 1 practice): skip alpha < alpha_min, clamp alpha at
+ * alpha_max, stop after the particle that brings transmittance below t_min. */
+typedef struct {
+  double alpha_min, alpha_max, t_min;
+} ut_render_params;
+
+/* Projection output, all device buffers sized for n particles (caller-allocated). */
+typedef struct {
+  void* records;       /* [n] UT_RECORD_BYTES each (layout private to the library) */
+  int32_t* rect;       /* [4][n] tile rect x0,y0,x1,y1 inclusive; LiDAR x = azimuth tile,
+                          x1 may exceed n_theta-1 where the rect wraps through 0 */
+  uint32_t* key;       /* [n] depth key: float32 bits of |mu - o|^2 computed
+                          (dx*dx + dy*dy) + dz*dz in float32 without fused multiply-add */
+  uint32_t* count;     /* [n] tiles touched; 0 = culled */
+  float* moments;      /* [5][n] UT mean (u, v) and covariance (uu, uv, vv); may be NULL */
+  uint32_t* n_culled;  /* [2] invalid particles, LiDAR ray-culled particles (set by the call) */
+} ut_projected;
+
+/* Tile lists: gauss[0..n_pairs) particle indices ordered by (tile, depth key, index);
+ * ranges[2][n_tiles] = [start, end) per tile.  Device, caller-allocated. */
+typedef struct {
+  uint32_t* gauss;
+  uint32_t* ranges;
+  uint64_t max_pairs;  /* capacity of gauss */
+} ut_tile_lists;
+
+/* Per-ray outputs, device, R = rays of the sensor.
+ * feat[3][R]: premultiplied colour sum w c (camera) or LiDAR features zeta (channel 0 =
+ * intensity); depth[R] = sum w t* (unnormalised); alpha[R] = omega = 1 - T_final;
+ * drop[R] = ray-drop probability softmax(zeta_1, zeta_2)[drop] (LiDAR only, may be NULL);
+ * t_final[R], n_proc[R] (list entries visited) are the state the adjoint replays
+ * (may be NULL when no backward follows). */
+typedef struct {
+  float* feat;
+  float* depth;
+  float* alpha;
+  float* drop;
+  double* t_final;
+  uint32_t* n_proc;
+} ut_render_out;
+
+/* Upstream gradients dL/d(output), device float32 arrays shaped like ut_render_out;
+ * any member may be NULL (= zero). */
+typedef struct {
+  const float* feat;
+  const float* depth;
+  const float* alpha;
+  const float* drop;
+} ut_upstream;
+
+/* Gradients with respect to the particle parameters, device float32, same shapes as
+ * ut_gaussians (feat: [K][3][n]).  Overwritten by the call. */
+typedef struct {
+  float* mean;
+  float* quat;
+  float* log_scale;
+  float* opacity_logit;
+  float* feat;
+} ut_gaussian_grads;
+
+const char* ut_status_str(ut_status s);
+int32_t ut_record_bytes(void);
+
+/* Alg. 1 (ElevationTiling), host only.  beam_elev: host [n_beams] radians sorted
+ * ascending; n_az azimuth steps per revolution; n_phi elevation tiles; M rays per tile
+ * bound.  Writes bounds[n_phi+1] (radians), beam_start[n_phi+1] (first beam of each
+ * elevation tile; beams of tile k are [beam_start[k], beam_start[k+1])) and *n_theta. */
+ut_status ut_lidar_tiling(const float* beam_elev, int32_t n_beams, int32_t n_az, int32_t n_phi,
+                          int32_t M, double* bounds, int32_t* beam_start, int32_t* n_theta);
+
+/* Bytes of the device tables of a sensor (0 for cameras). */
+ut_status ut_sensor_table_bytes(const ut_sensor* s, size_t* bytes);
+
+/* Sensor set-up, once per sensor definition (Sec. 3.3: the tiling is reused across calls).
+ * LiDAR: runs Alg. 1, builds the ray mask over the culling grid and its summed-area
+ * table (Appendix B) and copies them to s->tables (device, ut_sensor_table_bytes bytes);
+ * sets s->n_theta and s->max_tile_rays.  Cameras: sets max_tile_rays = 256.
+ * Synchronises the stream (the host tables are freed on return). */
+ut_status ut_sensor_build(ut_sensor* s, ut_stream stream);
+
+/* Number of tiles of a (built) sensor. */
+int32_t ut_sensor_tiles(const ut_sensor* s);
+/* Number of rays of a sensor. */
+int64_t ut_sensor_rays(const ut_sensor* s);
+
+/* Sigma-point projection (Sec. 3.2; LiDAR Eq. 3 and ray-based culling, Alg. 2 and 3).
+ * Per particle: normalise q, build R, s = exp(log_scale), sigma = sigmoid(logit); project
+ * the 7 sigma points mu +- sqrt(3 + lambda) s_j R[:,j] with the scaled unscented transform
+ * (ut_abk = alpha, beta, kappa; lambda = alpha^2 (3 + kappa) - 3); UT mean and covariance;
+ * 3-sigma extent of the covariance diagonal -> tile rect; for LiDAR with culling on, the
+ * count is zero when no ray falls in the extent on the culling grid; depth key; SH
+ * features; compositing record.  Any invalid sigma point culls the particle.
+ * ut_abk: host [3].  out: device buffers sized g->n. */
+ut_status ut_project(const ut_gaussians* g, const ut_sensor* s, const double* ut_abk,
+                     ut_projected* out, ut_stream stream);
+
+/* Workspace bytes for binning n particles into at most max_pairs (tile, particle) pairs
+ * over n_tiles tiles. */
+size_t ut_workspace_bytes(uint64_t max_pairs, int32_t n_tiles, int32_t n_gaussians);
+
+/* Tile binning and depth sort (Sec. 3.2, tiling as in 3DGS).  Step 1 (ut_bin_count,
+ * asynchronous): stable radix sort of the visible particles by depth key, exclusive scan
+ * of their tile counts; the pair total P is left in the workspace and, if n_pairs_host is
+ * non-NULL, copied there asynchronously (use pinned memory; read it after the stream is
+ * synchronised).  Step 2 (ut_bin_sort, asynchronous): with P known on the host, emit
+ * the pairs in depth order, stable radix sort them by tile, and write the tile ranges.
+ * Returns UT_ERR_CAPACITY if P > lists->max_pairs (nothing enqueued).
+ * ut_bin_and_sort runs both and synchronises the stream in between; *n_pairs (host,
+ * may be NULL) receives P.  ws: device workspace of ws_bytes >= ut_workspace_bytes(). */
+ut_status ut_bin_count(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws,
+                       size_t ws_bytes, uint64_t* n_pairs_host, ut_stream stream);
+ut_status ut_bin_sort(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws,
+                      size_t ws_bytes, uint64_t n_pairs, ut_tile_lists* lists, ut_stream stream);
+ut_status ut_bin_and_sort(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws,
+                          size_t ws_bytes, ut_tile_lists* lists, uint64_t* n_pairs,
+                          ut_stream stream);
+
+/* Front-to-back compositing (Eq. 1) of every ray of a camera over its tile's list: for
+ * each particle, t* = argmax of its 3D response along the ray (d^T B v / d^T B d with
+ * B = Sigma^{-1}, v = mu - o), rho = exp(-D^2/2) at t*, alpha = min(sigma rho, alpha_max),
+ * skipped when alpha < alpha_min or t* < near; w = alpha T; feat += w c; depth += w t*;
+ * T *= 1 - alpha; the ray stops after T < t_min.  Deterministic (no atomics). */
+ut_status ut_composite_camera(const ut_projected* p, const ut_tile_lists* lists,
+                              const ut_sensor* s, const ut_render_params* prm,
+                              ut_render_out* out, ut_stream stream);
+
+/* The same over the azimuth-elevation tiles of a spinning LiDAR; additionally
+ * drop = sigmoid(zeta_2 - zeta_1) (the softmax of Sec. 3.2 over hit/drop). */
+ut_status ut_composite_lidar(const ut_projected* p, const ut_tile_lists* lists,
+                             const ut_sensor* s, const ut_render_params* prm,
+                             ut_render_out* out, ut_stream stream);
+
+/* Bytes of the per-particle accumulator workspace of the adjoint. */
+size_t ut_backward_workspace_bytes(int32_t n_gaussians);
+
+/* Adjoint of ut_composite_* with the discrete structure of the forward held fixed (lists,
+ * culls, alpha_min skips, alpha_max clamps, colour clamps, the termination index).
+ * Replays each ray's list in reverse from fwd->n_proc, recovering T_i = T_{i+1}/(1 -
+ * alpha_i) from fwd->t_final; per-pair gradients are reduced per wavefront and added
+ * atomically into per-particle float64 accumulators (acc_ws, zeroed by the call), then a
+ * per-particle kernel applies the chain rule to (mean, quat, log_scale, opacity_logit,
+ * feat) including the SH direction's dependence on the mean.  fwd must hold feat,
+ * t_final and n_proc of the forward call with the same arguments.  Gradients are
+ * accumulated in float64 but their summation order is not fixed (atomics). */
+ut_status ut_composite_backward(const ut_gaussians* g, const ut_projected* p,
+                                const ut_tile_lists* lists, const ut_sensor* s,
+                                const ut_render_params* prm, const ut_render_out* fwd,
+                                const ut_upstream* up, void* acc_ws, size_t acc_ws_bytes,
+                                ut_gaussian_grads* grads, ut_stream stream);
+
+/* Batched persistent compositing for serving.  One launch composites the tiles of several
+ * independent render requests (any mix of camera and LiDAR sensors, each with its own
+ * projection, lists and outputs): a fixed grid of workgroups pulls (request, tile) work
+ * items from a device counter until the queue is exhausted.  Per-ray arithmetic is the
+ * same as ut_composite_camera / ut_composite_lidar, so every ray's output is bit-identical
+ * to the single-request call.  items: host array [n_items]; queue_ws: device workspace of
+ * ut_batch_workspace_bytes(n_items) bytes. */
+typedef struct {
+  const ut_projected* proj;
+  const ut_tile_lists* lists;
+  const ut_sensor* sensor;
+  ut_render_out* out;
+} ut_batch_item;
+
+size_t ut_batch_workspace_bytes(int32_t n_items);
+ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items,
+                             const ut_render_params* prm, void* queue_ws, size_t ws_bytes,
+                             int32_t n_workgroups, ut_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UTRAST_H */

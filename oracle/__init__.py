@@ -77,7 +77,8 @@ def lib():
         L.orc_count_pairs.argtypes = [P, C.c_int]
         L.orc_count_pairs.restype = C.c_uint64
         L.orc_bin.argtypes = [P, C.c_int, P, P, P, P, P, P]
-        L.orc_composite.argtypes = [P, P, P, P, P, C.c_int, P, P, P, P, P, P, P, P, P]
+        L.orc_composite.argtypes = [P, P, P, P, P, C.c_int, P, P, P, P, P, P, P, P, P, P]
+        L.orc_composite_rays.argtypes = [P, P, P, P, P, P, C.c_int, P, P, P, P, P, P, P]
         L.orc_backward.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_fd_grad.argtypes = [P, P, P, P, P, P, P, P, P, P, C.c_int, C.c_double, P]
         L.orc_sh_eval.argtypes = [C.c_int, P, C.c_int, P]
@@ -216,7 +217,7 @@ def composite(g, s, lists, proj, mode=0, abk=(1.0, 2.0, 0.0), alpha_min=ALPHA_MI
     g, s = _as_g(g), _as_s(s)
     R = s.n_rays
     out = dict(feat=np.zeros((3, R)), depth=np.zeros(R), alpha=np.zeros(R),
-               t_final=np.zeros(R), n_proc=np.zeros(R, np.uint32))
+               t_final=np.zeros(R), n_proc=np.zeros(R, np.uint32), margin=np.zeros(R))
     drop = np.zeros(R) if s.kind == 2 else None
     pg = np.ascontiguousarray(lists["pair_gauss"], np.uint32)
     if pg.size == 0:
@@ -229,7 +230,28 @@ def composite(g, s, lists, proj, mode=0, abk=(1.0, 2.0, 0.0), alpha_min=ALPHA_MI
     lib().orc_composite(C.byref(g.c), C.byref(s.c), C.byref(prm), _p(pg), _p(ranges), mode,
                         _p(rect), _p(count), _p(key), _p(out["feat"]), _p(out["depth"]),
                         _p(out["alpha"]), _p(out["t_final"]), _p(out["n_proc"]),
-                        _p(drop) if drop is not None else None)
+                        _p(drop) if drop is not None else None, _p(out["margin"]))
+    if drop is not None:
+        out["drop"] = drop
+    return out
+
+
+def composite_rays(g, s, lists, ray_ids, abk=(1.0, 2.0, 0.0)) -> dict:
+    """Composite only the given rays (for sampled checks of full-size renders)."""
+    g, s = _as_g(g), _as_s(s)
+    ids = np.ascontiguousarray(ray_ids, np.int64)
+    m = len(ids)
+    out = dict(feat=np.zeros((3, m)), depth=np.zeros(m), alpha=np.zeros(m), t_final=np.zeros(m),
+               n_proc=np.zeros(m, np.uint32), margin=np.zeros(m))
+    drop = np.zeros(m) if s.kind == 2 else None
+    pg = np.ascontiguousarray(lists["pair_gauss"], np.uint32)
+    if pg.size == 0:
+        pg = np.zeros(1, np.uint32)
+    ranges = np.ascontiguousarray(lists["ranges"], np.uint32)
+    prm = make_params(abk)
+    lib().orc_composite_rays(C.byref(g.c), C.byref(s.c), C.byref(prm), _p(pg), _p(ranges), _p(ids), m,
+                             _p(out["feat"]), _p(out["depth"]), _p(out["alpha"]), _p(out["t_final"]),
+                             _p(out["n_proc"]), _p(drop) if drop is not None else None, _p(out["margin"]))
     if drop is not None:
         out["drop"] = drop
     return out

@@ -525,7 +525,9 @@ int orc_project(const orc_gaussians* g, const orc_sensor* s, const orc_params* p
           const double f0 = (m[0] - eu) * s->n_theta / (2 * kPi);
           const double f1 = (m[0] + eu) * s->n_theta / (2 * kPi);
           margin = std::min({margin, frac_dist(f0), frac_dist(f1)});
-          long a0 = (long)std::floor(f0), a1 = (long)std::floor(f1);
+          /* an extent of at least 2 pi covers every azimuth tile */
+          const bool full_az = eu >= kPi;
+          long a0 = full_az ? 0 : (long)std::floor(f0), a1 = full_az ? s->n_theta - 1 : (long)std::floor(f1);
           if (a1 - a0 + 1 >= s->n_theta) { a0 = 0; a1 = s->n_theta - 1; }
           else {
             long a0w = ((a0 % s->n_theta) + s->n_theta) % s->n_theta;
@@ -541,7 +543,7 @@ int orc_project(const orc_gaussians* g, const orc_sensor* s, const orc_params* p
             const double c1 = (m[0] + eu) * s->cull_az / (2 * kPi);
             const double r0 = (lo - T[0]) * s->cull_el / span, r1 = (hi - T[0]) * s->cull_el / span;
             margin = std::min({margin, frac_dist(c0), frac_dist(c1), frac_dist(r0), frac_dist(r1)});
-            long ca0 = (long)std::floor(c0), ca1 = (long)std::floor(c1);
+            long ca0 = full_az ? 0 : (long)std::floor(c0), ca1 = full_az ? s->cull_az - 1 : (long)std::floor(c1);
             int ce0 = (int)std::max(std::floor(r0), 0.0), ce1 = (int)std::min(std::floor(r1), (double)(s->cull_el - 1));
             long occ = 0;
             if (ce0 <= ce1) {
@@ -690,6 +692,7 @@ Response response(const Particle& p, const double o[3], const double d[3]) {
 struct RayResult {
   double feat[3], depth, omega, T;
   uint32_t nproc;
+  double margin; /* smallest relative distance of a skip / clamp / stop decision to its threshold */
 };
 
 void ray_geometry(const orc_sensor* s, int r, long R, double o[3], double d[3]) {
@@ -704,14 +707,18 @@ RayResult composite_ray(const PerGaussian& pg, int n, const orc_params* prm, dou
   RayResult rr;
   std::memset(&rr, 0, sizeof rr);
   rr.T = 1.0;
+  rr.margin = 1e300;
   if (!ray_valid(d)) return rr;
   for (uint32_t j = 0; j < len; ++j) {
     const uint32_t gi = list[j];
     rr.nproc = j + 1;
     const Particle& p = pg.P[gi];
     const Response q = response(p, o, d);
+    rr.margin = std::min(rr.margin, std::fabs(q.tau - near_) / std::max(std::fabs(near_), 1e-300));
     if (q.tau < near_) continue;
     const double a = p.sigma * q.rho;
+    rr.margin = std::min({rr.margin, std::fabs(a - prm->alpha_min) / prm->alpha_min,
+                          std::fabs(a - prm->alpha_max) / prm->alpha_max});
     const int clamped = a > prm->alpha_max;
     const double alpha = clamped ? prm->alpha_max : a;
     if (alpha < prm->alpha_min) continue;
@@ -721,6 +728,7 @@ RayResult composite_ray(const PerGaussian& pg, int n, const orc_params* prm, dou
     rr.omega += w;
     rr.T *= (1 - alpha);
     if (rec) rec->push_back({gi, clamped});
+    if (prm->t_min > 0) rr.margin = std::min(rr.margin, std::fabs(rr.T - prm->t_min) / prm->t_min);
     if (rr.T < prm->t_min) break;
   }
   return rr;
@@ -763,7 +771,7 @@ int orc_composite(const orc_gaussians* g, const orc_sensor* s, const orc_params*
                   const uint32_t* pair_gauss, const uint32_t* ranges, int mode,
                   const int* rect, const uint32_t* count, const uint32_t* key,
                   double* feat, double* depth, double* omega, double* t_final, uint32_t* nproc,
-                  double* drop) {
+                  double* drop, double* margin) {
   const int n = g->n;
   const PerGaussian pg = per_gaussian(g, s);
   const int TX = sensor_tiles_x(s), TY = sensor_tiles_y(s), NT = TX * TY;
@@ -803,8 +811,46 @@ int orc_composite(const orc_gaussians* g, const orc_sensor* s, const orc_params*
       t_final[r] = rr.T;
       nproc[r] = rr.nproc;
       if (drop) drop[r] = softmax_drop(rr.feat);
+      if (margin) margin[r] = rr.margin;
     }
   }
+  return 0;
+}
+
+/* Composite only the listed rays (tiled lists); outputs are indexed like ray_ids. */
+int orc_composite_rays(const orc_gaussians* g, const orc_sensor* s, const orc_params* prm,
+                       const uint32_t* pair_gauss, const uint32_t* ranges, const long* ray_ids, int m,
+                       double* feat, double* depth, double* omega, double* t_final, uint32_t* nproc,
+                       double* drop, double* margin) {
+  const int n = g->n;
+  const PerGaussian pg = per_gaussian(g, s);
+  const int TX = sensor_tiles_x(s), TY = sensor_tiles_y(s), NT = TX * TY;
+  const long R = (s->kind == 2) ? (long)s->n_beams * s->n_az : (long)s->width * s->height;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int i = 0; i < m; ++i) {
+    const long r = ray_ids[i];
+    int t;
+    if (s->kind != 2) {
+      t = (int)((r / s->width) / s->tile) * TX + (int)((r % s->width) / s->tile);
+    } else {
+      const int b = (int)(r / s->n_az), a = (int)(r % s->n_az);
+      int k = 0;
+      while (k + 1 < s->n_phi && s->beam_start[k + 1] <= b) ++k;
+      t = k * TX + (int)((long)a * s->n_theta / s->n_az);
+    }
+    double o[3], d[3];
+    ray_geometry(s, (int)r, R, o, d);
+    const RayResult rr = composite_ray(pg, n, prm, s->near_, o, d, pair_gauss + ranges[t],
+                                       ranges[NT + t] - ranges[t], nullptr);
+    for (int c = 0; c < 3; ++c) feat[c * (long)m + i] = rr.feat[c];
+    depth[i] = rr.depth;
+    omega[i] = rr.omega;
+    t_final[i] = rr.T;
+    nproc[i] = rr.nproc;
+    if (drop) drop[i] = softmax_drop(rr.feat);
+    if (margin) margin[i] = rr.margin;
+  }
+  (void)TY;
   return 0;
 }
 

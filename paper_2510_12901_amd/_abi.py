@@ -1,0 +1,114 @@
+"""ctypes mirror of include/utrast.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libutrast.so")
+
+P = C.c_void_p
+i32 = C.c_int32
+f64 = C.c_double
+
+UT_OK, UT_ERR_ARG, UT_ERR_CAPACITY, UT_ERR_DEVICE, UT_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+PINHOLE, FISHEYE, LIDAR, ORTHO = 0, 1, 2, 3
+FEAT_CAMERA, FEAT_LIDAR = 0, 1
+RECORD_BYTES = 96
+ACC_FLOATS = 13
+
+
+class UtGaussians(C.Structure):
+    _fields_ = [("mean", P), ("quat", P), ("log_scale", P), ("opacity_logit", P), ("feat", P),
+                ("n", i32), ("sh_degree", i32), ("feat_kind", i32)]
+
+
+class UtSensor(C.Structure):
+    _fields_ = [("kind", i32), ("R_sw", C.c_float * 9), ("origin", C.c_float * 3), ("near_", f64),
+                ("width", i32), ("height", i32),
+                ("fx", f64), ("fy", f64), ("cx", f64), ("cy", f64), ("k", f64 * 4), ("theta_max", f64),
+                ("n_beams", i32), ("n_az", i32), ("n_phi", i32), ("max_per_tile", i32), ("cull", i32),
+                ("cull_az", i32), ("cull_el", i32), ("n_theta", i32), ("max_tile_rays", i32),
+                ("beam_elev_host", P), ("ray_dir", P), ("tables", P)]
+
+
+class UtRenderParams(C.Structure):
+    _fields_ = [("alpha_min", f64), ("alpha_max", f64), ("t_min", f64)]
+
+
+class UtProjected(C.Structure):
+    _fields_ = [("records", P), ("rect", P), ("key", P), ("count", P), ("moments", P), ("n_culled", P)]
+
+
+class UtTileLists(C.Structure):
+    _fields_ = [("gauss", P), ("ranges", P), ("max_pairs", C.c_uint64)]
+
+
+class UtRenderOut(C.Structure):
+    _fields_ = [("feat", P), ("depth", P), ("alpha", P), ("drop", P), ("t_final", P), ("n_proc", P)]
+
+
+class UtUpstream(C.Structure):
+    _fields_ = [("feat", P), ("depth", P), ("alpha", P), ("drop", P)]
+
+
+class UtGaussianGrads(C.Structure):
+    _fields_ = [("mean", P), ("quat", P), ("log_scale", P), ("opacity_logit", P), ("feat", P)]
+
+
+class UtBatchItem(C.Structure):
+    _fields_ = [("proj", P), ("lists", P), ("sensor", P), ("out", P)]
+
+
+# (name, restype, argtypes) of every exported entry point of include/utrast.h
+SIGNATURES = [
+    ("ut_status_str", C.c_char_p, [i32]),
+    ("ut_record_bytes", i32, []),
+    ("ut_lidar_tiling", i32, [P, i32, i32, i32, i32, P, P, P]),
+    ("ut_sensor_table_bytes", i32, [P, P]),
+    ("ut_sensor_build", i32, [P, P]),
+    ("ut_sensor_tiles", i32, [P]),
+    ("ut_sensor_rays", C.c_int64, [P]),
+    ("ut_project", i32, [P, P, P, P, P]),
+    ("ut_workspace_bytes", C.c_size_t, [C.c_uint64, i32, i32]),
+    ("ut_bin_count", i32, [P, i32, P, P, C.c_size_t, P, P]),
+    ("ut_bin_sort", i32, [P, i32, P, P, C.c_size_t, C.c_uint64, P, P]),
+    ("ut_bin_and_sort", i32, [P, i32, P, P, C.c_size_t, P, P, P]),
+    ("ut_composite_camera", i32, [P, P, P, P, P, P]),
+    ("ut_composite_lidar", i32, [P, P, P, P, P, P]),
+    ("ut_backward_workspace_bytes", C.c_size_t, [i32]),
+    ("ut_composite_backward", i32, [P, P, P, P, P, P, P, P, C.c_size_t, P, P]),
+    ("ut_batch_workspace_bytes", C.c_size_t, [i32]),
+    ("ut_composite_batch", i32, [P, i32, P, P, C.c_size_t, i32, P]),
+]
+
+_lib = None
+
+
+class UtError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libutrast.so.  There is no fallback: a missing library is an error."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "or python -m paper_2510_12901_amd.csrc.build")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str = "") -> None:
+    if status != UT_OK:
+        msg = lib().ut_status_str(status).decode()
+        raise UtError(f"{what}: {msg} ({status})")
+
+
+def ref(s):
+    return C.cast(C.pointer(s), P)

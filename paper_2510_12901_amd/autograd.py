@@ -1,0 +1,35 @@
+"""torch.autograd.Function around the render: forward = project, bin_and_sort, composite;
+backward = ut_composite_backward (hand-written adjoint replaying the saved tile lists)."""
+from __future__ import annotations
+
+import torch
+
+from .render import GaussianSet, Sensor, UT_ABK, backward, render, render_params
+
+
+class UTRender(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, mean, quat, log_scale, opacity_logit, feat, sh_degree: int, feat_kind: int,
+                sensor: Sensor, abk=UT_ABK, params=None):
+        g = GaussianSet(mean.detach().contiguous(), quat.detach().contiguous(), log_scale.detach().contiguous(),
+                        opacity_logit.detach().contiguous(), feat.detach().contiguous(), sh_degree, feat_kind)
+        prm = params or render_params()
+        p, lists, out = render(g, sensor, abk, prm, state=True)
+        ctx.state = (g, p, lists, out, sensor, prm)
+        drop = out.drop if out.drop is not None else torch.zeros(0, device=mean.device)
+        return out.feat, out.depth, out.alpha, drop
+
+    @staticmethod
+    def backward(ctx, g_feat, g_depth, g_alpha, g_drop):
+        g, p, lists, out, sensor, prm = ctx.state
+        if g_drop is not None and g_drop.numel() == 0:
+            g_drop = None
+        gr = backward(g, p, lists, sensor, out, g_feat, g_depth, g_alpha, g_drop, params=prm)
+        return gr["mean"], gr["quat"], gr["log_scale"], gr["opacity_logit"], gr["feat"], None, None, None, None, None
+
+
+def render_differentiable(g: GaussianSet, sensor: Sensor, abk=UT_ABK, params=None):
+    """Differentiable render of a particle set whose tensors may require grad.
+    Returns (feat [3,R], depth [R], alpha [R], drop [R] or empty)."""
+    return UTRender.apply(g.mean, g.quat, g.log_scale, g.opacity_logit, g.feat, g.sh_degree, g.feat_kind,
+                          sensor, abk, params)

@@ -1,0 +1,360 @@
+// api.hip -- the extern "C" boundary (include/utrast.h): argument checks, sensor set-up on
+// the host (Alg. 1 tiling, ray mask and summed-area table of Appendix B), kernel launches.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ut_internal.hpp"
+
+using namespace ut;
+
+namespace {
+
+hipStream_t as_stream(ut_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+ut_status from_hip(hipError_t e) { return e == hipSuccess ? UT_OK : UT_ERR_DEVICE; }
+
+int camera_tiles_x(const ut_sensor* s) { return (s->width + UT_CAMERA_TILE - 1) / UT_CAMERA_TILE; }
+int camera_tiles_y(const ut_sensor* s) { return (s->height + UT_CAMERA_TILE - 1) / UT_CAMERA_TILE; }
+
+bool sensor_ok(const ut_sensor* s) {
+  if (!s || !s->ray_dir) return false;
+  if (s->kind == UT_LIDAR)
+    return s->n_beams > 0 && s->n_az > 0 && s->n_phi > 0 && s->n_phi <= UT_MAX_ELEV_TILES &&
+           s->n_theta > 0 && s->tables && s->max_tile_rays > 0 && s->max_tile_rays <= UT_MAX_LIDAR_TILE_RAYS &&
+           (!s->cull || (s->cull_az > 0 && s->cull_el > 0));
+  if (s->kind == UT_PINHOLE || s->kind == UT_FISHEYE || s->kind == UT_ORTHO)
+    return s->width > 0 && s->height > 0;
+  return false;
+}
+
+bool gaussians_ok(const ut_gaussians* g) {
+  return g && g->n >= 0 && g->sh_degree >= 0 && g->sh_degree <= 3 &&
+         (g->feat_kind == UT_FEAT_CAMERA || g->feat_kind == UT_FEAT_LIDAR) &&
+         (g->n == 0 || (g->mean && g->quat && g->log_scale && g->opacity_logit && g->feat));
+}
+
+SensorK make_sensor_k(const ut_sensor* s) {
+  SensorK k;
+  std::memset(&k, 0, sizeof k);
+  k.kind = s->kind;
+  for (int i = 0; i < 9; ++i) k.R[i] = s->R_sw[i];
+  for (int i = 0; i < 3; ++i) { k.o[i] = s->origin[i]; k.of[i] = s->origin[i]; }
+  k.near_ = s->near_;
+  k.ray_dir = s->ray_dir;
+  if (s->kind == UT_LIDAR) {
+    k.n_beams = s->n_beams; k.n_az = s->n_az; k.n_phi = s->n_phi; k.n_theta = s->n_theta;
+    k.cull = s->cull; k.cull_az = s->cull_az; k.cull_el = s->cull_el;
+    k.tiles_x = s->n_theta; k.tiles_y = s->n_phi;
+    const TableLayout t = table_layout(s->n_phi, s->cull ? s->cull_az : 0, s->cull ? s->cull_el : 0);
+    char* base = static_cast<char*>(s->tables);
+    k.bounds = reinterpret_cast<const double*>(base + t.bounds);
+    k.beam_start = reinterpret_cast<const int*>(base + t.beam_start);
+    k.sat = reinterpret_cast<const int*>(base + t.sat);
+    k.n_rays = (long long)s->n_beams * s->n_az;
+  } else {
+    k.width = s->width; k.height = s->height;
+    k.tiles_x = camera_tiles_x(s); k.tiles_y = camera_tiles_y(s);
+    k.fx = s->fx; k.fy = s->fy; k.cx = s->cx; k.cy = s->cy;
+    for (int i = 0; i < 4; ++i) k.k[i] = s->k[i];
+    k.theta_max = s->theta_max;
+    k.n_rays = (long long)s->width * s->height;
+  }
+  return k;
+}
+
+RenderParamsK make_params(const ut_render_params* p) {
+  RenderParamsK k;
+  k.alpha_min = p->alpha_min;
+  k.alpha_max = p->alpha_max;
+  k.t_min = p->t_min;
+  k.log_alpha_min = std::log(p->alpha_min);
+  return k;
+}
+
+bool params_ok(const ut_render_params* p) {
+  return p && p->alpha_min > 0 && p->alpha_max >= p->alpha_min && p->alpha_max < 1 && p->t_min >= 0;
+}
+
+bool projected_ok(const ut_projected* p, int n) {
+  return p && (n == 0 || (p->records && p->rect && p->key && p->count)) && p->n_culled;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ut_status_str(ut_status s) {
+  switch (s) {
+    case UT_OK: return "ok";
+    case UT_ERR_ARG: return "invalid argument";
+    case UT_ERR_CAPACITY: return "tile-list capacity or workspace exceeded";
+    case UT_ERR_DEVICE: return "HIP device error";
+    case UT_ERR_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+int32_t ut_record_bytes(void) { return UT_RECORD_BYTES; }
+
+// Alg. 1.  Histogram of per-ray elevations (each beam counts n_az rays) over r = 400 bins
+// spanning [min, max] elevation; a boundary sits at the upper edge of every bin where the
+// cumulative count reaches b/N_phi of the total (tested while it holds, so one bin can
+// place several boundaries); N_theta = ceil(max rays of an elevation tile / M).
+ut_status ut_lidar_tiling(const float* beam_elev, int32_t n_beams, int32_t n_az, int32_t n_phi,
+                          int32_t M, double* bounds, int32_t* beam_start, int32_t* n_theta) {
+  if (!beam_elev || !bounds || !beam_start || !n_theta || n_beams <= 0 || n_az <= 0 || n_phi <= 0 ||
+      n_phi > UT_MAX_ELEV_TILES || M <= 0)
+    return UT_ERR_ARG;
+  for (int b = 1; b < n_beams; ++b)
+    if (!(beam_elev[b] >= beam_elev[b - 1])) return UT_ERR_ARG;
+  const int r_bins = 400;
+  const double lo = beam_elev[0], hi = beam_elev[n_beams - 1];
+  if (!(hi > lo)) return UT_ERR_ARG;
+  const double w = (hi - lo) / r_bins;
+  std::vector<long long> cum(r_bins, 0);
+  for (int b = 0; b < n_beams; ++b) {
+    int bin = (int)std::floor(((double)beam_elev[b] - lo) / w);
+    bin = std::min(std::max(bin, 0), r_bins - 1);
+    cum[bin] += n_az;
+  }
+  for (int i = 1; i < r_bins; ++i) cum[i] += cum[i - 1];
+  const long long total = cum[r_bins - 1];
+  int placed = 0;
+  bounds[0] = lo;
+  for (int i = 0; i < r_bins && placed < n_phi; ++i)
+    while (placed < n_phi && cum[i] * (long long)n_phi >= (long long)(placed + 1) * total) {
+      ++placed;
+      bounds[placed] = lo + (i + 1) * w;
+    }
+  long long most = 0;
+  int b = 0;
+  for (int k = 0; k < n_phi; ++k) {
+    beam_start[k] = b;
+    if (k == n_phi - 1) b = n_beams;
+    else
+      while (b < n_beams && (double)beam_elev[b] < bounds[k + 1]) ++b;
+    most = std::max(most, (long long)(b - beam_start[k]) * n_az);
+  }
+  beam_start[n_phi] = n_beams;
+  *n_theta = (int32_t)((most + M - 1) / M);
+  return UT_OK;
+}
+
+ut_status ut_sensor_table_bytes(const ut_sensor* s, size_t* bytes) {
+  if (!s || !bytes) return UT_ERR_ARG;
+  if (s->kind != UT_LIDAR) { *bytes = 0; return UT_OK; }
+  if (s->n_phi <= 0 || s->n_phi > UT_MAX_ELEV_TILES || (s->cull && (s->cull_az <= 0 || s->cull_el <= 0)))
+    return UT_ERR_ARG;
+  *bytes = table_layout(s->n_phi, s->cull ? s->cull_az : 0, s->cull ? s->cull_el : 0).total;
+  return UT_OK;
+}
+
+ut_status ut_sensor_build(ut_sensor* s, ut_stream stream) {
+  if (!s) return UT_ERR_ARG;
+  if (s->kind != UT_LIDAR) {
+    if (s->kind != UT_PINHOLE && s->kind != UT_FISHEYE && s->kind != UT_ORTHO) return UT_ERR_ARG;
+    if (s->width <= 0 || s->height <= 0) return UT_ERR_ARG;
+    s->max_tile_rays = UT_CAMERA_TILE * UT_CAMERA_TILE;
+    return UT_OK;
+  }
+  if (!s->beam_elev_host || !s->tables || s->n_beams <= 0 || s->n_az <= 0) return UT_ERR_ARG;
+  size_t bytes = 0;
+  ut_status st = ut_sensor_table_bytes(s, &bytes);
+  if (st != UT_OK) return st;
+  const int NP = s->n_phi;
+  std::vector<double> bounds(NP + 1);
+  std::vector<int32_t> bstart(NP + 1);
+  int32_t nth = 0;
+  st = ut_lidar_tiling(s->beam_elev_host, s->n_beams, s->n_az, NP, s->max_per_tile, bounds.data(), bstart.data(), &nth);
+  if (st != UT_OK) return st;
+  // largest number of rays in one tile
+  int max_beams = 0;
+  for (int k = 0; k < NP; ++k) max_beams = std::max(max_beams, bstart[k + 1] - bstart[k]);
+  int max_az = 0;
+  for (int j = 0; j < nth; ++j) {
+    const long long a0 = ((long long)j * s->n_az + nth - 1) / nth, a1 = ((long long)(j + 1) * s->n_az + nth - 1) / nth;
+    max_az = std::max(max_az, (int)(a1 - a0));
+  }
+  const int max_rays = max_beams * max_az;
+  if (max_rays > UT_MAX_LIDAR_TILE_RAYS) return UT_ERR_UNSUPPORTED;
+  const TableLayout t = table_layout(NP, s->cull ? s->cull_az : 0, s->cull ? s->cull_el : 0);
+  std::vector<char> host(t.total, 0);
+  std::memcpy(host.data() + t.bounds, bounds.data(), sizeof(double) * (NP + 1));
+  std::memcpy(host.data() + t.beam_start, bstart.data(), sizeof(int32_t) * (NP + 1));
+  if (s->cull) {
+    // ray mask over (cull_az azimuth cells over 360 deg) x (cull_el elevation cells over
+    // [T_0, T_N]); summed-area table sat[i][j] = occupied cells with az < i and el < j
+    const int CA = s->cull_az, CE = s->cull_el;
+    std::vector<uint8_t> mask((size_t)CA * CE, 0);
+    const double e0 = bounds[0], span = bounds[NP] - bounds[0];
+    for (int b = 0; b < s->n_beams; ++b) {
+      int ce = (int)std::floor(((double)s->beam_elev_host[b] - e0) * CE / span);
+      ce = std::min(std::max(ce, 0), CE - 1);
+      for (int a = 0; a < s->n_az; ++a) mask[(size_t)((long long)a * CA / s->n_az) * CE + ce] = 1;
+    }
+    int32_t* sat = reinterpret_cast<int32_t*>(host.data() + t.sat);
+    const size_t W = (size_t)CE + 1;
+    for (int i = 1; i <= CA; ++i) {
+      int32_t row = 0;
+      for (int j = 1; j <= CE; ++j) {
+        row += mask[(size_t)(i - 1) * CE + (j - 1)];
+        sat[i * W + j] = sat[(i - 1) * W + j] + row;
+      }
+    }
+  }
+  hipError_t e = hipMemcpyAsync(s->tables, host.data(), t.total, hipMemcpyHostToDevice, as_stream(stream));
+  if (e == hipSuccess) e = hipStreamSynchronize(as_stream(stream));
+  if (e != hipSuccess) return UT_ERR_DEVICE;
+  s->n_theta = nth;
+  s->max_tile_rays = max_rays;
+  return UT_OK;
+}
+
+int32_t ut_sensor_tiles(const ut_sensor* s) {
+  if (!s) return 0;
+  if (s->kind == UT_LIDAR) return s->n_phi * s->n_theta;
+  return camera_tiles_x(s) * camera_tiles_y(s);
+}
+
+int64_t ut_sensor_rays(const ut_sensor* s) {
+  if (!s) return 0;
+  if (s->kind == UT_LIDAR) return (int64_t)s->n_beams * s->n_az;
+  return (int64_t)s->width * s->height;
+}
+
+ut_status ut_project(const ut_gaussians* g, const ut_sensor* s, const double* ut_abk, ut_projected* out,
+                     ut_stream stream) {
+  if (!gaussians_ok(g) || !sensor_ok(s) || !ut_abk || !projected_ok(out, g ? g->n : 0)) return UT_ERR_ARG;
+  const SensorK k = make_sensor_k(s);
+  return from_hip(launch_project(*g, k, ut_abk, *out, as_stream(stream)));
+}
+
+size_t ut_workspace_bytes(uint64_t max_pairs, int32_t n_tiles, int32_t n_gaussians) {
+  return bin_workspace(nullptr, max_pairs, n_tiles, n_gaussians).bytes;
+}
+
+ut_status ut_bin_count(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws, size_t ws_bytes,
+                       uint64_t* n_pairs_host, ut_stream stream) {
+  if (n < 0 || !projected_ok(p, n) || !sensor_ok(s) || !ws) return UT_ERR_ARG;
+  BinWorkspace w = bin_workspace(ws, 0, ut_sensor_tiles(s), n);
+  if (w.bytes > ws_bytes) return UT_ERR_CAPACITY;
+  hipError_t e = launch_bin_count(*p, n, w, as_stream(stream));
+  if (e == hipSuccess && n_pairs_host)
+    e = hipMemcpyAsync(n_pairs_host, w.total, sizeof(uint64_t), hipMemcpyDeviceToHost, as_stream(stream));
+  return from_hip(e);
+}
+
+ut_status ut_bin_sort(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws, size_t ws_bytes,
+                      uint64_t n_pairs, ut_tile_lists* lists, ut_stream stream) {
+  if (n < 0 || !projected_ok(p, n) || !sensor_ok(s) || !ws || !lists || !lists->ranges ||
+      (n_pairs > 0 && !lists->gauss))
+    return UT_ERR_ARG;
+  if (n_pairs > lists->max_pairs || n_pairs >= 0xFFFFFFFFull) return UT_ERR_CAPACITY;
+  BinWorkspace w = bin_workspace(ws, n_pairs, ut_sensor_tiles(s), n);
+  if (w.bytes > ws_bytes) return UT_ERR_CAPACITY;
+  const SensorK k = make_sensor_k(s);
+  return from_hip(launch_bin_sort(*p, n, k, w, n_pairs, *lists, as_stream(stream)));
+}
+
+ut_status ut_bin_and_sort(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws, size_t ws_bytes,
+                          ut_tile_lists* lists, uint64_t* n_pairs, ut_stream stream) {
+  uint64_t P = 0;
+  ut_status st = ut_bin_count(p, n, s, ws, ws_bytes, &P, stream);
+  if (st != UT_OK) return st;
+  if (hipStreamSynchronize(as_stream(stream)) != hipSuccess) return UT_ERR_DEVICE;
+  if (n_pairs) *n_pairs = P;
+  return ut_bin_sort(p, n, s, ws, ws_bytes, P, lists, stream);
+}
+
+static ut_status composite_common(const ut_projected* p, const ut_tile_lists* lists, const ut_sensor* s,
+                                  const ut_render_params* prm, ut_render_out* out, ut_stream stream) {
+  if (!p || !p->records || !lists || !lists->ranges || !sensor_ok(s) || !params_ok(prm) || !out ||
+      !out->feat || !out->depth || !out->alpha)
+    return UT_ERR_ARG;
+  const SensorK k = make_sensor_k(s);
+  return from_hip(launch_composite(*p, *lists, k, make_params(prm), *out, s->max_tile_rays, as_stream(stream)));
+}
+
+ut_status ut_composite_camera(const ut_projected* p, const ut_tile_lists* lists, const ut_sensor* s,
+                              const ut_render_params* prm, ut_render_out* out, ut_stream stream) {
+  if (!s || s->kind == UT_LIDAR) return UT_ERR_ARG;
+  return composite_common(p, lists, s, prm, out, stream);
+}
+
+ut_status ut_composite_lidar(const ut_projected* p, const ut_tile_lists* lists, const ut_sensor* s,
+                             const ut_render_params* prm, ut_render_out* out, ut_stream stream) {
+  if (!s || s->kind != UT_LIDAR) return UT_ERR_ARG;
+  return composite_common(p, lists, s, prm, out, stream);
+}
+
+size_t ut_backward_workspace_bytes(int32_t n_gaussians) {
+  return (size_t)UT_ACC_FLOATS * sizeof(double) * (size_t)(n_gaussians > 0 ? n_gaussians : 1);
+}
+
+ut_status ut_composite_backward(const ut_gaussians* g, const ut_projected* p, const ut_tile_lists* lists,
+                                const ut_sensor* s, const ut_render_params* prm, const ut_render_out* fwd,
+                                const ut_upstream* up, void* acc_ws, size_t acc_ws_bytes,
+                                ut_gaussian_grads* grads, ut_stream stream) {
+  if (!gaussians_ok(g) || !p || !p->records || !lists || !lists->ranges || !sensor_ok(s) || !params_ok(prm) ||
+      !fwd || !fwd->feat || !fwd->t_final || !fwd->n_proc || !up || !acc_ws || !grads || !grads->mean ||
+      !grads->quat || !grads->log_scale || !grads->opacity_logit || !grads->feat)
+    return UT_ERR_ARG;
+  if (acc_ws_bytes < ut_backward_workspace_bytes(g->n)) return UT_ERR_CAPACITY;
+  const SensorK k = make_sensor_k(s);
+  return from_hip(launch_backward(*g, *p, *lists, k, make_params(prm), *fwd, *up, static_cast<double*>(acc_ws),
+                                  *grads, s->max_tile_rays, as_stream(stream)));
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------- batch
+namespace {
+
+__global__ void k_write_item(BatchItemK item, BatchItemK* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = item;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ut_batch_workspace_bytes(int32_t n_items) {
+  return 256 + sizeof(BatchItemK) * (size_t)(n_items > 0 ? n_items : 1);
+}
+
+ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items, const ut_render_params* prm,
+                             void* queue_ws, size_t ws_bytes, int32_t n_workgroups, ut_stream stream) {
+  if (!items || n_items <= 0 || !params_ok(prm) || !queue_ws || n_workgroups <= 0) return UT_ERR_ARG;
+  if (ws_bytes < ut_batch_workspace_bytes(n_items)) return UT_ERR_CAPACITY;
+  uint32_t* counter = static_cast<uint32_t*>(queue_ws);
+  BatchItemK* dev = reinterpret_cast<BatchItemK*>(static_cast<char*>(queue_ws) + 256);
+  int total = 0;
+  hipStream_t st = as_stream(stream);
+  for (int i = 0; i < n_items; ++i) {
+    const ut_batch_item& it = items[i];
+    if (!it.proj || !it.proj->records || !it.lists || !it.lists->ranges || !sensor_ok(it.sensor) || !it.out ||
+        !it.out->feat || !it.out->depth || !it.out->alpha)
+      return UT_ERR_ARG;
+  }
+  for (int i = 0; i < n_items; ++i) {
+    const ut_batch_item& it = items[i];
+    BatchItemK k;
+    std::memset(&k, 0, sizeof k);
+    k.s = make_sensor_k(it.sensor);
+    k.rec = reinterpret_cast<const Record*>(it.proj->records);
+    k.gauss = it.lists->gauss;
+    k.ranges = it.lists->ranges;
+    k.out = *it.out;
+    k.n_tiles = ut_sensor_tiles(it.sensor);
+    k.tile_base = total;
+    total += k.n_tiles;
+    hipLaunchKernelGGL(k_write_item, dim3(1), dim3(64), 0, st, k, dev + i);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return UT_ERR_DEVICE;
+  return from_hip(launch_composite_batch(dev, n_items, total, counter, make_params(prm), n_workgroups, st));
+}
+
+}  // extern "C"

@@ -1,0 +1,269 @@
+// backward.hip -- adjoint of the compositing with the forward's discrete structure fixed.
+//
+// k_backward: one workgroup per tile (same ray mapping as the forward).  The tile's list
+// is replayed from the largest n_proc of the workgroup down to 0, in LDS batches.  Each
+// lane recomputes its pair exactly as the forward did (same expressions), recovers
+// T_i = T_{i+1} / (1 - alpha_i) from the stored final transmittance, and keeps the suffix
+// sum S = sum_{j>i} w_j a_j.  Per pair it forms 13 partials (colour 3, opacity, mean 3,
+// the 6 unique entries of B = Sigma^{-1}); wavefronts whose lanes touched the particle
+// reduce them across 64 lanes and lane 0 adds them atomically (float64) into SoA
+// accumulators acc[13][n].
+// k_chain: one lane per particle, chain rule to (mean, quat, log_scale, logit, SH).
+#include "ut_internal.hpp"
+#include "ut_sh.hpp"
+
+namespace ut {
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __restrict__ rec,
+                                                     const uint32_t* __restrict__ gauss,
+                                                     const uint32_t* __restrict__ ranges, int n_tiles,
+                                                     RenderParamsK prm, ut_render_out fwd, ut_upstream up,
+                                                     double* __restrict__ acc, int n) {
+  __shared__ Record sh[BLOCK];
+  __shared__ uint32_t sh_g[BLOCK];
+  __shared__ uint32_t s_max;
+  const int tile = blockIdx.x;
+  const uint32_t start = ranges[tile];
+  const long long ray = tile_ray(s, tile, threadIdx.x);
+  const long long R = s.n_rays;
+  const double ox = s.o[0], oy = s.o[1], oz = s.o[2];
+  double dx = 0, dy = 0, dz = 0;
+  uint32_t np = 0;
+  double T = 1.0, gf0 = 0, gf1 = 0, gf2 = 0, gdep = 0, gom = 0;
+  if (ray >= 0) {
+    dx = s.ray_dir[ray];
+    dy = s.ray_dir[R + ray];
+    dz = s.ray_dir[2 * R + ray];
+    if (dx != 0 || dy != 0 || dz != 0) np = fwd.n_proc[ray];
+    T = fwd.t_final[ray];
+    if (up.feat) { gf0 = up.feat[ray]; gf1 = up.feat[R + ray]; gf2 = up.feat[2 * R + ray]; }
+    if (up.depth) gdep = up.depth[ray];
+    if (up.alpha) gom = up.alpha[ray];
+    if (up.drop && s.kind == UT_LIDAR) {
+      // drop = sigmoid(zeta_2 - zeta_1): d drop / d zeta_2 = p (1 - p) = -d drop / d zeta_1
+      const double z1 = fwd.feat[R + ray], z2 = fwd.feat[2 * R + ray];
+      const double p = 1.0 / (1.0 + exp(-(z2 - z1)));
+      const double gd = (double)up.drop[ray] * p * (1.0 - p);
+      gf1 -= gd;
+      gf2 += gd;
+    }
+  }
+  const double Tf = T;
+  const double cut_bias = 1e-3 - 2.0 * prm.log_alpha_min;
+  double S = 0.0;
+  if (threadIdx.x == 0) s_max = 0;
+  __syncthreads();
+  atomicMax(&s_max, np);
+  __syncthreads();
+  const int jmax = (int)s_max;
+  const int lane = __lane_id();
+
+  for (int hi = jmax; hi > 0; hi -= BLOCK) {
+    const int lo = hi > BLOCK ? hi - BLOCK : 0;
+    const int cnt = hi - lo;
+    __syncthreads();
+    for (int c = threadIdx.x; c < cnt * kRecordChunks; c += BLOCK) {
+      const int j = c / kRecordChunks, part = c - j * kRecordChunks;
+      const uint32_t g = gauss[start + lo + j];
+      reinterpret_cast<uint4*>(sh + j)[part] = reinterpret_cast<const uint4*>(rec + g)[part];
+      if (part == 0) sh_g[j] = g;
+    }
+    __syncthreads();
+    for (int jj = cnt - 1; jj >= 0; --jj) {
+      const int j = lo + jj;
+      if (__ballot(j < (int)np) == 0ull) continue;   // no lane of this wave visited entry j
+      const Record& r = sh[jj];
+      bool contrib = false;
+      double g[UT_ACC_FLOATS];
+#pragma unroll
+      for (int k = 0; k < UT_ACC_FLOATS; ++k) g[k] = 0.0;
+      if (j < (int)np) {
+        const double vx = r.mu[0] - ox, vy = r.mu[1] - oy, vz = r.mu[2] - oz;
+        const double b0 = r.b[0], b1 = r.b[1], b2 = r.b[2], b3 = r.b[3], b4 = r.b[4], b5 = r.b[5];
+        const double bdx = __builtin_fma(b0, dx, __builtin_fma(b3, dy, b4 * dz));
+        const double bdy = __builtin_fma(b3, dx, __builtin_fma(b1, dy, b5 * dz));
+        const double bdz = __builtin_fma(b4, dx, __builtin_fma(b5, dy, b2 * dz));
+        const double dBd = __builtin_fma(dx, bdx, __builtin_fma(dy, bdy, dz * bdz));
+        const double vBd = __builtin_fma(vx, bdx, __builtin_fma(vy, bdy, vz * bdz));
+        const double idBd = rcp_f64(dBd);
+        const double tau = vBd * idBd;
+        const double ux = __builtin_fma(-tau, dx, vx), uy = __builtin_fma(-tau, dy, vy), uz = __builtin_fma(-tau, dz, vz);
+        const double bux = __builtin_fma(b0, ux, __builtin_fma(b3, uy, b4 * uz));
+        const double buy = __builtin_fma(b3, ux, __builtin_fma(b1, uy, b5 * uz));
+        const double buz = __builtin_fma(b4, ux, __builtin_fma(b5, uy, b2 * uz));
+        const double D2 = __builtin_fma(ux, bux, __builtin_fma(uy, buy, uz * buz));
+        if (tau >= s.near_ && !(D2 > __builtin_fma(2.0, (double)r.log_sigma, cut_bias))) {
+          const double rho = exp_f64(-0.5 * D2);
+          const double a = r.sigma * rho;
+          const bool clamped = a > prm.alpha_max;
+          const double alpha = clamped ? prm.alpha_max : a;
+          if (alpha >= prm.alpha_min) {
+            contrib = true;
+            const double ioma = rcp_f64(1.0 - alpha);
+            const double Ti = T * ioma;
+            const double w = alpha * Ti;
+            const double ai = gf0 * r.feat[0] + gf1 * r.feat[1] + gf2 * r.feat[2] + gdep * tau;
+            const double dalpha = Ti * ai - S * ioma + gom * Tf * ioma;
+            S = __builtin_fma(w, ai, S);
+            T = Ti;
+            g[0] = gf0 * w;
+            g[1] = gf1 * w;
+            g[2] = gf2 * w;
+            const double dtau = gdep * w;
+            double dD2 = 0.0;
+            if (!clamped) {
+              g[3] = dalpha * rho;
+              dD2 = -0.5 * dalpha * r.sigma * rho;
+            }
+            const double t2 = 2.0 * dD2, ti = dtau * idBd;
+            g[4] = t2 * bux + ti * bdx;
+            g[5] = t2 * buy + ti * bdy;
+            g[6] = t2 * buz + ti * bdz;
+            g[7] = dD2 * ux * ux + ti * dx * ux;
+            g[8] = dD2 * uy * uy + ti * dy * uy;
+            g[9] = dD2 * uz * uz + ti * dz * uz;
+            g[10] = t2 * ux * uy + ti * (dx * uy + dy * ux);
+            g[11] = t2 * ux * uz + ti * (dx * uz + dz * ux);
+            g[12] = t2 * uy * uz + ti * (dy * uz + dz * uy);
+          }
+        }
+      }
+      if (__ballot(contrib)) {
+        const uint32_t gi = sh_g[jj];
+#pragma unroll
+        for (int k = 0; k < UT_ACC_FLOATS; ++k) {
+          const double v = wave_sum(g[k]);
+          if (lane == 0 && v != 0.0) unsafeAtomicAdd(acc + (size_t)k * n + gi, v);
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_chain(ut_gaussians g, SensorK s, const double* __restrict__ acc,
+                                                ut_gaussian_grads out) {
+  const int n = g.n;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int K = sh_count(g.sh_degree);
+  double a[UT_ACC_FLOATS];
+#pragma unroll
+  for (int k = 0; k < UT_ACC_FLOATS; ++k) a[k] = acc[(size_t)k * n + i];
+  const float q0 = g.quat[i], q1 = g.quat[n + i], q2 = g.quat[2 * n + i], q3 = g.quat[3 * n + i];
+  const float l0 = g.log_scale[i], l1 = g.log_scale[n + i], l2 = g.log_scale[2 * n + i];
+  const float lg = g.opacity_logit[i];
+  const double mx = g.mean[i], my = g.mean[n + i], mz = g.mean[2 * n + i];
+  const double qq = (double)q0 * q0 + (double)q1 * q1 + (double)q2 * q2 + (double)q3 * q3;
+  const bool ok = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(l0) && isfinite(l1) &&
+                  isfinite(l2) && isfinite(lg) && isfinite(qq) && qq > 0;
+  double dmean[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dls[3] = {0, 0, 0}, dlogit = 0;
+  double dcoef[16][3];
+  for (int k = 0; k < K; ++k) dcoef[k][0] = dcoef[k][1] = dcoef[k][2] = 0;
+  if (ok) {
+    const double qn = sqrt(qq), iq = 1.0 / qn;
+    const double w = q0 * iq, x = q1 * iq, y = q2 * iq, z = q3 * iq;
+    const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                         2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                         2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    const double sc[3] = {exp((double)l0), exp((double)l1), exp((double)l2)};
+    const double sigma = 1.0 / (1.0 + exp(-(double)lg));
+    dlogit = a[3] * sigma * (1.0 - sigma);
+    // unique-entry gradient of B -> full symmetric G
+    const double G[9] = {a[7], 0.5 * a[10], 0.5 * a[11], 0.5 * a[10], a[8], 0.5 * a[12], 0.5 * a[11], 0.5 * a[12], a[9]};
+    // B = R D R^T, D = diag(1/s^2): dL/dR = 2 G R D, dL/dD_jj = (R^T G R)_jj
+    double GR[9];
+    for (int r = 0; r < 3; ++r)
+      for (int j = 0; j < 3; ++j) {
+        const double gr = G[r * 3] * R[j] + G[r * 3 + 1] * R[3 + j] + G[r * 3 + 2] * R[6 + j];
+        GR[r * 3 + j] = gr;
+      }
+    double dR[9];
+    for (int r = 0; r < 3; ++r)
+      for (int j = 0; j < 3; ++j) dR[r * 3 + j] = 2.0 * GR[r * 3 + j] / (sc[j] * sc[j]);
+    for (int j = 0; j < 3; ++j) {
+      const double rtgr = R[j] * GR[j] + R[3 + j] * GR[3 + j] + R[6 + j] * GR[6 + j];
+      dls[j] = -2.0 * rtgr / (sc[j] * sc[j]);
+    }
+    // R(q_hat) -> q_hat
+    const double dw = 2 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    const double dxq = 2 * (y * dR[1] + z * dR[2] + y * dR[3] - 2 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] - 2 * x * dR[8]);
+    const double dyq = 2 * (-2 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] - 2 * y * dR[8]);
+    const double dzq = 2 * (-2 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2 * z * dR[4] + y * dR[5] + x * dR[6] + y * dR[7]);
+    const double dot = dw * w + dxq * x + dyq * y + dzq * z;
+    dq[0] = (dw - w * dot) * iq;
+    dq[1] = (dxq - x * dot) * iq;
+    dq[2] = (dyq - y * dot) * iq;
+    dq[3] = (dzq - z * dot) * iq;
+    // features: SH coefficients and the direction's dependence on the mean
+    const double vx = mx - s.o[0], vy = my - s.o[1], vz = mz - s.o[2];
+    const double len = sqrt(vx * vx + vy * vy + vz * vz);
+    double ex = 0, ey = 0, ez = 1;
+    if (len > 0) { ex = vx / len; ey = vy / len; ez = vz / len; }
+    double Y[16], GY[16][3];
+    sh_basis(g.sh_degree, ex, ey, ez, Y);
+    sh_basis_grad(g.sh_degree, ex, ey, ez, GY);
+    double ddir[3] = {0, 0, 0};
+    for (int c = 0; c < 3; ++c) {
+      double dc = a[c];
+      if (g.feat_kind == UT_FEAT_CAMERA) {
+        double f = 0;
+        for (int k = 0; k < K; ++k) f += (double)g.feat[(size_t)(k * 3 + c) * n + i] * Y[k];
+        if (!(f + 0.5 > 0)) dc = 0;
+      }
+      for (int k = 0; k < K; ++k) {
+        dcoef[k][c] = dc * Y[k];
+        const double coef = g.feat[(size_t)(k * 3 + c) * n + i];
+        ddir[0] += dc * coef * GY[k][0];
+        ddir[1] += dc * coef * GY[k][1];
+        ddir[2] += dc * coef * GY[k][2];
+      }
+    }
+    dmean[0] = a[4]; dmean[1] = a[5]; dmean[2] = a[6];
+    if (len > 0) {
+      const double dd = ddir[0] * ex + ddir[1] * ey + ddir[2] * ez;
+      dmean[0] += (ddir[0] - ex * dd) / len;
+      dmean[1] += (ddir[1] - ey * dd) / len;
+      dmean[2] += (ddir[2] - ez * dd) / len;
+    }
+  }
+  for (int c = 0; c < 3; ++c) out.mean[(size_t)c * n + i] = (float)dmean[c];
+  for (int c = 0; c < 4; ++c) out.quat[(size_t)c * n + i] = (float)dq[c];
+  for (int c = 0; c < 3; ++c) out.log_scale[(size_t)c * n + i] = (float)dls[c];
+  out.opacity_logit[i] = (float)dlogit;
+  for (int k = 0; k < K; ++k)
+    for (int c = 0; c < 3; ++c) out.feat[(size_t)(k * 3 + c) * n + i] = (float)dcoef[k][c];
+}
+
+}  // namespace
+
+hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const ut_tile_lists& lists,
+                           const SensorK& s, const RenderParamsK& prm, const ut_render_out& fwd,
+                           const ut_upstream& up, double* acc, const ut_gaussian_grads& grads,
+                           int max_tile_rays, hipStream_t st) {
+  hipError_t e = fill_f64(acc, 0.0, (size_t)UT_ACC_FLOATS * g.n, st);
+  if (e != hipSuccess || g.n == 0) return e;
+  const int n_tiles = s.tiles_x * s.tiles_y;
+  const Record* rec = reinterpret_cast<const Record*>(p.records);
+  if (n_tiles > 0) {
+    if (s.kind != UT_LIDAR || max_tile_rays > 128)
+      hipLaunchKernelGGL(k_backward<256>, dim3(n_tiles), dim3(256), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, fwd, up, acc, g.n);
+    else if (max_tile_rays > 64)
+      hipLaunchKernelGGL(k_backward<128>, dim3(n_tiles), dim3(128), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, fwd, up, acc, g.n);
+    else
+      hipLaunchKernelGGL(k_backward<64>, dim3(n_tiles), dim3(64), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, fwd, up, acc, g.n);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_chain, dim3((g.n + 255) / 256), dim3(256), 0, st, g, s, acc, grads);
+  return hipGetLastError();
+}
+
+}  // namespace ut

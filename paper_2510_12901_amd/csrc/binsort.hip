@@ -1,0 +1,369 @@
+// binsort.hip -- tile binning and depth sort.
+//
+// Order of work (all device, one HIP stream):
+//   1. stable LSD radix sort of the particles by their float32 depth key (4 x 8-bit passes);
+//   2. tile counts gathered in depth order, exclusive scan (uint64) -> pair offsets, total P;
+//   3. pairs emitted in depth order by whole wavefronts (prefix offsets + binary search, so
+//      a particle touching thousands of tiles is spread over 64 lanes and writes coalesce);
+//   4. stable LSD radix sort of the pairs by tile id only (ceil(log2 n_tiles) bits).
+// Sorting by depth first and then stably by tile yields exactly the (tile, depth, index)
+// order with far fewer pair passes than sorting 64-bit (tile, depth) keys.
+#include "ut_internal.hpp"
+
+namespace ut {
+
+// ---------------------------------------------------------------------------------- fills
+namespace {
+template <typename T>
+__global__ void k_fill(T* p, T v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+template <typename T>
+hipError_t fill(T* p, T v, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st) { return fill(p, v, n, st); }
+hipError_t fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t st) { return fill(p, v, n, st); }
+hipError_t fill_f64(double* p, double v, size_t n, hipStream_t st) { return fill(p, v, n, st); }
+
+namespace {
+
+// 32/64-bit lane shuffles (uint64_t is unsigned long here; HIP overloads take long long)
+__device__ __forceinline__ uint32_t shfl_up_t(uint32_t x, int d) { return __shfl_up(x, d); }
+__device__ __forceinline__ uint64_t shfl_up_t(uint64_t x, int d) {
+  return (uint64_t)__shfl_up((unsigned long long)x, d);
+}
+
+// ---------------------------------------------------------------------------------- scan
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// exclusive scan of one value per thread across a 256-thread block; returns the block total
+template <typename T>
+__device__ __forceinline__ T block_exclusive(T v, T* sh /*[4]*/, T& total) {
+  const int lane = __lane_id(), wave = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T y = shfl_up_t(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  T before = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    const T s = sh[w];
+    if (w < wave) before += s;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return before + x - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T* __restrict__ in, size_t n, T* __restrict__ sums) {
+  __shared__ T sh[4];
+  const size_t base = (size_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) s += in[base + k];
+  T total;
+  block_exclusive<T>(s, sh, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// single-block exclusive scan of the block sums, chunk by chunk with a running carry
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(T* sums, size_t nb, T* total_out) {
+  __shared__ T sh[4];
+  T carry = 0;
+  for (size_t base = 0; base < nb; base += kScanThreads) {
+    const size_t i = base + threadIdx.x;
+    const T v = i < nb ? sums[i] : 0;
+    T tot;
+    const T ex = block_exclusive<T>(v, sh, tot);
+    if (i < nb) sums[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const T* __restrict__ in, T* __restrict__ out, size_t n,
+                                                               const T* __restrict__ sums) {
+  __shared__ T sh[4];
+  const size_t base = (size_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  T v[kScanItems];
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < n ? in[base + k] : 0;
+    s += v[k];
+  }
+  T total;
+  T run = block_exclusive<T>(s, sh, total) + sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+}
+
+// in-place exclusive scan of n elements; aux needs ceil(n/1024) elements; *total_out = sum
+template <typename T>
+hipError_t exclusive_scan(T* data, size_t n, T* aux, T* total_out, hipStream_t st) {
+  const size_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, st, data, n, aux);
+  hipLaunchKernelGGL(k_scan_sums<T>, dim3(1), dim3(kScanThreads), 0, st, aux, nb, total_out);
+  hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, st, data, data, n, aux);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------- radix
+constexpr int kRadix = 256;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys, size_t n, int shift,
+                                                              uint32_t* __restrict__ hist, int nblocks) {
+  __shared__ uint32_t h[kRadix];
+  for (int i = threadIdx.x; i < kRadix; i += kSortThreads) h[i] = 0;
+  __syncthreads();
+  const size_t base = (size_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+  for (int k = 0; k < kSortItems; ++k) {
+    const size_t idx = base + (size_t)k * kSortThreads + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & (kRadix - 1)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kRadix; i += kSortThreads) hist[(size_t)i * nblocks + blockIdx.x] = h[i];
+}
+
+// Stable scatter.  Items of a block are taken in rounds of 256 in index order; inside a
+// round each wavefront ranks its lanes among equal digits with 8 ballots (peer masks), the
+// highest peer publishes the wave's count, and waves are ordered by index in LDS.
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* __restrict__ kin,
+                                                                 const uint32_t* __restrict__ vin,
+                                                                 uint32_t* __restrict__ kout,
+                                                                 uint32_t* __restrict__ vout, size_t n,
+                                                                 int shift, const uint32_t* __restrict__ hist,
+                                                                 int nblocks) {
+  __shared__ uint32_t base_off[kRadix];
+  __shared__ uint32_t wave_cnt[kSortThreads / 64][kRadix];
+  const int lane = __lane_id(), wave = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < kRadix; i += kSortThreads) base_off[i] = hist[(size_t)i * nblocks + blockIdx.x];
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const size_t tile = (size_t)blockIdx.x * kSortTile;
+  for (int k = 0; k < kSortItems; ++k) {
+    for (int i = threadIdx.x; i < (kSortThreads / 64) * kRadix; i += kSortThreads) (&wave_cnt[0][0])[i] = 0;
+    __syncthreads();
+    const size_t idx = tile + (size_t)k * kSortThreads + threadIdx.x;
+    const bool valid = idx < n;
+    const uint32_t key = valid ? kin[idx] : 0u;
+    const uint32_t digit = (key >> shift) & (kRadix - 1);
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (digit >> b) & 1u;
+      const unsigned long long m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    const bool leader = valid && (peers >> lane) == 1ull;
+    if (leader) wave_cnt[wave][digit] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t off = base_off[digit] + rank;
+      for (int w = 0; w < wave; ++w) off += wave_cnt[w][digit];
+      kout[off] = key;
+      vout[off] = vin[idx];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kRadix; i += kSortThreads) {
+      uint32_t add = 0;
+#pragma unroll
+      for (int w = 0; w < kSortThreads / 64; ++w) add += wave_cnt[w][i];
+      base_off[i] += add;
+    }
+    __syncthreads();
+  }
+}
+
+// Sorts (k, v) pairs of length n by the low `bits` bits of k, stable.  Buffers ping-pong;
+// *k_res / *v_res receive the buffers holding the result.
+hipError_t radix_sort(uint32_t* kA, uint32_t* kB, uint32_t* vA, uint32_t* vB, size_t n, int bits,
+                      uint32_t* hist, uint64_t* aux, hipStream_t st, uint32_t** k_res, uint32_t** v_res) {
+  *k_res = kA;
+  *v_res = vA;
+  if (n == 0) return hipSuccess;
+  const int nb = (int)((n + kSortTile - 1) / kSortTile);
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, st, kA, n, shift, hist, nb);
+    hipError_t e = exclusive_scan<uint32_t>(hist, (size_t)kRadix * nb, reinterpret_cast<uint32_t*>(aux), nullptr, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortThreads), 0, st, kA, vA, kB, vB, n, shift, hist, nb);
+    std::swap(kA, kB);
+    std::swap(vA, vB);
+  }
+  *k_res = kA;
+  *v_res = vA;
+  return hipGetLastError();
+}
+
+int radix_passes(int bits) { return (bits + 7) / 8; }
+
+// ---------------------------------------------------------------------------------- binning
+__global__ void k_init_depth(const uint32_t* __restrict__ key, uint32_t* __restrict__ dk, uint32_t* __restrict__ dv, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) { dk[i] = key[i]; dv[i] = (uint32_t)i; }
+}
+
+__global__ void k_gather_counts(const uint32_t* __restrict__ order, const uint32_t* __restrict__ count,
+                                uint64_t* __restrict__ offs, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) offs[i] = count[order[i]];
+}
+
+// One wavefront emits the pairs of 64 consecutive depth-ordered particles, 64 pairs per step.
+__global__ __launch_bounds__(256) void k_duplicate(const uint32_t* __restrict__ order, const uint64_t* __restrict__ offs,
+                                                    const uint32_t* __restrict__ count, const int32_t* __restrict__ rect,
+                                                    int n, int tiles_x, int wrap_x, uint32_t* __restrict__ pair_tile,
+                                                    uint32_t* __restrict__ pair_gauss) {
+  __shared__ uint32_t s_off[4][64], s_g[4][64];
+  __shared__ int s_x0[4][64], s_y0[4][64], s_w[4][64];
+  const int lane = __lane_id(), wave = threadIdx.x >> 6;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const bool valid = j < n;
+  uint32_t gi = 0, c = 0;
+  uint64_t off = 0;
+  if (valid) {
+    gi = order[j];
+    c = count[gi];
+    off = offs[j];
+  }
+  const uint64_t wbase = (uint64_t)__shfl((unsigned long long)off, 0);
+  const uint32_t local = (uint32_t)(off - wbase);
+  uint32_t end = valid ? local + c : 0u;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) end = max(end, (uint32_t)__shfl_xor(end, o));
+  const uint32_t wave_total = end;
+  s_off[wave][lane] = valid ? local : wave_total;
+  s_g[wave][lane] = gi;
+  if (valid && c) {
+    const int x0 = rect[gi], y0 = rect[n + gi], x1 = rect[2 * n + gi];
+    s_x0[wave][lane] = x0;
+    s_y0[wave][lane] = y0;
+    s_w[wave][lane] = x1 - x0 + 1;
+  } else {
+    s_x0[wave][lane] = 0; s_y0[wave][lane] = 0; s_w[wave][lane] = 1;
+  }
+  __syncthreads();
+  for (uint32_t p = lane; p < wave_total; p += 64) {
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+      if (s_off[wave][lo + step] <= p) lo += step;
+    const uint32_t q = p - s_off[wave][lo];
+    const int w = s_w[wave][lo];
+    const int y = s_y0[wave][lo] + (int)(q / (uint32_t)w);
+    int x = s_x0[wave][lo] + (int)(q % (uint32_t)w);
+    if (wrap_x && x >= tiles_x) x -= tiles_x;
+    pair_tile[wbase + p] = (uint32_t)(y * tiles_x + x);
+    pair_gauss[wbase + p] = s_g[wave][lo];
+  }
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ tiles, uint64_t P, uint32_t* __restrict__ ranges, int n_tiles) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  const uint32_t t = tiles[i];
+  if (i == 0 || tiles[i - 1] != t) ranges[t] = (uint32_t)i;
+  if (i == P - 1 || tiles[i + 1] != t) ranges[n_tiles + t] = (uint32_t)(i + 1);
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int tile_bits(int n_tiles) {
+  int b = 1;
+  while (b < 31 && (1u << b) < (uint32_t)n_tiles) ++b;
+  return b;
+}
+
+}  // namespace
+
+// Layout: the regions the count step uses depend on n only and come first; the pair
+// buffers (sized by max_pairs) come last, so ut_bin_count can run before P is known.
+BinWorkspace bin_workspace(void* base, uint64_t max_pairs, int n_tiles, int n) {
+  (void)n_tiles;
+  BinWorkspace w;
+  char* p = static_cast<char*>(base);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { char* r = p ? p + o : nullptr; o += align256(bytes); return r; };
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  const size_t mp = (size_t)(max_pairs > 0 ? max_pairs : 1);
+  w.dkA = reinterpret_cast<uint32_t*>(take(4 * nn));
+  w.dkB = reinterpret_cast<uint32_t*>(take(4 * nn));
+  w.dvA = reinterpret_cast<uint32_t*>(take(4 * nn));
+  w.dvB = reinterpret_cast<uint32_t*>(take(4 * nn));
+  w.offs = reinterpret_cast<uint64_t*>(take(8 * (nn + 1)));
+  w.total = reinterpret_cast<uint64_t*>(take(8));
+  const size_t nb = (std::max(nn, mp) + kSortTile - 1) / kSortTile;
+  w.hist = reinterpret_cast<uint32_t*>(take(4 * (size_t)kRadix * nb));
+  const size_t scan_len = std::max((size_t)kRadix * nb, nn + 1);
+  w.scan_aux = reinterpret_cast<uint64_t*>(take(8 * ((scan_len + kScanTile - 1) / kScanTile + 1)));
+  if (max_pairs > 0) {
+    w.tkA = reinterpret_cast<uint32_t*>(take(4 * mp));
+    w.tkB = reinterpret_cast<uint32_t*>(take(4 * mp));
+    w.tv = reinterpret_cast<uint32_t*>(take(4 * mp));
+  } else {
+    w.tkA = w.tkB = w.tv = nullptr;
+  }
+  w.bytes = o;
+  return w;
+}
+
+hipError_t launch_bin_count(const ut_projected& p, int n, BinWorkspace& ws, hipStream_t st) {
+  hipError_t e = fill_u64(ws.total, 0, 1, st);
+  if (e != hipSuccess || n == 0) return e;
+  const int blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_init_depth, dim3(blocks), dim3(256), 0, st, p.key, ws.dkA, ws.dvA, n);
+  uint32_t *kr, *vr;
+  e = radix_sort(ws.dkA, ws.dkB, ws.dvA, ws.dvB, (size_t)n, 32, ws.hist, ws.scan_aux, st, &kr, &vr);
+  if (e != hipSuccess) return e;
+  // 4 passes: the result is back in the A buffers
+  hipLaunchKernelGGL(k_gather_counts, dim3(blocks), dim3(256), 0, st, ws.dvA, p.count, ws.offs, n);
+  return exclusive_scan<uint64_t>(ws.offs, (size_t)n, ws.scan_aux, ws.total, st);
+}
+
+hipError_t launch_bin_sort(const ut_projected& p, int n, const SensorK& s, BinWorkspace& ws,
+                           uint64_t n_pairs, const ut_tile_lists& lists, hipStream_t st) {
+  const int n_tiles = s.tiles_x * s.tiles_y;
+  hipError_t e = fill_u32(lists.ranges, 0u, 2 * (size_t)n_tiles, st);
+  if (e != hipSuccess || n_pairs == 0 || n == 0) return e;
+  const int bits = tile_bits(n_tiles);
+  // place the emitted pair values so that the last radix pass writes into lists.gauss
+  uint32_t* v_first = (radix_passes(bits) % 2) ? ws.tv : lists.gauss;
+  uint32_t* v_second = (radix_passes(bits) % 2) ? lists.gauss : ws.tv;
+  const int blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(256), 0, st, ws.dvA, ws.offs, p.count, p.rect, n,
+                     s.tiles_x, s.kind == UT_LIDAR ? 1 : 0, ws.tkA, v_first);
+  uint32_t *kr, *vr;
+  e = radix_sort(ws.tkA, ws.tkB, v_first, v_second, (size_t)n_pairs, bits, ws.hist, ws.scan_aux, st, &kr, &vr);
+  if (e != hipSuccess) return e;
+  const unsigned rb = (unsigned)((n_pairs + 255) / 256);
+  hipLaunchKernelGGL(k_ranges, dim3(rb), dim3(256), 0, st, kr, n_pairs, lists.ranges, n_tiles);
+  return hipGetLastError();
+}
+
+}  // namespace ut

@@ -1,0 +1,268 @@
+// project.hip -- per-particle sigma-point projection (one lane per particle).
+//
+// Loads are structure-of-arrays and coalesced; the arithmetic is float64 (on gfx950 a
+// float64 FMA costs the same issue slot as an unpacked float32 FMA, and the stage is
+// bound by HBM traffic: ~(11 + 3K) floats in, 96 + 28 bytes out per particle).
+#include "ut_internal.hpp"
+#include "ut_sh.hpp"
+
+namespace ut {
+namespace {
+
+// Sensor map g(x) of one world point: (u, v) and validity (see utrast.h for each model).
+__device__ __forceinline__ bool project_point(const SensorK& s, const double xw[3], double& u, double& v) {
+  const double dx = xw[0] - s.o[0], dy = xw[1] - s.o[1], dz = xw[2] - s.o[2];
+  const double x = s.R[0] * dx + s.R[1] * dy + s.R[2] * dz;
+  const double y = s.R[3] * dx + s.R[4] * dy + s.R[5] * dz;
+  const double z = s.R[6] * dx + s.R[7] * dy + s.R[8] * dz;
+  if (s.kind == UT_PINHOLE) {
+    if (!(z > s.near_)) return false;
+    const double iz = 1.0 / z;
+    u = s.fx * x * iz + s.cx;
+    v = s.fy * y * iz + s.cy;
+    return true;
+  }
+  if (s.kind == UT_ORTHO) {
+    if (!(z > s.near_)) return false;
+    u = s.fx * x + s.cx;
+    v = s.fy * y + s.cy;
+    return true;
+  }
+  const double rho2 = x * x + y * y;
+  const double r = sqrt(rho2 + z * z);
+  if (!(r > s.near_)) return false;
+  const double rho = sqrt(rho2);
+  if (s.kind == UT_FISHEYE) {
+    const double theta = atan2(rho, z);
+    if (!(theta <= s.theta_max)) return false;
+    const double t2 = theta * theta;
+    const double td = theta * (1.0 + t2 * (s.k[0] + t2 * (s.k[1] + t2 * (s.k[2] + t2 * s.k[3]))));
+    if (rho > 0) {
+      const double f = td / rho;
+      u = s.cx + s.fx * f * x;
+      v = s.cy + s.fy * f * y;
+    } else {
+      u = s.cx;
+      v = s.cy;
+    }
+    return true;
+  }
+  // spinning LiDAR (Eq. 3): azimuth in [0, 2 pi), elevation
+  double phi = atan2(y, x);
+  if (phi < 0) phi += 2 * kPi;
+  u = phi;
+  v = atan2(z, rho);
+  return true;
+}
+
+// summed-area-table count over inclusive culling cells [x0,x1] x [y0,y1] (Alg. 2)
+__device__ __forceinline__ long sat_count(const SensorK& s, int x0, int x1, int y0, int y1) {
+  const long W = s.cull_el + 1;
+  const int* S = s.sat;
+  return (long)S[(x1 + 1) * W + (y1 + 1)] - S[(long)x0 * W + (y1 + 1)] - S[(x1 + 1) * W + y0] +
+         S[(long)x0 * W + y0];
+}
+
+// float32 squared distance to the sensor origin, fixed operation order, no contraction
+__device__ __forceinline__ uint32_t depth_key(float mx, float my, float mz, const float o[3]) {
+#pragma clang fp contract(off)
+  const float dx = __fsub_rn(mx, o[0]);
+  const float dy = __fsub_rn(my, o[1]);
+  const float dz = __fsub_rn(mz, o[2]);
+  const float k = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+  return __float_as_uint(k);
+}
+
+__global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, double ut_a, double ut_b,
+                                                  double ut_k, Record* __restrict__ rec,
+                                                  int32_t* __restrict__ rect, uint32_t* __restrict__ key,
+                                                  uint32_t* __restrict__ count, float* __restrict__ moments,
+                                                  uint32_t* __restrict__ n_culled) {
+  const int n = g.n;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int invalid = 0, raycull = 0;
+  if (i < n) {
+    const float mx = g.mean[i], my = g.mean[n + i], mz = g.mean[2 * n + i];
+    const float q0 = g.quat[i], q1 = g.quat[n + i], q2 = g.quat[2 * n + i], q3 = g.quat[3 * n + i];
+    const float l0 = g.log_scale[i], l1 = g.log_scale[n + i], l2 = g.log_scale[2 * n + i];
+    const float lg = g.opacity_logit[i];
+    const double qq = (double)q0 * q0 + (double)q1 * q1 + (double)q2 * q2 + (double)q3 * q3;
+    bool ok = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(l0) && isfinite(l1) &&
+              isfinite(l2) && isfinite(lg) && isfinite(qq) && qq > 0;
+    Record r;
+    r.mu[0] = mx; r.mu[1] = my; r.mu[2] = mz;
+    double Rm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, sc[3] = {1, 1, 1};
+    double sigma = 0;
+    if (ok) {
+      const double inv = 1.0 / sqrt(qq);
+      const double w = q0 * inv, x = q1 * inv, y = q2 * inv, z = q3 * inv;
+      Rm[0] = 1 - 2 * (y * y + z * z); Rm[1] = 2 * (x * y - w * z);     Rm[2] = 2 * (x * z + w * y);
+      Rm[3] = 2 * (x * y + w * z);     Rm[4] = 1 - 2 * (x * x + z * z); Rm[5] = 2 * (y * z - w * x);
+      Rm[6] = 2 * (x * z - w * y);     Rm[7] = 2 * (y * z + w * x);     Rm[8] = 1 - 2 * (x * x + y * y);
+      sc[0] = exp((double)l0); sc[1] = exp((double)l1); sc[2] = exp((double)l2);
+      sigma = 1.0 / (1.0 + exp(-(double)lg));
+    }
+    // B = R diag(1/s^2) R^T
+    const double is0 = 1.0 / (sc[0] * sc[0]), is1 = 1.0 / (sc[1] * sc[1]), is2 = 1.0 / (sc[2] * sc[2]);
+    r.b[0] = Rm[0] * Rm[0] * is0 + Rm[1] * Rm[1] * is1 + Rm[2] * Rm[2] * is2;
+    r.b[1] = Rm[3] * Rm[3] * is0 + Rm[4] * Rm[4] * is1 + Rm[5] * Rm[5] * is2;
+    r.b[2] = Rm[6] * Rm[6] * is0 + Rm[7] * Rm[7] * is1 + Rm[8] * Rm[8] * is2;
+    r.b[3] = Rm[0] * Rm[3] * is0 + Rm[1] * Rm[4] * is1 + Rm[2] * Rm[5] * is2;
+    r.b[4] = Rm[0] * Rm[6] * is0 + Rm[1] * Rm[7] * is1 + Rm[2] * Rm[8] * is2;
+    r.b[5] = Rm[3] * Rm[6] * is0 + Rm[4] * Rm[7] * is1 + Rm[5] * Rm[8] * is2;
+    r.sigma = sigma;
+    r.log_sigma = ok ? (float)log(sigma) : -1e30f;
+
+    // unscented transform over 7 sigma points
+    double m0 = 0, m1 = 0, c00 = 0, c01 = 0, c11 = 0;
+    if (ok) {
+      const double lam = ut_a * ut_a * (3.0 + ut_k) - 3.0;
+      const double cpl = 3.0 + lam;
+      ok = cpl > 0;
+      if (ok) {
+        const double gam = sqrt(cpl);
+        double gu[7], gv[7];
+        const double mu[3] = {r.mu[0], r.mu[1], r.mu[2]};
+        ok = project_point(s, mu, gu[0], gv[0]);
+        for (int j = 0; j < 3 && ok; ++j) {
+          const double e0 = gam * sc[j] * Rm[j], e1 = gam * sc[j] * Rm[3 + j], e2 = gam * sc[j] * Rm[6 + j];
+          const double pp[3] = {mu[0] + e0, mu[1] + e1, mu[2] + e2};
+          const double pm[3] = {mu[0] - e0, mu[1] - e1, mu[2] - e2};
+          ok = project_point(s, pp, gu[1 + j], gv[1 + j]) && project_point(s, pm, gu[4 + j], gv[4 + j]);
+        }
+        if (ok) {
+          if (s.kind == UT_LIDAR) {
+            for (int k = 1; k < 7; ++k) {
+              while (gu[k] - gu[0] > kPi) gu[k] -= 2 * kPi;
+              while (gu[k] - gu[0] <= -kPi) gu[k] += 2 * kPi;
+            }
+          }
+          const double wm0 = lam / cpl, wc0 = lam / cpl + 1.0 - ut_a * ut_a + ut_b, wi = 1.0 / (2.0 * cpl);
+          m0 = wm0 * gu[0];
+          m1 = wm0 * gv[0];
+          for (int k = 1; k < 7; ++k) { m0 += wi * gu[k]; m1 += wi * gv[k]; }
+          for (int k = 0; k < 7; ++k) {
+            const double w = k == 0 ? wc0 : wi;
+            const double du = gu[k] - m0, dv = gv[k] - m1;
+            c00 += w * du * du;
+            c01 += w * du * dv;
+            c11 += w * dv * dv;
+          }
+          ok = isfinite(c00) && isfinite(c11) && c00 >= 0 && c11 >= 0;
+        }
+      }
+    }
+    invalid = !ok;
+
+    int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
+    uint32_t cnt = 0;
+    if (ok) {
+      const double eu = 3.0 * sqrt(c00), ev = 3.0 * sqrt(c11);
+      if (s.kind != UT_LIDAR) {
+        const double T = UT_CAMERA_TILE;
+        double fx0 = floor((m0 - eu) / T), fx1 = floor((m0 + eu) / T);
+        double fy0 = floor((m1 - ev) / T), fy1 = floor((m1 + ev) / T);
+        if (!(fx1 < 0 || fy1 < 0 || fx0 > s.tiles_x - 1 || fy0 > s.tiles_y - 1)) {
+          x0 = (int)fmax(fx0, 0.0); y0 = (int)fmax(fy0, 0.0);
+          x1 = (int)fmin(fx1, (double)(s.tiles_x - 1)); y1 = (int)fmin(fy1, (double)(s.tiles_y - 1));
+          cnt = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+        }
+      } else {
+        const double lo = m1 - ev, hi = m1 + ev;
+        const int NP = s.n_phi;
+        if (!(hi < s.bounds[0] || lo > s.bounds[NP])) {
+          int e0 = 0, e1 = 0;
+          for (int k = 1; k < NP; ++k) {
+            const double tk = s.bounds[k];
+            if (tk <= lo) e0 = k;
+            if (tk <= hi) e1 = k;
+          }
+          const double two_pi = 2 * kPi;
+          // an extent of at least 2 pi covers every azimuth tile (and keeps the casts in range)
+          const bool full_az = eu >= kPi;
+          long a0 = full_az ? 0 : (long)floor((m0 - eu) * s.n_theta / two_pi);
+          long a1 = full_az ? s.n_theta - 1 : (long)floor((m0 + eu) * s.n_theta / two_pi);
+          if (a1 - a0 + 1 >= s.n_theta) { a0 = 0; a1 = s.n_theta - 1; }
+          else {
+            const long w0 = ((a0 % s.n_theta) + s.n_theta) % s.n_theta;
+            a1 = w0 + (a1 - a0);
+            a0 = w0;
+          }
+          x0 = (int)a0; x1 = (int)a1; y0 = e0; y1 = e1;
+          cnt = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+          if (s.cull) {
+            // Alg. 2 / Alg. 3: is any ray inside the extent on the denser culling grid?
+            const double span = s.bounds[NP] - s.bounds[0];
+            const long ca0 = full_az ? 0 : (long)floor((m0 - eu) * s.cull_az / two_pi);
+            const long ca1 = full_az ? s.cull_az - 1 : (long)floor((m0 + eu) * s.cull_az / two_pi);
+            const int ce0 = (int)fmax(floor((lo - s.bounds[0]) * s.cull_el / span), 0.0);
+            const int ce1 = (int)fmin(floor((hi - s.bounds[0]) * s.cull_el / span), (double)(s.cull_el - 1));
+            long occ = 0;
+            if (ce0 <= ce1) {
+              if (ca1 - ca0 + 1 >= s.cull_az) occ = sat_count(s, 0, s.cull_az - 1, ce0, ce1);
+              else {
+                const long w0 = ((ca0 % s.cull_az) + s.cull_az) % s.cull_az;
+                const long w1 = w0 + (ca1 - ca0);
+                if (w1 < s.cull_az) occ = sat_count(s, (int)w0, (int)w1, ce0, ce1);
+                else occ = sat_count(s, (int)w0, s.cull_az - 1, ce0, ce1) +
+                           sat_count(s, 0, (int)(w1 - s.cull_az), ce0, ce1);
+              }
+            }
+            if (occ == 0) { cnt = 0; raycull = 1; }
+          }
+        }
+      }
+    }
+
+    // features: SH at the unit direction from the sensor origin to the mean
+    double f[3] = {0, 0, 0};
+    if (ok) {
+      const double vx = r.mu[0] - s.o[0], vy = r.mu[1] - s.o[1], vz = r.mu[2] - s.o[2];
+      const double len = sqrt(vx * vx + vy * vy + vz * vz);
+      double dx = 0, dy = 0, dz = 1;
+      if (len > 0) { const double il = 1.0 / len; dx = vx * il; dy = vy * il; dz = vz * il; }
+      double Y[16];
+      sh_basis(g.sh_degree, dx, dy, dz, Y);
+      const int K = sh_count(g.sh_degree);
+      for (int c = 0; c < 3; ++c) {
+        double acc = 0;
+        for (int k = 0; k < K; ++k) acc += (double)g.feat[(size_t)(k * 3 + c) * n + i] * Y[k];
+        f[c] = (g.feat_kind == UT_FEAT_CAMERA) ? (acc + 0.5 > 0 ? acc + 0.5 : 0.0) : acc;
+      }
+    }
+    r.feat[0] = (float)f[0]; r.feat[1] = (float)f[1]; r.feat[2] = (float)f[2];
+
+    const uint4* src = reinterpret_cast<const uint4*>(&r);
+    uint4* dst = reinterpret_cast<uint4*>(rec + i);
+#pragma unroll
+    for (int c = 0; c < kRecordChunks; ++c) dst[c] = src[c];
+    rect[i] = x0; rect[n + i] = y0; rect[2 * n + i] = x1; rect[3 * n + i] = y1;
+    count[i] = cnt;
+    key[i] = depth_key(mx, my, mz, s.of);
+    if (moments) {
+      moments[i] = (float)m0; moments[n + i] = (float)m1;
+      moments[2 * n + i] = (float)c00; moments[3 * n + i] = (float)c01; moments[4 * n + i] = (float)c11;
+    }
+  }
+  const unsigned long long mi = __ballot(invalid), mr = __ballot(raycull);
+  if (__lane_id() == 0) {
+    if (mi) atomicAdd(&n_culled[0], (uint32_t)__popcll(mi));
+    if (mr) atomicAdd(&n_culled[1], (uint32_t)__popcll(mr));
+  }
+}
+
+}  // namespace
+
+hipError_t launch_project(const ut_gaussians& g, const SensorK& s, const double abk[3],
+                          const ut_projected& out, hipStream_t st) {
+  hipError_t e = fill_u32(out.n_culled, 0u, 2, st);
+  if (e != hipSuccess) return e;
+  if (g.n == 0) return hipSuccess;
+  const int blocks = (g.n + 255) / 256;
+  hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, st, g, s, abk[0], abk[1], abk[2],
+                     reinterpret_cast<Record*>(out.records), out.rect, out.key, out.count,
+                     out.moments, out.n_culled);
+  return hipGetLastError();
+}
+
+}  // namespace ut

@@ -1,0 +1,117 @@
+// ut_device.hpp -- device-side types and helpers shared by the gfx950 kernels.
+//
+// Design notes (MI355X / CDNA4):
+// * Geometry and accumulation are float64.  On gfx950 a float64 FMA issues at the same
+//   rate as an unpacked float32 FMA (packed float32 is disabled at build time), so the
+//   compositing loop pays register space and LDS bytes for float64, not VALU cycles.
+// * Wave64 everywhere: ballots are 64-bit, reductions run over 64 lanes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "utrast.h"
+
+namespace ut {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Per-particle compositing record written by the projection, read (gathered) by the
+// compositing and adjoint kernels.  96 bytes = six 16-byte chunks.
+struct alignas(16) Record {
+  double mu[3];     // mean (exact copy of the float32 input)
+  double b[6];      // Sigma^{-1}: xx, yy, zz, xy, xz, yz
+  double sigma;     // opacity
+  float feat[3];    // colour or LiDAR features evaluated at the particle's SH direction
+  float log_sigma;  // ln(opacity), for the conservative alpha_min pre-test
+};
+static_assert(sizeof(Record) == UT_RECORD_BYTES, "record size must match the ABI");
+constexpr int kRecordChunks = UT_RECORD_BYTES / 16;
+
+// Sensor description passed to kernels by value.
+struct SensorK {
+  int kind;
+  double R[9];
+  double o[3];
+  float of[3];
+  double near_;
+  int width, height, tiles_x, tiles_y;
+  double fx, fy, cx, cy, k[4], theta_max;
+  int n_beams, n_az, n_phi, n_theta;
+  int cull, cull_az, cull_el;
+  const double* bounds;     // [n_phi+1]
+  const int* beam_start;    // [n_phi+1]
+  const int* sat;           // [(cull_az+1)*(cull_el+1)]
+  const float* ray_dir;     // [3][R]
+  long long n_rays;
+};
+
+// Byte layout of the LiDAR device tables (bounds, beam_start, sat), 256-byte aligned parts.
+struct TableLayout {
+  size_t bounds, beam_start, sat, total;
+};
+inline TableLayout table_layout(int n_phi, int cull_az, int cull_el) {
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  TableLayout t;
+  t.bounds = 0;
+  t.beam_start = al(sizeof(double) * (n_phi + 1));
+  t.sat = t.beam_start + al(sizeof(int) * (n_phi + 1));
+  t.total = t.sat + al(sizeof(int) * (size_t)(cull_az + 1) * (cull_el + 1));
+  return t;
+}
+
+// exp(x) for x <= 0 in float64: Cody-Waite reduction x = n ln2 + r with a two-part ln2
+// (the high part keeps 32 significant bits so n * hi is exact), then the Taylor series of
+// e^r to degree 12 (truncation < 2e-16 for |r| <= ln2/2), then scaling by 2^n.
+__device__ __forceinline__ double exp_f64(double x) {
+  const double kLog2e = 1.4426950408889634;
+  const double kLn2Hi = 0.6931471803691238;
+  const double kLn2Lo = 1.9082149292705877e-10;
+  const double n = __builtin_rint(x * kLog2e);
+  double r = __builtin_fma(-n, kLn2Hi, x);
+  r = __builtin_fma(-n, kLn2Lo, r);
+  double p = 1.0 / 479001600.0;
+  p = __builtin_fma(p, r, 1.0 / 39916800.0);
+  p = __builtin_fma(p, r, 1.0 / 3628800.0);
+  p = __builtin_fma(p, r, 1.0 / 362880.0);
+  p = __builtin_fma(p, r, 1.0 / 40320.0);
+  p = __builtin_fma(p, r, 1.0 / 5040.0);
+  p = __builtin_fma(p, r, 1.0 / 720.0);
+  p = __builtin_fma(p, r, 1.0 / 120.0);
+  p = __builtin_fma(p, r, 1.0 / 24.0);
+  p = __builtin_fma(p, r, 1.0 / 6.0);
+  p = __builtin_fma(p, r, 0.5);
+  p = __builtin_fma(p, r, 1.0);
+  p = __builtin_fma(p, r, 1.0);
+  return __builtin_ldexp(p, (int)n);
+}
+
+// 1/x in float64 from the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rcp_f64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// Rays of a tile: camera 16x16 pixel block; LiDAR beams of the elevation tile times the
+// azimuth steps a with floor(a N_theta / n_az) == azimuth tile.  Returns -1 past the end.
+__device__ __forceinline__ long long tile_ray(const SensorK& s, int tile, int r) {
+  if (s.kind != UT_LIDAR) {
+    const int tx = tile % s.tiles_x, ty = tile / s.tiles_x;
+    const int px = tx * UT_CAMERA_TILE + (r & (UT_CAMERA_TILE - 1));
+    const int py = ty * UT_CAMERA_TILE + (r >> 4);
+    if (r >= UT_CAMERA_TILE * UT_CAMERA_TILE || px >= s.width || py >= s.height) return -1;
+    return (long long)py * s.width + px;
+  }
+  const int j = tile % s.n_theta, k = tile / s.n_theta;
+  const int b0 = s.beam_start[k], b1 = s.beam_start[k + 1];
+  const long long A = s.n_az, NT = s.n_theta;
+  const int a0 = (int)((j * A + NT - 1) / NT), a1 = (int)(((j + 1) * A + NT - 1) / NT);
+  const int naz = a1 - a0;
+  if (naz <= 0 || r >= (b1 - b0) * naz) return -1;
+  return (long long)(b0 + r / naz) * s.n_az + (a0 + r % naz);
+}
+
+}  // namespace ut

@@ -1,0 +1,59 @@
+// ut_internal.hpp -- launchers shared between the kernel files and the C-ABI layer.
+#pragma once
+
+#include "ut_device.hpp"
+
+namespace ut {
+
+// Plain fill kernels (used instead of hipMemsetAsync so the calls stay graph-capturable).
+hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
+hipError_t fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t st);
+hipError_t fill_f64(double* p, double v, size_t n, hipStream_t st);
+
+hipError_t launch_project(const ut_gaussians& g, const SensorK& s, const double abk[3],
+                          const ut_projected& out, hipStream_t st);
+
+// Workspace carve-up of the binning stage.
+struct BinWorkspace {
+  uint32_t *dkA, *dkB, *dvA, *dvB;   // depth sort keys / values, ping-pong [n]
+  uint64_t* offs;                    // [n + 1] counts in depth order -> exclusive offsets
+  uint32_t *tkA, *tkB, *tv;          // pair tile keys ping-pong, pair value scratch [max_pairs]
+  uint32_t* hist;                    // radix histograms
+  uint64_t* scan_aux;                // block sums of the device scans
+  uint64_t* total;                   // pair total
+  size_t bytes;
+};
+BinWorkspace bin_workspace(void* base, uint64_t max_pairs, int n_tiles, int n);
+
+hipError_t launch_bin_count(const ut_projected& p, int n, BinWorkspace& ws, hipStream_t st);
+hipError_t launch_bin_sort(const ut_projected& p, int n, const SensorK& s, BinWorkspace& ws,
+                           uint64_t n_pairs, const ut_tile_lists& lists, hipStream_t st);
+
+struct RenderParamsK {
+  double alpha_min, alpha_max, t_min, log_alpha_min;
+};
+
+hipError_t launch_composite(const ut_projected& p, const ut_tile_lists& lists, const SensorK& s,
+                            const RenderParamsK& prm, const ut_render_out& out, int max_tile_rays,
+                            hipStream_t st);
+
+// Batched persistent compositing over several requests.
+struct BatchItemK {
+  SensorK s;
+  const Record* rec;
+  const uint32_t* gauss;
+  const uint32_t* ranges;
+  ut_render_out out;
+  int n_tiles;
+  int tile_base;   // prefix over items of n_tiles
+};
+hipError_t launch_composite_batch(const BatchItemK* items_dev, int n_items, int total_tiles,
+                                  uint32_t* counter, const RenderParamsK& prm, int n_workgroups,
+                                  hipStream_t st);
+
+hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const ut_tile_lists& lists,
+                           const SensorK& s, const RenderParamsK& prm, const ut_render_out& fwd,
+                           const ut_upstream& up, double* acc, const ut_gaussian_grads& grads,
+                           int max_tile_rays, hipStream_t st);
+
+}  // namespace ut

@@ -1,0 +1,314 @@
+"""Python binding of the C-ABI: device buffers are torch CUDA (HIP) tensors, every step of
+the render runs in libutrast.so.  No CPU fallback exists; without the library or a GPU the
+calls raise."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _abi as A
+from ._abi import check, lib, ref
+
+ALPHA_MIN = 1.0 / 255.0
+ALPHA_MAX = 0.99
+T_MIN = 1e-4
+UT_ABK = (1.0, 2.0, 0.0)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _require_cuda(t: torch.Tensor, dtype, name):
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+
+
+# ---------------------------------------------------------------------------- particles
+@dataclass
+class GaussianSet:
+    """Device-resident particles, structure-of-arrays float32 (see utrast.h)."""
+    mean: torch.Tensor          # [3, N]
+    quat: torch.Tensor          # [4, N]
+    log_scale: torch.Tensor     # [3, N]
+    opacity_logit: torch.Tensor  # [N]
+    feat: torch.Tensor          # [K, 3, N]
+    sh_degree: int
+    feat_kind: int
+
+    @property
+    def n(self) -> int:
+        return int(self.mean.shape[1])
+
+    @classmethod
+    def from_numpy(cls, g: dict, device="cuda") -> "GaussianSet":
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=device)
+        return cls(t(g["mean"]), t(g["quat"]), t(g["log_scale"]), t(g["opacity_logit"]), t(g["feat"]),
+                   int(g["sh_degree"]), int(g["feat_kind"]))
+
+    def with_params(self, mean, quat, log_scale, opacity_logit, feat) -> "GaussianSet":
+        return GaussianSet(mean, quat, log_scale, opacity_logit, feat, self.sh_degree, self.feat_kind)
+
+    def c(self) -> A.UtGaussians:
+        for name in ("mean", "quat", "log_scale", "opacity_logit", "feat"):
+            _require_cuda(getattr(self, name), torch.float32, name)
+        return A.UtGaussians(self.mean.data_ptr(), self.quat.data_ptr(), self.log_scale.data_ptr(),
+                             self.opacity_logit.data_ptr(), self.feat.data_ptr(), self.n,
+                             self.sh_degree, self.feat_kind)
+
+
+# ---------------------------------------------------------------------------- sensors
+class Sensor:
+    """A sensor definition with its device ray table and (LiDAR) tiling/culling tables,
+    built once (ut_sensor_build) and reused across renders."""
+
+    def __init__(self, desc: dict, device="cuda"):
+        self.desc = desc
+        c = A.UtSensor()
+        c.kind = int(desc["kind"])
+        c.R_sw[:] = [float(x) for x in np.asarray(desc["R_sw"], np.float32).ravel()]
+        c.origin[:] = [float(x) for x in np.asarray(desc["origin"], np.float32)]
+        c.near_ = float(desc.get("near", 0.1))
+        self.ray_dir = torch.as_tensor(np.ascontiguousarray(desc["ray_dir"], np.float32), device=device)
+        c.ray_dir = self.ray_dir.data_ptr()
+        self._keep = []
+        if c.kind == A.LIDAR:
+            be = np.ascontiguousarray(desc["beam_elev"], np.float32)
+            self._keep.append(be)
+            c.beam_elev_host = be.ctypes.data
+            c.n_beams, c.n_az = len(be), int(desc["n_az"])
+            c.n_phi, c.max_per_tile = int(desc["n_phi"]), int(desc["max_per_tile"])
+            c.cull = int(bool(desc.get("cull", True)))
+            c.cull_az, c.cull_el = int(desc.get("cull_az", 1600)), int(desc.get("cull_el", 8 * c.n_phi))
+        else:
+            c.width, c.height = int(desc["width"]), int(desc["height"])
+            c.fx, c.fy, c.cx, c.cy = (float(desc[k]) for k in ("fx", "fy", "cx", "cy"))
+            c.k[:] = [float(x) for x in desc.get("k", [0, 0, 0, 0])]
+            c.theta_max = float(desc.get("theta_max", 0.0))
+        nb = C.c_size_t(0)
+        check(lib().ut_sensor_table_bytes(ref(c), C.byref(nb)), "ut_sensor_table_bytes")
+        self.tables = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=device)
+        c.tables = self.tables.data_ptr()
+        check(lib().ut_sensor_build(ref(c), _stream()), "ut_sensor_build")
+        self.c = c
+        self.kind = c.kind
+        self.n_tiles = int(lib().ut_sensor_tiles(ref(c)))
+        self.n_rays = int(lib().ut_sensor_rays(ref(c)))
+        self.max_tile_rays = int(c.max_tile_rays)
+
+    @property
+    def is_lidar(self) -> bool:
+        return self.kind == A.LIDAR
+
+    def image_shape(self):
+        if self.is_lidar:
+            return (self.c.n_beams, self.c.n_az)
+        return (self.c.height, self.c.width)
+
+
+def lidar_tiling(beam_elev, n_az, n_phi, M):
+    be = np.ascontiguousarray(beam_elev, np.float32)
+    bounds = np.zeros(n_phi + 1, np.float64)
+    bstart = np.zeros(n_phi + 1, np.int32)
+    nth = C.c_int32(0)
+    check(lib().ut_lidar_tiling(be.ctypes.data, len(be), n_az, n_phi, M, bounds.ctypes.data,
+                                bstart.ctypes.data, C.byref(nth)), "ut_lidar_tiling")
+    return bounds, bstart, int(nth.value)
+
+
+# ---------------------------------------------------------------------------- stages
+@dataclass
+class Projection:
+    records: torch.Tensor
+    rect: torch.Tensor
+    key: torch.Tensor
+    count: torch.Tensor
+    moments: torch.Tensor | None
+    n_culled: torch.Tensor
+    n: int
+    _c: A.UtProjected = field(default=None, repr=False)
+
+    def c(self) -> A.UtProjected:
+        if self._c is None:
+            self._c = A.UtProjected(self.records.data_ptr(), self.rect.data_ptr(), self.key.data_ptr(),
+                                    self.count.data_ptr(),
+                                    self.moments.data_ptr() if self.moments is not None else None,
+                                    self.n_culled.data_ptr())
+        return self._c
+
+
+def alloc_projection(n: int, device="cuda", moments=False) -> Projection:
+    nn = max(n, 1)
+    return Projection(torch.empty(nn * A.RECORD_BYTES, dtype=torch.uint8, device=device),
+                      torch.empty((4, nn), dtype=torch.int32, device=device),
+                      torch.empty(nn, dtype=torch.int32, device=device),
+                      torch.empty(nn, dtype=torch.int32, device=device),
+                      torch.empty((5, nn), dtype=torch.float32, device=device) if moments else None,
+                      torch.empty(2, dtype=torch.int32, device=device), n)
+
+
+def project(g: GaussianSet, sensor: Sensor, abk=UT_ABK, moments=False, out: Projection | None = None,
+            stream=None) -> Projection:
+    p = out if out is not None else alloc_projection(g.n, g.mean.device, moments)
+    gc = g.c()
+    abk_arr = (C.c_double * 3)(*abk)
+    check(lib().ut_project(ref(gc), ref(sensor.c), C.cast(abk_arr, C.c_void_p), ref(p.c()), _stream(stream)),
+          "ut_project")
+    return p
+
+
+@dataclass
+class TileLists:
+    gauss: torch.Tensor
+    ranges: torch.Tensor
+    n_pairs: int
+    _c: A.UtTileLists = field(default=None, repr=False)
+
+    def c(self) -> A.UtTileLists:
+        if self._c is None:
+            self._c = A.UtTileLists(self.gauss.data_ptr(), self.ranges.data_ptr(), int(self.gauss.numel()))
+        return self._c
+
+
+class Workspace:
+    """Growable device workspace; growth keeps the leading bytes (the count stage's results)."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = torch.empty(256, dtype=torch.uint8, device=device)
+
+    def ensure(self, nbytes: int, keep: int = 0) -> torch.Tensor:
+        if self.buf.numel() < nbytes:
+            new = torch.empty(int(nbytes * 1.25) + 256, dtype=torch.uint8, device=self.device)
+            if keep:
+                new[:keep].copy_(self.buf[:keep])
+            self.buf = new
+        return self.buf
+
+
+_default_ws: dict = {}
+
+
+def _ws(device) -> Workspace:
+    key = str(device)
+    if key not in _default_ws:
+        _default_ws[key] = Workspace(device)
+    return _default_ws[key]
+
+
+def bin_and_sort(p: Projection, sensor: Sensor, ws: Workspace | None = None, stream=None) -> TileLists:
+    """Two-phase binning: count (pair total read back), then sort into exact-size lists."""
+    dev = p.records.device
+    ws = ws or _ws(dev)
+    L = lib()
+    need0 = int(L.ut_workspace_bytes(0, sensor.n_tiles, p.n))
+    buf = ws.ensure(need0)
+    total = torch.zeros(1, dtype=torch.int64).pin_memory()
+    st = _stream(stream)
+    check(L.ut_bin_count(ref(p.c()), p.n, ref(sensor.c), buf.data_ptr(), buf.numel(), total.data_ptr(), st),
+          "ut_bin_count")
+    (stream or torch.cuda.current_stream()).synchronize()
+    P = int(total.item())
+    need = int(L.ut_workspace_bytes(P, sensor.n_tiles, p.n))
+    buf = ws.ensure(need, keep=need0)
+    lists = TileLists(torch.empty(max(P, 1), dtype=torch.int32, device=dev),
+                      torch.empty((2, sensor.n_tiles), dtype=torch.int32, device=dev), P)
+    check(L.ut_bin_sort(ref(p.c()), p.n, ref(sensor.c), buf.data_ptr(), buf.numel(), P, ref(lists.c()), st),
+          "ut_bin_sort")
+    return lists
+
+
+def render_params(alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX, t_min=T_MIN) -> A.UtRenderParams:
+    return A.UtRenderParams(alpha_min, alpha_max, t_min)
+
+
+@dataclass
+class RenderOut:
+    feat: torch.Tensor      # [3, R]
+    depth: torch.Tensor     # [R]
+    alpha: torch.Tensor     # [R]
+    drop: torch.Tensor | None
+    t_final: torch.Tensor | None
+    n_proc: torch.Tensor | None
+    _c: A.UtRenderOut = field(default=None, repr=False)
+
+    def c(self) -> A.UtRenderOut:
+        if self._c is None:
+            self._c = A.UtRenderOut(self.feat.data_ptr(), self.depth.data_ptr(), self.alpha.data_ptr(),
+                                    _ptr(self.drop), _ptr(self.t_final), _ptr(self.n_proc))
+        return self._c
+
+
+def alloc_out(sensor: Sensor, device="cuda", state=True) -> RenderOut:
+    R = sensor.n_rays
+    return RenderOut(torch.empty((3, R), dtype=torch.float32, device=device),
+                     torch.empty(R, dtype=torch.float32, device=device),
+                     torch.empty(R, dtype=torch.float32, device=device),
+                     torch.empty(R, dtype=torch.float32, device=device) if sensor.is_lidar else None,
+                     torch.empty(R, dtype=torch.float64, device=device) if state else None,
+                     torch.empty(R, dtype=torch.int32, device=device) if state else None)
+
+
+def composite(p: Projection, lists: TileLists, sensor: Sensor, params=None, out: RenderOut | None = None,
+              state=True, stream=None) -> RenderOut:
+    o = out if out is not None else alloc_out(sensor, p.records.device, state)
+    prm = params or render_params()
+    fn = lib().ut_composite_lidar if sensor.is_lidar else lib().ut_composite_camera
+    check(fn(ref(p.c()), ref(lists.c()), ref(sensor.c), ref(prm), ref(o.c()), _stream(stream)), "ut_composite")
+    return o
+
+
+def render(g: GaussianSet, sensor: Sensor, abk=UT_ABK, params=None, state=True, moments=False, stream=None):
+    """project -> bin_and_sort -> composite; returns (projection, lists, outputs)."""
+    p = project(g, sensor, abk, moments=moments, stream=stream)
+    lists = bin_and_sort(p, sensor, stream=stream)
+    out = composite(p, lists, sensor, params, state=state, stream=stream)
+    return p, lists, out
+
+
+def backward(g: GaussianSet, p: Projection, lists: TileLists, sensor: Sensor, fwd: RenderOut,
+             up_feat=None, up_depth=None, up_alpha=None, up_drop=None, params=None, stream=None) -> dict:
+    """Adjoint: gradients of sum(upstream * outputs) with respect to the particle parameters."""
+    dev = g.mean.device
+    prm = params or render_params()
+    acc = torch.empty(int(lib().ut_backward_workspace_bytes(g.n)), dtype=torch.uint8, device=dev)
+    grads = dict(mean=torch.empty_like(g.mean), quat=torch.empty_like(g.quat),
+                 log_scale=torch.empty_like(g.log_scale), opacity_logit=torch.empty_like(g.opacity_logit),
+                 feat=torch.empty_like(g.feat))
+    gg = A.UtGaussianGrads(*(grads[k].data_ptr() for k in ("mean", "quat", "log_scale", "opacity_logit", "feat")))
+    keep = [t.contiguous().float() if t is not None else None for t in (up_feat, up_depth, up_alpha, up_drop)]
+    up = A.UtUpstream(*(_ptr(t) for t in keep))
+    gc = g.c()
+    check(lib().ut_composite_backward(ref(gc), ref(p.c()), ref(lists.c()), ref(sensor.c), ref(prm), ref(fwd.c()),
+                                      ref(up), acc.data_ptr(), acc.numel(), ref(gg), _stream(stream)),
+          "ut_composite_backward")
+    return grads
+
+
+def composite_batch(items, params=None, n_workgroups=None, ws: torch.Tensor | None = None, stream=None):
+    """One persistent launch compositing several (projection, lists, sensor, out) requests."""
+    n = len(items)
+    prm = params or render_params()
+    arr = (A.UtBatchItem * n)()
+    keep = []
+    for i, (p, lists, sensor, out) in enumerate(items):
+        pc, lc, oc = p.c(), lists.c(), out.c()
+        keep += [pc, lc, oc]
+        arr[i] = A.UtBatchItem(ref(pc), ref(lc), ref(sensor.c), ref(oc))
+    need = int(lib().ut_batch_workspace_bytes(n))
+    dev = items[0][0].records.device
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    if n_workgroups is None:
+        n_workgroups = 256 * 4
+    check(lib().ut_composite_batch(C.cast(arr, C.c_void_p), n, ref(prm), ws.data_ptr(), ws.numel(), n_workgroups, _stream(stream)),
+          "ut_composite_batch")
+    return ws
