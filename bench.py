@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Benchmark of the UT Gaussian rasterizer on one MI355X.
+
+Workload (the multi-sensor simulation frame): 2,000,000 particles resident in HBM, one frame
+= 4 pinhole cameras 1920x1080 + 2 fisheye cameras 1920x1280 + 1 spinning LiDAR 128x2048
+(13,471,744 rays).  A timed step renders one frame through the whole hot path for every
+sensor: sigma-point projection (+ LiDAR ray culling), depth/tile radix sorts and tile
+lists, compositing.  Inputs are seeded and synthetic and already resident when timing
+starts.  Prints ONE JSON line (see the design doc for every field).
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6        # MI355X dense float64 vector (FMA = 2 FLOPs)
+PEAK_HBM_GBS = 8000.0
+# float64 FLOPs the compositing kernel spends on every visited (ray, list entry): the
+# response geometry v, B d, d.Bd, v.Bd, 1/d.Bd (2 Newton steps), t*, u, B u, D^2 -- see
+# the design doc; contributing pairs cost ~42 FLOPs more (exp, alpha, accumulation), not counted.
+FLOPS_PER_VISIT = 64
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "composite_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("composite.hip", "ut_device.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2510_12901_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--particles", type=int, default=2_000_000)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--served-seconds", type=float, default=3.0)
+    ap.add_argument("--vehicles", type=str, default="1,4,8")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 1 GiB device copy (reference kernel for HBM counters)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the rasterizer has no multi-GPU path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2510_12901_amd as ut
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    t_setup = time.time()
+    g_np, gl_np, sensors_np = synth.scene_multisensor(args.seed, n=args.particles)
+    g = ut.GaussianSet.from_numpy(g_np, dev)
+    gl = ut.GaussianSet(g.mean, g.quat, g.log_scale, g.opacity_logit,
+                        torch.as_tensor(gl_np["feat"], device=dev), 0, synth.FEAT_LIDAR)
+    sensors = [ut.Sensor(s, dev) for s in sensors_np]
+    pipes = [ut.SensorPipeline(gl if s.is_lidar else g, s) for s in sensors]
+    rays_per_frame = sum(s.n_rays for s in sensors)
+    log(f"setup {time.time() - t_setup:.1f}s, rays/frame {rays_per_frame}")
+
+    stream = torch.cuda.current_stream()
+
+    def frame(events=None):
+        for i, p in enumerate(pipes):
+            p.run(stream, None if events is None else events[i])
+
+    for _ in range(args.warmup):
+        frame()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    # ------------------------------------------------------------------ timed plain frames
+    K = args.steps
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in pipes]
+          for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        frame(ev[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / K
+    value = rays_per_frame * K / (t1 - t0) / 1e6
+    comp_ms = np.array([[e[0].elapsed_time(e[1]) for e in evk] for evk in ev])   # [K, sensors]
+    log(f"plain frame {ms_per_step:.2f} ms, {value:.1f} Mrays/s")
+
+    # visited list entries (untimed pass with per-ray state)
+    visits, launches = 0, 0
+    state_out = []
+    for p in pipes:
+        o = ut.alloc_out(p.sensor, dev, state=True)
+        ut.composite(p.p, p.lists, p.sensor, p.params, out=o)
+        state_out.append(o)
+    torch.cuda.synchronize()
+    for o in state_out:
+        visits += int(o.n_proc.to(torch.int64).sum().item())
+    per_launch_ms = float(comp_ms.mean())
+    flops_per_launch = visits * FLOPS_PER_VISIT / len(pipes)
+    achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
+    pairs = [p.n_pairs for p in pipes]
+
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC):
+        prof = json.load(open(PROFILE_TRAFFIC))
+        if prof.get("kernel_source_hash") == kernel_source_hash() and prof.get("workload") == "multisensor":
+            traffic = prof.get("bytes_per_launch")
+
+    result = {
+        "metric": "Mrays/s rendered (camera+LiDAR) and served p50/p99 frame latency vs plain",
+        "value": round(value, 2),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "multisensor frame: 2,000,000 particles (SH degree 3 colour + LiDAR features), "
+                               "4 pinhole 1920x1080 + 2 fisheye 1920x1280 + 1 LiDAR 128x2048",
+                   "particles": args.particles, "rays_per_frame": rays_per_frame, "seed": args.seed,
+                   "pairs_per_sensor": pairs},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+                     "kernel": "k_composite (camera and LiDAR compositing)",
+                     "flops_per_visit": FLOPS_PER_VISIT, "visits_per_frame": visits,
+                     "avg_launch_ms": round(per_launch_ms, 4)},
+        "composite_ms_per_sensor": [round(float(x), 4) for x in comp_ms.mean(axis=0)],
+    }
+
+    if not args.no_backward:
+        result["backward"] = bench_backward(ut, synth, dev, args)
+    if not args.no_served:
+        from paper_2510_12901_amd import serve
+        result["served"] = serve.bench_served(g, gl, sensors_np, sensors, dev, args, log)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(g_np, gl_np, sensors_np, log)
+    print(json.dumps(result), flush=True)
+
+
+def bench_backward(ut, synth, dev, args):
+    """Forward + adjoint of the 1,000,000-particle pinhole 1920x1080 scene with the L1 upstream."""
+    import torch
+    g_np, s_np = synth.scene_pinhole_large(args.seed)
+    g = ut.GaussianSet.from_numpy(g_np, dev)
+    s = ut.Sensor(s_np, dev)
+    target = torch.as_tensor(synth.l1_target(7, (3, s.n_rays)), device=dev)
+    pipe = ut.SensorPipeline(g, s, state=True)
+
+    def step():
+        out = pipe.run()
+        up = torch.sign(out.feat - target) / out.feat.numel()
+        return ut.backward(g, pipe.p, pipe.lists, s, out, up_feat=up)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    n = 5
+    t0 = time.perf_counter()
+    for _ in range(n):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / n
+    return {"workload": "1,000,000 particles, pinhole 1920x1080, forward + adjoint of mean L1",
+            "ms_per_step": round(ms, 3), "mrays_per_s": round(s.n_rays / ms / 1e3, 2), "pairs": pipe.n_pairs}
+
+
+def cpu_baseline(g_np, gl_np, sensors_np, log):
+    """The oracle (FP64, OpenMP over rays/tiles) on a bounded sample of the frame: the LiDAR
+    rendered in full and one pinhole camera with every 8th ray composited (its projection and
+    binning in full)."""
+    import oracle
+    t0 = time.perf_counter()
+    lid = [s for s in sensors_np if s["kind"] == 2][0]
+    cam = [s for s in sensors_np if s["kind"] == 0][0]
+    rays = 0
+    og_l = oracle.OracleGaussians(gl_np)
+    os_l = oracle.OracleSensor(lid)
+    _, _, out = oracle.render(og_l, os_l)
+    rays += os_l.n_rays
+    og_c = oracle.OracleGaussians(g_np)
+    os_c = oracle.OracleSensor(cam)
+    pr = oracle.project(og_c, os_c)
+    lists = oracle.bin_pairs(os_c, pr["rect"], pr["count"], pr["key"])
+    ids = np.arange(0, os_c.n_rays, 8)
+    oracle.composite_rays(og_c, os_c, lists, ids)
+    rays += len(ids)
+    dt = time.perf_counter() - t0
+    log(f"cpu baseline {dt:.1f}s for {rays} rays")
+    return {"value": round(rays / dt / 1e6, 4), "unit": "Mrays/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "2,000,000-particle frame: LiDAR 128x2048 in full + pinhole 1920x1080 every 8th ray "
+                      "(projection and binning in full)", "seconds": round(dt, 2), "rays": rays}
+
+
+if __name__ == "__main__":
+    main()

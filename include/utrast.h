@@ -205,23 +205,30 @@ int64_t ut_sensor_rays(const ut_sensor* s);
 ut_status ut_project(const ut_gaussians* g, const ut_sensor* s, const double* ut_abk,
                      ut_projected* out, ut_stream stream);
 
-/* Workspace bytes for binning n particles into at most max_pairs (tile, particle) pairs
- * over n_tiles tiles. */
+/* Workspace sizes of the binning stage.  The count workspace depends on the particle count
+ * only; the pair workspace on the pair total P reported by ut_bin_count, so a scheduler can
+ * reserve it after counting.  ut_workspace_bytes = count + pair bytes for max_pairs (one
+ * buffer, as ut_bin_and_sort takes it). */
+size_t ut_count_workspace_bytes(int32_t n_gaussians);
+size_t ut_pair_workspace_bytes(uint64_t n_pairs);
 size_t ut_workspace_bytes(uint64_t max_pairs, int32_t n_tiles, int32_t n_gaussians);
 
 /* Tile binning and depth sort (Sec. 3.2, tiling as in 3DGS).  Step 1 (ut_bin_count,
- * asynchronous): stable radix sort of the visible particles by depth key, exclusive scan
- * of their tile counts; the pair total P is left in the workspace and, if n_pairs_host is
- * non-NULL, copied there asynchronously (use pinned memory; read it after the stream is
- * synchronised).  Step 2 (ut_bin_sort, asynchronous): with P known on the host, emit
- * the pairs in depth order, stable radix sort them by tile, and write the tile ranges.
- * Returns UT_ERR_CAPACITY if P > lists->max_pairs (nothing enqueued).
- * ut_bin_and_sort runs both and synchronises the stream in between; *n_pairs (host,
- * may be NULL) receives P.  ws: device workspace of ws_bytes >= ut_workspace_bytes(). */
+ * asynchronous): stable radix sort of the particles by depth key, exclusive scan of their
+ * tile counts in that order; the pair total P stays in the count workspace ws and, if
+ * n_pairs_host is non-NULL, is copied there asynchronously (pinned memory; read it after
+ * the stream is synchronised).  Step 2 (ut_bin_sort, asynchronous, same ws untouched in
+ * between): emit the pairs in depth order, stable radix sort them by tile id (pair_ws of
+ * at least ut_pair_workspace_bytes(n_pairs) bytes), write lists->gauss[0..P) and the tile
+ * ranges.  The result is ordered by (tile, depth key, particle index).  UT_ERR_CAPACITY if
+ * P > lists->max_pairs or a workspace is too small (nothing enqueued).
+ * ut_bin_and_sort runs both with one buffer ws (count part first, pair part after it) and
+ * synchronises the stream in between; *n_pairs (host, may be NULL) receives P. */
 ut_status ut_bin_count(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws,
                        size_t ws_bytes, uint64_t* n_pairs_host, ut_stream stream);
 ut_status ut_bin_sort(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws,
-                      size_t ws_bytes, uint64_t n_pairs, ut_tile_lists* lists, ut_stream stream);
+                      size_t ws_bytes, void* pair_ws, size_t pair_ws_bytes, uint64_t n_pairs,
+                      ut_tile_lists* lists, ut_stream stream);
 ut_status ut_bin_and_sort(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws,
                           size_t ws_bytes, ut_tile_lists* lists, uint64_t* n_pairs,
                           ut_stream stream);

@@ -83,6 +83,7 @@ def lib():
         L.orc_fd_grad.argtypes = [P, P, P, P, P, P, P, P, P, P, C.c_int, C.c_double, P]
         L.orc_sh_eval.argtypes = [C.c_int, P, C.c_int, P]
         L.orc_project_points.argtypes = [P, P, C.c_int, P, P]
+        L.orc_num_threads.argtypes = []
         _lib = L
     return _lib
 
@@ -334,3 +335,7 @@ def project_points(s, pts):
     ok = np.zeros(pts.shape[0], np.int32)
     lib().orc_project_points(C.byref(s.c), _p(pts), pts.shape[0], _p(uv), _p(ok))
     return uv, ok.astype(bool)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())

@@ -21,6 +21,8 @@
 #include <cstring>
 #include <vector>
 
+#include <omp.h>
+
 extern "C" {
 
 /* Particles (Sec. 3.1, "Particle Representation"): float64 copies of the inputs.
@@ -1144,6 +1146,17 @@ int orc_fd_grad(const orc_gaussians* g, const orc_sensor* s, const orc_params* p
     }
   }
   return 0;
+}
+
+/* OpenMP threads the oracle runs with. */
+int orc_num_threads(void) {
+  int t = 1;
+#pragma omp parallel
+  {
+#pragma omp single
+    t = omp_get_num_threads();
+  }
+  return t;
 }
 
 /* Plain SH values (for pinning the basis against an independent library). */

@@ -69,9 +69,11 @@ SIGNATURES = [
     ("ut_sensor_tiles", i32, [P]),
     ("ut_sensor_rays", C.c_int64, [P]),
     ("ut_project", i32, [P, P, P, P, P]),
+    ("ut_count_workspace_bytes", C.c_size_t, [i32]),
+    ("ut_pair_workspace_bytes", C.c_size_t, [C.c_uint64]),
     ("ut_workspace_bytes", C.c_size_t, [C.c_uint64, i32, i32]),
     ("ut_bin_count", i32, [P, i32, P, P, C.c_size_t, P, P]),
-    ("ut_bin_sort", i32, [P, i32, P, P, C.c_size_t, C.c_uint64, P, P]),
+    ("ut_bin_sort", i32, [P, i32, P, P, C.c_size_t, P, C.c_size_t, C.c_uint64, P, P]),
     ("ut_bin_and_sort", i32, [P, i32, P, P, C.c_size_t, P, P, P]),
     ("ut_composite_camera", i32, [P, P, P, P, P, P]),
     ("ut_composite_lidar", i32, [P, P, P, P, P, P]),

@@ -231,14 +231,19 @@ ut_status ut_project(const ut_gaussians* g, const ut_sensor* s, const double* ut
   return from_hip(launch_project(*g, k, ut_abk, *out, as_stream(stream)));
 }
 
+size_t ut_count_workspace_bytes(int32_t n_gaussians) { return count_workspace(nullptr, n_gaussians).bytes; }
+
+size_t ut_pair_workspace_bytes(uint64_t n_pairs) { return pair_workspace(nullptr, n_pairs).bytes; }
+
 size_t ut_workspace_bytes(uint64_t max_pairs, int32_t n_tiles, int32_t n_gaussians) {
-  return bin_workspace(nullptr, max_pairs, n_tiles, n_gaussians).bytes;
+  (void)n_tiles;
+  return ut_count_workspace_bytes(n_gaussians) + ut_pair_workspace_bytes(max_pairs);
 }
 
 ut_status ut_bin_count(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws, size_t ws_bytes,
                        uint64_t* n_pairs_host, ut_stream stream) {
   if (n < 0 || !projected_ok(p, n) || !sensor_ok(s) || !ws) return UT_ERR_ARG;
-  BinWorkspace w = bin_workspace(ws, 0, ut_sensor_tiles(s), n);
+  CountWorkspace w = count_workspace(ws, n);
   if (w.bytes > ws_bytes) return UT_ERR_CAPACITY;
   hipError_t e = launch_bin_count(*p, n, w, as_stream(stream));
   if (e == hipSuccess && n_pairs_host)
@@ -247,15 +252,17 @@ ut_status ut_bin_count(const ut_projected* p, int32_t n, const ut_sensor* s, voi
 }
 
 ut_status ut_bin_sort(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws, size_t ws_bytes,
-                      uint64_t n_pairs, ut_tile_lists* lists, ut_stream stream) {
+                      void* pair_ws, size_t pair_ws_bytes, uint64_t n_pairs, ut_tile_lists* lists,
+                      ut_stream stream) {
   if (n < 0 || !projected_ok(p, n) || !sensor_ok(s) || !ws || !lists || !lists->ranges ||
-      (n_pairs > 0 && !lists->gauss))
+      (n_pairs > 0 && (!lists->gauss || !pair_ws)))
     return UT_ERR_ARG;
   if (n_pairs > lists->max_pairs || n_pairs >= 0xFFFFFFFFull) return UT_ERR_CAPACITY;
-  BinWorkspace w = bin_workspace(ws, n_pairs, ut_sensor_tiles(s), n);
-  if (w.bytes > ws_bytes) return UT_ERR_CAPACITY;
+  CountWorkspace w = count_workspace(ws, n);
+  PairWorkspace pw = pair_workspace(pair_ws, n_pairs);
+  if (w.bytes > ws_bytes || (n_pairs > 0 && pw.bytes > pair_ws_bytes)) return UT_ERR_CAPACITY;
   const SensorK k = make_sensor_k(s);
-  return from_hip(launch_bin_sort(*p, n, k, w, n_pairs, *lists, as_stream(stream)));
+  return from_hip(launch_bin_sort(*p, n, k, w, pw, n_pairs, *lists, as_stream(stream)));
 }
 
 ut_status ut_bin_and_sort(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws, size_t ws_bytes,
@@ -265,7 +272,9 @@ ut_status ut_bin_and_sort(const ut_projected* p, int32_t n, const ut_sensor* s, 
   if (st != UT_OK) return st;
   if (hipStreamSynchronize(as_stream(stream)) != hipSuccess) return UT_ERR_DEVICE;
   if (n_pairs) *n_pairs = P;
-  return ut_bin_sort(p, n, s, ws, ws_bytes, P, lists, stream);
+  const size_t cb = ut_count_workspace_bytes(n);
+  char* pair_ws = static_cast<char*>(ws) + cb;
+  return ut_bin_sort(p, n, s, ws, cb, pair_ws, ws_bytes - cb, P, lists, stream);
 }
 
 static ut_status composite_common(const ut_projected* p, const ut_tile_lists* lists, const ut_sensor* s,

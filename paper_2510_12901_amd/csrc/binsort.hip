@@ -302,38 +302,43 @@ int tile_bits(int n_tiles) {
 
 }  // namespace
 
-// Layout: the regions the count step uses depend on n only and come first; the pair
-// buffers (sized by max_pairs) come last, so ut_bin_count can run before P is known.
-BinWorkspace bin_workspace(void* base, uint64_t max_pairs, int n_tiles, int n) {
-  (void)n_tiles;
-  BinWorkspace w;
+CountWorkspace count_workspace(void* base, int n) {
+  CountWorkspace w;
   char* p = static_cast<char*>(base);
   size_t o = 0;
   auto take = [&](size_t bytes) { char* r = p ? p + o : nullptr; o += align256(bytes); return r; };
   const size_t nn = (size_t)(n > 0 ? n : 1);
-  const size_t mp = (size_t)(max_pairs > 0 ? max_pairs : 1);
   w.dkA = reinterpret_cast<uint32_t*>(take(4 * nn));
   w.dkB = reinterpret_cast<uint32_t*>(take(4 * nn));
   w.dvA = reinterpret_cast<uint32_t*>(take(4 * nn));
   w.dvB = reinterpret_cast<uint32_t*>(take(4 * nn));
   w.offs = reinterpret_cast<uint64_t*>(take(8 * (nn + 1)));
   w.total = reinterpret_cast<uint64_t*>(take(8));
-  const size_t nb = (std::max(nn, mp) + kSortTile - 1) / kSortTile;
+  const size_t nb = (nn + kSortTile - 1) / kSortTile;
   w.hist = reinterpret_cast<uint32_t*>(take(4 * (size_t)kRadix * nb));
   const size_t scan_len = std::max((size_t)kRadix * nb, nn + 1);
   w.scan_aux = reinterpret_cast<uint64_t*>(take(8 * ((scan_len + kScanTile - 1) / kScanTile + 1)));
-  if (max_pairs > 0) {
-    w.tkA = reinterpret_cast<uint32_t*>(take(4 * mp));
-    w.tkB = reinterpret_cast<uint32_t*>(take(4 * mp));
-    w.tv = reinterpret_cast<uint32_t*>(take(4 * mp));
-  } else {
-    w.tkA = w.tkB = w.tv = nullptr;
-  }
   w.bytes = o;
   return w;
 }
 
-hipError_t launch_bin_count(const ut_projected& p, int n, BinWorkspace& ws, hipStream_t st) {
+PairWorkspace pair_workspace(void* base, uint64_t n_pairs) {
+  PairWorkspace w;
+  char* p = static_cast<char*>(base);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { char* r = p ? p + o : nullptr; o += align256(bytes); return r; };
+  const size_t mp = (size_t)(n_pairs > 0 ? n_pairs : 1);
+  w.tkA = reinterpret_cast<uint32_t*>(take(4 * mp));
+  w.tkB = reinterpret_cast<uint32_t*>(take(4 * mp));
+  w.tv = reinterpret_cast<uint32_t*>(take(4 * mp));
+  const size_t nb = (mp + kSortTile - 1) / kSortTile;
+  w.hist = reinterpret_cast<uint32_t*>(take(4 * (size_t)kRadix * nb));
+  w.scan_aux = reinterpret_cast<uint64_t*>(take(8 * (((size_t)kRadix * nb + kScanTile - 1) / kScanTile + 1)));
+  w.bytes = o;
+  return w;
+}
+
+hipError_t launch_bin_count(const ut_projected& p, int n, CountWorkspace& ws, hipStream_t st) {
   hipError_t e = fill_u64(ws.total, 0, 1, st);
   if (e != hipSuccess || n == 0) return e;
   const int blocks = (n + 255) / 256;
@@ -346,20 +351,20 @@ hipError_t launch_bin_count(const ut_projected& p, int n, BinWorkspace& ws, hipS
   return exclusive_scan<uint64_t>(ws.offs, (size_t)n, ws.scan_aux, ws.total, st);
 }
 
-hipError_t launch_bin_sort(const ut_projected& p, int n, const SensorK& s, BinWorkspace& ws,
-                           uint64_t n_pairs, const ut_tile_lists& lists, hipStream_t st) {
+hipError_t launch_bin_sort(const ut_projected& p, int n, const SensorK& s, CountWorkspace& ws,
+                           PairWorkspace& pw, uint64_t n_pairs, const ut_tile_lists& lists, hipStream_t st) {
   const int n_tiles = s.tiles_x * s.tiles_y;
   hipError_t e = fill_u32(lists.ranges, 0u, 2 * (size_t)n_tiles, st);
   if (e != hipSuccess || n_pairs == 0 || n == 0) return e;
   const int bits = tile_bits(n_tiles);
   // place the emitted pair values so that the last radix pass writes into lists.gauss
-  uint32_t* v_first = (radix_passes(bits) % 2) ? ws.tv : lists.gauss;
-  uint32_t* v_second = (radix_passes(bits) % 2) ? lists.gauss : ws.tv;
+  uint32_t* v_first = (radix_passes(bits) % 2) ? pw.tv : lists.gauss;
+  uint32_t* v_second = (radix_passes(bits) % 2) ? lists.gauss : pw.tv;
   const int blocks = (n + 255) / 256;
   hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(256), 0, st, ws.dvA, ws.offs, p.count, p.rect, n,
-                     s.tiles_x, s.kind == UT_LIDAR ? 1 : 0, ws.tkA, v_first);
+                     s.tiles_x, s.kind == UT_LIDAR ? 1 : 0, pw.tkA, v_first);
   uint32_t *kr, *vr;
-  e = radix_sort(ws.tkA, ws.tkB, v_first, v_second, (size_t)n_pairs, bits, ws.hist, ws.scan_aux, st, &kr, &vr);
+  e = radix_sort(pw.tkA, pw.tkB, v_first, v_second, (size_t)n_pairs, bits, pw.hist, pw.scan_aux, st, &kr, &vr);
   if (e != hipSuccess) return e;
   const unsigned rb = (unsigned)((n_pairs + 255) / 256);
   hipLaunchKernelGGL(k_ranges, dim3(rb), dim3(256), 0, st, kr, n_pairs, lists.ranges, n_tiles);

@@ -13,21 +13,29 @@ hipError_t fill_f64(double* p, double v, size_t n, hipStream_t st);
 hipError_t launch_project(const ut_gaussians& g, const SensorK& s, const double abk[3],
                           const ut_projected& out, hipStream_t st);
 
-// Workspace carve-up of the binning stage.
-struct BinWorkspace {
+// Workspace carve-up of the binning stage: the count part depends on the particle count
+// only; the pair part (tile keys, value scratch, histograms of the pair sort) on the pair
+// total P, so it can be reserved after ut_bin_count has reported P.
+struct CountWorkspace {
   uint32_t *dkA, *dkB, *dvA, *dvB;   // depth sort keys / values, ping-pong [n]
   uint64_t* offs;                    // [n + 1] counts in depth order -> exclusive offsets
-  uint32_t *tkA, *tkB, *tv;          // pair tile keys ping-pong, pair value scratch [max_pairs]
-  uint32_t* hist;                    // radix histograms
-  uint64_t* scan_aux;                // block sums of the device scans
   uint64_t* total;                   // pair total
+  uint32_t* hist;                    // radix histograms of the depth sort
+  uint64_t* scan_aux;                // block sums of the device scans
   size_t bytes;
 };
-BinWorkspace bin_workspace(void* base, uint64_t max_pairs, int n_tiles, int n);
+struct PairWorkspace {
+  uint32_t *tkA, *tkB, *tv;          // pair tile keys ping-pong, pair value scratch [P]
+  uint32_t* hist;
+  uint64_t* scan_aux;
+  size_t bytes;
+};
+CountWorkspace count_workspace(void* base, int n);
+PairWorkspace pair_workspace(void* base, uint64_t n_pairs);
 
-hipError_t launch_bin_count(const ut_projected& p, int n, BinWorkspace& ws, hipStream_t st);
-hipError_t launch_bin_sort(const ut_projected& p, int n, const SensorK& s, BinWorkspace& ws,
-                           uint64_t n_pairs, const ut_tile_lists& lists, hipStream_t st);
+hipError_t launch_bin_count(const ut_projected& p, int n, CountWorkspace& ws, hipStream_t st);
+hipError_t launch_bin_sort(const ut_projected& p, int n, const SensorK& s, CountWorkspace& ws,
+                           PairWorkspace& pw, uint64_t n_pairs, const ut_tile_lists& lists, hipStream_t st);
 
 struct RenderParamsK {
   double alpha_min, alpha_max, t_min, log_alpha_min;

@@ -197,32 +197,32 @@ class Workspace:
 _default_ws: dict = {}
 
 
-def _ws(device) -> Workspace:
-    key = str(device)
+def _ws(key) -> Workspace:
+    key = str(key)
     if key not in _default_ws:
-        _default_ws[key] = Workspace(device)
+        _default_ws[key] = Workspace(key.split("/")[0])
     return _default_ws[key]
 
 
-def bin_and_sort(p: Projection, sensor: Sensor, ws: Workspace | None = None, stream=None) -> TileLists:
+def bin_and_sort(p: Projection, sensor: Sensor, ws: Workspace | None = None, pair_ws: Workspace | None = None,
+                 stream=None) -> TileLists:
     """Two-phase binning: count (pair total read back), then sort into exact-size lists."""
     dev = p.records.device
     ws = ws or _ws(dev)
+    pair_ws = pair_ws or _ws(str(dev) + "/pairs")
     L = lib()
-    need0 = int(L.ut_workspace_bytes(0, sensor.n_tiles, p.n))
-    buf = ws.ensure(need0)
+    buf = ws.ensure(int(L.ut_count_workspace_bytes(p.n)))
     total = torch.zeros(1, dtype=torch.int64).pin_memory()
     st = _stream(stream)
     check(L.ut_bin_count(ref(p.c()), p.n, ref(sensor.c), buf.data_ptr(), buf.numel(), total.data_ptr(), st),
           "ut_bin_count")
     (stream or torch.cuda.current_stream()).synchronize()
     P = int(total.item())
-    need = int(L.ut_workspace_bytes(P, sensor.n_tiles, p.n))
-    buf = ws.ensure(need, keep=need0)
+    pbuf = pair_ws.ensure(int(L.ut_pair_workspace_bytes(P)))
     lists = TileLists(torch.empty(max(P, 1), dtype=torch.int32, device=dev),
                       torch.empty((2, sensor.n_tiles), dtype=torch.int32, device=dev), P)
-    check(L.ut_bin_sort(ref(p.c()), p.n, ref(sensor.c), buf.data_ptr(), buf.numel(), P, ref(lists.c()), st),
-          "ut_bin_sort")
+    check(L.ut_bin_sort(ref(p.c()), p.n, ref(sensor.c), buf.data_ptr(), buf.numel(), pbuf.data_ptr(), pbuf.numel(),
+                        P, ref(lists.c()), st), "ut_bin_sort")
     return lists
 
 
@@ -312,3 +312,64 @@ def composite_batch(items, params=None, n_workgroups=None, ws: torch.Tensor | No
     check(lib().ut_composite_batch(C.cast(arr, C.c_void_p), n, ref(prm), ws.data_ptr(), ws.numel(), n_workgroups, _stream(stream)),
           "ut_composite_batch")
     return ws
+
+
+class SensorPipeline:
+    """Preallocated per-sensor render path: projection, two-phase binning and compositing
+    with buffers reused across calls (no device allocation once the list capacity fits)."""
+
+    def __init__(self, g: GaussianSet, sensor: Sensor, params=None, state=False, abk=UT_ABK):
+        self.g, self.sensor, self.abk = g, sensor, abk
+        dev = g.mean.device
+        self.params = params or render_params()
+        self.p = alloc_projection(g.n, dev)
+        self.ws = Workspace(dev)
+        self.pair_ws = Workspace(dev)
+        self.out = alloc_out(sensor, dev, state=state)
+        self.total = torch.zeros(1, dtype=torch.int64).pin_memory()
+        self.lists: TileLists | None = None
+        self.n_pairs = 0
+
+    def _ensure_lists(self, P: int):
+        dev = self.g.mean.device
+        if self.lists is None or self.lists.gauss.numel() < P:
+            self.lists = TileLists(torch.empty(max(int(P * 1.1), 1), dtype=torch.int32, device=dev),
+                                   torch.empty((2, self.sensor.n_tiles), dtype=torch.int32, device=dev), P)
+        self.lists.n_pairs = P
+
+    def project_and_count(self, stream=None):
+        L = lib()
+        st = _stream(stream)
+        gc = self.g.c()
+        abk_arr = (C.c_double * 3)(*self.abk)
+        check(L.ut_project(ref(gc), ref(self.sensor.c), C.cast(abk_arr, C.c_void_p), ref(self.p.c()), st),
+              "ut_project")
+        buf = self.ws.ensure(int(L.ut_count_workspace_bytes(self.g.n)))
+        check(L.ut_bin_count(ref(self.p.c()), self.g.n, ref(self.sensor.c), buf.data_ptr(), buf.numel(),
+                             self.total.data_ptr(), st), "ut_bin_count")
+
+    def sort_and_composite(self, stream=None, composite_events=None):
+        """Call after the count has completed on the host (stream synchronised)."""
+        L = lib()
+        st = _stream(stream)
+        P = int(self.total.item())
+        buf = self.ws.buf
+        pbuf = self.pair_ws.ensure(int(L.ut_pair_workspace_bytes(P)))
+        self._ensure_lists(P)
+        self.n_pairs = P
+        check(L.ut_bin_sort(ref(self.p.c()), self.g.n, ref(self.sensor.c), buf.data_ptr(), buf.numel(),
+                            pbuf.data_ptr(), pbuf.numel(), P, ref(self.lists.c()), st), "ut_bin_sort")
+        if composite_events is not None:
+            composite_events[0].record(stream)
+        fn = L.ut_composite_lidar if self.sensor.is_lidar else L.ut_composite_camera
+        check(fn(ref(self.p.c()), ref(self.lists.c()), ref(self.sensor.c), ref(self.params), ref(self.out.c()), st),
+              "ut_composite")
+        if composite_events is not None:
+            composite_events[1].record(stream)
+
+    def run(self, stream=None, composite_events=None):
+        s = stream or torch.cuda.current_stream()
+        self.project_and_count(s)
+        s.synchronize()
+        self.sort_and_composite(s, composite_events)
+        return self.out

@@ -181,8 +181,10 @@ def fisheye(width, height, k, theta_max_deg=95.0, R_sw=None, origin=None, near=0
     # Newton inversion of the (monotone) distortion polynomial; beyond theta_max no ray
     th = np.minimum(rd, tmax)
     for _ in range(60):
-        th = th - (dist(th) - rd) / ddist(th)
-        th = np.clip(th, 0.0, 2 * tmax)
+        step = (dist(th) - rd) / ddist(th)
+        th = np.clip(th - step, 0.0, 2 * tmax)
+        if np.abs(step).max() < 1e-15:
+            break
     valid = (rd <= dist(tmax))
     s = np.where(rd > 0, np.sin(th) / np.where(rd > 0, rd, 1.0), 0.0)
     d = np.stack([du * s, dv * s, np.cos(th)])

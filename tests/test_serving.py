@@ -1,0 +1,98 @@
+"""Serving loop: host-side logic on the CPU (allocator, arrival process, latency maths with a
+fake clock) and, on the GPU, served results bit-identical to plain renders under memory
+pressure and overlap."""
+import numpy as np
+import pytest
+
+from paper_2510_12901_amd import serve
+
+
+def test_pool_first_fit_and_merge():
+    pool = serve.DevicePool(4096, device="cpu")
+    a = pool.alloc(1000)          # rounds to 1024
+    b = pool.alloc(1000)
+    c = pool.alloc(2048)
+    assert a == (0, 1024) and b == (1024, 1024) and c == (2048, 2048)
+    assert pool.alloc(1) is None  # full: admission must wait
+    pool.release(b)
+    assert pool.alloc(2000) is None
+    pool.release(a)               # merges with b's hole
+    assert pool.alloc(2000) == (0, 2048)
+    assert pool.peak == 4096
+
+
+def test_poisson_trace_rate_and_frames():
+    tr = serve.poisson_trace(240.0, 20.0, 7, seed=3)
+    frames = len(tr) // 7
+    assert abs(frames / 20.0 - 240.0) < 240.0 * 0.05
+    assert all(tr[i][0] <= tr[i + 1][0] for i in range(len(tr) - 1))
+    assert [t[2] for t in tr[:7]] == list(range(7))
+
+
+def test_latency_summary_with_fake_clock():
+    reqs = []
+    for f in range(100):
+        for s in range(2):
+            reqs.append(serve.Request(len(reqs), f, s, arrival=f * 0.01, t_done=f * 0.01 + 0.002 + 0.001 * s + (0.05 if f == 99 else 0)))
+    out = serve.summarize(reqs, [100, 200])
+    assert out["frames"] == 100
+    assert abs(out["p50_frame_ms"] - 3.0) < 1e-6
+    assert out["p99_frame_ms"] > 3.0
+    span = reqs[-1].t_done - reqs[0].arrival
+    assert abs(out["mrays_per_s"] - 300 * 100 / span / 1e6) < 0.01
+
+
+@pytest.mark.gpu
+def test_served_results_bit_identical_to_plain_under_memory_pressure():
+    import torch
+    import paper_2510_12901_amd as ut
+    import synth
+    g_np, gl_np, sensors_np = synth.scene_multisensor(5, n=30000, n_cameras_pinhole=2, n_cameras_fisheye=1,
+                                                      pinhole_size=(160, 96), fisheye_size=(128, 96),
+                                                      lidar_beams=32, lidar_az=512)
+    dev = torch.device("cuda")
+    g = ut.GaussianSet.from_numpy(g_np, dev)
+    gl = ut.GaussianSet(g.mean, g.quat, g.log_scale, g.opacity_logit,
+                        torch.as_tensor(gl_np["feat"], device=dev), 0, synth.FEAT_LIDAR)
+    sensors = [ut.Sensor(s, dev) for s in sensors_np]
+    ref = []
+    for s in sensors:
+        _, lists, out = ut.render(gl if s.is_lidar else g, s, state=False)
+        ref.append({k: getattr(out, k).cpu().numpy() for k in ("feat", "depth", "alpha")} |
+                   ({"drop": out.drop.cpu().numpy()} if out.drop is not None else {}))
+        ref[-1]["pairs"] = lists.n_pairs
+    # a pool that holds about two requests at a time forces admission waits
+    need = max(int(ut.lib().ut_pair_workspace_bytes(r["pairs"])) + 4 * r["pairs"] + 8 * s.n_tiles + 1024
+               for r, s in zip(ref, sensors))
+    server = serve.Server(g, gl, sensors, pool_bytes=2 * need + 4096, n_slots=4, n_workgroups=512)
+    trace = serve.poisson_trace(2000.0, 0.05, len(sensors), seed=1)
+    assert len(trace) >= 40
+    seen = []
+
+    def check(r):
+        got = {k: getattr(r.out, k).cpu().numpy() for k in ("feat", "depth", "alpha")}
+        if r.out.drop is not None:
+            got["drop"] = r.out.drop.cpu().numpy()
+        for k, v in got.items():
+            assert np.array_equal(v, ref[r.sensor][k]), (r.rid, k)
+        seen.append(r.rid)
+
+    reqs = server.run(trace, on_done=check)
+    assert sorted(seen) == list(range(len(trace)))
+    assert server.stats["max_waiting_for_memory"] >= 1
+    assert server.stats["pool_peak_bytes"] <= server.pool.nbytes
+    assert server.stats["mean_batch"] >= 1.0
+    assert all(r.t_done >= r.arrival for r in reqs)
+
+
+@pytest.mark.gpu
+def test_request_larger_than_pool_is_rejected():
+    import torch
+    import paper_2510_12901_amd as ut
+    import synth
+    g_np, s_np = synth.scene_pinhole_small(0)
+    g = ut.GaussianSet.from_numpy(g_np)
+    s = ut.Sensor(s_np)
+    server = serve.Server(g, g, [s], pool_bytes=4096, n_slots=2)
+    with pytest.raises(RuntimeError, match="whole pool"):
+        server.run([(0.0, 0, 0)])
