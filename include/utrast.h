@@ -7,10 +7,12 @@
  * r(t) = o + t d (Sec. 3.2, "Volume Rendering").  The hot path is five calls:
  *
  *   ut_project            sigma-point projection, tile rect, LiDAR ray-based culling
- *   ut_bin_and_sort       (tile, depth, index)-ordered tile lists
+ *   ut_bin_and_sort       depth sort and super-tile bins; each tile's (depth, index)-ordered
+ *                         list is the super-tile list filtered by the particle's tile rect
  *   ut_composite_camera   front-to-back compositing of the 3D response (Eq. 1)
  *   ut_composite_lidar    the same over azimuth-elevation tiles, plus LiDAR outputs
  *   ut_composite_backward adjoint of the above with respect to every particle parameter
+ *                         (on per-tile lists materialised by ut_tile_lists_fill)
  *
  * plus host set-up (ut_lidar_tiling = Alg. 1, ut_sensor_build = ray mask / summed-area
  * table of Appendix B) and a batched, persistent composite for serving.
@@ -47,9 +49,10 @@ enum { UT_OK = 0, UT_ERR_ARG = -1, UT_ERR_CAPACITY = -2, UT_ERR_DEVICE = -3, UT_
 enum { UT_PINHOLE = 0, UT_FISHEYE = 1, UT_LIDAR = 2, UT_ORTHO = 3 };
 enum { UT_FEAT_CAMERA = 0, UT_FEAT_LIDAR = 1 };
 
-#define UT_RECORD_BYTES 96      /* per-particle compositing record written by ut_project */
+#define UT_RECORD_BYTES 128     /* per-particle compositing record written by ut_project */
 #define UT_MAX_ELEV_TILES 256   /* largest N_phi accepted */
 #define UT_CAMERA_TILE 16       /* camera tiles are 16 x 16 pixels */
+#define UT_SUPER_TILE 8         /* binning super-tiles are 8 x 8 tiles */
 #define UT_MAX_LIDAR_TILE_RAYS 256
 #define UT_ACC_FLOATS 13        /* per-particle adjoint accumulator width (doubles) */
 
@@ -123,16 +126,31 @@ typedef struct {
   uint32_t* key;       /* [n] depth key: float32 bits of |mu - o|^2 computed
                           (dx*dx + dy*dy) + dz*dz in float32 without fused multiply-add */
   uint32_t* count;     /* [n] tiles touched; 0 = culled */
+  uint32_t* trect;     /* [n][2] the same rect packed (x0 | y0 << 16, x1 | y1 << 16) */
   float* moments;      /* [5][n] UT mean (u, v) and covariance (uu, uv, vv); may be NULL */
   uint32_t* n_culled;  /* [2] invalid particles, LiDAR ray-culled particles (set by the call) */
 } ut_projected;
 
-/* Tile lists: gauss[0..n_pairs) particle indices ordered by (tile, depth key, index);
- * ranges[2][n_tiles] = [start, end) per tile.  Device, caller-allocated. */
+/* Super-tile bins (what the compositing consumes).  Tiles are grouped in super-tiles of
+ * UT_SUPER_TILE x UT_SUPER_TILE tiles (super id = (ty / 8) * super_x + tx / 8,
+ * super_x = ceil(tiles_x / 8)); gauss[0..n_pairs) holds, per super-tile, every particle
+ * whose rect touches it, ordered by (super-tile, depth key, particle index); ranges[2][n_super]
+ * = [start, end).  A tile's list -- its particles ordered by (depth key, index) -- is its
+ * super-tile's list filtered by "the particle's rect contains the tile".  Device,
+ * caller-allocated. */
 typedef struct {
   uint32_t* gauss;
   uint32_t* ranges;
   uint64_t max_pairs;  /* capacity of gauss */
+} ut_bin_lists;
+
+/* Per-tile lists, materialised from the bins (for the adjoint and for checking the order):
+ * gauss[0..n_pairs) ordered by (tile, depth key, particle index), ranges[2][n_tiles]. */
+typedef struct {
+  uint32_t* gauss;
+  uint32_t* ranges;
+  uint64_t max_pairs;
+  uint64_t* n_pairs_dev;  /* device [1]: total written by ut_tile_lists_count */
 } ut_tile_lists;
 
 /* Per-ray outputs, device, R = rays of the sensor.
@@ -206,45 +224,58 @@ ut_status ut_project(const ut_gaussians* g, const ut_sensor* s, const double* ut
                      ut_projected* out, ut_stream stream);
 
 /* Workspace sizes of the binning stage.  The count workspace depends on the particle count
- * only; the pair workspace on the pair total P reported by ut_bin_count, so a scheduler can
- * reserve it after counting.  ut_workspace_bytes = count + pair bytes for max_pairs (one
- * buffer, as ut_bin_and_sort takes it). */
+ * only; the pair workspace on the super-tile pair total P reported by ut_bin_count, so a
+ * scheduler can reserve it after counting.  ut_workspace_bytes = count + pair bytes for
+ * max_pairs (one buffer, as ut_bin_and_sort takes it). */
 size_t ut_count_workspace_bytes(int32_t n_gaussians);
 size_t ut_pair_workspace_bytes(uint64_t n_pairs);
 size_t ut_workspace_bytes(uint64_t max_pairs, int32_t n_tiles, int32_t n_gaussians);
+/* Number of super-tiles of a (built) sensor. */
+int32_t ut_sensor_super_tiles(const ut_sensor* s);
 
-/* Tile binning and depth sort (Sec. 3.2, tiling as in 3DGS).  Step 1 (ut_bin_count,
- * asynchronous): stable radix sort of the particles by depth key, exclusive scan of their
- * tile counts in that order; the pair total P stays in the count workspace ws and, if
- * n_pairs_host is non-NULL, is copied there asynchronously (pinned memory; read it after
- * the stream is synchronised).  Step 2 (ut_bin_sort, asynchronous, same ws untouched in
- * between): emit the pairs in depth order, stable radix sort them by tile id (pair_ws of
- * at least ut_pair_workspace_bytes(n_pairs) bytes), write lists->gauss[0..P) and the tile
- * ranges.  The result is ordered by (tile, depth key, particle index).  UT_ERR_CAPACITY if
- * P > lists->max_pairs or a workspace is too small (nothing enqueued).
+/* Binning and depth sort (Sec. 3.2, tiling as in 3DGS, binned per super-tile).
+ * Step 1 (ut_bin_count, asynchronous): stable radix sort of the particles by depth key,
+ * exclusive scan of their super-tile counts in that order; the pair total P stays in the
+ * count workspace ws and, if n_pairs_host is non-NULL, is copied there asynchronously
+ * (pinned memory; read it after the stream is synchronised).  Step 2 (ut_bin_sort,
+ * asynchronous, same ws untouched in between): emit the (super-tile, particle) pairs in
+ * depth order, stable radix sort them by super-tile id (pair_ws of at least
+ * ut_pair_workspace_bytes(n_pairs) bytes), write bins->gauss[0..P) and bins->ranges.
+ * UT_ERR_CAPACITY if P > bins->max_pairs or a workspace is too small (nothing enqueued).
  * ut_bin_and_sort runs both with one buffer ws (count part first, pair part after it) and
  * synchronises the stream in between; *n_pairs (host, may be NULL) receives P. */
 ut_status ut_bin_count(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws,
                        size_t ws_bytes, uint64_t* n_pairs_host, ut_stream stream);
 ut_status ut_bin_sort(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws,
                       size_t ws_bytes, void* pair_ws, size_t pair_ws_bytes, uint64_t n_pairs,
-                      ut_tile_lists* lists, ut_stream stream);
+                      ut_bin_lists* bins, ut_stream stream);
 ut_status ut_bin_and_sort(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws,
-                          size_t ws_bytes, ut_tile_lists* lists, uint64_t* n_pairs,
+                          size_t ws_bytes, ut_bin_lists* bins, uint64_t* n_pairs,
                           ut_stream stream);
 
-/* Front-to-back compositing (Eq. 1) of every ray of a camera over its tile's list: for
+/* Per-tile lists from the bins.  ut_tile_lists_count writes each tile's list length into
+ * lists->ranges and turns it into [start, end) ranges; the total (the number of (tile,
+ * particle) pairs) is copied to *n_pairs_host (pinned, asynchronous) if non-NULL.
+ * ut_tile_lists_fill then writes lists->gauss (capacity lists->max_pairs >= total). */
+ut_status ut_tile_lists_count(const ut_projected* p, const ut_sensor* s, const ut_bin_lists* bins,
+                              ut_tile_lists* lists, uint64_t* n_pairs_host, ut_stream stream);
+ut_status ut_tile_lists_fill(const ut_projected* p, const ut_sensor* s, const ut_bin_lists* bins,
+                             ut_tile_lists* lists, ut_stream stream);
+
+/* Front-to-back compositing (Eq. 1) of every ray of a camera over its tile's list (the
+ * workgroup of a tile compacts that list from its super-tile bin with wavefront ballots and
+ * prefix sums while it composites, so per-tile lists never go through HBM): for
  * each particle, t* = argmax of its 3D response along the ray (d^T B v / d^T B d with
  * B = Sigma^{-1}, v = mu - o), rho = exp(-D^2/2) at t*, alpha = min(sigma rho, alpha_max),
  * skipped when alpha < alpha_min or t* < near; w = alpha T; feat += w c; depth += w t*;
  * T *= 1 - alpha; the ray stops after T < t_min.  Deterministic (no atomics). */
-ut_status ut_composite_camera(const ut_projected* p, const ut_tile_lists* lists,
+ut_status ut_composite_camera(const ut_projected* p, const ut_bin_lists* bins,
                               const ut_sensor* s, const ut_render_params* prm,
                               ut_render_out* out, ut_stream stream);
 
 /* The same over the azimuth-elevation tiles of a spinning LiDAR; additionally
  * drop = sigmoid(zeta_2 - zeta_1) (the softmax of Sec. 3.2 over hit/drop). */
-ut_status ut_composite_lidar(const ut_projected* p, const ut_tile_lists* lists,
+ut_status ut_composite_lidar(const ut_projected* p, const ut_bin_lists* bins,
                              const ut_sensor* s, const ut_render_params* prm,
                              ut_render_out* out, ut_stream stream);
 
@@ -253,6 +284,7 @@ size_t ut_backward_workspace_bytes(int32_t n_gaussians);
 
 /* Adjoint of ut_composite_* with the discrete structure of the forward held fixed (lists,
  * culls, alpha_min skips, alpha_max clamps, colour clamps, the termination index).
+ * lists: per-tile lists from ut_tile_lists_count / ut_tile_lists_fill of the forward's bins.
  * Replays each ray's list in reverse from fwd->n_proc, recovering T_i = T_{i+1}/(1 -
  * alpha_i) from fwd->t_final; per-pair gradients are reduced per wavefront and added
  * atomically into per-particle float64 accumulators (acc_ws, zeroed by the call), then a
@@ -275,7 +307,7 @@ ut_status ut_composite_backward(const ut_gaussians* g, const ut_projected* p,
  * ut_batch_workspace_bytes(n_items) bytes. */
 typedef struct {
   const ut_projected* proj;
-  const ut_tile_lists* lists;
+  const ut_bin_lists* bins;
   const ut_sensor* sensor;
   ut_render_out* out;
 } ut_batch_item;

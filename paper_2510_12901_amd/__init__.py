@@ -4,12 +4,12 @@ Every stage runs as a hand-written HIP kernel in ``libutrast.so`` behind the C-A
 ``include/utrast.h``; this package only marshals arguments (torch supplies device memory
 and streams)."""
 from ._abi import LIB_PATH, UtError, lib
-from .render import (ALPHA_MAX, ALPHA_MIN, T_MIN, UT_ABK, GaussianSet, Projection, RenderOut, Sensor, SensorPipeline,
+from .render import (ALPHA_MAX, ALPHA_MIN, T_MIN, UT_ABK, BinLists, GaussianSet, Projection, RenderOut, Sensor, SensorPipeline,
                      TileLists, Workspace, alloc_out, alloc_projection, backward, bin_and_sort, composite,
-                     composite_batch, lidar_tiling, project, render, render_params)
+                     composite_batch, lidar_tiling, project, render, render_params, tile_lists)
 from .autograd import UTRender, render_differentiable
 
 __all__ = ["LIB_PATH", "UtError", "lib", "GaussianSet", "Sensor", "Projection", "TileLists", "RenderOut",
-           "Workspace", "SensorPipeline", "project", "bin_and_sort", "composite", "composite_batch", "backward", "render",
+           "Workspace", "SensorPipeline", "BinLists", "tile_lists", "project", "bin_and_sort", "composite", "composite_batch", "backward", "render",
            "render_params", "alloc_out", "alloc_projection", "lidar_tiling", "UTRender",
            "render_differentiable", "ALPHA_MIN", "ALPHA_MAX", "T_MIN", "UT_ABK"]

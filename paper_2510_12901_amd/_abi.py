@@ -13,7 +13,7 @@ f64 = C.c_double
 UT_OK, UT_ERR_ARG, UT_ERR_CAPACITY, UT_ERR_DEVICE, UT_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 PINHOLE, FISHEYE, LIDAR, ORTHO = 0, 1, 2, 3
 FEAT_CAMERA, FEAT_LIDAR = 0, 1
-RECORD_BYTES = 96
+RECORD_BYTES = 128
 ACC_FLOATS = 13
 
 
@@ -36,11 +36,16 @@ class UtRenderParams(C.Structure):
 
 
 class UtProjected(C.Structure):
-    _fields_ = [("records", P), ("rect", P), ("key", P), ("count", P), ("moments", P), ("n_culled", P)]
+    _fields_ = [("records", P), ("rect", P), ("key", P), ("count", P), ("trect", P), ("moments", P),
+                ("n_culled", P)]
+
+
+class UtBinLists(C.Structure):
+    _fields_ = [("gauss", P), ("ranges", P), ("max_pairs", C.c_uint64)]
 
 
 class UtTileLists(C.Structure):
-    _fields_ = [("gauss", P), ("ranges", P), ("max_pairs", C.c_uint64)]
+    _fields_ = [("gauss", P), ("ranges", P), ("max_pairs", C.c_uint64), ("n_pairs_dev", P)]
 
 
 class UtRenderOut(C.Structure):
@@ -56,7 +61,7 @@ class UtGaussianGrads(C.Structure):
 
 
 class UtBatchItem(C.Structure):
-    _fields_ = [("proj", P), ("lists", P), ("sensor", P), ("out", P)]
+    _fields_ = [("proj", P), ("bins", P), ("sensor", P), ("out", P)]
 
 
 # (name, restype, argtypes) of every exported entry point of include/utrast.h
@@ -68,6 +73,7 @@ SIGNATURES = [
     ("ut_sensor_build", i32, [P, P]),
     ("ut_sensor_tiles", i32, [P]),
     ("ut_sensor_rays", C.c_int64, [P]),
+    ("ut_sensor_super_tiles", i32, [P]),
     ("ut_project", i32, [P, P, P, P, P]),
     ("ut_count_workspace_bytes", C.c_size_t, [i32]),
     ("ut_pair_workspace_bytes", C.c_size_t, [C.c_uint64]),
@@ -75,6 +81,8 @@ SIGNATURES = [
     ("ut_bin_count", i32, [P, i32, P, P, C.c_size_t, P, P]),
     ("ut_bin_sort", i32, [P, i32, P, P, C.c_size_t, P, C.c_size_t, C.c_uint64, P, P]),
     ("ut_bin_and_sort", i32, [P, i32, P, P, C.c_size_t, P, P, P]),
+    ("ut_tile_lists_count", i32, [P, P, P, P, P, P]),
+    ("ut_tile_lists_fill", i32, [P, P, P, P, P]),
     ("ut_composite_camera", i32, [P, P, P, P, P, P]),
     ("ut_composite_lidar", i32, [P, P, P, P, P, P]),
     ("ut_backward_workspace_bytes", C.c_size_t, [i32]),

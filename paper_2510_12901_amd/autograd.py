@@ -14,8 +14,8 @@ class UTRender(torch.autograd.Function):
         g = GaussianSet(mean.detach().contiguous(), quat.detach().contiguous(), log_scale.detach().contiguous(),
                         opacity_logit.detach().contiguous(), feat.detach().contiguous(), sh_degree, feat_kind)
         prm = params or render_params()
-        p, lists, out = render(g, sensor, abk, prm, state=True)
-        ctx.state = (g, p, lists, out, sensor, prm)
+        p, bins, out = render(g, sensor, abk, prm, state=True)
+        ctx.state = (g, p, bins, out, sensor, prm)
         drop = out.drop if out.drop is not None else torch.zeros(0, device=mean.device)
         return out.feat, out.depth, out.alpha, drop
 

@@ -61,6 +61,8 @@ SensorK make_sensor_k(const ut_sensor* s) {
     k.theta_max = s->theta_max;
     k.n_rays = (long long)s->width * s->height;
   }
+  k.super_x = (k.tiles_x + kSuper - 1) / kSuper;
+  k.super_y = (k.tiles_y + kSuper - 1) / kSuper;
   return k;
 }
 
@@ -78,7 +80,7 @@ bool params_ok(const ut_render_params* p) {
 }
 
 bool projected_ok(const ut_projected* p, int n) {
-  return p && (n == 0 || (p->records && p->rect && p->key && p->count)) && p->n_culled;
+  return p && (n == 0 || (p->records && p->rect && p->trect && p->key && p->count)) && p->n_culled;
 }
 
 }  // namespace
@@ -218,6 +220,13 @@ int32_t ut_sensor_tiles(const ut_sensor* s) {
   return camera_tiles_x(s) * camera_tiles_y(s);
 }
 
+int32_t ut_sensor_super_tiles(const ut_sensor* s) {
+  if (!s) return 0;
+  const int tx = s->kind == UT_LIDAR ? s->n_theta : camera_tiles_x(s);
+  const int ty = s->kind == UT_LIDAR ? s->n_phi : camera_tiles_y(s);
+  return ((tx + kSuper - 1) / kSuper) * ((ty + kSuper - 1) / kSuper);
+}
+
 int64_t ut_sensor_rays(const ut_sensor* s) {
   if (!s) return 0;
   if (s->kind == UT_LIDAR) return (int64_t)s->n_beams * s->n_az;
@@ -245,28 +254,29 @@ ut_status ut_bin_count(const ut_projected* p, int32_t n, const ut_sensor* s, voi
   if (n < 0 || !projected_ok(p, n) || !sensor_ok(s) || !ws) return UT_ERR_ARG;
   CountWorkspace w = count_workspace(ws, n);
   if (w.bytes > ws_bytes) return UT_ERR_CAPACITY;
-  hipError_t e = launch_bin_count(*p, n, w, as_stream(stream));
+  const SensorK k = make_sensor_k(s);
+  hipError_t e = launch_bin_count(*p, n, k, w, as_stream(stream));
   if (e == hipSuccess && n_pairs_host)
     e = hipMemcpyAsync(n_pairs_host, w.total, sizeof(uint64_t), hipMemcpyDeviceToHost, as_stream(stream));
   return from_hip(e);
 }
 
 ut_status ut_bin_sort(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws, size_t ws_bytes,
-                      void* pair_ws, size_t pair_ws_bytes, uint64_t n_pairs, ut_tile_lists* lists,
+                      void* pair_ws, size_t pair_ws_bytes, uint64_t n_pairs, ut_bin_lists* bins,
                       ut_stream stream) {
-  if (n < 0 || !projected_ok(p, n) || !sensor_ok(s) || !ws || !lists || !lists->ranges ||
-      (n_pairs > 0 && (!lists->gauss || !pair_ws)))
+  if (n < 0 || !projected_ok(p, n) || !sensor_ok(s) || !ws || !bins || !bins->ranges ||
+      (n_pairs > 0 && (!bins->gauss || !pair_ws)))
     return UT_ERR_ARG;
-  if (n_pairs > lists->max_pairs || n_pairs >= 0xFFFFFFFFull) return UT_ERR_CAPACITY;
+  if (n_pairs > bins->max_pairs || n_pairs >= 0xFFFFFFFFull) return UT_ERR_CAPACITY;
   CountWorkspace w = count_workspace(ws, n);
   PairWorkspace pw = pair_workspace(pair_ws, n_pairs);
   if (w.bytes > ws_bytes || (n_pairs > 0 && pw.bytes > pair_ws_bytes)) return UT_ERR_CAPACITY;
   const SensorK k = make_sensor_k(s);
-  return from_hip(launch_bin_sort(*p, n, k, w, pw, n_pairs, *lists, as_stream(stream)));
+  return from_hip(launch_bin_sort(*p, n, k, w, pw, n_pairs, *bins, as_stream(stream)));
 }
 
 ut_status ut_bin_and_sort(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws, size_t ws_bytes,
-                          ut_tile_lists* lists, uint64_t* n_pairs, ut_stream stream) {
+                          ut_bin_lists* bins, uint64_t* n_pairs, ut_stream stream) {
   uint64_t P = 0;
   ut_status st = ut_bin_count(p, n, s, ws, ws_bytes, &P, stream);
   if (st != UT_OK) return st;
@@ -274,28 +284,49 @@ ut_status ut_bin_and_sort(const ut_projected* p, int32_t n, const ut_sensor* s, 
   if (n_pairs) *n_pairs = P;
   const size_t cb = ut_count_workspace_bytes(n);
   char* pair_ws = static_cast<char*>(ws) + cb;
-  return ut_bin_sort(p, n, s, ws, cb, pair_ws, ws_bytes - cb, P, lists, stream);
+  return ut_bin_sort(p, n, s, ws, cb, pair_ws, ws_bytes - cb, P, bins, stream);
 }
 
-static ut_status composite_common(const ut_projected* p, const ut_tile_lists* lists, const ut_sensor* s,
+static bool bins_ok(const ut_bin_lists* b) { return b && b->ranges && (b->gauss || b->max_pairs == 0); }
+
+ut_status ut_tile_lists_count(const ut_projected* p, const ut_sensor* s, const ut_bin_lists* bins,
+                              ut_tile_lists* lists, uint64_t* n_pairs_host, ut_stream stream) {
+  if (!p || !p->trect || !sensor_ok(s) || !bins_ok(bins) || !lists || !lists->ranges || !lists->n_pairs_dev)
+    return UT_ERR_ARG;
+  const SensorK k = make_sensor_k(s);
+  hipError_t e = launch_tile_lists_count(*p, k, *bins, *lists, as_stream(stream));
+  if (e == hipSuccess && n_pairs_host)
+    e = hipMemcpyAsync(n_pairs_host, lists->n_pairs_dev, sizeof(uint64_t), hipMemcpyDeviceToHost, as_stream(stream));
+  return from_hip(e);
+}
+
+ut_status ut_tile_lists_fill(const ut_projected* p, const ut_sensor* s, const ut_bin_lists* bins,
+                             ut_tile_lists* lists, ut_stream stream) {
+  if (!p || !p->trect || !sensor_ok(s) || !bins_ok(bins) || !lists || !lists->ranges || !lists->gauss)
+    return UT_ERR_ARG;
+  const SensorK k = make_sensor_k(s);
+  return from_hip(launch_tile_lists_fill(*p, k, *bins, *lists, as_stream(stream)));
+}
+
+static ut_status composite_common(const ut_projected* p, const ut_bin_lists* bins, const ut_sensor* s,
                                   const ut_render_params* prm, ut_render_out* out, ut_stream stream) {
-  if (!p || !p->records || !lists || !lists->ranges || !sensor_ok(s) || !params_ok(prm) || !out ||
+  if (!p || !p->records || !p->trect || !bins_ok(bins) || !sensor_ok(s) || !params_ok(prm) || !out ||
       !out->feat || !out->depth || !out->alpha)
     return UT_ERR_ARG;
   const SensorK k = make_sensor_k(s);
-  return from_hip(launch_composite(*p, *lists, k, make_params(prm), *out, s->max_tile_rays, as_stream(stream)));
+  return from_hip(launch_composite(*p, *bins, k, make_params(prm), *out, s->max_tile_rays, as_stream(stream)));
 }
 
-ut_status ut_composite_camera(const ut_projected* p, const ut_tile_lists* lists, const ut_sensor* s,
+ut_status ut_composite_camera(const ut_projected* p, const ut_bin_lists* bins, const ut_sensor* s,
                               const ut_render_params* prm, ut_render_out* out, ut_stream stream) {
   if (!s || s->kind == UT_LIDAR) return UT_ERR_ARG;
-  return composite_common(p, lists, s, prm, out, stream);
+  return composite_common(p, bins, s, prm, out, stream);
 }
 
-ut_status ut_composite_lidar(const ut_projected* p, const ut_tile_lists* lists, const ut_sensor* s,
+ut_status ut_composite_lidar(const ut_projected* p, const ut_bin_lists* bins, const ut_sensor* s,
                              const ut_render_params* prm, ut_render_out* out, ut_stream stream) {
   if (!s || s->kind != UT_LIDAR) return UT_ERR_ARG;
-  return composite_common(p, lists, s, prm, out, stream);
+  return composite_common(p, bins, s, prm, out, stream);
 }
 
 size_t ut_backward_workspace_bytes(int32_t n_gaussians) {
@@ -343,7 +374,7 @@ ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items, const 
   hipStream_t st = as_stream(stream);
   for (int i = 0; i < n_items; ++i) {
     const ut_batch_item& it = items[i];
-    if (!it.proj || !it.proj->records || !it.lists || !it.lists->ranges || !sensor_ok(it.sensor) || !it.out ||
+    if (!it.proj || !it.proj->records || !it.proj->trect || !bins_ok(it.bins) || !sensor_ok(it.sensor) || !it.out ||
         !it.out->feat || !it.out->depth || !it.out->alpha)
       return UT_ERR_ARG;
   }
@@ -353,8 +384,9 @@ ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items, const 
     std::memset(&k, 0, sizeof k);
     k.s = make_sensor_k(it.sensor);
     k.rec = reinterpret_cast<const Record*>(it.proj->records);
-    k.gauss = it.lists->gauss;
-    k.ranges = it.lists->ranges;
+    k.trect = reinterpret_cast<const uint2*>(it.proj->trect);
+    k.gauss = it.bins->gauss;
+    k.ranges = it.bins->ranges;
     k.out = *it.out;
     k.n_tiles = ut_sensor_tiles(it.sensor);
     k.tile_base = total;

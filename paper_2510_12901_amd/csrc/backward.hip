@@ -26,7 +26,8 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
                                                      const uint32_t* __restrict__ gauss,
                                                      const uint32_t* __restrict__ ranges, int n_tiles,
                                                      RenderParamsK prm, ut_render_out fwd, ut_upstream up,
-                                                     double* __restrict__ acc, int n) {
+                                                     const float* __restrict__ mean, double* __restrict__ acc,
+                                                     int n) {
   __shared__ Record sh[BLOCK];
   __shared__ uint32_t sh_g[BLOCK];
   __shared__ uint32_t s_max;
@@ -86,20 +87,8 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
 #pragma unroll
       for (int k = 0; k < UT_ACC_FLOATS; ++k) g[k] = 0.0;
       if (j < (int)np) {
-        const double vx = r.mu[0] - ox, vy = r.mu[1] - oy, vz = r.mu[2] - oz;
-        const double b0 = r.b[0], b1 = r.b[1], b2 = r.b[2], b3 = r.b[3], b4 = r.b[4], b5 = r.b[5];
-        const double bdx = __builtin_fma(b0, dx, __builtin_fma(b3, dy, b4 * dz));
-        const double bdy = __builtin_fma(b3, dx, __builtin_fma(b1, dy, b5 * dz));
-        const double bdz = __builtin_fma(b4, dx, __builtin_fma(b5, dy, b2 * dz));
-        const double dBd = __builtin_fma(dx, bdx, __builtin_fma(dy, bdy, dz * bdz));
-        const double vBd = __builtin_fma(vx, bdx, __builtin_fma(vy, bdy, vz * bdz));
-        const double idBd = rcp_f64(dBd);
-        const double tau = vBd * idBd;
-        const double ux = __builtin_fma(-tau, dx, vx), uy = __builtin_fma(-tau, dy, vy), uz = __builtin_fma(-tau, dz, vz);
-        const double bux = __builtin_fma(b0, ux, __builtin_fma(b3, uy, b4 * uz));
-        const double buy = __builtin_fma(b3, ux, __builtin_fma(b1, uy, b5 * uz));
-        const double buz = __builtin_fma(b4, ux, __builtin_fma(b5, uy, b2 * uz));
-        const double D2 = __builtin_fma(ux, bux, __builtin_fma(uy, buy, uz * buz));
+        const PairGeom q = pair_geometry(r, dx, dy, dz);
+        const double tau = q.tau, D2 = q.D2;
         if (tau >= s.near_ && !(D2 > __builtin_fma(2.0, (double)r.log_sigma, cut_bias))) {
           const double rho = exp_f64(-0.5 * D2);
           const double a = r.sigma * rho;
@@ -123,7 +112,19 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
               g[3] = dalpha * rho;
               dD2 = -0.5 * dalpha * r.sigma * rho;
             }
-            const double t2 = 2.0 * dD2, ti = dtau * idBd;
+            // B = M^T M: B u = M^T r and B d = M^T w with u = mu - o - t* d
+            const double* M = r.m;
+            const double bux = M[0] * q.r[0] + M[3] * q.r[1] + M[6] * q.r[2];
+            const double buy = M[1] * q.r[0] + M[4] * q.r[1] + M[7] * q.r[2];
+            const double buz = M[2] * q.r[0] + M[5] * q.r[1] + M[8] * q.r[2];
+            const double bdx = M[0] * q.w[0] + M[3] * q.w[1] + M[6] * q.w[2];
+            const double bdy = M[1] * q.w[0] + M[4] * q.w[1] + M[7] * q.w[2];
+            const double bdz = M[2] * q.w[0] + M[5] * q.w[1] + M[8] * q.w[2];
+            const uint32_t gi = sh_g[jj];
+            const double ux = ((double)mean[gi] - ox) - tau * dx;
+            const double uy = ((double)mean[n + gi] - oy) - tau * dy;
+            const double uz = ((double)mean[2 * n + gi] - oz) - tau * dz;
+            const double t2 = 2.0 * dD2, ti = dtau * q.iww;
             g[4] = t2 * bux + ti * bdx;
             g[5] = t2 * buy + ti * bdy;
             g[6] = t2 * buz + ti * bdz;
@@ -254,11 +255,11 @@ hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const u
   const Record* rec = reinterpret_cast<const Record*>(p.records);
   if (n_tiles > 0) {
     if (s.kind != UT_LIDAR || max_tile_rays > 128)
-      hipLaunchKernelGGL(k_backward<256>, dim3(n_tiles), dim3(256), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, fwd, up, acc, g.n);
+      hipLaunchKernelGGL(k_backward<256>, dim3(n_tiles), dim3(256), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, fwd, up, g.mean, acc, g.n);
     else if (max_tile_rays > 64)
-      hipLaunchKernelGGL(k_backward<128>, dim3(n_tiles), dim3(128), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, fwd, up, acc, g.n);
+      hipLaunchKernelGGL(k_backward<128>, dim3(n_tiles), dim3(128), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, fwd, up, g.mean, acc, g.n);
     else
-      hipLaunchKernelGGL(k_backward<64>, dim3(n_tiles), dim3(64), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, fwd, up, acc, g.n);
+      hipLaunchKernelGGL(k_backward<64>, dim3(n_tiles), dim3(64), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, fwd, up, g.mean, acc, g.n);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -1,28 +1,39 @@
 // composite.hip -- per-ray front-to-back compositing (Eq. 1) over tile lists.
 //
-// One workgroup per tile, one lane per ray.  The tile's sorted list is streamed through
-// LDS in batches of BLOCK records (96 B each, gathered cooperatively as 16-byte chunks so
-// neighbouring lanes read neighbouring bytes); every lane then walks the batch for its
-// own ray.  A lane that reaches T < t_min stops (its wavefront stops when all 64 lanes
-// have), and the workgroup stops streaming once every lane is done.
+// One workgroup per tile, one lane per ray.  The workgroup streams its super-tile bin,
+// keeps the entries whose rect contains the tile (ballot + popcount per wavefront, wave
+// counts combined in LDS, appended in order to an LDS ring of candidate indices), and
+// stages batches of BLOCK candidates' records (96 B each, gathered cooperatively as
+// 16-byte chunks) in LDS; every lane then walks the batch for its own ray.  The candidate
+// order is the tile's exact (depth, index) list.  A lane that reaches T < t_min stops (its
+// wavefront stops when all 64 lanes have), and the workgroup stops once every lane is done.
 //
-// Per (ray, particle): v = mu - o, Bd = B d, t* = v.Bd / d.Bd, u = v - t* d,
-// D^2 = u.B u, rho = exp(-D^2/2) -- all float64 with explicit FMAs (no contraction
-// flags can change the arithmetic between the plain and the batched kernel).
+// Per (ray, particle): w = M d, t* = a.w / w.w, r = a - t* w, D^2 = r.r (see Record),
+// rho = exp(-D^2/2) -- all float64 with explicit FMAs (no contraction flags can change
+// the arithmetic between the plain and the batched kernel, or between forward and adjoint).
 #include "ut_internal.hpp"
 
 namespace ut {
 namespace {
 
 template <int BLOCK>
+struct CompositeShared {
+  Record rec[BLOCK];
+  uint32_t cand[2 * BLOCK];   // ring of candidate particle indices
+  uint32_t wcnt[BLOCK / 64];
+};
+
+template <int BLOCK>
 __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* __restrict__ rec,
-                                               const uint32_t* __restrict__ gauss,
-                                               const uint32_t* __restrict__ ranges, int tile, int n_tiles,
+                                               const uint2* __restrict__ trect,
+                                               const uint32_t* __restrict__ bgauss,
+                                               const uint32_t* __restrict__ branges, int tile, int n_super,
                                                const RenderParamsK& prm, const ut_render_out& out,
-                                               Record* sh) {
-  const uint32_t start = ranges[tile], end = ranges[n_tiles + tile];
+                                               CompositeShared<BLOCK>& sm) {
+  const int tx = tile % s.tiles_x, ty = tile / s.tiles_x;
+  const int sid = super_of_tile(tile, s);
+  const uint32_t start = branges[sid], end = branges[n_super + sid];
   const long long ray = tile_ray(s, tile, threadIdx.x);
-  const double ox = s.o[0], oy = s.o[1], oz = s.o[2];
   double dx = 0, dy = 0, dz = 0;
   if (ray >= 0) {
     dx = s.ray_dir[ray];
@@ -33,33 +44,51 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
   double T = 1.0, f0 = 0, f1 = 0, f2 = 0, dep = 0;
   uint32_t nproc = 0;
   const double cut_bias = 1e-3 - 2.0 * prm.log_alpha_min;
+  const int lane = __lane_id(), wave = threadIdx.x >> 6;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  constexpr uint32_t kRing = 2 * BLOCK - 1;
+  uint32_t pos = start, head = 0, n_cand = 0, list_base = 0;   // uniform across the workgroup
 
-  for (uint32_t base = start; base < end; base += BLOCK) {
+  for (;;) {
     if (__syncthreads_and(done)) break;
-    const uint32_t cnt = min((uint32_t)BLOCK, end - base);
+    // refill the candidate ring with this tile's entries of the super-tile bin
+    while (n_cand < (uint32_t)BLOCK && pos < end) {
+      const uint32_t j = pos + threadIdx.x;
+      uint32_t g = 0;
+      bool hit = false;
+      if (j < end) {
+        g = bgauss[j];
+        hit = rect_covers(trect[g], tx, ty, s);
+      }
+      const unsigned long long m = __ballot(hit);
+      if (lane == 0) sm.wcnt[wave] = (uint32_t)__popcll(m);
+      __syncthreads();
+      uint32_t before = 0, total = 0;
+#pragma unroll
+      for (int w = 0; w < BLOCK / 64; ++w) {
+        const uint32_t c = sm.wcnt[w];
+        if (w < wave) before += c;
+        total += c;
+      }
+      if (hit) sm.cand[(head + n_cand + before + (uint32_t)__popcll(m & lt)) & kRing] = g;
+      n_cand += total;
+      pos += BLOCK;
+      __syncthreads();
+    }
+    if (n_cand == 0) break;
+    const uint32_t cnt = min(n_cand, (uint32_t)BLOCK);
     for (uint32_t c = threadIdx.x; c < cnt * kRecordChunks; c += BLOCK) {
       const uint32_t j = c / kRecordChunks, part = c - j * kRecordChunks;
-      const uint32_t g = gauss[base + j];
-      reinterpret_cast<uint4*>(sh + j)[part] = reinterpret_cast<const uint4*>(rec + g)[part];
+      const uint32_t g = sm.cand[(head + j) & kRing];
+      reinterpret_cast<uint4*>(sm.rec + j)[part] = reinterpret_cast<const uint4*>(rec + g)[part];
     }
     __syncthreads();
     if (!done) {
       for (uint32_t j = 0; j < cnt; ++j) {
-        const Record& r = sh[j];
-        nproc = base - start + j + 1;
-        const double vx = r.mu[0] - ox, vy = r.mu[1] - oy, vz = r.mu[2] - oz;
-        const double b0 = r.b[0], b1 = r.b[1], b2 = r.b[2], b3 = r.b[3], b4 = r.b[4], b5 = r.b[5];
-        const double bdx = __builtin_fma(b0, dx, __builtin_fma(b3, dy, b4 * dz));
-        const double bdy = __builtin_fma(b3, dx, __builtin_fma(b1, dy, b5 * dz));
-        const double bdz = __builtin_fma(b4, dx, __builtin_fma(b5, dy, b2 * dz));
-        const double dBd = __builtin_fma(dx, bdx, __builtin_fma(dy, bdy, dz * bdz));
-        const double vBd = __builtin_fma(vx, bdx, __builtin_fma(vy, bdy, vz * bdz));
-        const double tau = vBd * rcp_f64(dBd);
-        const double ux = __builtin_fma(-tau, dx, vx), uy = __builtin_fma(-tau, dy, vy), uz = __builtin_fma(-tau, dz, vz);
-        const double bux = __builtin_fma(b0, ux, __builtin_fma(b3, uy, b4 * uz));
-        const double buy = __builtin_fma(b3, ux, __builtin_fma(b1, uy, b5 * uz));
-        const double buz = __builtin_fma(b4, ux, __builtin_fma(b5, uy, b2 * uz));
-        const double D2 = __builtin_fma(ux, bux, __builtin_fma(uy, buy, uz * buz));
+        const Record& r = sm.rec[j];
+        nproc = list_base + j + 1;
+        const PairGeom q = pair_geometry(r, dx, dy, dz);
+        const double tau = q.tau, D2 = q.D2;
         if (tau < s.near_) continue;
         // conservative pre-test: beyond this D^2, sigma rho < alpha_min for certain
         if (D2 > __builtin_fma(2.0, (double)r.log_sigma, cut_bias)) continue;
@@ -79,6 +108,9 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
         }
       }
     }
+    head = (head + cnt) & kRing;
+    n_cand -= cnt;
+    list_base += cnt;
   }
   if (ray >= 0) {
     const long long R = s.n_rays;
@@ -103,20 +135,21 @@ __device__ __forceinline__ int xcd_tile(int b, int n_tiles) {
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_composite(SensorK s, const Record* __restrict__ rec,
-                                                      const uint32_t* __restrict__ gauss,
-                                                      const uint32_t* __restrict__ ranges, int n_tiles,
+                                                      const uint2* __restrict__ trect,
+                                                      const uint32_t* __restrict__ bgauss,
+                                                      const uint32_t* __restrict__ branges, int n_tiles,
                                                       RenderParamsK prm, ut_render_out out) {
-  __shared__ Record sh[BLOCK];
+  __shared__ CompositeShared<BLOCK> sm;
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   if (tile < 0) return;
-  composite_tile<BLOCK>(s, rec, gauss, ranges, tile, n_tiles, prm, out, sh);
+  composite_tile<BLOCK>(s, rec, trect, bgauss, branges, tile, s.super_x * s.super_y, prm, out, sm);
 }
 
 // Persistent batched compositing: workgroups pull (request, tile) items from a counter.
 __global__ __launch_bounds__(256) void k_composite_batch(const BatchItemK* __restrict__ items, int n_items,
                                                           int total_tiles, uint32_t* counter,
                                                           RenderParamsK prm) {
-  __shared__ Record sh[256];
+  __shared__ CompositeShared<256> sm;
   __shared__ uint32_t s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
@@ -127,25 +160,27 @@ __global__ __launch_bounds__(256) void k_composite_batch(const BatchItemK* __res
     int it = 0;
     while (it + 1 < n_items && (uint32_t)items[it + 1].tile_base <= w) ++it;
     const BatchItemK& I = items[it];
-    composite_tile<256>(I.s, I.rec, I.gauss, I.ranges, (int)(w - I.tile_base), I.n_tiles, prm, I.out, sh);
+    composite_tile<256>(I.s, I.rec, I.trect, I.gauss, I.ranges, (int)(w - I.tile_base),
+                        I.s.super_x * I.s.super_y, prm, I.out, sm);
   }
 }
 
 }  // namespace
 
-hipError_t launch_composite(const ut_projected& p, const ut_tile_lists& lists, const SensorK& s,
+hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, const SensorK& s,
                             const RenderParamsK& prm, const ut_render_out& out, int max_tile_rays,
                             hipStream_t st) {
   const int n_tiles = s.tiles_x * s.tiles_y;
   if (n_tiles == 0) return hipSuccess;
   const int grid = 8 * ((n_tiles + 7) / 8);
   const Record* rec = reinterpret_cast<const Record*>(p.records);
+  const uint2* tr = reinterpret_cast<const uint2*>(p.trect);
   if (s.kind != UT_LIDAR || max_tile_rays > 128)
-    hipLaunchKernelGGL(k_composite<256>, dim3(grid), dim3(256), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, out);
+    hipLaunchKernelGGL(k_composite<256>, dim3(grid), dim3(256), 0, st, s, rec, tr, bins.gauss, bins.ranges, n_tiles, prm, out);
   else if (max_tile_rays > 64)
-    hipLaunchKernelGGL(k_composite<128>, dim3(grid), dim3(128), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, out);
+    hipLaunchKernelGGL(k_composite<128>, dim3(grid), dim3(128), 0, st, s, rec, tr, bins.gauss, bins.ranges, n_tiles, prm, out);
   else
-    hipLaunchKernelGGL(k_composite<64>, dim3(grid), dim3(64), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, out);
+    hipLaunchKernelGGL(k_composite<64>, dim3(grid), dim3(64), 0, st, s, rec, tr, bins.gauss, bins.ranges, n_tiles, prm, out);
   return hipGetLastError();
 }
 

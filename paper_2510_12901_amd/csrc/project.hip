@@ -3,6 +3,8 @@
 // Loads are structure-of-arrays and coalesced; the arithmetic is float64 (on gfx950 a
 // float64 FMA costs the same issue slot as an unpacked float32 FMA, and the stage is
 // bound by HBM traffic: ~(11 + 3K) floats in, 96 + 28 bytes out per particle).
+#include <algorithm>
+
 #include "ut_internal.hpp"
 #include "ut_sh.hpp"
 
@@ -73,15 +75,19 @@ __device__ __forceinline__ uint32_t depth_key(float mx, float my, float mz, cons
   return __float_as_uint(k);
 }
 
+// DEG is the SH degree as a compile-time constant, so the (DEG+1)^2 x 3 coefficient loads are
+// unrolled and issued together instead of one dependent loop trip at a time.
+template <int DEG>
 __global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, double ut_a, double ut_b,
                                                   double ut_k, Record* __restrict__ rec,
-                                                  int32_t* __restrict__ rect, uint32_t* __restrict__ key,
+                                                  int32_t* __restrict__ rect, uint2* __restrict__ trect,
+                                                  uint32_t* __restrict__ key,
                                                   uint32_t* __restrict__ count, float* __restrict__ moments,
                                                   uint32_t* __restrict__ n_culled) {
   const int n = g.n;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int invalid = 0, raycull = 0;
-  if (i < n) {
+  uint32_t n_invalid = 0, n_raycull = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    int invalid = 0, raycull = 0;
     const float mx = g.mean[i], my = g.mean[n + i], mz = g.mean[2 * n + i];
     const float q0 = g.quat[i], q1 = g.quat[n + i], q2 = g.quat[2 * n + i], q3 = g.quat[3 * n + i];
     const float l0 = g.log_scale[i], l1 = g.log_scale[n + i], l2 = g.log_scale[2 * n + i];
@@ -90,7 +96,6 @@ __global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, doub
     bool ok = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(l0) && isfinite(l1) &&
               isfinite(l2) && isfinite(lg) && isfinite(qq) && qq > 0;
     Record r;
-    r.mu[0] = mx; r.mu[1] = my; r.mu[2] = mz;
     double Rm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, sc[3] = {1, 1, 1};
     double sigma = 0;
     if (ok) {
@@ -102,14 +107,18 @@ __global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, doub
       sc[0] = exp((double)l0); sc[1] = exp((double)l1); sc[2] = exp((double)l2);
       sigma = 1.0 / (1.0 + exp(-(double)lg));
     }
-    // B = R diag(1/s^2) R^T
-    const double is0 = 1.0 / (sc[0] * sc[0]), is1 = 1.0 / (sc[1] * sc[1]), is2 = 1.0 / (sc[2] * sc[2]);
-    r.b[0] = Rm[0] * Rm[0] * is0 + Rm[1] * Rm[1] * is1 + Rm[2] * Rm[2] * is2;
-    r.b[1] = Rm[3] * Rm[3] * is0 + Rm[4] * Rm[4] * is1 + Rm[5] * Rm[5] * is2;
-    r.b[2] = Rm[6] * Rm[6] * is0 + Rm[7] * Rm[7] * is1 + Rm[8] * Rm[8] * is2;
-    r.b[3] = Rm[0] * Rm[3] * is0 + Rm[1] * Rm[4] * is1 + Rm[2] * Rm[5] * is2;
-    r.b[4] = Rm[0] * Rm[6] * is0 + Rm[1] * Rm[7] * is1 + Rm[2] * Rm[8] * is2;
-    r.b[5] = Rm[3] * Rm[6] * is0 + Rm[4] * Rm[7] * is1 + Rm[5] * Rm[8] * is2;
+    // M = S^{-1} R^T and a = M (mu - o)
+    {
+      const double i0 = 1.0 / sc[0], i1 = 1.0 / sc[1], i2 = 1.0 / sc[2];
+      r.m[0] = Rm[0] * i0; r.m[1] = Rm[3] * i0; r.m[2] = Rm[6] * i0;
+      r.m[3] = Rm[1] * i1; r.m[4] = Rm[4] * i1; r.m[5] = Rm[7] * i1;
+      r.m[6] = Rm[2] * i2; r.m[7] = Rm[5] * i2; r.m[8] = Rm[8] * i2;
+      const double vx = (double)mx - s.o[0], vy = (double)my - s.o[1], vz = (double)mz - s.o[2];
+      r.a[0] = __builtin_fma(r.m[0], vx, __builtin_fma(r.m[1], vy, r.m[2] * vz));
+      r.a[1] = __builtin_fma(r.m[3], vx, __builtin_fma(r.m[4], vy, r.m[5] * vz));
+      r.a[2] = __builtin_fma(r.m[6], vx, __builtin_fma(r.m[7], vy, r.m[8] * vz));
+      r.pad = 0.0;
+    }
     r.sigma = sigma;
     r.log_sigma = ok ? (float)log(sigma) : -1e30f;
 
@@ -122,7 +131,7 @@ __global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, doub
       if (ok) {
         const double gam = sqrt(cpl);
         double gu[7], gv[7];
-        const double mu[3] = {r.mu[0], r.mu[1], r.mu[2]};
+        const double mu[3] = {(double)mx, (double)my, (double)mz};
         ok = project_point(s, mu, gu[0], gv[0]);
         for (int j = 0; j < 3 && ok; ++j) {
           const double e0 = gam * sc[j] * Rm[j], e1 = gam * sc[j] * Rm[3 + j], e2 = gam * sc[j] * Rm[6 + j];
@@ -217,15 +226,16 @@ __global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, doub
     // features: SH at the unit direction from the sensor origin to the mean
     double f[3] = {0, 0, 0};
     if (ok) {
-      const double vx = r.mu[0] - s.o[0], vy = r.mu[1] - s.o[1], vz = r.mu[2] - s.o[2];
+      const double vx = (double)mx - s.o[0], vy = (double)my - s.o[1], vz = (double)mz - s.o[2];
       const double len = sqrt(vx * vx + vy * vy + vz * vz);
       double dx = 0, dy = 0, dz = 1;
       if (len > 0) { const double il = 1.0 / len; dx = vx * il; dy = vy * il; dz = vz * il; }
       double Y[16];
-      sh_basis(g.sh_degree, dx, dy, dz, Y);
-      const int K = sh_count(g.sh_degree);
+      sh_basis(DEG, dx, dy, dz, Y);
+      constexpr int K = (DEG + 1) * (DEG + 1);
       for (int c = 0; c < 3; ++c) {
         double acc = 0;
+#pragma unroll
         for (int k = 0; k < K; ++k) acc += (double)g.feat[(size_t)(k * 3 + c) * n + i] * Y[k];
         f[c] = (g.feat_kind == UT_FEAT_CAMERA) ? (acc + 0.5 > 0 ? acc + 0.5 : 0.0) : acc;
       }
@@ -237,17 +247,35 @@ __global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, doub
 #pragma unroll
     for (int c = 0; c < kRecordChunks; ++c) dst[c] = src[c];
     rect[i] = x0; rect[n + i] = y0; rect[2 * n + i] = x1; rect[3 * n + i] = y1;
+    trect[i] = make_uint2(((uint32_t)x0 & 0xFFFFu) | ((uint32_t)y0 << 16), ((uint32_t)x1 & 0xFFFFu) | ((uint32_t)y1 << 16));
     count[i] = cnt;
     key[i] = depth_key(mx, my, mz, s.of);
     if (moments) {
       moments[i] = (float)m0; moments[n + i] = (float)m1;
       moments[2 * n + i] = (float)c00; moments[3 * n + i] = (float)c01; moments[4 * n + i] = (float)c11;
     }
+    n_invalid += invalid;
+    n_raycull += raycull;
   }
-  const unsigned long long mi = __ballot(invalid), mr = __ballot(raycull);
+  // culled counts: wavefront sums, then one atomic per counter per workgroup (every
+  // wavefront adding to the same two words serialises in L2 when half the particles are
+  // behind the camera)
+  __shared__ uint32_t s_cnt[2][4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    n_invalid += (uint32_t)__shfl_xor(n_invalid, o);
+    n_raycull += (uint32_t)__shfl_xor(n_raycull, o);
+  }
   if (__lane_id() == 0) {
-    if (mi) atomicAdd(&n_culled[0], (uint32_t)__popcll(mi));
-    if (mr) atomicAdd(&n_culled[1], (uint32_t)__popcll(mr));
+    s_cnt[0][threadIdx.x >> 6] = n_invalid;
+    s_cnt[1][threadIdx.x >> 6] = n_raycull;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t a = s_cnt[0][0] + s_cnt[0][1] + s_cnt[0][2] + s_cnt[0][3];
+    const uint32_t b = s_cnt[1][0] + s_cnt[1][1] + s_cnt[1][2] + s_cnt[1][3];
+    if (a) atomicAdd(&n_culled[0], a);
+    if (b) atomicAdd(&n_culled[1], b);
   }
 }
 
@@ -258,10 +286,19 @@ hipError_t launch_project(const ut_gaussians& g, const SensorK& s, const double 
   hipError_t e = fill_u32(out.n_culled, 0u, 2, st);
   if (e != hipSuccess) return e;
   if (g.n == 0) return hipSuccess;
-  const int blocks = (g.n + 255) / 256;
-  hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, st, g, s, abk[0], abk[1], abk[2],
-                     reinterpret_cast<Record*>(out.records), out.rect, out.key, out.count,
-                     out.moments, out.n_culled);
+  const int blocks = std::min((g.n + 255) / 256, 2048);
+  Record* rec = reinterpret_cast<Record*>(out.records);
+  uint2* tr = reinterpret_cast<uint2*>(out.trect);
+#define UT_LAUNCH_PROJECT(D)                                                                          \
+  hipLaunchKernelGGL(k_project<D>, dim3(blocks), dim3(256), 0, st, g, s, abk[0], abk[1], abk[2], rec, \
+                     out.rect, tr, out.key, out.count, out.moments, out.n_culled)
+  switch (g.sh_degree) {
+    case 0: UT_LAUNCH_PROJECT(0); break;
+    case 1: UT_LAUNCH_PROJECT(1); break;
+    case 2: UT_LAUNCH_PROJECT(2); break;
+    default: UT_LAUNCH_PROJECT(3); break;
+  }
+#undef UT_LAUNCH_PROJECT
   return hipGetLastError();
 }
 

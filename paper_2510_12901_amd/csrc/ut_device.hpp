@@ -16,14 +16,22 @@ namespace ut {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// Per-particle compositing record written by the projection, read (gathered) by the
-// compositing and adjoint kernels.  96 bytes = six 16-byte chunks.
+// Tiles are binned in super-tiles of kSuper x kSuper tiles; a tile's exact list is the
+// super-tile list filtered by "the particle's rect contains this tile" (order preserved).
+constexpr int kSuper = UT_SUPER_TILE;
+
+// Per-particle compositing record written by the projection for one sensor, read
+// (gathered) by the compositing and adjoint kernels.  128 bytes = eight 16-byte chunks.
+// With M = S^{-1} R^T (so Sigma^{-1} = M^T M) and a = M (mu - o) fixed per particle and
+// sensor, a ray d gives w = M d, t* = a.w / w.w, r = a - t* w and D^2 = r.r: the distance
+// of maximum response and the squared Mahalanobis distance there.
 struct alignas(16) Record {
-  double mu[3];     // mean (exact copy of the float32 input)
-  double b[6];      // Sigma^{-1}: xx, yy, zz, xy, xz, yz
+  double m[9];      // M, row-major: row j = R[:, j]^T / s_j
+  double a[3];      // M (mu - o), o = sensor origin
   double sigma;     // opacity
   float feat[3];    // colour or LiDAR features evaluated at the particle's SH direction
   float log_sigma;  // ln(opacity), for the conservative alpha_min pre-test
+  double pad;
 };
 static_assert(sizeof(Record) == UT_RECORD_BYTES, "record size must match the ABI");
 constexpr int kRecordChunks = UT_RECORD_BYTES / 16;
@@ -44,6 +52,7 @@ struct SensorK {
   const int* sat;           // [(cull_az+1)*(cull_el+1)]
   const float* ray_dir;     // [3][R]
   long long n_rays;
+  int super_x, super_y;     // super-tile grid
 };
 
 // Byte layout of the LiDAR device tables (bounds, beam_start, sat), 256-byte aligned parts.
@@ -93,6 +102,48 @@ __device__ __forceinline__ double rcp_f64(double x) {
   r = __builtin_fma(r, e, r);
   e = __builtin_fma(-x, r, 1.0);
   return __builtin_fma(r, e, r);
+}
+
+// Response geometry of one (ray, particle) pair; shared verbatim by the compositing and the
+// adjoint so both take identical skip / clamp / stop decisions.
+struct PairGeom {
+  double w[3];   // M d
+  double iww;    // 1 / (w.w) = 1 / (d^T Sigma^{-1} d)
+  double tau;    // distance of maximum response t*
+  double r[3];   // a - t* w = M (mu - o - t* d)
+  double D2;     // r.r
+};
+
+__device__ __forceinline__ PairGeom pair_geometry(const Record& c, double dx, double dy, double dz) {
+  PairGeom p;
+  p.w[0] = __builtin_fma(c.m[0], dx, __builtin_fma(c.m[1], dy, c.m[2] * dz));
+  p.w[1] = __builtin_fma(c.m[3], dx, __builtin_fma(c.m[4], dy, c.m[5] * dz));
+  p.w[2] = __builtin_fma(c.m[6], dx, __builtin_fma(c.m[7], dy, c.m[8] * dz));
+  const double aw = __builtin_fma(c.a[0], p.w[0], __builtin_fma(c.a[1], p.w[1], c.a[2] * p.w[2]));
+  const double ww = __builtin_fma(p.w[0], p.w[0], __builtin_fma(p.w[1], p.w[1], p.w[2] * p.w[2]));
+  p.iww = rcp_f64(ww);
+  p.tau = aw * p.iww;
+  p.r[0] = __builtin_fma(-p.tau, p.w[0], c.a[0]);
+  p.r[1] = __builtin_fma(-p.tau, p.w[1], c.a[1]);
+  p.r[2] = __builtin_fma(-p.tau, p.w[2], c.a[2]);
+  p.D2 = __builtin_fma(p.r[0], p.r[0], __builtin_fma(p.r[1], p.r[1], p.r[2] * p.r[2]));
+  return p;
+}
+
+// Packed tile rect of a particle: (x0 | y0 << 16, x1 | y1 << 16); LiDAR x1 may exceed
+// n_theta - 1 where the rect wraps through azimuth 0.
+__device__ __forceinline__ bool rect_covers(uint2 r, int tx, int ty, const SensorK& s) {
+  const int x0 = (int)(r.x & 0xFFFFu), y0 = (int)(r.x >> 16), x1 = (int)(r.y & 0xFFFFu), y1 = (int)(r.y >> 16);
+  if (ty < y0 || ty > y1) return false;
+  if (s.kind != UT_LIDAR) return tx >= x0 && tx <= x1;
+  int dx = tx - x0;
+  if (dx < 0) dx += s.n_theta;
+  return dx <= x1 - x0;
+}
+
+__device__ __forceinline__ int super_of_tile(int tile, const SensorK& s) {
+  const int tx = tile % s.tiles_x, ty = tile / s.tiles_x;
+  return (ty / kSuper) * s.super_x + tx / kSuper;
 }
 
 // Rays of a tile: camera 16x16 pixel block; LiDAR beams of the elevation tile times the

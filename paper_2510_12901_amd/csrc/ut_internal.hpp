@@ -20,6 +20,8 @@ struct CountWorkspace {
   uint32_t *dkA, *dkB, *dvA, *dvB;   // depth sort keys / values, ping-pong [n]
   uint64_t* offs;                    // [n + 1] counts in depth order -> exclusive offsets
   uint64_t* total;                   // pair total
+  uint32_t* scount;                  // [n] super-tile count per particle (index order)
+  uint32_t* m_dev;                   // number of visible particles
   uint32_t* hist;                    // radix histograms of the depth sort
   uint64_t* scan_aux;                // block sums of the device scans
   size_t bytes;
@@ -33,15 +35,19 @@ struct PairWorkspace {
 CountWorkspace count_workspace(void* base, int n);
 PairWorkspace pair_workspace(void* base, uint64_t n_pairs);
 
-hipError_t launch_bin_count(const ut_projected& p, int n, CountWorkspace& ws, hipStream_t st);
+hipError_t launch_bin_count(const ut_projected& p, int n, const SensorK& s, CountWorkspace& ws, hipStream_t st);
 hipError_t launch_bin_sort(const ut_projected& p, int n, const SensorK& s, CountWorkspace& ws,
-                           PairWorkspace& pw, uint64_t n_pairs, const ut_tile_lists& lists, hipStream_t st);
+                           PairWorkspace& pw, uint64_t n_pairs, const ut_bin_lists& bins, hipStream_t st);
+hipError_t launch_tile_lists_count(const ut_projected& p, const SensorK& s, const ut_bin_lists& bins,
+                                   const ut_tile_lists& lists, hipStream_t st);
+hipError_t launch_tile_lists_fill(const ut_projected& p, const SensorK& s, const ut_bin_lists& bins,
+                                  const ut_tile_lists& lists, hipStream_t st);
 
 struct RenderParamsK {
   double alpha_min, alpha_max, t_min, log_alpha_min;
 };
 
-hipError_t launch_composite(const ut_projected& p, const ut_tile_lists& lists, const SensorK& s,
+hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, const SensorK& s,
                             const RenderParamsK& prm, const ut_render_out& out, int max_tile_rays,
                             hipStream_t st);
 
@@ -49,7 +55,8 @@ hipError_t launch_composite(const ut_projected& p, const ut_tile_lists& lists, c
 struct BatchItemK {
   SensorK s;
   const Record* rec;
-  const uint32_t* gauss;
+  const uint2* trect;
+  const uint32_t* gauss;    // super-tile bins
   const uint32_t* ranges;
   ut_render_out out;
   int n_tiles;

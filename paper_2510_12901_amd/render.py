@@ -101,6 +101,7 @@ class Sensor:
         self.c = c
         self.kind = c.kind
         self.n_tiles = int(lib().ut_sensor_tiles(ref(c)))
+        self.n_super = int(lib().ut_sensor_super_tiles(ref(c)))
         self.n_rays = int(lib().ut_sensor_rays(ref(c)))
         self.max_tile_rays = int(c.max_tile_rays)
 
@@ -131,6 +132,7 @@ class Projection:
     rect: torch.Tensor
     key: torch.Tensor
     count: torch.Tensor
+    trect: torch.Tensor
     moments: torch.Tensor | None
     n_culled: torch.Tensor
     n: int
@@ -139,7 +141,7 @@ class Projection:
     def c(self) -> A.UtProjected:
         if self._c is None:
             self._c = A.UtProjected(self.records.data_ptr(), self.rect.data_ptr(), self.key.data_ptr(),
-                                    self.count.data_ptr(),
+                                    self.count.data_ptr(), self.trect.data_ptr(),
                                     self.moments.data_ptr() if self.moments is not None else None,
                                     self.n_culled.data_ptr())
         return self._c
@@ -151,6 +153,7 @@ def alloc_projection(n: int, device="cuda", moments=False) -> Projection:
                       torch.empty((4, nn), dtype=torch.int32, device=device),
                       torch.empty(nn, dtype=torch.int32, device=device),
                       torch.empty(nn, dtype=torch.int32, device=device),
+                      torch.empty((nn, 2), dtype=torch.int32, device=device),
                       torch.empty((5, nn), dtype=torch.float32, device=device) if moments else None,
                       torch.empty(2, dtype=torch.int32, device=device), n)
 
@@ -166,15 +169,32 @@ def project(g: GaussianSet, sensor: Sensor, abk=UT_ABK, moments=False, out: Proj
 
 
 @dataclass
-class TileLists:
+class BinLists:
+    """Super-tile bins: gauss ordered by (super-tile, depth key, index), ranges [2, n_super]."""
     gauss: torch.Tensor
     ranges: torch.Tensor
     n_pairs: int
+    _c: A.UtBinLists = field(default=None, repr=False)
+
+    def c(self) -> A.UtBinLists:
+        if self._c is None:
+            self._c = A.UtBinLists(self.gauss.data_ptr(), self.ranges.data_ptr(), int(self.gauss.numel()))
+        return self._c
+
+
+@dataclass
+class TileLists:
+    """Per-tile lists: gauss ordered by (tile, depth key, index), ranges [2, n_tiles]."""
+    gauss: torch.Tensor
+    ranges: torch.Tensor
+    n_pairs: int
+    total: torch.Tensor = None
     _c: A.UtTileLists = field(default=None, repr=False)
 
     def c(self) -> A.UtTileLists:
         if self._c is None:
-            self._c = A.UtTileLists(self.gauss.data_ptr(), self.ranges.data_ptr(), int(self.gauss.numel()))
+            self._c = A.UtTileLists(self.gauss.data_ptr(), self.ranges.data_ptr(), int(self.gauss.numel()),
+                                    self.total.data_ptr())
         return self._c
 
 
@@ -205,8 +225,8 @@ def _ws(key) -> Workspace:
 
 
 def bin_and_sort(p: Projection, sensor: Sensor, ws: Workspace | None = None, pair_ws: Workspace | None = None,
-                 stream=None) -> TileLists:
-    """Two-phase binning: count (pair total read back), then sort into exact-size lists."""
+                 stream=None) -> BinLists:
+    """Two-phase binning: count (pair total read back), then sort into exact-size bins."""
     dev = p.records.device
     ws = ws or _ws(dev)
     pair_ws = pair_ws or _ws(str(dev) + "/pairs")
@@ -219,10 +239,28 @@ def bin_and_sort(p: Projection, sensor: Sensor, ws: Workspace | None = None, pai
     (stream or torch.cuda.current_stream()).synchronize()
     P = int(total.item())
     pbuf = pair_ws.ensure(int(L.ut_pair_workspace_bytes(P)))
-    lists = TileLists(torch.empty(max(P, 1), dtype=torch.int32, device=dev),
-                      torch.empty((2, sensor.n_tiles), dtype=torch.int32, device=dev), P)
+    bins = BinLists(torch.empty(max(P, 1), dtype=torch.int32, device=dev),
+                    torch.empty((2, sensor.n_super), dtype=torch.int32, device=dev), P)
     check(L.ut_bin_sort(ref(p.c()), p.n, ref(sensor.c), buf.data_ptr(), buf.numel(), pbuf.data_ptr(), pbuf.numel(),
-                        P, ref(lists.c()), st), "ut_bin_sort")
+                        P, ref(bins.c()), st), "ut_bin_sort")
+    return bins
+
+
+def tile_lists(p: Projection, sensor: Sensor, bins: BinLists, stream=None) -> TileLists:
+    """Materialise the per-tile (depth, index)-ordered lists from the bins."""
+    dev = p.records.device
+    L = lib()
+    st = _stream(stream)
+    tot_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+    lists = TileLists(torch.empty(1, dtype=torch.int32, device=dev),
+                      torch.empty((2, sensor.n_tiles), dtype=torch.int32, device=dev), 0, tot_dev)
+    host = torch.zeros(1, dtype=torch.int64).pin_memory()
+    check(L.ut_tile_lists_count(ref(p.c()), ref(sensor.c), ref(bins.c()), ref(lists.c()), host.data_ptr(), st),
+          "ut_tile_lists_count")
+    (stream or torch.cuda.current_stream()).synchronize()
+    P = int(host.item())
+    lists = TileLists(torch.empty(max(P, 1), dtype=torch.int32, device=dev), lists.ranges, P, tot_dev)
+    check(L.ut_tile_lists_fill(ref(p.c()), ref(sensor.c), ref(bins.c()), ref(lists.c()), st), "ut_tile_lists_fill")
     return lists
 
 
@@ -257,27 +295,30 @@ def alloc_out(sensor: Sensor, device="cuda", state=True) -> RenderOut:
                      torch.empty(R, dtype=torch.int32, device=device) if state else None)
 
 
-def composite(p: Projection, lists: TileLists, sensor: Sensor, params=None, out: RenderOut | None = None,
+def composite(p: Projection, bins: BinLists, sensor: Sensor, params=None, out: RenderOut | None = None,
               state=True, stream=None) -> RenderOut:
     o = out if out is not None else alloc_out(sensor, p.records.device, state)
     prm = params or render_params()
     fn = lib().ut_composite_lidar if sensor.is_lidar else lib().ut_composite_camera
-    check(fn(ref(p.c()), ref(lists.c()), ref(sensor.c), ref(prm), ref(o.c()), _stream(stream)), "ut_composite")
+    check(fn(ref(p.c()), ref(bins.c()), ref(sensor.c), ref(prm), ref(o.c()), _stream(stream)), "ut_composite")
     return o
 
 
 def render(g: GaussianSet, sensor: Sensor, abk=UT_ABK, params=None, state=True, moments=False, stream=None):
-    """project -> bin_and_sort -> composite; returns (projection, lists, outputs)."""
+    """project -> bin_and_sort -> composite; returns (projection, bins, outputs)."""
     p = project(g, sensor, abk, moments=moments, stream=stream)
-    lists = bin_and_sort(p, sensor, stream=stream)
-    out = composite(p, lists, sensor, params, state=state, stream=stream)
-    return p, lists, out
+    bins = bin_and_sort(p, sensor, stream=stream)
+    out = composite(p, bins, sensor, params, state=state, stream=stream)
+    return p, bins, out
 
 
-def backward(g: GaussianSet, p: Projection, lists: TileLists, sensor: Sensor, fwd: RenderOut,
+def backward(g: GaussianSet, p: Projection, lists, sensor: Sensor, fwd: RenderOut,
              up_feat=None, up_depth=None, up_alpha=None, up_drop=None, params=None, stream=None) -> dict:
-    """Adjoint: gradients of sum(upstream * outputs) with respect to the particle parameters."""
+    """Adjoint: gradients of sum(upstream * outputs) with respect to the particle parameters.
+    ``lists`` are the forward's bins (materialised here) or already materialised TileLists."""
     dev = g.mean.device
+    if isinstance(lists, BinLists):
+        lists = tile_lists(p, sensor, lists, stream=stream)
     prm = params or render_params()
     acc = torch.empty(int(lib().ut_backward_workspace_bytes(g.n)), dtype=torch.uint8, device=dev)
     grads = dict(mean=torch.empty_like(g.mean), quat=torch.empty_like(g.quat),
@@ -299,8 +340,8 @@ def composite_batch(items, params=None, n_workgroups=None, ws: torch.Tensor | No
     prm = params or render_params()
     arr = (A.UtBatchItem * n)()
     keep = []
-    for i, (p, lists, sensor, out) in enumerate(items):
-        pc, lc, oc = p.c(), lists.c(), out.c()
+    for i, (p, bins, sensor, out) in enumerate(items):
+        pc, lc, oc = p.c(), bins.c(), out.c()
         keep += [pc, lc, oc]
         arr[i] = A.UtBatchItem(ref(pc), ref(lc), ref(sensor.c), ref(oc))
     need = int(lib().ut_batch_workspace_bytes(n))
@@ -327,15 +368,15 @@ class SensorPipeline:
         self.pair_ws = Workspace(dev)
         self.out = alloc_out(sensor, dev, state=state)
         self.total = torch.zeros(1, dtype=torch.int64).pin_memory()
-        self.lists: TileLists | None = None
+        self.bins: BinLists | None = None
         self.n_pairs = 0
 
-    def _ensure_lists(self, P: int):
+    def _ensure_bins(self, P: int):
         dev = self.g.mean.device
-        if self.lists is None or self.lists.gauss.numel() < P:
-            self.lists = TileLists(torch.empty(max(int(P * 1.1), 1), dtype=torch.int32, device=dev),
-                                   torch.empty((2, self.sensor.n_tiles), dtype=torch.int32, device=dev), P)
-        self.lists.n_pairs = P
+        if self.bins is None or self.bins.gauss.numel() < P:
+            self.bins = BinLists(torch.empty(max(int(P * 1.1), 1), dtype=torch.int32, device=dev),
+                                 torch.empty((2, self.sensor.n_super), dtype=torch.int32, device=dev), P)
+        self.bins.n_pairs = P
 
     def project_and_count(self, stream=None):
         L = lib()
@@ -355,17 +396,25 @@ class SensorPipeline:
         P = int(self.total.item())
         buf = self.ws.buf
         pbuf = self.pair_ws.ensure(int(L.ut_pair_workspace_bytes(P)))
-        self._ensure_lists(P)
+        self._ensure_bins(P)
         self.n_pairs = P
         check(L.ut_bin_sort(ref(self.p.c()), self.g.n, ref(self.sensor.c), buf.data_ptr(), buf.numel(),
-                            pbuf.data_ptr(), pbuf.numel(), P, ref(self.lists.c()), st), "ut_bin_sort")
+                            pbuf.data_ptr(), pbuf.numel(), P, ref(self.bins.c()), st), "ut_bin_sort")
         if composite_events is not None:
             composite_events[0].record(stream)
         fn = L.ut_composite_lidar if self.sensor.is_lidar else L.ut_composite_camera
-        check(fn(ref(self.p.c()), ref(self.lists.c()), ref(self.sensor.c), ref(self.params), ref(self.out.c()), st),
+        check(fn(ref(self.p.c()), ref(self.bins.c()), ref(self.sensor.c), ref(self.params), ref(self.out.c()), st),
               "ut_composite")
         if composite_events is not None:
             composite_events[1].record(stream)
+
+    def composite_only(self, stream=None, out: RenderOut | None = None):
+        L = lib()
+        fn = L.ut_composite_lidar if self.sensor.is_lidar else L.ut_composite_camera
+        o = out or self.out
+        check(fn(ref(self.p.c()), ref(self.bins.c()), ref(self.sensor.c), ref(self.params), ref(o.c()),
+                 _stream(stream)), "ut_composite")
+        return o
 
     def run(self, stream=None, composite_events=None):
         s = stream or torch.cuda.current_stream()

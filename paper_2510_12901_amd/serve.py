@@ -28,7 +28,7 @@ import torch
 
 from . import _abi as A
 from ._abi import check, lib, ref
-from .render import (GaussianSet, RenderOut, Sensor, SensorPipeline, TileLists, _stream, alloc_projection,
+from .render import (BinLists, GaussianSet, RenderOut, Sensor, SensorPipeline, _stream, alloc_projection,
                      render_params)
 
 ALIGN = 256
@@ -84,7 +84,7 @@ class Request:
     n_pairs: int = 0
     slot: "Slot" = None
     mem: tuple = None
-    lists: TileLists = None
+    bins: BinLists = None
     out: RenderOut = None
 
 
@@ -149,7 +149,7 @@ class Server:
         sensor = self.sensors[r.sensor]
         pw = int(lib().ut_pair_workspace_bytes(r.n_pairs))
         lb = 4 * max(r.n_pairs, 1)
-        rb = 8 * sensor.n_tiles
+        rb = 8 * sensor.n_super
         return pw, lb, rb
 
     def _sort(self, r: Request):
@@ -161,10 +161,10 @@ class Server:
         al = lambda v: (v + ALIGN - 1) // ALIGN * ALIGN
         pbuf = self.pool.view(r.mem, 0, pw)
         gauss = self.pool.view(r.mem, al(pw), lb).view(torch.int32)
-        ranges = self.pool.view(r.mem, al(pw) + al(lb), rb).view(torch.int32).view(2, sensor.n_tiles)
-        r.lists = TileLists(gauss, ranges, r.n_pairs)
+        ranges = self.pool.view(r.mem, al(pw) + al(lb), rb).view(torch.int32).view(2, sensor.n_super)
+        r.bins = BinLists(gauss, ranges, r.n_pairs)
         check(L.ut_bin_sort(ref(s.p.c()), g.n, ref(sensor.c), s.ws.data_ptr(), s.ws.numel(), pbuf.data_ptr(), pw,
-                            r.n_pairs, ref(r.lists.c()), _stream(s.stream)), "ut_bin_sort")
+                            r.n_pairs, ref(r.bins.c()), _stream(s.stream)), "ut_bin_sort")
         s.ev_sort.record(s.stream)
 
     def _composite(self, reqs, k):
@@ -176,7 +176,7 @@ class Server:
             cs.wait_event(r.slot.ev_sort)
             sensor = self.sensors[r.sensor]
             r.out = r.slot.out_for(sensor)
-            pc, lc, oc = r.slot.p.c(), r.lists.c(), r.out.c()
+            pc, lc, oc = r.slot.p.c(), r.bins.c(), r.out.c()
             keep += [pc, lc, oc]
             arr[i] = A.UtBatchItem(ref(pc), ref(lc), ref(sensor.c), ref(oc))
         import ctypes as C

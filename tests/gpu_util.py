@@ -9,8 +9,8 @@ import oracle
 AMBIG = 1e-9          # decisions closer than this to their threshold are ambiguous
 TOL = 1e-4            # max-abs bound on feat / depth / alpha / drop
 
-REC_DTYPE = np.dtype([("mu", "<f8", 3), ("b", "<f8", 6), ("sigma", "<f8"), ("feat", "<f4", 3),
-                      ("log_sigma", "<f4")])
+REC_DTYPE = np.dtype([("m", "<f8", 9), ("a", "<f8", 3), ("sigma", "<f8"), ("feat", "<f4", 3),
+                      ("log_sigma", "<f4"), ("pad", "<f8")])
 
 
 def to_np(t):
@@ -22,19 +22,27 @@ def gpu_render(g_np, s_np, moments=True, state=True):
     import paper_2510_12901_amd as ut
     g = ut.GaussianSet.from_numpy(g_np)
     s = ut.Sensor(s_np)
-    p, lists, out = ut.render(g, s, moments=moments, state=state)
+    p, bins, out = ut.render(g, s, moments=moments, state=state)
+    lists = ut.tile_lists(p, s, bins)
     torch.cuda.synchronize()
     P = lists.n_pairs
     res = dict(
         count=to_np(p.count).view(np.uint32)[:g.n], rect=to_np(p.rect)[:, :g.n], key=to_np(p.key).view(np.uint32)[:g.n],
         moments=to_np(p.moments)[:, :g.n] if moments else None, n_culled=to_np(p.n_culled),
-        records=to_np(p.records)[: g.n * 96].view(REC_DTYPE), gauss=to_np(lists.gauss).view(np.uint32)[:P],
-        ranges=to_np(lists.ranges).view(np.uint32), n_pairs=P,
+        records=to_np(p.records)[: g.n * REC_DTYPE.itemsize].view(REC_DTYPE), gauss=to_np(lists.gauss).view(np.uint32)[:P],
+        ranges=to_np(lists.ranges).view(np.uint32), n_pairs=P, n_bin_pairs=bins.n_pairs,
         feat=to_np(out.feat), depth=to_np(out.depth), alpha=to_np(out.alpha),
         drop=to_np(out.drop) if out.drop is not None else None,
         t_final=to_np(out.t_final) if out.t_final is not None else None,
         n_proc=to_np(out.n_proc).view(np.uint32) if out.n_proc is not None else None)
-    return res, (g, s, p, lists, out)
+    return res, (g, s, p, bins, out)
+
+
+def same_ranges(a, b):
+    """[start, end) tile ranges describe the same lists: equal lengths, equal starts wherever
+    a tile is non-empty (an empty range may sit at any offset)."""
+    la, lb = a[1].astype(np.int64) - a[0], b[1].astype(np.int64) - b[0]
+    return np.array_equal(la, lb) and np.array_equal(a[0][la > 0], b[0][lb > 0])
 
 
 def ambiguous_tiles(op, gp, n_tiles, tiles_x, lidar):
@@ -106,7 +114,7 @@ def full_parity(g_np, s_np):
     ol_g = oracle.bin_pairs(os_, gp["rect"], gp["count"], gp["key"])
     assert gp["n_pairs"] == ol_g["n_pairs"]
     assert np.array_equal(gp["gauss"], ol_g["pair_gauss"])
-    assert np.array_equal(gp["ranges"], ol_g["ranges"])
+    assert same_ranges(gp["ranges"], ol_g["ranges"])
     excl = None
     if n_amb:
         _, tiles = ambiguous_tiles(op, gp, os_.n_tiles, os_.tiles_x, os_.kind == 2)

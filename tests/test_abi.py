@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_record_size_and_status(L):
-    assert L.ut_record_bytes() == 96
+    assert L.ut_record_bytes() == 128
     assert L.ut_status_str(0) == b"ok"
     assert b"argument" in L.ut_status_str(-1)
 

@@ -65,20 +65,23 @@ def test_render_parity(name):
 
 
 def test_records_match_particle_definition():
-    """Record contents: opacity = sigmoid(logit) and B = Sigma^{-1} built from scipy's rotation."""
+    """Record contents: opacity = sigmoid(logit); M^T M = Sigma^{-1} with Sigma from scipy's
+    rotation; a = M (mu - o)."""
     from scipy.spatial.transform import Rotation
     g, s = _scene("pinhole_sh3_posed")
     gp, _ = gpu_render(g, s)
     rec = gp["records"]
+    o = s["origin"].astype(np.float64)
     for i in range(0, 3000, 97):
         w, x, y, z = g["quat"][:, i].astype(np.float64)
         R = Rotation.from_quat([x, y, z, w]).as_matrix()
         sc = np.exp(g["log_scale"][:, i].astype(np.float64))
         B = np.linalg.inv(R @ np.diag(sc * sc) @ R.T)
-        ref = np.array([B[0, 0], B[1, 1], B[2, 2], B[0, 1], B[0, 2], B[1, 2]])
-        np.testing.assert_allclose(rec["b"][i], ref, rtol=1e-9, atol=1e-9 * np.abs(B).max())
+        M = rec["m"][i].reshape(3, 3)
+        np.testing.assert_allclose(M.T @ M, B, rtol=1e-9, atol=1e-9 * np.abs(B).max())
+        v = g["mean"][:, i].astype(np.float64) - o
+        np.testing.assert_allclose(rec["a"][i], M @ v, rtol=1e-12, atol=1e-12 * np.abs(M @ v).max())
         np.testing.assert_allclose(rec["sigma"][i], 1 / (1 + np.exp(-np.float64(g["opacity_logit"][i]))), rtol=1e-14)
-        np.testing.assert_array_equal(rec["mu"][i], g["mean"][:, i].astype(np.float64))
 
 
 def test_determinism_and_permutation_invariance():
