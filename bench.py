@@ -27,10 +27,11 @@ if ROOT not in sys.path:
 
 PEAK_FP64_TFLOPS = 78.6        # MI355X dense float64 vector (FMA = 2 FLOPs)
 PEAK_HBM_GBS = 8000.0
-# float64 FLOPs the compositing kernel spends on every visited (ray, list entry): the
-# response geometry v, B d, d.Bd, v.Bd, 1/d.Bd (2 Newton steps), t*, u, B u, D^2 -- see
-# the design doc; contributing pairs cost ~42 FLOPs more (exp, alpha, accumulation), not counted.
-FLOPS_PER_VISIT = 64
+# float64 FLOPs (FMA = 2) that deciding one visited (ray, list entry) takes: w = M d (15),
+# c = a x w (9), c.c (5), w.w (5) and the comparison c.c > cut * w.w (1).  Entries that pass
+# the test cost ~60 FLOPs more (1/w.w, t*, D^2, exp, alpha, accumulation); they are not
+# counted, so the reported rate is a lower bound.
+FLOPS_PER_VISIT = 35
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "composite_traffic.json")
 
 
@@ -129,7 +130,7 @@ def main():
     comp_ms = np.array([[e[0].elapsed_time(e[1]) for e in evk] for evk in ev])   # [K, sensors]
     log(f"plain frame {ms_per_step:.2f} ms, {value:.1f} Mrays/s")
 
-    # Dominant kernel: camera compositing (k_composite<256>).  Its average launch duration is
+    # Dominant kernel: camera compositing (k_composite on 16x16 tiles).  Its average launch duration is
     # taken from HIP events on the rendering stream around REPS back-to-back launches per
     # camera (the queue stays full, so host launch latency is excluded); its work is the
     # visited list entries of the same launches (per-ray n_proc of an identical launch).
@@ -179,7 +180,7 @@ def main():
                    "tile_pairs_per_sensor": tile_pairs, "bin_pairs_per_sensor": bin_pairs},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
-                     "kernel": "k_composite<256> (camera compositing)",
+                     "kernel": "k_composite<256, 1, 128> (camera compositing)",
                      "flops_per_visit": FLOPS_PER_VISIT, "visits_per_launch": int(visits / len(cams)),
                      "avg_launch_ms": round(per_launch_ms, 4)},
         "composite_ms_per_camera": [round(float(x), 4) for x in cam_ms],

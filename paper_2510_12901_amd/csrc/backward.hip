@@ -58,7 +58,6 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
     }
   }
   const double Tf = T;
-  const double cut_bias = 1e-3 - 2.0 * prm.log_alpha_min;
   double S = 0.0;
   if (threadIdx.x == 0) s_max = 0;
   __syncthreads();
@@ -88,9 +87,10 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
       for (int k = 0; k < UT_ACC_FLOATS; ++k) g[k] = 0.0;
       if (j < (int)np) {
         const PairGeom q = pair_geometry(r, dx, dy, dz);
-        const double tau = q.tau, D2 = q.D2;
-        if (tau >= s.near_ && !(D2 > __builtin_fma(2.0, (double)r.log_sigma, cut_bias))) {
-          const double rho = exp_f64(-0.5 * D2);
+        const PairResp pr = pair_response(r, q);
+        const double tau = pr.tau;
+        if (!pair_cut(q, cut_threshold(r.log_sigma, prm.log_alpha_min)) && tau >= s.near_) {
+          const double rho = exp_f64(-0.5 * pr.D2);
           const double a = r.sigma * rho;
           const bool clamped = a > prm.alpha_max;
           const double alpha = clamped ? prm.alpha_max : a;
@@ -114,9 +114,12 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
             }
             // B = M^T M: B u = M^T r and B d = M^T w with u = mu - o - t* d
             const double* M = r.m;
-            const double bux = M[0] * q.r[0] + M[3] * q.r[1] + M[6] * q.r[2];
-            const double buy = M[1] * q.r[0] + M[4] * q.r[1] + M[7] * q.r[2];
-            const double buz = M[2] * q.r[0] + M[5] * q.r[1] + M[8] * q.r[2];
+            const double rx = __builtin_fma(-tau, q.w[0], r.a[0]);   // M (mu - o - t* d)
+            const double ry = __builtin_fma(-tau, q.w[1], r.a[1]);
+            const double rz = __builtin_fma(-tau, q.w[2], r.a[2]);
+            const double bux = M[0] * rx + M[3] * ry + M[6] * rz;
+            const double buy = M[1] * rx + M[4] * ry + M[7] * rz;
+            const double buz = M[2] * rx + M[5] * ry + M[8] * rz;
             const double bdx = M[0] * q.w[0] + M[3] * q.w[1] + M[6] * q.w[2];
             const double bdy = M[1] * q.w[0] + M[4] * q.w[1] + M[7] * q.w[2];
             const double bdz = M[2] * q.w[0] + M[5] * q.w[1] + M[8] * q.w[2];
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
             const double ux = ((double)mean[gi] - ox) - tau * dx;
             const double uy = ((double)mean[n + gi] - oy) - tau * dy;
             const double uz = ((double)mean[2 * n + gi] - oz) - tau * dz;
-            const double t2 = 2.0 * dD2, ti = dtau * q.iww;
+            const double t2 = 2.0 * dD2, ti = dtau * pr.iww;
             g[4] = t2 * bux + ti * bdx;
             g[5] = t2 * buy + ti * bdy;
             g[6] = t2 * buz + ti * bdz;

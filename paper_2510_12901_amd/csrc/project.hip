@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, doub
       r.a[0] = __builtin_fma(r.m[0], vx, __builtin_fma(r.m[1], vy, r.m[2] * vz));
       r.a[1] = __builtin_fma(r.m[3], vx, __builtin_fma(r.m[4], vy, r.m[5] * vz));
       r.a[2] = __builtin_fma(r.m[6], vx, __builtin_fma(r.m[7], vy, r.m[8] * vz));
-      r.pad = 0.0;
+      r.aux = 0.0;
     }
     r.sigma = sigma;
     r.log_sigma = ok ? (float)log(sigma) : -1e30f;

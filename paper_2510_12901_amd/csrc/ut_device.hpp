@@ -31,7 +31,7 @@ struct alignas(16) Record {
   double sigma;     // opacity
   float feat[3];    // colour or LiDAR features evaluated at the particle's SH direction
   float log_sigma;  // ln(opacity), for the conservative alpha_min pre-test
-  double pad;
+  double aux;       // zero in HBM; the compositing's LDS copy holds the pre-test threshold here
 };
 static_assert(sizeof(Record) == UT_RECORD_BYTES, "record size must match the ABI");
 constexpr int kRecordChunks = UT_RECORD_BYTES / 16;
@@ -104,14 +104,16 @@ __device__ __forceinline__ double rcp_f64(double x) {
   return __builtin_fma(r, e, r);
 }
 
-// Response geometry of one (ray, particle) pair; shared verbatim by the compositing and the
-// adjoint so both take identical skip / clamp / stop decisions.
+// Response geometry of one (ray, particle) pair in the particle's whitened frame, where the
+// particle is the unit ball: w = M d and a = M (mu - o).  The whitened ray passes the centre at
+// squared distance D^2 = |a x w|^2 / |w|^2 and reaches the maximum response at
+// t* = (a . w) / |w|^2 (Sec. 3, the 3D response replacing the 2D splat).  The compositing and
+// the adjoint evaluate it through the same functions, so both take identical skip / clamp /
+// stop decisions.
 struct PairGeom {
   double w[3];   // M d
-  double iww;    // 1 / (w.w) = 1 / (d^T Sigma^{-1} d)
-  double tau;    // distance of maximum response t*
-  double r[3];   // a - t* w = M (mu - o - t* d)
-  double D2;     // r.r
+  double ww;     // w.w = d^T Sigma^{-1} d
+  double cc;     // |a x w|^2 = D^2 w.w
 };
 
 __device__ __forceinline__ PairGeom pair_geometry(const Record& c, double dx, double dy, double dz) {
@@ -119,15 +121,36 @@ __device__ __forceinline__ PairGeom pair_geometry(const Record& c, double dx, do
   p.w[0] = __builtin_fma(c.m[0], dx, __builtin_fma(c.m[1], dy, c.m[2] * dz));
   p.w[1] = __builtin_fma(c.m[3], dx, __builtin_fma(c.m[4], dy, c.m[5] * dz));
   p.w[2] = __builtin_fma(c.m[6], dx, __builtin_fma(c.m[7], dy, c.m[8] * dz));
-  const double aw = __builtin_fma(c.a[0], p.w[0], __builtin_fma(c.a[1], p.w[1], c.a[2] * p.w[2]));
-  const double ww = __builtin_fma(p.w[0], p.w[0], __builtin_fma(p.w[1], p.w[1], p.w[2] * p.w[2]));
-  p.iww = rcp_f64(ww);
-  p.tau = aw * p.iww;
-  p.r[0] = __builtin_fma(-p.tau, p.w[0], c.a[0]);
-  p.r[1] = __builtin_fma(-p.tau, p.w[1], c.a[1]);
-  p.r[2] = __builtin_fma(-p.tau, p.w[2], c.a[2]);
-  p.D2 = __builtin_fma(p.r[0], p.r[0], __builtin_fma(p.r[1], p.r[1], p.r[2] * p.r[2]));
+  const double cx = __builtin_fma(c.a[1], p.w[2], -(c.a[2] * p.w[1]));
+  const double cy = __builtin_fma(c.a[2], p.w[0], -(c.a[0] * p.w[2]));
+  const double cz = __builtin_fma(c.a[0], p.w[1], -(c.a[1] * p.w[0]));
+  p.ww = __builtin_fma(p.w[0], p.w[0], __builtin_fma(p.w[1], p.w[1], p.w[2] * p.w[2]));
+  p.cc = __builtin_fma(cx, cx, __builtin_fma(cy, cy, cz * cz));
   return p;
+}
+
+// D^2 threshold of the conservative pre-test: beyond it sigma * rho < alpha_min for certain
+// (ln rho = -D^2 / 2, with 1e-3 of slack for rounding).
+__device__ __forceinline__ double cut_threshold(float log_sigma, double log_alpha_min) {
+  return __builtin_fma(2.0, (double)log_sigma, 1e-3 - 2.0 * log_alpha_min);
+}
+
+// True when the pair cannot reach alpha_min: D^2 > cut, tested as |a x w|^2 > cut w.w.
+__device__ __forceinline__ bool pair_cut(const PairGeom& q, double cut) { return q.cc > q.ww * cut; }
+
+struct PairResp {
+  double iww;   // 1 / (w.w)
+  double tau;   // t*
+  double D2;    // squared whitened distance
+};
+
+__device__ __forceinline__ PairResp pair_response(const Record& c, const PairGeom& q) {
+  PairResp r;
+  r.iww = rcp_f64(q.ww);
+  const double aw = __builtin_fma(c.a[0], q.w[0], __builtin_fma(c.a[1], q.w[1], c.a[2] * q.w[2]));
+  r.tau = aw * r.iww;
+  r.D2 = q.cc * r.iww;
+  return r;
 }
 
 // Packed tile rect of a particle: (x0 | y0 << 16, x1 | y1 << 16); LiDAR x1 may exceed
