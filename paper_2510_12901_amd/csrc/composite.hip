@@ -1,16 +1,18 @@
 // composite.hip -- per-ray front-to-back compositing (Eq. 1) over tile lists.
 //
-// One workgroup per tile, one lane per ray.  The workgroup streams its super-tile bin,
+// One workgroup per tile, one lane per ray.  The workgroup streams its super-tile bin and
 // keeps the entries whose rect contains the tile (ballot + popcount per wavefront, wave
-// counts combined in LDS, appended in order to an LDS ring of candidate indices), and
-// stages batches of BLOCK candidates' records (96 B each, gathered cooperatively as
-// 16-byte chunks) in LDS; every lane then walks the batch for its own ray.  The candidate
-// order is the tile's exact (depth, index) list.  A lane that reaches T < t_min stops (its
-// wavefront stops when all 64 lanes have), and the workgroup stops once every lane is done.
+// counts combined in LDS); these form the tile's exact (depth, index) list.  Of those it
+// appends to an LDS ring only the entries that can reach alpha_min on at least one ray of
+// the tile (the tile-cone test below), stages batches of their 128-byte records in LDS
+// (gathered cooperatively as 16-byte chunks), and every lane walks the batch for its own ray.
+// A lane that reaches T < t_min stops (its wavefront stops when all 64 lanes have), and the
+// workgroup stops once every lane is done.
 //
-// Per (ray, particle): w = M d, t* = a.w / w.w, r = a - t* w, D^2 = r.r (see Record),
-// rho = exp(-D^2/2) -- all float64 with explicit FMAs (no contraction flags can change
-// the arithmetic between the plain and the batched kernel, or between forward and adjoint).
+// Per (ray, particle): w = M d, rejected when |a x w|^2 > cut w.w, else t* = a.w / w.w and
+// D^2 = |a x w|^2 / w.w, rho = exp(-D^2/2) -- all float64 with explicit FMAs (no contraction
+// flags can change the arithmetic between the plain and the batched kernel, or between
+// forward and adjoint).
 #include "ut_internal.hpp"
 
 namespace ut {
@@ -20,6 +22,15 @@ namespace {
 // threads with RPL rays per lane and stage BATCH records per step.
 constexpr int kCamBlock = 256, kCamRpl = 1, kCamBatch = 128;
 static_assert(kCamBlock * kCamRpl >= UT_MAX_LIDAR_TILE_RAYS, "batched tiles must fit one workgroup");
+
+// Bounding cone of a tile's rays: unit axis u, orthonormal e1, e2 spanning u's complement,
+// and cos / sin of twice the half-angle.  `on` is false when the tile has no ray or the cone
+// is too wide for the bound below (half-angle > 45 degrees).
+struct TileCone {
+  double u[3], e1[3], e2[3];
+  double cos2t, sin2t;
+  int on;
+};
 
 // BLOCK threads, RPL rays per lane: one workgroup covers up to BLOCK * RPL rays.  Records are
 // staged BATCH at a time; the ring of candidate indices holds a batch plus one refill step of
@@ -32,9 +43,79 @@ struct CompositeShared {
   static constexpr uint32_t kRing = BATCH + BLOCK <= 2 * BATCH ? 2 * BATCH : 4 * BATCH;
   static_assert(BATCH + BLOCK <= (int)kRing, "ring must hold a batch plus one refill step");
   Record rec[BATCH];
-  uint32_t cand[kRing];   // ring of candidate particle indices
-  uint32_t wcnt[BLOCK / 64];
+  uint32_t rpos[BATCH];    // position of each staged record in the tile's list
+  uint32_t cand[kRing];    // ring of candidate particle indices ...
+  uint32_t cpos[kRing];    // ... and their positions in the tile's list
+  uint2 wcnt[BLOCK / 64];  // per wavefront: (rect hits, kept entries) of one refill step
+  double red[4][BLOCK / 64];
+  TileCone cone;
 };
+
+// Conservative tile-cone test: true when no unit direction d within the cone can bring the
+// particle's response to alpha_min, i.e. h(d) = |a x Md|^2 - cut |Md|^2 > 0 on the whole cone.
+// With d = cos(phi) u + sin(phi) e, e a unit vector in span(e1, e2) and phi <= theta,
+//   h >= cos^2(phi) A - 2 sin(phi) cos(phi) B + sin^2(phi) C,
+// where A = h(u), B bounds the mixed term over all e and C is the smallest eigenvalue of the
+// form on span(e1, e2).  In psi = 2 phi this is P + Rc cos(psi) - B sin(psi), minimised over
+// psi in [0, 2 theta] in closed form.  The threshold carries 0.05 of slack over the per-ray
+// cut so that rounding cannot drop an entry that a ray would keep; the dropped entries are
+// exactly ones every ray of the tile would skip, so outputs are unchanged.
+__device__ __forceinline__ bool cone_rejects(const Record* __restrict__ rp, const TileCone& tc,
+                                             double log_alpha_min) {
+  const double cut = cut_threshold(rp->log_sigma, log_alpha_min) + 0.05;
+  double m[9], a[3];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) m[i] = rp->m[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) a[i] = rp->a[i];
+  double w[3][3], x[3][3];   // w_k = M v_k and x_k = a x w_k for v = (u, e1, e2)
+  const double* v[3] = {tc.u, tc.e1, tc.e2};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      w[k][i] = __builtin_fma(m[3 * i], v[k][0], __builtin_fma(m[3 * i + 1], v[k][1], m[3 * i + 2] * v[k][2]));
+    x[k][0] = __builtin_fma(a[1], w[k][2], -(a[2] * w[k][1]));
+    x[k][1] = __builtin_fma(a[2], w[k][0], -(a[0] * w[k][2]));
+    x[k][2] = __builtin_fma(a[0], w[k][1], -(a[1] * w[k][0]));
+  }
+  auto H = [&](int i, int j) {
+    const double xx = __builtin_fma(x[i][0], x[j][0], __builtin_fma(x[i][1], x[j][1], x[i][2] * x[j][2]));
+    const double ww = __builtin_fma(w[i][0], w[j][0], __builtin_fma(w[i][1], w[j][1], w[i][2] * w[j][2]));
+    return __builtin_fma(-cut, ww, xx);
+  };
+  const double A = H(0, 0), H01 = H(0, 1), H02 = H(0, 2);
+  const double H11 = H(1, 1), H12 = H(1, 2), H22 = H(2, 2);
+  const double B = __builtin_sqrt(__builtin_fma(H01, H01, H02 * H02));
+  const double hd = 0.5 * (H11 - H22);
+  const double C = 0.5 * (H11 + H22) - __builtin_sqrt(__builtin_fma(hd, hd, H12 * H12));
+  const double P = 0.5 * (A + C), Rc = 0.5 * (A - C);
+  const double rad = __builtin_sqrt(__builtin_fma(Rc, Rc, B * B));
+  double fmin;
+  if (-Rc >= rad * tc.cos2t) {
+    fmin = P - rad;   // the minimiser psi* = pi - atan2(B, Rc) lies inside [0, 2 theta]
+  } else {
+    const double f1 = __builtin_fma(Rc, tc.cos2t, P) - B * tc.sin2t;
+    fmin = A < f1 ? A : f1;
+  }
+  return fmin > 0.0;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ double block_reduce(double v, bool is_min, double (&red)[BLOCK / 64], int wave, int lane) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(v, off);
+    v = is_min ? (o < v ? o : v) : v + o;
+  }
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int w = 1; w < BLOCK / 64; ++w) r = is_min ? (red[w] < r ? red[w] : r) : r + red[w];
+  __syncthreads();
+  return r;
+}
 
 template <int BLOCK, int RPL, int BATCH>
 __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* __restrict__ rec,
@@ -53,6 +134,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
   uint32_t nproc[RPL];
   bool rdone[RPL];
   bool done = true;
+  double sx = 0, sy = 0, sz = 0;
 #pragma unroll
   for (int k = 0; k < RPL; ++k) {
     ray[k] = tile_ray(s, tile, threadIdx.x + k * BLOCK);
@@ -67,14 +149,58 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
     T[k] = 1.0;
     f0[k] = f1[k] = f2[k] = dep[k] = 0;
     nproc[k] = 0;
+    if (!rdone[k]) {
+      const double il = rcp_f64(__builtin_sqrt(__builtin_fma(dx[k], dx[k], __builtin_fma(dy[k], dy[k], dz[k] * dz[k]))));
+      sx = __builtin_fma(dx[k], il, sx);
+      sy = __builtin_fma(dy[k], il, sy);
+      sz = __builtin_fma(dz[k], il, sz);
+    }
   }
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
   const unsigned long long lt = (1ull << lane) - 1ull;
-  uint32_t pos = start, head = 0, n_cand = 0, list_base = 0;   // uniform across the workgroup
+
+  // bounding cone of the tile's rays (identical in every lane: built from block reductions)
+  sx = block_reduce<BLOCK>(sx, false, sm.red[0], wave, lane);
+  sy = block_reduce<BLOCK>(sy, false, sm.red[1], wave, lane);
+  sz = block_reduce<BLOCK>(sz, false, sm.red[2], wave, lane);
+  const double sn = __builtin_sqrt(__builtin_fma(sx, sx, __builtin_fma(sy, sy, sz * sz)));
+  const double ux = sx / sn, uy = sy / sn, uz = sz / sn;
+  double cmin = 1.0;
+#pragma unroll
+  for (int k = 0; k < RPL; ++k) {
+    if (rdone[k]) continue;
+    const double l = __builtin_sqrt(__builtin_fma(dx[k], dx[k], __builtin_fma(dy[k], dy[k], dz[k] * dz[k])));
+    const double c = __builtin_fma(ux, dx[k], __builtin_fma(uy, dy[k], uz * dz[k])) / l;
+    cmin = c < cmin ? c : cmin;
+  }
+  cmin = block_reduce<BLOCK>(cmin, true, sm.red[3], wave, lane);
+  if (threadIdx.x == 0) {
+    TileCone& tc = sm.cone;
+    const double ct = cmin - 1e-9;                       // widen for rounding
+    tc.on = (sn > 0.0 && ct > 0.7071067811865476) ? 1 : 0;
+    const double st = __builtin_sqrt(1.0 - ct * ct);
+    tc.cos2t = 2.0 * ct * ct - 1.0;
+    tc.sin2t = 2.0 * st * ct;
+    tc.u[0] = ux, tc.u[1] = uy, tc.u[2] = uz;
+    // e1 = normalise(u x t) with t the coordinate axis least aligned with u; e2 = u x e1
+    double t0 = 0, t1 = 0, t2 = 0;
+    if (__builtin_fabs(ux) <= __builtin_fabs(uy) && __builtin_fabs(ux) <= __builtin_fabs(uz)) t0 = 1;
+    else if (__builtin_fabs(uy) <= __builtin_fabs(uz)) t1 = 1;
+    else t2 = 1;
+    double e0 = uy * t2 - uz * t1, e1 = uz * t0 - ux * t2, e2 = ux * t1 - uy * t0;
+    const double en = __builtin_sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    e0 /= en, e1 /= en, e2 /= en;
+    tc.e1[0] = e0, tc.e1[1] = e1, tc.e1[2] = e2;
+    tc.e2[0] = uy * e2 - uz * e1, tc.e2[1] = uz * e0 - ux * e2, tc.e2[2] = ux * e1 - uy * e0;
+  }
+  __syncthreads();
+  const bool cull = sm.cone.on != 0;
+
+  uint32_t pos = start, head = 0, n_cand = 0, n_hits = 0;   // uniform across the workgroup
 
   for (;;) {
     if (__syncthreads_and(done)) break;
-    // refill the candidate ring with this tile's entries of the super-tile bin
+    // refill the candidate ring with this tile's list entries that pass the tile-cone test
     while (n_cand < (uint32_t)kBatch && pos < end) {
       const uint32_t j = pos + threadIdx.x;
       uint32_t g = 0;
@@ -83,18 +209,24 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
         g = bgauss[j];
         hit = rect_covers(trect[g], tx, ty, s);
       }
-      const unsigned long long m = __ballot(hit);
-      if (lane == 0) sm.wcnt[wave] = (uint32_t)__popcll(m);
+      const bool keep = hit && !(cull && cone_rejects(rec + g, sm.cone, prm.log_alpha_min));
+      const unsigned long long mh = __ballot(hit), mk = __ballot(keep);
+      if (lane == 0) sm.wcnt[wave] = make_uint2((uint32_t)__popcll(mh), (uint32_t)__popcll(mk));
       __syncthreads();
-      uint32_t before = 0, total = 0;
+      uint32_t hb = 0, kb = 0, ht = 0, kt = 0;
 #pragma unroll
       for (int w = 0; w < BLOCK / 64; ++w) {
-        const uint32_t c = sm.wcnt[w];
-        if (w < wave) before += c;
-        total += c;
+        const uint2 c = sm.wcnt[w];
+        if (w < wave) hb += c.x, kb += c.y;
+        ht += c.x, kt += c.y;
       }
-      if (hit) sm.cand[(head + n_cand + before + (uint32_t)__popcll(m & lt)) & kRing] = g;
-      n_cand += total;
+      if (keep) {
+        const uint32_t slot = (head + n_cand + kb + (uint32_t)__popcll(mk & lt)) & kRing;
+        sm.cand[slot] = g;
+        sm.cpos[slot] = n_hits + hb + (uint32_t)__popcll(mh & lt);
+      }
+      n_cand += kt;
+      n_hits += ht;
       pos += BLOCK;
       __syncthreads();
     }
@@ -102,12 +234,14 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
     const uint32_t cnt = min(n_cand, (uint32_t)kBatch);
     for (uint32_t c = threadIdx.x; c < cnt * kRecordChunks; c += BLOCK) {
       const uint32_t j = c / kRecordChunks, part = c - j * kRecordChunks;
-      const uint32_t g = sm.cand[(head + j) & kRing];
+      const uint32_t slot = (head + j) & kRing;
+      const uint32_t g = sm.cand[slot];
       uint4 v = reinterpret_cast<const uint4*>(rec + g)[part];
       if (part == kRecordChunks - 1) {   // bytes 112..127: feat[2], log_sigma, aux
         const double cut = cut_threshold(__uint_as_float(v.y), prm.log_alpha_min);
         v.z = (uint32_t)__double2loint(cut);
         v.w = (uint32_t)__double2hiint(cut);
+        sm.rpos[j] = sm.cpos[slot];
       }
       reinterpret_cast<uint4*>(sm.rec + j)[part] = v;
     }
@@ -135,7 +269,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
           T[k] = T[k] * (1.0 - alpha);
           if (T[k] < prm.t_min) {
             rdone[k] = true;
-            nproc[k] = list_base + j + 1;   // entries up to and including the terminating one
+            nproc[k] = sm.rpos[j] + 1;   // list entries up to and including the terminating one
           }
         }
         bool all = true;
@@ -149,12 +283,11 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
     }
     head = (head + cnt) & kRing;
     n_cand -= cnt;
-    list_base += cnt;
   }
   // a ray still open here has visited the whole list of its tile
 #pragma unroll
   for (int k = 0; k < RPL; ++k)
-    if (!rdone[k]) nproc[k] = list_base;
+    if (!rdone[k]) nproc[k] = n_hits;
 #pragma unroll
   for (int k = 0; k < RPL; ++k) {
     if (ray[k] < 0) continue;

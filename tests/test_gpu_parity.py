@@ -47,11 +47,17 @@ def _scene(name):
         s = synth.lidar(synth.beams_uniform(rng, 48), 600, R_sw=synth.yaw_lidar_pose(2.1), origin=o,
                         n_phi=6, max_per_tile=64)
         return g, s
+    if name == "pinhole_wide_aniso":                   # wide field of view, needle/disc particles
+        rng = np.random.default_rng(6)                 # (1:1000 axis ratios) close to the camera
+        n = 6000
+        mean = np.stack([rng.uniform(-6, 6, n), rng.uniform(-4, 4, n), rng.uniform(0.3, 8, n)])
+        g = synth.particles(rng, mean, 0.002, 2.0, 0, synth.FEAT_CAMERA)
+        return g, synth.pinhole(160, 120, 55.0, 55.0)
     raise KeyError(name)
 
 
-SCENES = ["pinhole_128x96", "pinhole_ragged", "pinhole_sh3_posed", "fisheye_small", "lidar_small",
-          "lidar_nocull", "lidar_posed_m64"]
+SCENES = ["pinhole_128x96", "pinhole_ragged", "pinhole_sh3_posed", "pinhole_wide_aniso", "fisheye_small",
+          "lidar_small", "lidar_nocull", "lidar_posed_m64"]
 
 
 @pytest.mark.parametrize("name", SCENES)
