@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--particles", type=int, default=2_000_000)
+    ap.add_argument("--streams", type=int, default=4, help="HIP streams the sensors of a frame are spread over")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -100,15 +101,20 @@ def main():
     log(f"setup {time.time() - t_setup:.1f}s, rays/frame {rays_per_frame}")
 
     stream = torch.cuda.current_stream()
+    # the sensors of a frame are independent: spread them over a few streams (default
+    # priority) so that one sensor's small binning kernels overlap another's compositing
+    streams = [torch.cuda.Stream(device=dev) for _ in range(min(args.streams, len(pipes)))]
+    torch.cuda.synchronize()
 
     def frame(events=None):
         # every sensor's projection + pair count first, one host synchronisation for the
         # seven pair totals, then every sensor's sort + compositing
-        for p in pipes:
-            p.project_and_count(stream)
-        stream.synchronize()
         for i, p in enumerate(pipes):
-            p.sort_and_composite(stream, None if events is None else events[i])
+            p.project_and_count(streams[i % len(streams)])
+        for st in streams:
+            st.synchronize()
+        for i, p in enumerate(pipes):
+            p.sort_and_composite(streams[i % len(streams)], None if events is None else events[i])
 
     for _ in range(args.warmup):
         frame()
