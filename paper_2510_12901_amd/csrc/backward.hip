@@ -90,7 +90,7 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
         const PairResp pr = pair_response(r, q);
         const double tau = pr.tau;
         if (!pair_cut(q, cut_threshold(r.log_sigma, prm.log_alpha_min)) && tau >= s.near_) {
-          const double rho = exp_f64(-0.5 * pr.D2);
+          const double rho = exp_neg(-0.5 * pr.D2, kExp2Frac);
           const double a = r.sigma * rho;
           const bool clamped = a > prm.alpha_max;
           const double alpha = clamped ? prm.alpha_max : a;

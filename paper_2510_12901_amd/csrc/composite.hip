@@ -48,6 +48,7 @@ struct CompositeShared {
   uint32_t cpos[kRing];    // ... and their positions in the tile's list
   uint2 wcnt[BLOCK / 64];  // per wavefront: (rect hits, kept entries) of one refill step
   double red[4][BLOCK / 64];
+  double etab[32];         // LDS copy of kExp2Frac for the response's exponential
   TileCone cone;
 };
 
@@ -158,6 +159,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
   }
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
   const unsigned long long lt = (1ull << lane) - 1ull;
+  if (threadIdx.x < 32) sm.etab[threadIdx.x] = kExp2Frac[threadIdx.x];
 
   // bounding cone of the tile's rays (identical in every lane: built from block reductions)
   sx = block_reduce<BLOCK>(sx, false, sm.red[0], wave, lane);
@@ -257,9 +259,8 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
           const PairResp pr = pair_response(r, q);
           const double tau = pr.tau;
           if (tau < s.near_) continue;
-          const double rho = exp_f64(-0.5 * pr.D2);
-          const double a = r.sigma * rho;
-          const double alpha = a > prm.alpha_max ? prm.alpha_max : a;
+          const double rho = exp_neg(-0.5 * pr.D2, sm.etab);
+          const double alpha = __builtin_fmin(r.sigma * rho, prm.alpha_max);
           if (alpha < prm.alpha_min) continue;
           const double w = alpha * T[k];
           f0[k] = __builtin_fma(w, (double)r.feat[0], f0[k]);
@@ -312,7 +313,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n_tiles) {
 }
 
 template <int BLOCK, int RPL, int BATCH>
-__global__ __launch_bounds__(BLOCK) void k_composite(SensorK s, const Record* __restrict__ rec,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void k_composite(SensorK s, const Record* __restrict__ rec,
                                                       const uint2* __restrict__ trect,
                                                       const uint32_t* __restrict__ bgauss,
                                                       const uint32_t* __restrict__ branges, int n_tiles,

@@ -69,30 +69,37 @@ inline TableLayout table_layout(int n_phi, int cull_az, int cull_el) {
   return t;
 }
 
-// exp(x) for x <= 0 in float64: Cody-Waite reduction x = n ln2 + r with a two-part ln2
-// (the high part keeps 32 significant bits so n * hi is exact), then the Taylor series of
-// e^r to degree 12 (truncation < 2e-16 for |r| <= ln2/2), then scaling by 2^n.
-__device__ __forceinline__ double exp_f64(double x) {
-  const double kLog2e = 1.4426950408889634;
-  const double kLn2Hi = 0.6931471803691238;
-  const double kLn2Lo = 1.9082149292705877e-10;
-  const double n = __builtin_rint(x * kLog2e);
-  double r = __builtin_fma(-n, kLn2Hi, x);
-  r = __builtin_fma(-n, kLn2Lo, r);
-  double p = 1.0 / 479001600.0;
-  p = __builtin_fma(p, r, 1.0 / 39916800.0);
-  p = __builtin_fma(p, r, 1.0 / 3628800.0);
-  p = __builtin_fma(p, r, 1.0 / 362880.0);
-  p = __builtin_fma(p, r, 1.0 / 40320.0);
-  p = __builtin_fma(p, r, 1.0 / 5040.0);
-  p = __builtin_fma(p, r, 1.0 / 720.0);
-  p = __builtin_fma(p, r, 1.0 / 120.0);
-  p = __builtin_fma(p, r, 1.0 / 24.0);
+// 2^(j/32), j = 0..31, correctly rounded to float64 (evaluated in 60-digit decimal arithmetic).
+__constant__ static const double kExp2Frac[32] = {
+    0x1.0000000000000p+0, 0x1.059b0d3158574p+0, 0x1.0b5586cf9890fp+0, 0x1.11301d0125b51p+0,
+    0x1.172b83c7d517bp+0, 0x1.1d4873168b9aap+0, 0x1.2387a6e756238p+0, 0x1.29e9df51fdee1p+0,
+    0x1.306fe0a31b715p+0, 0x1.371a7373aa9cbp+0, 0x1.3dea64c123422p+0, 0x1.44e086061892dp+0,
+    0x1.4bfdad5362a27p+0, 0x1.5342b569d4f82p+0, 0x1.5ab07dd485429p+0, 0x1.6247eb03a5585p+0,
+    0x1.6a09e667f3bcdp+0, 0x1.71f75e8ec5f74p+0, 0x1.7a11473eb0187p+0, 0x1.82589994cce13p+0,
+    0x1.8ace5422aa0dbp+0, 0x1.93737b0cdc5e5p+0, 0x1.9c49182a3f090p+0, 0x1.a5503b23e255dp+0,
+    0x1.ae89f995ad3adp+0, 0x1.b7f76f2fb5e47p+0, 0x1.c199bdd85529cp+0, 0x1.cb720dcef9069p+0,
+    0x1.d5818dcfba487p+0, 0x1.dfc97337b9b5fp+0, 0x1.ea4afa2a490dap+0, 0x1.f50765b6e4540p+0};
+
+// e^x in float64 for the response (x <= 0; results below the smallest normal flush towards 0).
+// Table-driven reduction: x = (32 n + j) ln2/32 + r with |r| <= ln2/64 (Cody-Waite: ln2/32 split
+// into a 40-bit head, so k * head is exact, and a tail), e^x = 2^n 2^(j/32) e^r, and e^r by its
+// degree-5 Taylor polynomial (truncation < 2.3e-15 relative).  `tab` holds the 32 values of
+// kExp2Frac; the compositing passes an LDS copy, the adjoint the constant array itself, and
+// both get bit-identical results.
+__device__ __forceinline__ double exp_neg(double x, const double* tab) {
+  const double kInvLn2x32 = 0x1.71547652b82fep+5;   // 32 / ln 2
+  const double kHi = 0x1.62e42fefa2000p-6;          // head of ln 2 / 32
+  const double kLo = 0x1.9ef35793c7673p-46;         // ln 2 / 32 - head
+  const double k = __builtin_rint(x * kInvLn2x32);
+  double r = __builtin_fma(-k, kHi, x);
+  r = __builtin_fma(-k, kLo, r);
+  const int ki = (int)k;
+  double p = __builtin_fma(r, 1.0 / 120.0, 1.0 / 24.0);
   p = __builtin_fma(p, r, 1.0 / 6.0);
   p = __builtin_fma(p, r, 0.5);
   p = __builtin_fma(p, r, 1.0);
   p = __builtin_fma(p, r, 1.0);
-  return __builtin_ldexp(p, (int)n);
+  return __builtin_ldexp(p * tab[ki & 31], ki >> 5);
 }
 
 // 1/x in float64 from the hardware estimate refined by two Newton steps.
