@@ -120,7 +120,8 @@ typedef struct {
 
 /* Projection output, all device buffers sized for n particles (caller-allocated). */
 typedef struct {
-  void* records;       /* [n] UT_RECORD_BYTES each (layout private to the library) */
+  void* records;       /* [n] UT_RECORD_BYTES each (layout private to the library); written only
+                          for particles with count > 0, the rest are left untouched */
   int32_t* rect;       /* [4][n] tile rect x0,y0,x1,y1 inclusive; LiDAR x = azimuth tile,
                           x1 may exceed n_theta-1 where the rect wraps through 0 */
   uint32_t* key;       /* [n] depth key: float32 bits of |mu - o|^2 computed

@@ -1,8 +1,9 @@
 // project.hip -- per-particle sigma-point projection (one lane per particle).
 //
 // Loads are structure-of-arrays and coalesced; the arithmetic is float64 (on gfx950 a
-// float64 FMA costs the same issue slot as an unpacked float32 FMA, and the stage is
-// bound by HBM traffic: ~(11 + 3K) floats in, 96 + 28 bytes out per particle).
+// float64 FMA costs the same issue slot as an unpacked float32 FMA).  Every particle reads
+// 11 floats and writes 32 bytes (rects, key, count); a particle that reaches a tile also
+// reads its 3K SH floats and writes its 128-byte record.
 #include <algorithm>
 
 #include "ut_internal.hpp"
@@ -12,29 +13,31 @@ namespace ut {
 namespace {
 
 // Sensor map g(x) of one world point: (u, v) and validity (see utrast.h for each model).
+template <int KIND>
 __device__ __forceinline__ bool project_point(const SensorK& s, const double xw[3], double& u, double& v) {
   const double dx = xw[0] - s.o[0], dy = xw[1] - s.o[1], dz = xw[2] - s.o[2];
   const double x = s.R[0] * dx + s.R[1] * dy + s.R[2] * dz;
   const double y = s.R[3] * dx + s.R[4] * dy + s.R[5] * dz;
   const double z = s.R[6] * dx + s.R[7] * dy + s.R[8] * dz;
-  if (s.kind == UT_PINHOLE) {
+  if constexpr (KIND == UT_PINHOLE) {
     if (!(z > s.near_)) return false;
     const double iz = 1.0 / z;
     u = s.fx * x * iz + s.cx;
     v = s.fy * y * iz + s.cy;
     return true;
   }
-  if (s.kind == UT_ORTHO) {
+  if constexpr (KIND == UT_ORTHO) {
     if (!(z > s.near_)) return false;
     u = s.fx * x + s.cx;
     v = s.fy * y + s.cy;
     return true;
   }
+  if constexpr (KIND != UT_FISHEYE && KIND != UT_LIDAR) return false;
   const double rho2 = x * x + y * y;
   const double r = sqrt(rho2 + z * z);
   if (!(r > s.near_)) return false;
   const double rho = sqrt(rho2);
-  if (s.kind == UT_FISHEYE) {
+  if constexpr (KIND == UT_FISHEYE) {
     const double theta = atan2(rho, z);
     if (!(theta <= s.theta_max)) return false;
     const double t2 = theta * theta;
@@ -76,14 +79,16 @@ __device__ __forceinline__ uint32_t depth_key(float mx, float my, float mz, cons
 }
 
 // DEG is the SH degree as a compile-time constant, so the (DEG+1)^2 x 3 coefficient loads are
-// unrolled and issued together instead of one dependent loop trip at a time.
-template <int DEG>
-__global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, double ut_a, double ut_b,
-                                                  double ut_k, Record* __restrict__ rec,
-                                                  int32_t* __restrict__ rect, uint2* __restrict__ trect,
-                                                  uint32_t* __restrict__ key,
-                                                  uint32_t* __restrict__ count, float* __restrict__ moments,
-                                                  uint32_t* __restrict__ n_culled) {
+// unrolled and issued together instead of one dependent loop trip at a time.  KIND is the
+// sensor model, so each instantiation carries only its own projection code (the LiDAR and
+// fisheye arctangents would otherwise set the register count of every camera).
+template <int DEG, int KIND>
+__device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK& s, double ut_a, double ut_b,
+                                            double ut_k, Record* __restrict__ rec,
+                                            int32_t* __restrict__ rect, uint2* __restrict__ trect,
+                                            uint32_t* __restrict__ key,
+                                            uint32_t* __restrict__ count, float* __restrict__ moments,
+                                            uint32_t* __restrict__ n_culled) {
   const int n = g.n;
   uint32_t n_invalid = 0, n_raycull = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -132,15 +137,18 @@ __global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, doub
         const double gam = sqrt(cpl);
         double gu[7], gv[7];
         const double mu[3] = {(double)mx, (double)my, (double)mz};
-        ok = project_point(s, mu, gu[0], gv[0]);
-        for (int j = 0; j < 3 && ok; ++j) {
+        ok = project_point<KIND>(s, mu, gu[0], gv[0]);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          if (!ok) break;
           const double e0 = gam * sc[j] * Rm[j], e1 = gam * sc[j] * Rm[3 + j], e2 = gam * sc[j] * Rm[6 + j];
           const double pp[3] = {mu[0] + e0, mu[1] + e1, mu[2] + e2};
           const double pm[3] = {mu[0] - e0, mu[1] - e1, mu[2] - e2};
-          ok = project_point(s, pp, gu[1 + j], gv[1 + j]) && project_point(s, pm, gu[4 + j], gv[4 + j]);
+          ok = project_point<KIND>(s, pp, gu[1 + j], gv[1 + j]) && project_point<KIND>(s, pm, gu[4 + j], gv[4 + j]);
         }
         if (ok) {
-          if (s.kind == UT_LIDAR) {
+          if constexpr (KIND == UT_LIDAR) {
+#pragma unroll
             for (int k = 1; k < 7; ++k) {
               while (gu[k] - gu[0] > kPi) gu[k] -= 2 * kPi;
               while (gu[k] - gu[0] <= -kPi) gu[k] += 2 * kPi;
@@ -149,7 +157,9 @@ __global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, doub
           const double wm0 = lam / cpl, wc0 = lam / cpl + 1.0 - ut_a * ut_a + ut_b, wi = 1.0 / (2.0 * cpl);
           m0 = wm0 * gu[0];
           m1 = wm0 * gv[0];
+#pragma unroll
           for (int k = 1; k < 7; ++k) { m0 += wi * gu[k]; m1 += wi * gv[k]; }
+#pragma unroll
           for (int k = 0; k < 7; ++k) {
             const double w = k == 0 ? wc0 : wi;
             const double du = gu[k] - m0, dv = gv[k] - m1;
@@ -167,7 +177,7 @@ __global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, doub
     uint32_t cnt = 0;
     if (ok) {
       const double eu = 3.0 * sqrt(c00), ev = 3.0 * sqrt(c11);
-      if (s.kind != UT_LIDAR) {
+      if constexpr (KIND != UT_LIDAR) {
         const double T = UT_CAMERA_TILE;
         double fx0 = floor((m0 - eu) / T), fx1 = floor((m0 + eu) / T);
         double fy0 = floor((m1 - ev) / T), fy1 = floor((m1 + ev) / T);
@@ -223,9 +233,12 @@ __global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, doub
       }
     }
 
-    // features: SH at the unit direction from the sensor origin to the mean
-    double f[3] = {0, 0, 0};
-    if (ok) {
+    // Features and the record only for particles that reach a tile: nothing downstream reads
+    // the record of a particle with count 0, and skipping it saves most of the SH loads and
+    // record stores (most particles of a scene lie outside any one camera's view).
+    if (cnt > 0) {
+      // features: SH at the unit direction from the sensor origin to the mean
+      double f[3] = {0, 0, 0};
       const double vx = (double)mx - s.o[0], vy = (double)my - s.o[1], vz = (double)mz - s.o[2];
       const double len = sqrt(vx * vx + vy * vy + vz * vz);
       double dx = 0, dy = 0, dz = 1;
@@ -239,13 +252,12 @@ __global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, doub
         for (int k = 0; k < K; ++k) acc += (double)g.feat[(size_t)(k * 3 + c) * n + i] * Y[k];
         f[c] = (g.feat_kind == UT_FEAT_CAMERA) ? (acc + 0.5 > 0 ? acc + 0.5 : 0.0) : acc;
       }
-    }
-    r.feat[0] = (float)f[0]; r.feat[1] = (float)f[1]; r.feat[2] = (float)f[2];
-
-    const uint4* src = reinterpret_cast<const uint4*>(&r);
-    uint4* dst = reinterpret_cast<uint4*>(rec + i);
+      r.feat[0] = (float)f[0]; r.feat[1] = (float)f[1]; r.feat[2] = (float)f[2];
+      const uint4* src = reinterpret_cast<const uint4*>(&r);
+      uint4* dst = reinterpret_cast<uint4*>(rec + i);
 #pragma unroll
-    for (int c = 0; c < kRecordChunks; ++c) dst[c] = src[c];
+      for (int c = 0; c < kRecordChunks; ++c) dst[c] = src[c];
+    }
     rect[i] = x0; rect[n + i] = y0; rect[2 * n + i] = x1; rect[3 * n + i] = y1;
     trect[i] = make_uint2(((uint32_t)x0 & 0xFFFFu) | ((uint32_t)y0 << 16), ((uint32_t)x1 & 0xFFFFu) | ((uint32_t)y1 << 16));
     count[i] = cnt;
@@ -279,6 +291,26 @@ __global__ __launch_bounds__(256) void k_project(ut_gaussians g, SensorK s, doub
   }
 }
 
+// Occupancy is set per sensor model from measurement: the LiDAR kernel fits 168 VGPRs without
+// spilling and runs best at three waves per SIMD; the camera kernels run best at two waves,
+// where the compiler keeps all (DEG+1)^2 x 3 coefficient loads in flight (left to itself it
+// trades them for a third wave, and the pinhole then takes over twice as long).
+template <int DEG, int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_project_capped(
+    ut_gaussians g, SensorK s, double ut_a, double ut_b, double ut_k, Record* __restrict__ rec,
+    int32_t* __restrict__ rect, uint2* __restrict__ trect, uint32_t* __restrict__ key,
+    uint32_t* __restrict__ count, float* __restrict__ moments, uint32_t* __restrict__ n_culled) {
+  project_all<DEG, KIND>(g, s, ut_a, ut_b, ut_k, rec, rect, trect, key, count, moments, n_culled);
+}
+
+template <int DEG, int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_project(
+    ut_gaussians g, SensorK s, double ut_a, double ut_b, double ut_k, Record* __restrict__ rec,
+    int32_t* __restrict__ rect, uint2* __restrict__ trect, uint32_t* __restrict__ key,
+    uint32_t* __restrict__ count, float* __restrict__ moments, uint32_t* __restrict__ n_culled) {
+  project_all<DEG, KIND>(g, s, ut_a, ut_b, ut_k, rec, rect, trect, key, count, moments, n_culled);
+}
+
 }  // namespace
 
 hipError_t launch_project(const ut_gaussians& g, const SensorK& s, const double abk[3],
@@ -289,15 +321,23 @@ hipError_t launch_project(const ut_gaussians& g, const SensorK& s, const double 
   const int blocks = std::min((g.n + 255) / 256, 2048);
   Record* rec = reinterpret_cast<Record*>(out.records);
   uint2* tr = reinterpret_cast<uint2*>(out.trect);
-#define UT_LAUNCH_PROJECT(D)                                                                          \
-  hipLaunchKernelGGL(k_project<D>, dim3(blocks), dim3(256), 0, st, g, s, abk[0], abk[1], abk[2], rec, \
+#define UT_LAUNCH_PROJECT(KERNEL, D, K)                                                                \
+  hipLaunchKernelGGL((KERNEL<D, K>), dim3(blocks), dim3(256), 0, st, g, s, abk[0], abk[1], abk[2], rec, \
                      out.rect, tr, out.key, out.count, out.moments, out.n_culled)
-  switch (g.sh_degree) {
-    case 0: UT_LAUNCH_PROJECT(0); break;
-    case 1: UT_LAUNCH_PROJECT(1); break;
-    case 2: UT_LAUNCH_PROJECT(2); break;
-    default: UT_LAUNCH_PROJECT(3); break;
+#define UT_LAUNCH_PROJECT_KIND(D)                                          \
+  switch (s.kind) {                                                        \
+    case UT_PINHOLE: UT_LAUNCH_PROJECT(k_project, D, UT_PINHOLE); break;   \
+    case UT_FISHEYE: UT_LAUNCH_PROJECT(k_project, D, UT_FISHEYE); break;   \
+    case UT_LIDAR: UT_LAUNCH_PROJECT(k_project_capped, D, UT_LIDAR); break; \
+    default: UT_LAUNCH_PROJECT(k_project, D, UT_ORTHO); break;             \
   }
+  switch (g.sh_degree) {
+    case 0: UT_LAUNCH_PROJECT_KIND(0); break;
+    case 1: UT_LAUNCH_PROJECT_KIND(1); break;
+    case 2: UT_LAUNCH_PROJECT_KIND(2); break;
+    default: UT_LAUNCH_PROJECT_KIND(3); break;
+  }
+#undef UT_LAUNCH_PROJECT_KIND
 #undef UT_LAUNCH_PROJECT
   return hipGetLastError();
 }
