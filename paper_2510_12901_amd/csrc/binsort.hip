@@ -137,95 +137,236 @@ hipError_t exclusive_scan(T* data, size_t n, T* aux, T* total_out, hipStream_t s
 
 // ---------------------------------------------------------------------------------- radix
 constexpr int kRadix = 256;
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortThreads = 256;   // one thread per digit in the look-back
+constexpr int kSortItems = 16;      // keys per lane
 constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kMaxPasses = 4;
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys, size_t n_max,
-                                                              const uint32_t* __restrict__ n_dev, int shift,
-                                                              uint32_t* __restrict__ hist, int nblocks) {
-  __shared__ uint32_t h[kRadix];
+// Look-back words: bits 30..31 hold the state, bits 0..29 the count.
+constexpr uint32_t kLbAggregate = 1u << 30;   // the tile's own digit count is published
+constexpr uint32_t kLbPrefix = 2u << 30;      // the inclusive prefix over tiles 0..t is published
+constexpr uint32_t kLbCount = (1u << 30) - 1u;
+
+// Digit histograms of every pass in one read of the keys: one workgroup per tile of
+// kSortTile keys, every lane's loads issued up front.  Depth keys concentrate in a few
+// high-byte values, so lanes are first grouped by equal digit (8 ballots) and only one lane
+// per group adds the group's size to the LDS counter; one global atomic per digit present
+// follows.
+__global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __restrict__ keys, size_t n_max,
+                                                              const uint32_t* __restrict__ n_dev, int passes,
+                                                              uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kMaxPasses][kRadix];
   const size_t n = n_dev ? (size_t)*n_dev : n_max;
-  for (int i = threadIdx.x; i < kRadix; i += kSortThreads) h[i] = 0;
+  const size_t tile0 = (size_t)blockIdx.x * kSortTile;
+  if (tile0 >= n) return;
+  const int lane = __lane_id(), wave = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kSortThreads) (&h[0][0])[i] = 0;
   __syncthreads();
-  const size_t base = (size_t)blockIdx.x * kSortTile;
-#pragma unroll 4
+  const size_t base = tile0 + (size_t)wave * (kSortItems * 64) + lane;
+  uint32_t key[kSortItems];
+#pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
-    const size_t idx = base + (size_t)k * kSortThreads + threadIdx.x;
-    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & (kRadix - 1)], 1u);
+    const size_t i = base + (size_t)k * 64;
+    key[k] = i < n ? keys[i] : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    const bool valid = base + (size_t)k * 64 < n;
+    for (int p = 0; p < passes; ++p) {
+      const uint32_t d = (key[k] >> (8 * p)) & (kRadix - 1);
+      unsigned long long peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const unsigned long long m = __ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      if (valid && (peers >> lane) == 1ull) atomicAdd(&h[p][d], (uint32_t)__popcll(peers));
+    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kRadix; i += kSortThreads) hist[(size_t)i * nblocks + blockIdx.x] = h[i];
+  for (int i = threadIdx.x; i < passes * kRadix; i += kSortThreads) {
+    const uint32_t c = (&h[0][0])[i];
+    if (c) atomicAdd(&hist[i], c);
+  }
 }
 
-// Stable scatter.  Items of a block are taken in rounds of 256 in index order; inside a
-// round each wavefront ranks its lanes among equal digits with 8 ballots (peer masks), the
-// highest peer publishes the wave's count, and waves are ordered by index in LDS.
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* __restrict__ kin,
-                                                                 const uint32_t* __restrict__ vin,
-                                                                 uint32_t* __restrict__ kout,
-                                                                 uint32_t* __restrict__ vout, size_t n_max,
-                                                                 const uint32_t* __restrict__ n_dev,
-                                                                 int shift, const uint32_t* __restrict__ hist,
-                                                                 int nblocks) {
-  __shared__ uint32_t base_off[kRadix];
-  const size_t n = n_dev ? (size_t)*n_dev : n_max;
-  __shared__ uint32_t wave_cnt[kSortThreads / 64][kRadix];
-  const int lane = __lane_id(), wave = threadIdx.x >> 6;
-  for (int i = threadIdx.x; i < kRadix; i += kSortThreads) base_off[i] = hist[(size_t)i * nblocks + blockIdx.x];
-  const unsigned long long lt = (1ull << lane) - 1ull;
-  const size_t tile = (size_t)blockIdx.x * kSortTile;
-  for (int k = 0; k < kSortItems; ++k) {
-    for (int i = threadIdx.x; i < (kSortThreads / 64) * kRadix; i += kSortThreads) (&wave_cnt[0][0])[i] = 0;
+// hist[p][d] -> exclusive prefix over digits (one workgroup, thread d)
+__global__ __launch_bounds__(kSortThreads) void k_digit_offsets(uint32_t* __restrict__ hist, int passes) {
+  __shared__ uint32_t sh[4];
+  for (int p = 0; p < passes; ++p) {
+    uint32_t total;
+    const uint32_t v = hist[p * kRadix + threadIdx.x];
+    const uint32_t ex = block_exclusive<uint32_t>(v, sh, total);
+    hist[p * kRadix + threadIdx.x] = ex;
     __syncthreads();
-    const size_t idx = tile + (size_t)k * kSortThreads + threadIdx.x;
-    const bool valid = idx < n;
-    const uint32_t key = valid ? kin[idx] : 0u;
-    const uint32_t digit = (key >> shift) & (kRadix - 1);
+  }
+}
+
+// One stable pass by digit (key >> shift) & 255 with decoupled look-back (single kernel per
+// pass).  A look-back word carries its state and count together, so relaxed device-scope
+// atomics suffice (an acquire would invalidate the XCD's L2 on every poll).  Workgroups take
+// tiles of kSortTile keys in launch order from a ticket counter, so every tile a workgroup
+// waits on belongs to a workgroup that is already running and publishes its own digit counts
+// before it waits on anything: the waits always end.  Inside a tile, wave w owns keys
+// [w*1024, (w+1)*1024) in the order (item, lane); a lane's rank among equal digits of its
+// wave comes from 8 ballots (peer mask) plus the wave's running digit count in LDS.  The
+// tile is then reordered by digit in LDS so that the global writes form one contiguous run
+// per digit.
+__global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __restrict__ kin,
+                                                           const uint32_t* __restrict__ vin,
+                                                           uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                           size_t n_max, const uint32_t* __restrict__ n_dev, int shift,
+                                                           const uint32_t* __restrict__ digit_base,
+                                                           uint32_t* __restrict__ look, uint32_t* __restrict__ ticket) {
+  constexpr int kWaves = kSortThreads / 64;
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t wcnt[kWaves][kRadix];
+  __shared__ uint32_t local_start[kRadix];   // tile-local exclusive prefix over digits
+  __shared__ uint32_t dst_shift[kRadix];     // global start of digit d minus its local start
+  __shared__ uint32_t sk[kSortTile], sv[kSortTile];
+  __shared__ uint32_t scan_sh[4];
+  if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+  for (int i = threadIdx.x; i < kWaves * kRadix; i += kSortThreads) (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  const size_t n = n_dev ? (size_t)*n_dev : n_max;
+  const size_t n_tiles = (n + kSortTile - 1) / kSortTile;
+  if (tile >= n_tiles) return;
+  const int lane = __lane_id(), wave = threadIdx.x >> 6;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const size_t tile0 = (size_t)tile * kSortTile;
+  const size_t base = tile0 + (size_t)wave * (kSortItems * 64) + lane;
+  const uint32_t tile_n = (uint32_t)std::min<size_t>(kSortTile, n - tile0);
+
+  uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    const size_t i = base + (size_t)k * 64;
+    key[k] = i < n ? kin[i] : 0u;
+    val[k] = i < n ? vin[i] : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    const bool valid = base + (size_t)k * 64 < n;
+    const uint32_t d = (key[k] >> shift) & (kRadix - 1);
     unsigned long long peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const bool bit = (digit >> b) & 1u;
+      const bool bit = (d >> b) & 1u;
       const unsigned long long m = __ballot(bit);
       peers &= bit ? m : ~m;
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    const bool leader = valid && (peers >> lane) == 1ull;
-    if (leader) wave_cnt[wave][digit] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t off = base_off[digit] + rank;
-      for (int w = 0; w < wave; ++w) off += wave_cnt[w][digit];
-      kout[off] = key;
-      vout[off] = vin[idx];
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kRadix; i += kSortThreads) {
-      uint32_t add = 0;
+    uint32_t r = 0;
+    if (valid) r = wcnt[wave][d] + (uint32_t)__popcll(peers & lt);
+    rank[k] = r;
+    // the highest lane of each peer group advances the wave's count for that digit (the
+    // reads above complete first: one wavefront's LDS operations stay in program order)
+    if (valid && (peers >> lane) == 1ull) wcnt[wave][d] += (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+
+  // thread d: the tile's count of digit d, each wave's offset, the tile-local digit start and
+  // the look-back for the digit's global start
+  {
+    const int d = threadIdx.x;
+    uint32_t total = 0;
 #pragma unroll
-      for (int w = 0; w < kSortThreads / 64; ++w) add += wave_cnt[w][i];
-      base_off[i] += add;
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t c = wcnt[w][d];
+      wcnt[w][d] = total;
+      total += c;
     }
-    __syncthreads();
+    uint32_t* my = look + (size_t)tile * kRadix + d;
+    __hip_atomic_store(my, (tile == 0 ? kLbPrefix : kLbAggregate) | total, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t tile_total;
+    const uint32_t lstart = block_exclusive<uint32_t>(total, scan_sh, tile_total);
+    local_start[d] = lstart;
+    uint32_t excl = 0;
+    if (tile > 0) {
+      // walk back over the predecessors kLookWindow at a time (independent loads in flight),
+      // adding aggregates until a published inclusive prefix; tile 0 always publishes one
+      constexpr int kLookWindow = 8;
+      int64_t j = (int64_t)tile - 1;
+      for (;;) {
+        uint32_t v[kLookWindow];
+#pragma unroll
+        for (int q = 0; q < kLookWindow; ++q)
+          v[q] = j - q >= 0 ? __hip_atomic_load(look + (size_t)(j - q) * kRadix + d, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT)
+                            : kLbPrefix;
+        int used = 0;
+        bool found = false;
+#pragma unroll
+        for (int q = 0; q < kLookWindow; ++q) {
+          if (found || used < q) continue;   // stop at the first prefix or the first gap
+          const uint32_t st = v[q] & ~kLbCount;
+          if (st == 0u) continue;
+          excl += v[q] & kLbCount;
+          used = q + 1;
+          found = st == kLbPrefix;
+        }
+        if (found) break;
+        j -= used;
+        if (used == 0) __builtin_amdgcn_s_sleep(1);
+      }
+      __hip_atomic_store(my, kLbPrefix | (excl + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    dst_shift[d] = digit_base[d] + excl - lstart;
+  }
+  __syncthreads();
+  // reorder the tile by digit in LDS ...
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    if (base + (size_t)k * 64 < n) {
+      const uint32_t d = (key[k] >> shift) & (kRadix - 1);
+      const uint32_t lp = local_start[d] + wcnt[wave][d] + rank[k];
+      sk[lp] = key[k];
+      sv[lp] = val[k];
+    }
+  }
+  __syncthreads();
+  // ... and write it out: consecutive local positions of one digit go to consecutive addresses
+  for (uint32_t lp = threadIdx.x; lp < tile_n; lp += kSortThreads) {
+    const uint32_t k = sk[lp];
+    const uint32_t dst = dst_shift[(k >> shift) & (kRadix - 1)] + lp;
+    kout[dst] = k;
+    vout[dst] = sv[lp];
   }
 }
 
-// Sorts (k, v) pairs by the low `bits` bits of k, stable.  n_max sizes the grid; when n_dev
-// is given the kernels read the actual length from it.  Buffers ping-pong; *k_res / *v_res
-// receive the buffers holding the result.
+// Bytes of the sort's own workspace for up to n_max keys: per-pass digit offsets, per-pass
+// look-back words and tickets.
+size_t radix_ws_bytes(size_t n_max) {
+  const size_t tiles = (std::max<size_t>(n_max, 1) + kSortTile - 1) / kSortTile;
+  return 4 * ((size_t)kMaxPasses * kRadix + (size_t)kMaxPasses * tiles * kRadix + kMaxPasses);
+}
+
+}  // namespace
+
+// Sorts (k, v) pairs by the low `bits` bits of k (bits <= 32), stable.  n_max sizes the grid;
+// when n_dev is given the kernels read the actual length from it.  Buffers ping-pong;
+// *k_res / *v_res receive the buffers holding the result.  `ws` holds radix_ws_bytes(n_max).
 hipError_t radix_sort(uint32_t* kA, uint32_t* kB, uint32_t* vA, uint32_t* vB, size_t n_max,
-                      const uint32_t* n_dev, int bits, uint32_t* hist, uint64_t* aux, hipStream_t st,
+                      const uint32_t* n_dev, int bits, uint32_t* ws, hipStream_t st,
                       uint32_t** k_res, uint32_t** v_res) {
   *k_res = kA;
   *v_res = vA;
-  if (n_max == 0) return hipSuccess;
-  const int nb = (int)((n_max + kSortTile - 1) / kSortTile);
-  for (int shift = 0; shift < bits; shift += 8) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, st, kA, n_max, n_dev, shift, hist, nb);
-    hipError_t e = exclusive_scan<uint32_t>(hist, (size_t)kRadix * nb, reinterpret_cast<uint32_t*>(aux), nullptr, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortThreads), 0, st, kA, vA, kB, vB, n_max, n_dev, shift,
-                       hist, nb);
+  if (n_max == 0 || bits <= 0) return hipSuccess;
+  if (n_max > kLbCount || bits > 8 * kMaxPasses) return hipErrorInvalidValue;   // look-back counts are 30-bit
+  const int passes = (bits + 7) / 8;
+  const size_t tiles = (n_max + kSortTile - 1) / kSortTile;
+  uint32_t* hist = ws;
+  uint32_t* look = ws + (size_t)kMaxPasses * kRadix;
+  uint32_t* tickets = look + (size_t)kMaxPasses * tiles * kRadix;
+  hipError_t e = fill_u32(ws, 0u, radix_ws_bytes(n_max) / 4, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)tiles), dim3(kSortThreads), 0, st, kA, n_max, n_dev, passes, hist);
+  hipLaunchKernelGGL(k_digit_offsets, dim3(1), dim3(kSortThreads), 0, st, hist, passes);
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL(k_onesweep, dim3((unsigned)tiles), dim3(kSortThreads), 0, st, kA, vA, kB, vB, n_max, n_dev,
+                       8 * p, hist + p * kRadix, look + (size_t)p * tiles * kRadix, tickets + p);
     std::swap(kA, kB);
     std::swap(vA, vB);
   }
@@ -233,6 +374,8 @@ hipError_t radix_sort(uint32_t* kA, uint32_t* kB, uint32_t* vA, uint32_t* vB, si
   *v_res = vA;
   return hipGetLastError();
 }
+
+namespace {
 
 int radix_passes(int bits) { return (bits + 7) / 8; }
 
@@ -454,10 +597,8 @@ CountWorkspace count_workspace(void* base, int n) {
   w.total = reinterpret_cast<uint64_t*>(take(8));
   w.scount = reinterpret_cast<uint32_t*>(take(4 * nn));
   w.m_dev = reinterpret_cast<uint32_t*>(take(4));
-  const size_t nb = (nn + kSortTile - 1) / kSortTile;
-  w.hist = reinterpret_cast<uint32_t*>(take(4 * (size_t)kRadix * nb));
-  const size_t scan_len = std::max((size_t)kRadix * nb, nn + 1);
-  w.scan_aux = reinterpret_cast<uint64_t*>(take(8 * ((scan_len + kScanTile - 1) / kScanTile + 1)));
+  w.hist = reinterpret_cast<uint32_t*>(take(radix_ws_bytes(nn)));
+  w.scan_aux = reinterpret_cast<uint64_t*>(take(8 * ((nn + 1 + kScanTile - 1) / kScanTile + 1)));
   w.bytes = o;
   return w;
 }
@@ -471,9 +612,7 @@ PairWorkspace pair_workspace(void* base, uint64_t n_pairs) {
   w.tkA = reinterpret_cast<uint32_t*>(take(4 * mp));
   w.tkB = reinterpret_cast<uint32_t*>(take(4 * mp));
   w.tv = reinterpret_cast<uint32_t*>(take(4 * mp));
-  const size_t nb = (mp + kSortTile - 1) / kSortTile;
-  w.hist = reinterpret_cast<uint32_t*>(take(4 * (size_t)kRadix * nb));
-  w.scan_aux = reinterpret_cast<uint64_t*>(take(8 * (((size_t)kRadix * nb + kScanTile - 1) / kScanTile + 1)));
+  w.hist = reinterpret_cast<uint32_t*>(take(radix_ws_bytes(mp)));
   w.bytes = o;
   return w;
 }
@@ -491,7 +630,7 @@ hipError_t launch_bin_count(const ut_projected& p, int n, const SensorK& s, Coun
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, st, p.key, ws.scount, ws.dkB, ws.dkA, ws.dvA, n);
   uint32_t *kr, *vr;
-  e = radix_sort(ws.dkA, ws.dkB, ws.dvA, ws.dvB, (size_t)n, ws.m_dev, 32, ws.hist, ws.scan_aux, st, &kr, &vr);
+  e = radix_sort(ws.dkA, ws.dkB, ws.dvA, ws.dvB, (size_t)n, ws.m_dev, 32, ws.hist, st, &kr, &vr);
   if (e != hipSuccess) return e;
   // 4 passes: the result is back in the A buffers
   hipLaunchKernelGGL(k_gather_counts, dim3(blocks), dim3(256), 0, st, ws.dvA, ws.scount, ws.m_dev, ws.offs, n);
@@ -512,8 +651,7 @@ hipError_t launch_bin_sort(const ut_projected& p, int n, const SensorK& s, Count
                      reinterpret_cast<const uint2*>(p.trect), n, s.tiles_x, s.super_x, s.kind == UT_LIDAR ? 1 : 0,
                      pw.tkA, v_first);
   uint32_t *kr, *vr;
-  e = radix_sort(pw.tkA, pw.tkB, v_first, v_second, (size_t)n_pairs, nullptr, bits, pw.hist, pw.scan_aux, st,
-                 &kr, &vr);
+  e = radix_sort(pw.tkA, pw.tkB, v_first, v_second, (size_t)n_pairs, nullptr, bits, pw.hist, st, &kr, &vr);
   if (e != hipSuccess) return e;
   const unsigned rb = (unsigned)((n_pairs + 255) / 256);
   hipLaunchKernelGGL(k_ranges, dim3(rb), dim3(256), 0, st, kr, n_pairs, bins.ranges, n_super);

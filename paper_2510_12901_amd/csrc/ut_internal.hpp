@@ -22,14 +22,13 @@ struct CountWorkspace {
   uint64_t* total;                   // pair total
   uint32_t* scount;                  // [n] super-tile count per particle (index order)
   uint32_t* m_dev;                   // number of visible particles
-  uint32_t* hist;                    // radix histograms of the depth sort
+  uint32_t* hist;                    // the depth sort's digit offsets, look-back words, tickets
   uint64_t* scan_aux;                // block sums of the device scans
   size_t bytes;
 };
 struct PairWorkspace {
   uint32_t *tkA, *tkB, *tv;          // pair tile keys ping-pong, pair value scratch [P]
-  uint32_t* hist;
-  uint64_t* scan_aux;
+  uint32_t* hist;                    // the pair sort's digit offsets, look-back words, tickets
   size_t bytes;
 };
 CountWorkspace count_workspace(void* base, int n);
