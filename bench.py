@@ -57,7 +57,84 @@ def parse():
     ap.add_argument("--vehicles", type=str, default="1,4,8")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (reference kernel for HBM counters)")
+    ap.add_argument("--summarize-profiles", nargs=3, metavar=("STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/ summaries from rocprofv3 CSV output (kernel stats, FETCH_SIZE "
+                         "and WRITE_SIZE counter collections) instead of benchmarking")
     return ap.parse_args()
+
+
+CAMERA_KERNEL = "k_composite<256, 1, 128>"
+PROFILE_CMDS = {
+    "stats": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_stats -o kt -- "
+             "python -u bench.py --no-served --no-backward --no-cpu-baseline --steps 5 --warmup 1 --streams 1",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- "
+             "python -u bench.py --no-served --no-backward --no-cpu-baseline --steps 2 --warmup 1 --streams 1 --calib-copy",
+    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o w -- "
+             "python -u bench.py --no-served --no-backward --no-cpu-baseline --steps 2 --warmup 1 --streams 1 --calib-copy",
+}
+
+
+def _short_kernel(name: str) -> str:
+    import re
+    m = re.search(r"(k_\w+(<[^>]*>)?|__amd_\w+|\w+_kernel\w*)", name)
+    return m.group(1) if m else name[:40]
+
+
+def summarize_profiles(stats_csv: str, fetch_csv: str, write_csv: str):
+    """Turn rocprofv3 CSV output into profiles/*.md and profiles/composite_traffic.json.
+
+    HBM traffic of the camera compositing kernel: FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) averaged over its dispatches, each scaled by the factor that makes the same
+    counter read exactly 1 GiB for the 1 GiB device copy of --calib-copy."""
+    import csv
+
+    stats = list(csv.DictReader(open(stats_csv)))
+    lines = ["# Kernel time, multisensor frame (2M particles, 7 sensors, one stream)", "",
+             "Command (from the repository root, on the GPU):", "", "    cd /tmp && export TMPDIR=/tmp  # then, in the repo:",
+             "    " + PROFILE_CMDS["stats"], "",
+             "The run covers 1 warm-up + 5 timed frames, the 5 back-to-back compositing launches per camera "
+             "that bench.py times for the roofline, and one state pass.", "",
+             "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
+    for r in stats[:20]:
+        lines.append(f"| `{_short_kernel(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    cam = [r for r in stats if CAMERA_KERNEL in r["Name"]]
+    cam_avg_us = float(cam[0]["AverageNs"]) / 1e3 if cam else None
+    lines += ["", f"`{CAMERA_KERNEL}` (camera compositing) average: {cam_avg_us:.1f} us over "
+              f"{cam[0]['Calls'] if cam else 0} calls."]
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    open(os.path.join(ROOT, "profiles", "kernels_multisensor_frame.md"), "w").write("\n".join(lines) + "\n")
+
+    def counter(path, cname):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == cname]
+        comp = [float(r["Counter_Value"]) for r in rows if CAMERA_KERNEL in r["Kernel_Name"]]
+        copies = [(int(r["Grid_Size"]), float(r["Counter_Value"])) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        ref_kib = max(copies)[1]              # the largest copy is the 1 GiB reference
+        factor = (1 << 20) / ref_kib          # KiB that 1 GiB should read as / KiB measured
+        return float(np.mean(comp)), len(comp), ref_kib, factor
+
+    f_kib, nf, f_ref, f_fac = counter(fetch_csv, "FETCH_SIZE")
+    w_kib, nw, w_ref, w_fac = counter(write_csv, "WRITE_SIZE")
+    fetch_b = f_kib * 1024 * f_fac
+    write_b = w_kib * 1024 * w_fac
+    traffic = {"kernel": CAMERA_KERNEL, "workload": "multisensor", "kernel_source_hash": kernel_source_hash(),
+               "bytes_per_launch": round(fetch_b + write_b), "fetch_bytes": round(fetch_b), "write_bytes": round(write_b),
+               "fetch_kib_raw": round(f_kib, 1), "write_kib_raw": round(w_kib, 1), "dispatches": [nf, nw],
+               "calibration": {"copy_bytes": 1 << 30, "fetch_kib_read": f_ref, "write_kib_read": w_ref,
+                               "fetch_factor": round(f_fac, 4), "write_factor": round(w_fac, 4)}}
+    json.dump(traffic, open(PROFILE_TRAFFIC, "w"), indent=1)
+    md = ["# HBM traffic of the camera compositing kernel (multisensor frame)", "",
+          "Commands (two separate counter passes; from the repository root on the GPU, TMPDIR=/tmp):", "",
+          "    " + PROFILE_CMDS["fetch"], "    " + PROFILE_CMDS["write"], "",
+          f"Averaged over {nf} / {nw} dispatches of `{CAMERA_KERNEL}` (the 6 cameras equally).", "",
+          "| counter | raw KiB per dispatch | 1 GiB copy reads as (KiB) | factor | bytes per launch |",
+          "|---|---|---|---|---|",
+          f"| FETCH_SIZE | {f_kib:.1f} | {f_ref:.1f} | {f_fac:.4f} | {fetch_b / 1e6:.1f} MB |",
+          f"| WRITE_SIZE | {w_kib:.1f} | {w_ref:.1f} | {w_fac:.4f} | {write_b / 1e6:.1f} MB |", "",
+          f"Traffic per launch: {(fetch_b + write_b) / 1e6:.1f} MB (kernel source hash {traffic['kernel_source_hash']}; "
+          "bench.py reports it only while the hash matches)."]
+    open(os.path.join(ROOT, "profiles", "composite_traffic_multisensor.md"), "w").write("\n".join(md) + "\n")
+    print(json.dumps(traffic))
 
 
 def log(*a):
@@ -66,6 +143,9 @@ def log(*a):
 
 def main():
     args = parse()
+    if args.summarize_profiles:
+        summarize_profiles(*args.summarize_profiles)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
