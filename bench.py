@@ -27,11 +27,15 @@ if ROOT not in sys.path:
 
 PEAK_FP64_TFLOPS = 78.6        # MI355X dense float64 vector (FMA = 2 FLOPs)
 PEAK_HBM_GBS = 8000.0
-# float64 FLOPs (FMA = 2) that deciding one visited (ray, list entry) takes: w = M d (15),
-# c = a x w (9), c.c (5), w.w (5) and the comparison c.c > cut * w.w (1).  Entries that pass
-# the test cost ~60 FLOPs more (1/w.w, t*, D^2, exp, alpha, accumulation); they are not
-# counted, so the reported rate is a lower bound.
+# float64 FLOPs (FMA = 2) of the compositing's work, counted from the arithmetic of the
+# method: every (ray, list entry) pair a ray evaluates needs the whitened geometry w = M d (15),
+# c = a x w (9), c.c (5), w.w (5) and the pre-test c.c > cut * w.w (1); a pair that passes the
+# pre-test adds 1/w.w with two Newton steps (9), a.w (5), t* (1), D^2 (1), the exponent (1),
+# exp (17), alpha = min(sigma rho, alpha_max) (2), w = alpha T (1), 4 accumulations (8) and
+# T (1 - alpha) (2).  The kernel counts both kinds of pair per ray (n_visit, n_pass) in an
+# untimed pass; entries dropped by the tile-cone test are never evaluated and not counted.
 FLOPS_PER_VISIT = 35
+FLOPS_PER_PASS = 47
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "composite_traffic.json")
 
 
@@ -222,9 +226,9 @@ def main():
     # visited list entries of the same launches (per-ray n_proc of an identical launch).
     REPS = 5
     cams = [p for p in pipes if not p.sensor.is_lidar]
-    cam_ms, visits = [], 0
+    cam_ms, visits, passes, positions = [], 0, 0, 0
     for p in cams:
-        o = ut.alloc_out(p.sensor, dev, state=True)
+        o = ut.alloc_out(p.sensor, dev, state=True, counters=True)
         p.composite_only(stream, o)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -233,10 +237,12 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         cam_ms.append(e0.elapsed_time(e1) / REPS)
-        visits += int(o.n_proc.to(torch.int64).sum().item())
+        visits += int(o.n_visit.to(torch.int64).sum().item())
+        passes += int(o.n_pass.to(torch.int64).sum().item())
+        positions += int(o.n_proc.to(torch.int64).sum().item())
         del o
     per_launch_ms = float(np.mean(cam_ms))
-    flops_per_launch = visits * FLOPS_PER_VISIT / len(cams)
+    flops_per_launch = (visits * FLOPS_PER_VISIT + passes * FLOPS_PER_PASS) / len(cams)
     achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
     bin_pairs = [p.n_pairs for p in pipes]
     tile_pairs = [int(p.p.count[: p.g.n].to(torch.int64).sum().item()) for p in pipes]
@@ -267,7 +273,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
                      "kernel": "k_composite<256, 1, 128> (camera compositing)",
-                     "flops_per_visit": FLOPS_PER_VISIT, "visits_per_launch": int(visits / len(cams)),
+                     "flops_per_visit": FLOPS_PER_VISIT, "flops_per_pass": FLOPS_PER_PASS,
+                     "visits_per_launch": int(visits / len(cams)), "passes_per_launch": int(passes / len(cams)),
+                     "list_positions_per_launch": int(positions / len(cams)),
                      "avg_launch_ms": round(per_launch_ms, 4)},
         "composite_ms_per_camera": [round(float(x), 4) for x in cam_ms],
     }

@@ -159,7 +159,11 @@ typedef struct {
  * intensity); depth[R] = sum w t* (unnormalised); alpha[R] = omega = 1 - T_final;
  * drop[R] = ray-drop probability softmax(zeta_1, zeta_2)[drop] (LiDAR only, may be NULL);
  * t_final[R], n_proc[R] (list entries visited) are the state the adjoint replays
- * (may be NULL when no backward follows). */
+ * (may be NULL when no backward follows).
+ * n_visit[R], n_pass[R] (optional, may be NULL; written by ut_composite_camera/_lidar, not by
+ * ut_composite_batch): work counters -- list entries the ray actually evaluated (entries that
+ * no ray of the tile can reach are dropped before the rays see them) and, of those, entries
+ * that passed the alpha_min pre-test. */
 typedef struct {
   float* feat;
   float* depth;
@@ -167,6 +171,8 @@ typedef struct {
   float* drop;
   double* t_final;
   uint32_t* n_proc;
+  uint32_t* n_visit;
+  uint32_t* n_pass;
 } ut_render_out;
 
 /* Upstream gradients dL/d(output), device float32 arrays shaped like ut_render_out;

@@ -49,7 +49,8 @@ class UtTileLists(C.Structure):
 
 
 class UtRenderOut(C.Structure):
-    _fields_ = [("feat", P), ("depth", P), ("alpha", P), ("drop", P), ("t_final", P), ("n_proc", P)]
+    _fields_ = [("feat", P), ("depth", P), ("alpha", P), ("drop", P), ("t_final", P), ("n_proc", P),
+                ("n_visit", P), ("n_pass", P)]
 
 
 class UtUpstream(C.Structure):

@@ -118,7 +118,7 @@ __device__ __forceinline__ double block_reduce(double v, bool is_min, double (&r
   return r;
 }
 
-template <int BLOCK, int RPL, int BATCH>
+template <int BLOCK, int RPL, int BATCH, bool STATS = false>
 __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* __restrict__ rec,
                                                const uint2* __restrict__ trect,
                                                const uint32_t* __restrict__ bgauss,
@@ -132,7 +132,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
   const uint32_t start = branges[sid], end = branges[n_super + sid];
   long long ray[RPL];
   double dx[RPL], dy[RPL], dz[RPL], T[RPL], f0[RPL], f1[RPL], f2[RPL], dep[RPL];
-  uint32_t nproc[RPL];
+  uint32_t nproc[RPL], nvisit[RPL], npass[RPL];
   bool rdone[RPL];
   bool done = true;
   double sx = 0, sy = 0, sz = 0;
@@ -149,7 +149,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
     done = done && rdone[k];
     T[k] = 1.0;
     f0[k] = f1[k] = f2[k] = dep[k] = 0;
-    nproc[k] = 0;
+    nproc[k] = nvisit[k] = npass[k] = 0;
     if (!rdone[k]) {
       const double il = rcp_f64(__builtin_sqrt(__builtin_fma(dx[k], dx[k], __builtin_fma(dy[k], dy[k], dz[k] * dz[k]))));
       sx = __builtin_fma(dx[k], il, sx);
@@ -255,7 +255,9 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
         for (int k = 0; k < RPL; ++k) {
           if (rdone[k]) continue;
           const PairGeom q = pair_geometry(r, dx[k], dy[k], dz[k]);
+          if constexpr (STATS) ++nvisit[k];
           if (pair_cut(q, r.aux)) continue;
+          if constexpr (STATS) ++npass[k];
           const PairResp pr = pair_response(r, q);
           const double tau = pr.tau;
           if (tau < s.near_) continue;
@@ -300,6 +302,10 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
     out.alpha[id] = (float)(1.0 - T[k]);
     if (out.t_final) out.t_final[id] = T[k];
     if (out.n_proc) out.n_proc[id] = nproc[k];
+    if constexpr (STATS) {
+      if (out.n_visit) out.n_visit[id] = nvisit[k];
+      if (out.n_pass) out.n_pass[id] = npass[k];
+    }
     if (s.kind == UT_LIDAR && out.drop) out.drop[id] = (float)(1.0 / (1.0 + exp(-(f2[k] - f1[k]))));
   }
 }
@@ -312,7 +318,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n_tiles) {
   return t < n_tiles ? t : -1;
 }
 
-template <int BLOCK, int RPL, int BATCH>
+template <int BLOCK, int RPL, int BATCH, bool STATS>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void k_composite(SensorK s, const Record* __restrict__ rec,
                                                       const uint2* __restrict__ trect,
                                                       const uint32_t* __restrict__ bgauss,
@@ -321,7 +327,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
   __shared__ CompositeShared<BLOCK, RPL, BATCH> sm;
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   if (tile < 0) return;
-  composite_tile<BLOCK, RPL, BATCH>(s, rec, trect, bgauss, branges, tile, s.super_x * s.super_y, prm, out, sm);
+  composite_tile<BLOCK, RPL, BATCH, STATS>(s, rec, trect, bgauss, branges, tile, s.super_x * s.super_y, prm, out, sm);
 }
 
 // Persistent batched compositing: workgroups pull (request, tile) items from a counter.
@@ -354,12 +360,23 @@ hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, con
   const int grid = 8 * ((n_tiles + 7) / 8);
   const Record* rec = reinterpret_cast<const Record*>(p.records);
   const uint2* tr = reinterpret_cast<const uint2*>(p.trect);
+  const bool stats = out.n_visit != nullptr || out.n_pass != nullptr;
+#define UT_LAUNCH_COMPOSITE(B, R, N)                                                                        \
+  do {                                                                                                    \
+    if (stats)                                                                                            \
+      hipLaunchKernelGGL((k_composite<B, R, N, true>), dim3(grid), dim3(B), 0, st, s, rec, tr, bins.gauss,  \
+                         bins.ranges, n_tiles, prm, out);                                                 \
+    else                                                                                                  \
+      hipLaunchKernelGGL((k_composite<B, R, N, false>), dim3(grid), dim3(B), 0, st, s, rec, tr, bins.gauss, \
+                         bins.ranges, n_tiles, prm, out);                                                 \
+  } while (0)
   if (s.kind != UT_LIDAR || max_tile_rays > 128)
-    hipLaunchKernelGGL((k_composite<kCamBlock, kCamRpl, kCamBatch>), dim3(grid), dim3(kCamBlock), 0, st, s, rec, tr, bins.gauss, bins.ranges, n_tiles, prm, out);
+    UT_LAUNCH_COMPOSITE(kCamBlock, kCamRpl, kCamBatch);
   else if (max_tile_rays > 64)
-    hipLaunchKernelGGL((k_composite<128, 1, 128>), dim3(grid), dim3(128), 0, st, s, rec, tr, bins.gauss, bins.ranges, n_tiles, prm, out);
+    UT_LAUNCH_COMPOSITE(128, 1, 128);
   else
-    hipLaunchKernelGGL((k_composite<64, 1, 64>), dim3(grid), dim3(64), 0, st, s, rec, tr, bins.gauss, bins.ranges, n_tiles, prm, out);
+    UT_LAUNCH_COMPOSITE(64, 1, 64);
+#undef UT_LAUNCH_COMPOSITE
   return hipGetLastError();
 }
 

@@ -276,23 +276,28 @@ class RenderOut:
     drop: torch.Tensor | None
     t_final: torch.Tensor | None
     n_proc: torch.Tensor | None
+    n_visit: torch.Tensor | None = None     # work counters (optional)
+    n_pass: torch.Tensor | None = None
     _c: A.UtRenderOut = field(default=None, repr=False)
 
     def c(self) -> A.UtRenderOut:
         if self._c is None:
             self._c = A.UtRenderOut(self.feat.data_ptr(), self.depth.data_ptr(), self.alpha.data_ptr(),
-                                    _ptr(self.drop), _ptr(self.t_final), _ptr(self.n_proc))
+                                    _ptr(self.drop), _ptr(self.t_final), _ptr(self.n_proc),
+                                    _ptr(self.n_visit), _ptr(self.n_pass))
         return self._c
 
 
-def alloc_out(sensor: Sensor, device="cuda", state=True) -> RenderOut:
+def alloc_out(sensor: Sensor, device="cuda", state=True, counters=False) -> RenderOut:
     R = sensor.n_rays
     return RenderOut(torch.empty((3, R), dtype=torch.float32, device=device),
                      torch.empty(R, dtype=torch.float32, device=device),
                      torch.empty(R, dtype=torch.float32, device=device),
                      torch.empty(R, dtype=torch.float32, device=device) if sensor.is_lidar else None,
                      torch.empty(R, dtype=torch.float64, device=device) if state else None,
-                     torch.empty(R, dtype=torch.int32, device=device) if state else None)
+                     torch.empty(R, dtype=torch.int32, device=device) if state else None,
+                     torch.empty(R, dtype=torch.int32, device=device) if counters else None,
+                     torch.empty(R, dtype=torch.int32, device=device) if counters else None)
 
 
 def composite(p: Projection, bins: BinLists, sensor: Sensor, params=None, out: RenderOut | None = None,

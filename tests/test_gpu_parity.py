@@ -169,3 +169,23 @@ def test_culling_only_removes_particles_without_rays():
     assert on["n_pairs"] < off["n_pairs"]
     d = np.abs(on["alpha"] - off["alpha"])
     assert np.mean(d == 0) > 0.99
+
+
+def test_work_counters_leave_outputs_unchanged():
+    """The counting variant of the compositing (n_visit, n_pass) writes the same outputs bit for
+    bit, and its counters are ordered: entries passing the pre-test <= entries evaluated <= list
+    positions visited (n_proc)."""
+    import torch
+    import paper_2510_12901_amd as ut
+    g_np, s_np = _scene("pinhole_sh3_posed")
+    g = ut.GaussianSet.from_numpy(g_np)
+    s = ut.Sensor(s_np)
+    p, bins, a = ut.render(g, s, state=True)
+    b = ut.alloc_out(s, g.mean.device, state=True, counters=True)
+    ut.composite(p, bins, s, out=b)
+    torch.cuda.synchronize()
+    for k in ("feat", "depth", "alpha", "t_final", "n_proc"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
+    nproc, nvis, npass = (to_np(t).view(np.uint32).astype(np.int64) for t in (b.n_proc, b.n_visit, b.n_pass))
+    assert np.all(npass <= nvis) and np.all(nvis <= nproc)
+    assert nvis.sum() < nproc.sum() and npass.sum() > 0
