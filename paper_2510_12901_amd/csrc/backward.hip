@@ -90,8 +90,7 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
         const PairResp pr = pair_response(r, q);
         const double tau = pr.tau;
         if (!pair_cut(q, cut_threshold(r.log_sigma, prm.log_alpha_min)) && tau >= s.near_) {
-          const double rho = exp_neg(-0.5 * pr.D2, kExp2Frac);
-          const double a = r.sigma * rho;
+          const double a = pair_alpha(r, pr, kExp2Frac);
           const bool clamped = a > prm.alpha_max;
           const double alpha = clamped ? prm.alpha_max : a;
           if (alpha >= prm.alpha_min) {
@@ -109,8 +108,8 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
             const double dtau = gdep * w;
             double dD2 = 0.0;
             if (!clamped) {
-              g[3] = dalpha * rho;
-              dD2 = -0.5 * dalpha * r.sigma * rho;
+              g[3] = dalpha * (a / exp_neg(r.log_sigma, kExp2Frac));   // dL/dsigma = dL/dalpha * rho
+              dD2 = -0.5 * dalpha * a;
             }
             // B = M^T M: B u = M^T r and B d = M^T w with u = mu - o - t* d
             const double* M = r.m;

@@ -238,14 +238,8 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
       const uint32_t j = c / kRecordChunks, part = c - j * kRecordChunks;
       const uint32_t slot = (head + j) & kRing;
       const uint32_t g = sm.cand[slot];
-      uint4 v = reinterpret_cast<const uint4*>(rec + g)[part];
-      if (part == kRecordChunks - 1) {   // bytes 112..127: feat[2], log_sigma, aux
-        const double cut = cut_threshold(__uint_as_float(v.y), prm.log_alpha_min);
-        v.z = (uint32_t)__double2loint(cut);
-        v.w = (uint32_t)__double2hiint(cut);
-        sm.rpos[j] = sm.cpos[slot];
-      }
-      reinterpret_cast<uint4*>(sm.rec + j)[part] = v;
+      reinterpret_cast<uint4*>(sm.rec + j)[part] = reinterpret_cast<const uint4*>(rec + g)[part];
+      if (part == 0) sm.rpos[j] = sm.cpos[slot];
     }
     __syncthreads();
     if (!done) {
@@ -256,18 +250,17 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
           if (rdone[k]) continue;
           const PairGeom q = pair_geometry(r, dx[k], dy[k], dz[k]);
           if constexpr (STATS) ++nvisit[k];
-          if (pair_cut(q, r.aux)) continue;
+          if (pair_cut(q, cut_threshold(r.log_sigma, prm.log_alpha_min))) continue;
           if constexpr (STATS) ++npass[k];
           const PairResp pr = pair_response(r, q);
           const double tau = pr.tau;
           if (tau < s.near_) continue;
-          const double rho = exp_neg(-0.5 * pr.D2, sm.etab);
-          const double alpha = __builtin_fmin(r.sigma * rho, prm.alpha_max);
+          const double alpha = __builtin_fmin(pair_alpha(r, pr, sm.etab), prm.alpha_max);
           if (alpha < prm.alpha_min) continue;
           const double w = alpha * T[k];
-          f0[k] = __builtin_fma(w, (double)r.feat[0], f0[k]);
-          f1[k] = __builtin_fma(w, (double)r.feat[1], f1[k]);
-          f2[k] = __builtin_fma(w, (double)r.feat[2], f2[k]);
+          f0[k] = __builtin_fma(w, r.feat[0], f0[k]);
+          f1[k] = __builtin_fma(w, r.feat[1], f1[k]);
+          f2[k] = __builtin_fma(w, r.feat[2], f2[k]);
           dep[k] = __builtin_fma(w, tau, dep[k]);
           T[k] = T[k] * (1.0 - alpha);
           if (T[k] < prm.t_min) {

@@ -102,7 +102,6 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
               isfinite(l2) && isfinite(lg) && isfinite(qq) && qq > 0;
     Record r;
     double Rm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, sc[3] = {1, 1, 1};
-    double sigma = 0;
     if (ok) {
       const double inv = 1.0 / sqrt(qq);
       const double w = q0 * inv, x = q1 * inv, y = q2 * inv, z = q3 * inv;
@@ -110,7 +109,6 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
       Rm[3] = 2 * (x * y + w * z);     Rm[4] = 1 - 2 * (x * x + z * z); Rm[5] = 2 * (y * z - w * x);
       Rm[6] = 2 * (x * z - w * y);     Rm[7] = 2 * (y * z + w * x);     Rm[8] = 1 - 2 * (x * x + y * y);
       sc[0] = exp((double)l0); sc[1] = exp((double)l1); sc[2] = exp((double)l2);
-      sigma = 1.0 / (1.0 + exp(-(double)lg));
     }
     // M = S^{-1} R^T and a = M (mu - o)
     {
@@ -122,10 +120,8 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
       r.a[0] = __builtin_fma(r.m[0], vx, __builtin_fma(r.m[1], vy, r.m[2] * vz));
       r.a[1] = __builtin_fma(r.m[3], vx, __builtin_fma(r.m[4], vy, r.m[5] * vz));
       r.a[2] = __builtin_fma(r.m[6], vx, __builtin_fma(r.m[7], vy, r.m[8] * vz));
-      r.aux = 0.0;
     }
-    r.sigma = sigma;
-    r.log_sigma = ok ? (float)log(sigma) : -1e30f;
+    r.log_sigma = ok ? -log1p(exp(-(double)lg)) : -1e30;   // ln sigmoid(logit)
 
     // unscented transform over 7 sigma points
     double m0 = 0, m1 = 0, c00 = 0, c01 = 0, c11 = 0;
@@ -252,7 +248,7 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
         for (int k = 0; k < K; ++k) acc += (double)g.feat[(size_t)(k * 3 + c) * n + i] * Y[k];
         f[c] = (g.feat_kind == UT_FEAT_CAMERA) ? (acc + 0.5 > 0 ? acc + 0.5 : 0.0) : acc;
       }
-      r.feat[0] = (float)f[0]; r.feat[1] = (float)f[1]; r.feat[2] = (float)f[2];
+      r.feat[0] = f[0]; r.feat[1] = f[1]; r.feat[2] = f[2];
       const uint4* src = reinterpret_cast<const uint4*>(&r);
       uint4* dst = reinterpret_cast<uint4*>(rec + i);
 #pragma unroll

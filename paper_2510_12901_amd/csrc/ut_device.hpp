@@ -26,12 +26,10 @@ constexpr int kSuper = UT_SUPER_TILE;
 // sensor, a ray d gives w = M d, t* = a.w / w.w, r = a - t* w and D^2 = r.r: the distance
 // of maximum response and the squared Mahalanobis distance there.
 struct alignas(16) Record {
-  double m[9];      // M, row-major: row j = R[:, j]^T / s_j
-  double a[3];      // M (mu - o), o = sensor origin
-  double sigma;     // opacity
-  float feat[3];    // colour or LiDAR features evaluated at the particle's SH direction
-  float log_sigma;  // ln(opacity), for the conservative alpha_min pre-test
-  double aux;       // zero in HBM; the compositing's LDS copy holds the pre-test threshold here
+  double m[9];       // M, row-major: row j = R[:, j]^T / s_j
+  double a[3];       // M (mu - o), o = sensor origin
+  double log_sigma;  // ln(opacity): alpha = exp(ln sigma - D^2 / 2), and the pre-test threshold
+  double feat[3];    // colour or LiDAR features evaluated at the particle's SH direction
 };
 static_assert(sizeof(Record) == UT_RECORD_BYTES, "record size must match the ABI");
 constexpr int kRecordChunks = UT_RECORD_BYTES / 16;
@@ -138,8 +136,8 @@ __device__ __forceinline__ PairGeom pair_geometry(const Record& c, double dx, do
 
 // D^2 threshold of the conservative pre-test: beyond it sigma * rho < alpha_min for certain
 // (ln rho = -D^2 / 2, with 1e-3 of slack for rounding).
-__device__ __forceinline__ double cut_threshold(float log_sigma, double log_alpha_min) {
-  return __builtin_fma(2.0, (double)log_sigma, 1e-3 - 2.0 * log_alpha_min);
+__device__ __forceinline__ double cut_threshold(double log_sigma, double log_alpha_min) {
+  return __builtin_fma(2.0, log_sigma, 1e-3 - 2.0 * log_alpha_min);
 }
 
 // True when the pair cannot reach alpha_min: D^2 > cut, tested as |a x w|^2 > cut w.w.
@@ -158,6 +156,11 @@ __device__ __forceinline__ PairResp pair_response(const Record& c, const PairGeo
   r.tau = aw * r.iww;
   r.D2 = q.cc * r.iww;
   return r;
+}
+
+// Unclamped opacity of the pair, sigma * exp(-D^2 / 2), evaluated as exp(ln sigma - D^2 / 2).
+__device__ __forceinline__ double pair_alpha(const Record& c, const PairResp& r, const double* tab) {
+  return exp_neg(__builtin_fma(-0.5, r.D2, c.log_sigma), tab);
 }
 
 // Packed tile rect of a particle: (x0 | y0 << 16, x1 | y1 << 16); LiDAR x1 may exceed

@@ -9,8 +9,7 @@ import oracle
 AMBIG = 1e-9          # decisions closer than this to their threshold are ambiguous
 TOL = 1e-4            # max-abs bound on feat / depth / alpha / drop
 
-REC_DTYPE = np.dtype([("m", "<f8", 9), ("a", "<f8", 3), ("sigma", "<f8"), ("feat", "<f4", 3),
-                      ("log_sigma", "<f4"), ("pad", "<f8")])
+REC_DTYPE = np.dtype([("m", "<f8", 9), ("a", "<f8", 3), ("log_sigma", "<f8"), ("feat", "<f8", 3)])
 
 
 def to_np(t):

@@ -71,8 +71,8 @@ def test_render_parity(name):
 
 
 def test_records_match_particle_definition():
-    """Record contents: opacity = sigmoid(logit); M^T M = Sigma^{-1} with Sigma from scipy's
-    rotation; a = M (mu - o)."""
+    """Record contents: exp(log opacity) = sigmoid(logit); M^T M = Sigma^{-1} with Sigma from
+    scipy's rotation; a = M (mu - o)."""
     from scipy.spatial.transform import Rotation
     g, s = _scene("pinhole_sh3_posed")
     gp, _ = gpu_render(g, s)
@@ -89,7 +89,8 @@ def test_records_match_particle_definition():
         np.testing.assert_allclose(M.T @ M, B, rtol=1e-9, atol=1e-9 * np.abs(B).max())
         v = g["mean"][:, i].astype(np.float64) - o
         np.testing.assert_allclose(rec["a"][i], M @ v, rtol=1e-12, atol=1e-12 * np.abs(M @ v).max())
-        np.testing.assert_allclose(rec["sigma"][i], 1 / (1 + np.exp(-np.float64(g["opacity_logit"][i]))), rtol=1e-14)
+        np.testing.assert_allclose(np.exp(rec["log_sigma"][i]), 1 / (1 + np.exp(-np.float64(g["opacity_logit"][i]))),
+                                   rtol=1e-14)
 
 
 def test_determinism_and_permutation_invariance():
