@@ -9,6 +9,7 @@
 // reduce them across 64 lanes and lane 0 adds them atomically (float64) into SoA
 // accumulators acc[13][n].
 // k_chain: one lane per particle, chain rule to (mean, quat, log_scale, logit, SH).
+#include "ut_cone.hpp"
 #include "ut_internal.hpp"
 #include "ut_sh.hpp"
 
@@ -30,7 +31,10 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
                                                      int n) {
   __shared__ Record sh[BLOCK];
   __shared__ uint32_t sh_g[BLOCK];
+  __shared__ uint32_t sh_dead[BLOCK];   // 1: no ray of the tile can reach alpha_min on the entry
   __shared__ uint32_t s_max;
+  __shared__ double red[4][BLOCK / 64];
+  __shared__ TileCone cone;
   const int tile = blockIdx.x;
   const uint32_t start = ranges[tile];
   const long long ray = tile_ray(s, tile, threadIdx.x);
@@ -59,12 +63,21 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
   }
   const double Tf = T;
   double S = 0.0;
+  const int lane = __lane_id(), wave = threadIdx.x >> 6;
+  // the forward's tile cone, rebuilt from the same rays: entries it drops are skipped here too
+  const bool has_ray = ray >= 0 && (dx != 0 || dy != 0 || dz != 0);
+  double ux, uy, uz, sn;
+  {
+    const double il = has_ray ? rcp_f64(__builtin_sqrt(__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)))) : 0.0;
+    tile_cone_axis<BLOCK>(dx * il, dy * il, dz * il, red, wave, lane, ux, uy, uz, sn);
+  }
+  tile_cone_finish<BLOCK>(has_ray ? cone_cos(ux, uy, uz, dx, dy, dz) : 1.0, sn, ux, uy, uz, red, wave, lane, cone);
+  const bool cull = cone.on != 0;
   if (threadIdx.x == 0) s_max = 0;
   __syncthreads();
   atomicMax(&s_max, np);
   __syncthreads();
   const int jmax = (int)s_max;
-  const int lane = __lane_id();
 
   for (int hi = jmax; hi > 0; hi -= BLOCK) {
     const int lo = hi > BLOCK ? hi - BLOCK : 0;
@@ -77,8 +90,11 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
       if (part == 0) sh_g[j] = g;
     }
     __syncthreads();
+    if (threadIdx.x < cnt) sh_dead[threadIdx.x] = cull && cone_rejects(sh + threadIdx.x, cone, prm.log_alpha_min);
+    __syncthreads();
     for (int jj = cnt - 1; jj >= 0; --jj) {
       const int j = lo + jj;
+      if (sh_dead[jj]) continue;                      // every ray of the tile skips this entry
       if (__ballot(j < (int)np) == 0ull) continue;   // no lane of this wave visited entry j
       const Record& r = sh[jj];
       bool contrib = false;

@@ -13,6 +13,7 @@
 // D^2 = |a x w|^2 / w.w, rho = exp(-D^2/2) -- all float64 with explicit FMAs (no contraction
 // flags can change the arithmetic between the plain and the batched kernel, or between
 // forward and adjoint).
+#include "ut_cone.hpp"
 #include "ut_internal.hpp"
 
 namespace ut {
@@ -22,15 +23,6 @@ namespace {
 // threads with RPL rays per lane and stage BATCH records per step.
 constexpr int kCamBlock = 256, kCamRpl = 1, kCamBatch = 128;
 static_assert(kCamBlock * kCamRpl >= UT_MAX_LIDAR_TILE_RAYS, "batched tiles must fit one workgroup");
-
-// Bounding cone of a tile's rays: unit axis u, orthonormal e1, e2 spanning u's complement,
-// and cos / sin of twice the half-angle.  `on` is false when the tile has no ray or the cone
-// is too wide for the bound below (half-angle > 45 degrees).
-struct TileCone {
-  double u[3], e1[3], e2[3];
-  double cos2t, sin2t;
-  int on;
-};
 
 // BLOCK threads, RPL rays per lane: one workgroup covers up to BLOCK * RPL rays.  Records are
 // staged BATCH at a time; the ring of candidate indices holds a batch plus one refill step of
@@ -51,72 +43,6 @@ struct CompositeShared {
   double etab[32];         // LDS copy of kExp2Frac for the response's exponential
   TileCone cone;
 };
-
-// Conservative tile-cone test: true when no unit direction d within the cone can bring the
-// particle's response to alpha_min, i.e. h(d) = |a x Md|^2 - cut |Md|^2 > 0 on the whole cone.
-// With d = cos(phi) u + sin(phi) e, e a unit vector in span(e1, e2) and phi <= theta,
-//   h >= cos^2(phi) A - 2 sin(phi) cos(phi) B + sin^2(phi) C,
-// where A = h(u), B bounds the mixed term over all e and C is the smallest eigenvalue of the
-// form on span(e1, e2).  In psi = 2 phi this is P + Rc cos(psi) - B sin(psi), minimised over
-// psi in [0, 2 theta] in closed form.  The threshold carries 0.05 of slack over the per-ray
-// cut so that rounding cannot drop an entry that a ray would keep; the dropped entries are
-// exactly ones every ray of the tile would skip, so outputs are unchanged.
-__device__ __forceinline__ bool cone_rejects(const Record* __restrict__ rp, const TileCone& tc,
-                                             double log_alpha_min) {
-  const double cut = cut_threshold(rp->log_sigma, log_alpha_min) + 0.05;
-  double m[9], a[3];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) m[i] = rp->m[i];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) a[i] = rp->a[i];
-  double w[3][3], x[3][3];   // w_k = M v_k and x_k = a x w_k for v = (u, e1, e2)
-  const double* v[3] = {tc.u, tc.e1, tc.e2};
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      w[k][i] = __builtin_fma(m[3 * i], v[k][0], __builtin_fma(m[3 * i + 1], v[k][1], m[3 * i + 2] * v[k][2]));
-    x[k][0] = __builtin_fma(a[1], w[k][2], -(a[2] * w[k][1]));
-    x[k][1] = __builtin_fma(a[2], w[k][0], -(a[0] * w[k][2]));
-    x[k][2] = __builtin_fma(a[0], w[k][1], -(a[1] * w[k][0]));
-  }
-  auto H = [&](int i, int j) {
-    const double xx = __builtin_fma(x[i][0], x[j][0], __builtin_fma(x[i][1], x[j][1], x[i][2] * x[j][2]));
-    const double ww = __builtin_fma(w[i][0], w[j][0], __builtin_fma(w[i][1], w[j][1], w[i][2] * w[j][2]));
-    return __builtin_fma(-cut, ww, xx);
-  };
-  const double A = H(0, 0), H01 = H(0, 1), H02 = H(0, 2);
-  const double H11 = H(1, 1), H12 = H(1, 2), H22 = H(2, 2);
-  const double B = __builtin_sqrt(__builtin_fma(H01, H01, H02 * H02));
-  const double hd = 0.5 * (H11 - H22);
-  const double C = 0.5 * (H11 + H22) - __builtin_sqrt(__builtin_fma(hd, hd, H12 * H12));
-  const double P = 0.5 * (A + C), Rc = 0.5 * (A - C);
-  const double rad = __builtin_sqrt(__builtin_fma(Rc, Rc, B * B));
-  double fmin;
-  if (-Rc >= rad * tc.cos2t) {
-    fmin = P - rad;   // the minimiser psi* = pi - atan2(B, Rc) lies inside [0, 2 theta]
-  } else {
-    const double f1 = __builtin_fma(Rc, tc.cos2t, P) - B * tc.sin2t;
-    fmin = A < f1 ? A : f1;
-  }
-  return fmin > 0.0;
-}
-
-template <int BLOCK>
-__device__ __forceinline__ double block_reduce(double v, bool is_min, double (&red)[BLOCK / 64], int wave, int lane) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double o = __shfl_xor(v, off);
-    v = is_min ? (o < v ? o : v) : v + o;
-  }
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double r = red[0];
-#pragma unroll
-  for (int w = 1; w < BLOCK / 64; ++w) r = is_min ? (red[w] < r ? red[w] : r) : r + red[w];
-  __syncthreads();
-  return r;
-}
 
 template <int BLOCK, int RPL, int BATCH, bool STATS = false>
 __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* __restrict__ rec,
@@ -162,40 +88,13 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
   if (threadIdx.x < 32) sm.etab[threadIdx.x] = kExp2Frac[threadIdx.x];
 
   // bounding cone of the tile's rays (identical in every lane: built from block reductions)
-  sx = block_reduce<BLOCK>(sx, false, sm.red[0], wave, lane);
-  sy = block_reduce<BLOCK>(sy, false, sm.red[1], wave, lane);
-  sz = block_reduce<BLOCK>(sz, false, sm.red[2], wave, lane);
-  const double sn = __builtin_sqrt(__builtin_fma(sx, sx, __builtin_fma(sy, sy, sz * sz)));
-  const double ux = sx / sn, uy = sy / sn, uz = sz / sn;
+  double ux, uy, uz, sn;
+  tile_cone_axis<BLOCK>(sx, sy, sz, sm.red, wave, lane, ux, uy, uz, sn);
   double cmin = 1.0;
 #pragma unroll
-  for (int k = 0; k < RPL; ++k) {
-    if (rdone[k]) continue;
-    const double l = __builtin_sqrt(__builtin_fma(dx[k], dx[k], __builtin_fma(dy[k], dy[k], dz[k] * dz[k])));
-    const double c = __builtin_fma(ux, dx[k], __builtin_fma(uy, dy[k], uz * dz[k])) / l;
-    cmin = c < cmin ? c : cmin;
-  }
-  cmin = block_reduce<BLOCK>(cmin, true, sm.red[3], wave, lane);
-  if (threadIdx.x == 0) {
-    TileCone& tc = sm.cone;
-    const double ct = cmin - 1e-9;                       // widen for rounding
-    tc.on = (sn > 0.0 && ct > 0.7071067811865476) ? 1 : 0;
-    const double st = __builtin_sqrt(1.0 - ct * ct);
-    tc.cos2t = 2.0 * ct * ct - 1.0;
-    tc.sin2t = 2.0 * st * ct;
-    tc.u[0] = ux, tc.u[1] = uy, tc.u[2] = uz;
-    // e1 = normalise(u x t) with t the coordinate axis least aligned with u; e2 = u x e1
-    double t0 = 0, t1 = 0, t2 = 0;
-    if (__builtin_fabs(ux) <= __builtin_fabs(uy) && __builtin_fabs(ux) <= __builtin_fabs(uz)) t0 = 1;
-    else if (__builtin_fabs(uy) <= __builtin_fabs(uz)) t1 = 1;
-    else t2 = 1;
-    double e0 = uy * t2 - uz * t1, e1 = uz * t0 - ux * t2, e2 = ux * t1 - uy * t0;
-    const double en = __builtin_sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-    e0 /= en, e1 /= en, e2 /= en;
-    tc.e1[0] = e0, tc.e1[1] = e1, tc.e1[2] = e2;
-    tc.e2[0] = uy * e2 - uz * e1, tc.e2[1] = uz * e0 - ux * e2, tc.e2[2] = ux * e1 - uy * e0;
-  }
-  __syncthreads();
+  for (int k = 0; k < RPL; ++k)
+    if (!rdone[k]) cmin = fmin(cmin, cone_cos(ux, uy, uz, dx[k], dy[k], dz[k]));
+  tile_cone_finish<BLOCK>(cmin, sn, ux, uy, uz, sm.red, wave, lane, sm.cone);
   const bool cull = sm.cone.on != 0;
 
   uint32_t pos = start, head = 0, n_cand = 0, n_hits = 0;   // uniform across the workgroup

@@ -1,0 +1,134 @@
+// ut_cone.hpp -- conservative per-tile culling of list entries (device code shared by the
+// compositing and its adjoint).
+//
+// A tile's rays are bounded by a cone (unit axis u, half-angle theta, built from block
+// reductions over the tile's actual ray directions).  An entry whose response cannot reach
+// alpha_min on any direction of the cone is dropped for the whole tile; every ray of the tile
+// would skip it, so results do not change.
+#pragma once
+#include "ut_device.hpp"
+
+namespace ut {
+
+// Bounding cone of a tile's rays: unit axis u, orthonormal e1, e2 spanning u's complement,
+// and cos / sin of twice the half-angle.  `on` is false when the tile has no ray or the cone
+// is too wide for the bound below (half-angle > 45 degrees).
+struct TileCone {
+  double u[3], e1[3], e2[3];
+  double cos2t, sin2t;
+  int on;
+};
+
+template <int BLOCK>
+__device__ __forceinline__ double block_reduce(double v, bool is_min, double (&red)[BLOCK / 64], int wave, int lane) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(v, off);
+    v = is_min ? (o < v ? o : v) : v + o;
+  }
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int w = 1; w < BLOCK / 64; ++w) r = is_min ? (red[w] < r ? red[w] : r) : r + red[w];
+  __syncthreads();
+  return r;
+}
+
+// cosine of the angle between the unit axis u and a (not necessarily unit) ray direction d
+__device__ __forceinline__ double cone_cos(double ux, double uy, double uz, double dx, double dy, double dz) {
+  const double l = __builtin_sqrt(__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)));
+  return __builtin_fma(ux, dx, __builtin_fma(uy, dy, uz * dz)) / l;
+}
+
+// Axis of the tile's cone: every thread passes the sum of its rays' unit directions (zero when
+// it has none) and receives the normalised block sum u and its length sn (0 = no ray).
+template <int BLOCK>
+__device__ __forceinline__ void tile_cone_axis(double sx, double sy, double sz, double (&red)[4][BLOCK / 64],
+                                               int wave, int lane, double& ux, double& uy, double& uz,
+                                               double& sn) {
+  sx = block_reduce<BLOCK>(sx, false, red[0], wave, lane);
+  sy = block_reduce<BLOCK>(sy, false, red[1], wave, lane);
+  sz = block_reduce<BLOCK>(sz, false, red[2], wave, lane);
+  sn = __builtin_sqrt(__builtin_fma(sx, sx, __builtin_fma(sy, sy, sz * sz)));
+  ux = sx / sn, uy = sy / sn, uz = sz / sn;
+}
+
+// Half-angle from the block minimum of cone_cos over all rays (each thread passes its own
+// minimum, 1 when it has no ray); thread 0 writes the cone, then the block synchronises.
+template <int BLOCK>
+__device__ __forceinline__ void tile_cone_finish(double cmin, double sn, double ux, double uy, double uz,
+                                                 double (&red)[4][BLOCK / 64], int wave, int lane, TileCone& tc) {
+  cmin = block_reduce<BLOCK>(cmin, true, red[3], wave, lane);
+  if (threadIdx.x == 0) {
+    const double ct = cmin - 1e-9;                       // widen for rounding
+    tc.on = (sn > 0.0 && ct > 0.7071067811865476) ? 1 : 0;
+    const double st = __builtin_sqrt(1.0 - ct * ct);
+    tc.cos2t = 2.0 * ct * ct - 1.0;
+    tc.sin2t = 2.0 * st * ct;
+    tc.u[0] = ux, tc.u[1] = uy, tc.u[2] = uz;
+    // e1 = normalise(u x t) with t the coordinate axis least aligned with u; e2 = u x e1
+    double t0 = 0, t1 = 0, t2 = 0;
+    if (__builtin_fabs(ux) <= __builtin_fabs(uy) && __builtin_fabs(ux) <= __builtin_fabs(uz)) t0 = 1;
+    else if (__builtin_fabs(uy) <= __builtin_fabs(uz)) t1 = 1;
+    else t2 = 1;
+    double e0 = uy * t2 - uz * t1, e1 = uz * t0 - ux * t2, e2 = ux * t1 - uy * t0;
+    const double en = __builtin_sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    e0 /= en, e1 /= en, e2 /= en;
+    tc.e1[0] = e0, tc.e1[1] = e1, tc.e1[2] = e2;
+    tc.e2[0] = uy * e2 - uz * e1, tc.e2[1] = uz * e0 - ux * e2, tc.e2[2] = ux * e1 - uy * e0;
+  }
+  __syncthreads();
+}
+
+// Conservative tile-cone test: true when no unit direction d within the cone can bring the
+// particle's response to alpha_min, i.e. h(d) = |a x Md|^2 - cut |Md|^2 > 0 on the whole cone.
+// With d = cos(phi) u + sin(phi) e, e a unit vector in span(e1, e2) and phi <= theta,
+//   h >= cos^2(phi) A - 2 sin(phi) cos(phi) B + sin^2(phi) C,
+// where A = h(u), B bounds the mixed term over all e and C is the smallest eigenvalue of the
+// form on span(e1, e2).  In psi = 2 phi this is P + Rc cos(psi) - B sin(psi), minimised over
+// psi in [0, 2 theta] in closed form.  The threshold carries 0.05 of slack over the per-ray
+// cut so that rounding cannot drop an entry that a ray would keep; the dropped entries are
+// exactly ones every ray of the tile would skip, so outputs are unchanged.
+__device__ __forceinline__ bool cone_rejects(const Record* __restrict__ rp, const TileCone& tc,
+                                             double log_alpha_min) {
+  const double cut = cut_threshold(rp->log_sigma, log_alpha_min) + 0.05;
+  double m[9], a[3];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) m[i] = rp->m[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) a[i] = rp->a[i];
+  double w[3][3], x[3][3];   // w_k = M v_k and x_k = a x w_k for v = (u, e1, e2)
+  const double* v[3] = {tc.u, tc.e1, tc.e2};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      w[k][i] = __builtin_fma(m[3 * i], v[k][0], __builtin_fma(m[3 * i + 1], v[k][1], m[3 * i + 2] * v[k][2]));
+    x[k][0] = __builtin_fma(a[1], w[k][2], -(a[2] * w[k][1]));
+    x[k][1] = __builtin_fma(a[2], w[k][0], -(a[0] * w[k][2]));
+    x[k][2] = __builtin_fma(a[0], w[k][1], -(a[1] * w[k][0]));
+  }
+  auto H = [&](int i, int j) {
+    const double xx = __builtin_fma(x[i][0], x[j][0], __builtin_fma(x[i][1], x[j][1], x[i][2] * x[j][2]));
+    const double ww = __builtin_fma(w[i][0], w[j][0], __builtin_fma(w[i][1], w[j][1], w[i][2] * w[j][2]));
+    return __builtin_fma(-cut, ww, xx);
+  };
+  const double A = H(0, 0), H01 = H(0, 1), H02 = H(0, 2);
+  const double H11 = H(1, 1), H12 = H(1, 2), H22 = H(2, 2);
+  const double B = __builtin_sqrt(__builtin_fma(H01, H01, H02 * H02));
+  const double hd = 0.5 * (H11 - H22);
+  const double C = 0.5 * (H11 + H22) - __builtin_sqrt(__builtin_fma(hd, hd, H12 * H12));
+  const double P = 0.5 * (A + C), Rc = 0.5 * (A - C);
+  const double rad = __builtin_sqrt(__builtin_fma(Rc, Rc, B * B));
+  double fmin;
+  if (-Rc >= rad * tc.cos2t) {
+    fmin = P - rad;   // the minimiser psi* = pi - atan2(B, Rc) lies inside [0, 2 theta]
+  } else {
+    const double f1 = __builtin_fma(Rc, tc.cos2t, P) - B * tc.sin2t;
+    fmin = A < f1 ? A : f1;
+  }
+  return fmin > 0.0;
+}
+
+}  // namespace ut
