@@ -167,15 +167,32 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
   }
 }
 
+// DEG is the SH degree as a compile-time constant, so the per-coefficient arrays below are
+// indexed statically and stay in registers.  A particle that no pair touched has zero
+// accumulators and therefore zero gradients; it only writes the zeros.
+template <int DEG>
 __global__ __launch_bounds__(256) void k_chain(ut_gaussians g, SensorK s, const double* __restrict__ acc,
                                                 ut_gaussian_grads out) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
   const int n = g.n;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int K = sh_count(g.sh_degree);
   double a[UT_ACC_FLOATS];
+  bool touched = false;
 #pragma unroll
-  for (int k = 0; k < UT_ACC_FLOATS; ++k) a[k] = acc[(size_t)k * n + i];
+  for (int k = 0; k < UT_ACC_FLOATS; ++k) {
+    a[k] = acc[(size_t)k * n + i];
+    touched = touched || a[k] != 0.0;
+  }
+  if (!touched) {
+    for (int c = 0; c < 3; ++c) out.mean[(size_t)c * n + i] = 0.0f;
+    for (int c = 0; c < 4; ++c) out.quat[(size_t)c * n + i] = 0.0f;
+    for (int c = 0; c < 3; ++c) out.log_scale[(size_t)c * n + i] = 0.0f;
+    out.opacity_logit[i] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) out.feat[(size_t)k * n + i] = 0.0f;
+    return;
+  }
   const float q0 = g.quat[i], q1 = g.quat[n + i], q2 = g.quat[2 * n + i], q3 = g.quat[3 * n + i];
   const float l0 = g.log_scale[i], l1 = g.log_scale[n + i], l2 = g.log_scale[2 * n + i];
   const float lg = g.opacity_logit[i];
@@ -184,7 +201,8 @@ __global__ __launch_bounds__(256) void k_chain(ut_gaussians g, SensorK s, const 
   const bool ok = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(l0) && isfinite(l1) &&
                   isfinite(l2) && isfinite(lg) && isfinite(qq) && qq > 0;
   double dmean[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dls[3] = {0, 0, 0}, dlogit = 0;
-  double dcoef[16][3];
+  double dcoef[K][3];
+#pragma unroll
   for (int k = 0; k < K; ++k) dcoef[k][0] = dcoef[k][1] = dcoef[k][2] = 0;
   if (ok) {
     const double qn = sqrt(qq), iq = 1.0 / qn;
@@ -227,16 +245,19 @@ __global__ __launch_bounds__(256) void k_chain(ut_gaussians g, SensorK s, const 
     double ex = 0, ey = 0, ez = 1;
     if (len > 0) { ex = vx / len; ey = vy / len; ez = vz / len; }
     double Y[16], GY[16][3];
-    sh_basis(g.sh_degree, ex, ey, ez, Y);
-    sh_basis_grad(g.sh_degree, ex, ey, ez, GY);
+    sh_basis(DEG, ex, ey, ez, Y);
+    sh_basis_grad(DEG, ex, ey, ez, GY);
     double ddir[3] = {0, 0, 0};
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
       double dc = a[c];
       if (g.feat_kind == UT_FEAT_CAMERA) {
         double f = 0;
+#pragma unroll
         for (int k = 0; k < K; ++k) f += (double)g.feat[(size_t)(k * 3 + c) * n + i] * Y[k];
         if (!(f + 0.5 > 0)) dc = 0;
       }
+#pragma unroll
       for (int k = 0; k < K; ++k) {
         dcoef[k][c] = dc * Y[k];
         const double coef = g.feat[(size_t)(k * 3 + c) * n + i];
@@ -257,6 +278,7 @@ __global__ __launch_bounds__(256) void k_chain(ut_gaussians g, SensorK s, const 
   for (int c = 0; c < 4; ++c) out.quat[(size_t)c * n + i] = (float)dq[c];
   for (int c = 0; c < 3; ++c) out.log_scale[(size_t)c * n + i] = (float)dls[c];
   out.opacity_logit[i] = (float)dlogit;
+#pragma unroll
   for (int k = 0; k < K; ++k)
     for (int c = 0; c < 3; ++c) out.feat[(size_t)(k * 3 + c) * n + i] = (float)dcoef[k][c];
 }
@@ -281,7 +303,13 @@ hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const u
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_chain, dim3((g.n + 255) / 256), dim3(256), 0, st, g, s, acc, grads);
+  const dim3 cg((g.n + 255) / 256);
+  switch (g.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_chain<0>, cg, dim3(256), 0, st, g, s, acc, grads); break;
+    case 1: hipLaunchKernelGGL(k_chain<1>, cg, dim3(256), 0, st, g, s, acc, grads); break;
+    case 2: hipLaunchKernelGGL(k_chain<2>, cg, dim3(256), 0, st, g, s, acc, grads); break;
+    default: hipLaunchKernelGGL(k_chain<3>, cg, dim3(256), 0, st, g, s, acc, grads); break;
+  }
   return hipGetLastError();
 }
 
