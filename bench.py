@@ -68,7 +68,7 @@ def parse():
     return ap.parse_args()
 
 
-CAMERA_KERNEL = "k_composite<256, 1, 128>"
+CAMERA_KERNEL = "k_composite<256, 1, 128, false>"
 PROFILE_CMDS = {
     "stats": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_stats -o kt -- "
              "python -u bench.py --no-served --no-backward --no-cpu-baseline --steps 5 --warmup 1 --streams 1",
@@ -279,7 +279,7 @@ def main():
                    "tile_pairs_per_sensor": tile_pairs, "bin_pairs_per_sensor": bin_pairs},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
-                     "kernel": "k_composite<256, 1, 128> (camera compositing)",
+                     "kernel": CAMERA_KERNEL + " (camera compositing)",
                      "flops_per_visit": FLOPS_PER_VISIT, "flops_per_pass": FLOPS_PER_PASS,
                      "visits_per_launch": int(visits / len(cams)), "passes_per_launch": int(passes / len(cams)),
                      "list_positions_per_launch": int(positions / len(cams)),
