@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--vehicles", type=str, default="1,4,8")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (reference kernel for HBM counters)")
+    ap.add_argument("--lidar-sweep", action="store_true",
+                    help="instead of the frame benchmark: LiDAR tiling sweep (N_phi x M) and culling ablation "
+                         "on the 300,000-particle 128x2048 LiDAR workload")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/ summaries from rocprofv3 CSV output (kernel stats, FETCH_SIZE "
                          "and WRITE_SIZE counter collections) instead of benchmarking")
@@ -146,10 +149,65 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def lidar_sweep(args):
+    """Tiling sweep and culling ablation on the LiDAR workload (300,000 particles, 128 beams x
+    2048 azimuth steps): for every (N_phi, M) the whole LiDAR render (projection with culling,
+    binning, sort, compositing) is timed frame by frame over K frames after W warm-up frames
+    (median), and the compositing alone over 5 back-to-back launches."""
+    import torch
+
+    import paper_2510_12901_amd as ut
+    import synth
+
+    dev = torch.device("cuda:0")
+    g_np, s0 = synth.scene_lidar(args.seed, n=300_000)
+    g = ut.GaussianSet.from_numpy(g_np, dev)
+    beams = s0["beam_elev"]
+    stream = torch.cuda.current_stream()
+
+    def time_config(n_phi, M, cull):
+        s = ut.Sensor(synth.lidar(beams, 2048, n_phi=n_phi, max_per_tile=M, cull=cull), dev)
+        pipe = ut.SensorPipeline(g, s)
+        for _ in range(SETUP_FRAMES + args.warmup):
+            pipe.run(stream)
+        torch.cuda.synchronize()
+        times = []     # per-frame wall time, median: robust to a one-off host stall in a launch
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            pipe.run(stream)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        frame_ms = float(np.median(times)) * 1e3
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            pipe.composite_only(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return {"n_phi": n_phi, "M": M, "cull": cull, "n_theta": int(s.c.n_theta),
+                "max_tile_rays": s.max_tile_rays, "bin_pairs": pipe.n_pairs, "frame_ms": round(frame_ms, 4),
+                "mrays_per_s": round(s.n_rays / frame_ms / 1e3, 2),
+                "composite_ms": round(e0.elapsed_time(e1) / 5, 4)}
+
+    rows = []
+    for n_phi in (64, 32, 16, 8):
+        for M in (256, 128, 64, 32):
+            r = time_config(n_phi, M, True)
+            rows.append(r)
+            log(json.dumps(r))
+    abl = [time_config(16, 32, c) for c in (True, False)]
+    for r in abl:
+        log(json.dumps(r))
+    print(json.dumps({"lidar_tiling_sweep": rows, "culling_ablation": abl}))
+
+
 def main():
     args = parse()
     if args.summarize_profiles:
         summarize_profiles(*args.summarize_profiles)
+        return
+    if args.lidar_sweep:
+        lidar_sweep(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

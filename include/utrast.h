@@ -53,7 +53,7 @@ enum { UT_FEAT_CAMERA = 0, UT_FEAT_LIDAR = 1 };
 #define UT_MAX_ELEV_TILES 256   /* largest N_phi accepted */
 #define UT_CAMERA_TILE 16       /* camera tiles are 16 x 16 pixels */
 #define UT_SUPER_TILE 8         /* binning super-tiles are 8 x 8 tiles */
-#define UT_MAX_LIDAR_TILE_RAYS 256
+#define UT_MAX_LIDAR_TILE_RAYS 512   /* ut_composite_batch and the adjoint take up to 256 */
 #define UT_ACC_FLOATS 13        /* per-particle adjoint accumulator width (doubles) */
 
 typedef void* ut_stream; /* hipStream_t */
@@ -298,7 +298,8 @@ size_t ut_backward_workspace_bytes(int32_t n_gaussians);
  * per-particle kernel applies the chain rule to (mean, quat, log_scale, opacity_logit,
  * feat) including the SH direction's dependence on the mean.  fwd must hold feat,
  * t_final and n_proc of the forward call with the same arguments.  Gradients are
- * accumulated in float64 but their summation order is not fixed (atomics). */
+ * accumulated in float64 but their summation order is not fixed (atomics).  Sensors whose
+ * tiles hold more than 256 rays (LiDAR with large M) return UT_ERR_UNSUPPORTED. */
 ut_status ut_composite_backward(const ut_gaussians* g, const ut_projected* p,
                                 const ut_tile_lists* lists, const ut_sensor* s,
                                 const ut_render_params* prm, const ut_render_out* fwd,
@@ -311,7 +312,8 @@ ut_status ut_composite_backward(const ut_gaussians* g, const ut_projected* p,
  * items from a device counter until the queue is exhausted.  Per-ray arithmetic is the
  * same as ut_composite_camera / ut_composite_lidar, so every ray's output is bit-identical
  * to the single-request call.  items: host array [n_items]; queue_ws: device workspace of
- * ut_batch_workspace_bytes(n_items) bytes. */
+ * ut_batch_workspace_bytes(n_items) bytes.  Sensors whose tiles hold more than 256 rays
+ * return UT_ERR_UNSUPPORTED (n_visit / n_pass are not written on this path). */
 typedef struct {
   const ut_projected* proj;
   const ut_bin_lists* bins;

@@ -342,6 +342,7 @@ ut_status ut_composite_backward(const ut_gaussians* g, const ut_projected* p, co
       !grads->quat || !grads->log_scale || !grads->opacity_logit || !grads->feat)
     return UT_ERR_ARG;
   if (acc_ws_bytes < ut_backward_workspace_bytes(g->n)) return UT_ERR_CAPACITY;
+  if (s->max_tile_rays > 256) return UT_ERR_UNSUPPORTED;   // the adjoint runs one lane per ray of a tile
   const SensorK k = make_sensor_k(s);
   return from_hip(launch_backward(*g, *p, *lists, k, make_params(prm), *fwd, *up, static_cast<double*>(acc_ws),
                                   *grads, s->max_tile_rays, as_stream(stream)));
@@ -377,6 +378,7 @@ ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items, const 
     if (!it.proj || !it.proj->records || !it.proj->trect || !bins_ok(it.bins) || !sensor_ok(it.sensor) || !it.out ||
         !it.out->feat || !it.out->depth || !it.out->alpha)
       return UT_ERR_ARG;
+    if (it.sensor->max_tile_rays > 256) return UT_ERR_UNSUPPORTED;   // one lane per ray of a 256-lane group
   }
   for (int i = 0; i < n_items; ++i) {
     const ut_batch_item& it = items[i];

@@ -22,7 +22,7 @@ namespace {
 // Camera tiles (16 x 16 rays) and the batched kernel (any tile of up to 256 rays) run BLOCK
 // threads with RPL rays per lane and stage BATCH records per step.
 constexpr int kCamBlock = 256, kCamRpl = 1, kCamBatch = 128;
-static_assert(kCamBlock * kCamRpl >= UT_MAX_LIDAR_TILE_RAYS, "batched tiles must fit one workgroup");
+static_assert(kCamBlock * kCamRpl >= 256, "batched tiles (up to 256 rays) must fit one workgroup");
 
 // BLOCK threads, RPL rays per lane: one workgroup covers up to BLOCK * RPL rays.  Records are
 // staged BATCH at a time; the ring of candidate indices holds a batch plus one refill step of
@@ -262,7 +262,9 @@ hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, con
       hipLaunchKernelGGL((k_composite<B, R, N, false>), dim3(grid), dim3(B), 0, st, s, rec, tr, bins.gauss, \
                          bins.ranges, n_tiles, prm, out);                                                 \
   } while (0)
-  if (s.kind != UT_LIDAR || max_tile_rays > 128)
+  if (s.kind == UT_LIDAR && max_tile_rays > 256)
+    UT_LAUNCH_COMPOSITE(256, 2, 256);   // LiDAR tiles of up to 512 rays: two rays per lane
+  else if (s.kind != UT_LIDAR || max_tile_rays > 128)
     UT_LAUNCH_COMPOSITE(kCamBlock, kCamRpl, kCamBatch);
   else if (max_tile_rays > 64)
     UT_LAUNCH_COMPOSITE(128, 1, 128);
