@@ -23,6 +23,7 @@ ALPHA_MIN = 1.0 / 255.0
 ALPHA_MAX = 0.99
 T_MIN = 1e-4
 R_BINS = 400          # Alg. 1 histogram resolution
+RS_ITERS = 3          # fixed-point iterations of the time-dependent projection (reading)
 
 
 def build(force: bool = False) -> str:
@@ -47,7 +48,9 @@ class Sensor(C.Structure):
                 ("n_beams", C.c_int), ("n_az", C.c_int), ("n_phi", C.c_int), ("n_theta", C.c_int),
                 ("elev_bounds", C.c_void_p), ("beam_start", C.c_void_p),
                 ("cull", C.c_int), ("cull_az", C.c_int), ("cull_el", C.c_int),
-                ("sat", C.c_void_p), ("ray_dir", C.c_void_p)]
+                ("sat", C.c_void_p), ("ray_dir", C.c_void_p),
+                ("moving", C.c_int), ("R_sw1", C.c_float * 9), ("origin1", C.c_float * 3),
+                ("ray_org", C.c_void_p), ("rs_iters", C.c_int)]
 
 
 class Params(C.Structure):
@@ -82,6 +85,7 @@ def lib():
         L.orc_backward.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_fd_grad.argtypes = [P, P, P, P, P, P, P, P, P, P, C.c_int, C.c_double, P]
         L.orc_sh_eval.argtypes = [C.c_int, P, C.c_int, P]
+        L.orc_pose_at.argtypes = [P, C.c_double, P, P]
         L.orc_project_points.argtypes = [P, P, C.c_int, P, P]
         L.orc_num_threads.argtypes = []
         _lib = L
@@ -145,6 +149,13 @@ class OracleSensor:
         c.origin[:] = [float(x) for x in np.asarray(s["origin"], np.float32)]
         c.near_ = float(s.get("near", 0.1))
         c.ray_dir = _p(self.ray_dir).value
+        if s.get("moving"):
+            self.ray_org = np.ascontiguousarray(s["ray_org"], dtype=np.float32)
+            c.moving = 1
+            c.R_sw1[:] = [float(x) for x in np.asarray(s["R_sw1"], np.float32).ravel()]
+            c.origin1[:] = [float(x) for x in np.asarray(s["origin1"], np.float32)]
+            c.ray_org = _p(self.ray_org).value
+            c.rs_iters = int(s.get("rs_iters", RS_ITERS))
         self.kind = c.kind
         if c.kind == 2:
             self.beam_elev = np.ascontiguousarray(s["beam_elev"], dtype=np.float32)
@@ -335,6 +346,15 @@ def project_points(s, pts):
     ok = np.zeros(pts.shape[0], np.int32)
     lib().orc_project_points(C.byref(s.c), _p(pts), pts.shape[0], _p(uv), _p(ok))
     return uv, ok.astype(bool)
+
+
+def pose_at(s, t: float):
+    """(R_sw, origin) of a (moving) sensor at frame time t, as the oracle interpolates it."""
+    s = _as_s(s)
+    R = np.zeros(9)
+    o = np.zeros(3)
+    lib().orc_pose_at(C.byref(s.c), float(t), _p(R), _p(o))
+    return R.reshape(3, 3), o
 
 
 def num_threads() -> int:

@@ -47,6 +47,15 @@ typedef struct {
   int cull, cull_az, cull_el;
   const int* sat;            /* [(cull_az+1)*(cull_el+1)] summed-area table */
   const float* ray_dir;      /* [3][R] world frame */
+  /* Time-dependent sensor (Sec. 3.2 and the appendix on time-dependent effects): moving = 1
+   * means the pose (R_sw, origin) holds at frame time t = 0 and (R_sw1, origin1) at t = 1,
+   * every ray carries its own origin ray_org[3][R] (and direction), and a projected point is
+   * observed at the time of the row (camera) or azimuth (LiDAR) it falls on. */
+  int moving;
+  float R_sw1[9];
+  float origin1[3];
+  const float* ray_org;      /* [3][R] world frame, moving sensors only */
+  int rs_iters;              /* fixed-point iterations of the time-dependent projection */
 } orc_sensor;
 
 typedef struct {
@@ -273,17 +282,101 @@ void gaussian_features(const orc_gaussians* g, int i, const double mu[3], const 
  * valid iff r > near; orthographic (fx x + cx, fy y + cy), valid iff z > near.
  * margin receives the distance of the validity decision to its threshold.
  * ---------------------------------------------------------------------------------- */
-void to_sensor(const orc_sensor* s, const double xw[3], double xs[3]) {
-  double d[3];
-  for (int a = 0; a < 3; ++a) d[a] = xw[a] - (double)s->origin[a];
-  for (int r = 0; r < 3; ++r)
-    xs[r] = (double)s->R_sw[r * 3 + 0] * d[0] + (double)s->R_sw[r * 3 + 1] * d[1] +
-            (double)s->R_sw[r * 3 + 2] * d[2];
+/* ------------------------------------------------------------------------------------
+ * Sensor pose.  A static sensor has one pose.  A moving one (rolling shutter, spinning LiDAR)
+ * interpolates between its poses at t = 0 and t = 1.  READING (the paper gives no formula):
+ * the origin moves linearly, o(t) = (1 - t) o0 + t o1, and the rotation by spherical linear
+ * interpolation of the two unit quaternions (shorter arc), i.e. constant angular velocity.
+ * ---------------------------------------------------------------------------------- */
+void rot_to_quat(const float Rf[9], double q[4]) {
+  double R[9];
+  for (int i = 0; i < 9; ++i) R[i] = Rf[i];
+  /* largest of the four |q_i| first, for a well-conditioned extraction */
+  const double t = R[0] + R[4] + R[8];
+  if (t > 0) {
+    const double r = std::sqrt(1 + t), f = 0.5 / r;
+    q[0] = 0.5 * r; q[1] = (R[7] - R[5]) * f; q[2] = (R[2] - R[6]) * f; q[3] = (R[3] - R[1]) * f;
+  } else if (R[0] >= R[4] && R[0] >= R[8]) {
+    const double r = std::sqrt(1 + R[0] - R[4] - R[8]), f = 0.5 / r;
+    q[0] = (R[7] - R[5]) * f; q[1] = 0.5 * r; q[2] = (R[1] + R[3]) * f; q[3] = (R[2] + R[6]) * f;
+  } else if (R[4] >= R[8]) {
+    const double r = std::sqrt(1 - R[0] + R[4] - R[8]), f = 0.5 / r;
+    q[0] = (R[2] - R[6]) * f; q[1] = (R[1] + R[3]) * f; q[2] = 0.5 * r; q[3] = (R[5] + R[7]) * f;
+  } else {
+    const double r = std::sqrt(1 - R[0] - R[4] + R[8]), f = 0.5 / r;
+    q[0] = (R[3] - R[1]) * f; q[1] = (R[2] + R[6]) * f; q[2] = (R[5] + R[7]) * f; q[3] = 0.5 * r;
+  }
+  const double nq = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int i = 0; i < 4; ++i) q[i] /= nq;
 }
 
+void pose_at(const orc_sensor* s, double t, double R[9], double o[3]) {
+  if (!s->moving) {
+    for (int i = 0; i < 9; ++i) R[i] = s->R_sw[i];
+    for (int a = 0; a < 3; ++a) o[a] = s->origin[a];
+    return;
+  }
+  double q0[4], q1[4];
+  rot_to_quat(s->R_sw, q0);
+  rot_to_quat(s->R_sw1, q1);
+  double dot = q0[0] * q1[0] + q0[1] * q1[1] + q0[2] * q1[2] + q0[3] * q1[3];
+  if (dot < 0) {
+    for (int i = 0; i < 4; ++i) q1[i] = -q1[i];
+    dot = -dot;
+  }
+  double w0 = 1 - t, w1 = t;
+  if (dot < 1 - 1e-12) {
+    const double th = std::acos(std::min(dot, 1.0));
+    w0 = std::sin((1 - t) * th) / std::sin(th);
+    w1 = std::sin(t * th) / std::sin(th);
+  }
+  double q[4];
+  for (int i = 0; i < 4; ++i) q[i] = w0 * q0[i] + w1 * q1[i];
+  const double nq = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int i = 0; i < 4; ++i) q[i] /= nq;
+  quat_to_rot(q, R);
+  for (int a = 0; a < 3; ++a) o[a] = (1 - t) * (double)s->origin[a] + t * (double)s->origin1[a];
+}
+
+void to_sensor_pose(const double R[9], const double o[3], const double xw[3], double xs[3]) {
+  double d[3];
+  for (int a = 0; a < 3; ++a) d[a] = xw[a] - o[a];
+  for (int r = 0; r < 3; ++r) xs[r] = R[r * 3 + 0] * d[0] + R[r * 3 + 1] * d[1] + R[r * 3 + 2] * d[2];
+}
+
+bool project_point_pose(const orc_sensor* s, const double R[9], const double o[3], const double xw[3],
+                        double uv[2], double* margin);
+
+/* Time-dependent projection (the appendix on time-dependent effects: sensor motion inside
+ * the projection function, sigma points projected independently).  READING: the frame time
+ * of a camera row v is v / H (rows read out top to bottom, row r at (r + 0.5) / H) and of a
+ * LiDAR azimuth phi in [0, 2 pi) is phi / (2 pi) (column a fired at a / n_az); a point is
+ * projected with the pose at t = 1/2, then rs_iters - 1 more times with the pose at the time
+ * of its previous projection (fixed point t = time(g(x; pose(t)))). */
 bool project_point(const orc_sensor* s, const double xw[3], double uv[2], double* margin) {
+  double R[9], o[3];
+  if (!s->moving) {
+    pose_at(s, 0.0, R, o);
+    return project_point_pose(s, R, o, xw, uv, margin);
+  }
+  double t = 0.5;
+  for (int it = 0; it < std::max(s->rs_iters, 1); ++it) {
+    pose_at(s, t, R, o);
+    if (!project_point_pose(s, R, o, xw, uv, margin)) return false;
+    if (s->kind == 2) {
+      t = uv[0] / (2 * kPi);
+      *margin = std::min(*margin, std::min(uv[0], 2 * kPi - uv[0]));   /* the sweep's seam */
+    } else {
+      t = std::min(std::max(uv[1] / s->height, 0.0), 1.0);
+    }
+  }
+  return true;
+}
+
+bool project_point_pose(const orc_sensor* s, const double R[9], const double o[3], const double xw[3],
+                        double uv[2], double* margin) {
   double p[3];
-  to_sensor(s, xw, p);
+  to_sensor_pose(R, o, xw, p);
   const double x = p[0], y = p[1], z = p[2];
   switch (s->kind) {
     case 0: {
@@ -698,7 +791,10 @@ struct RayResult {
 };
 
 void ray_geometry(const orc_sensor* s, int r, long R, double o[3], double d[3]) {
-  for (int a = 0; a < 3; ++a) { o[a] = s->origin[a]; d[a] = s->ray_dir[a * R + r]; }
+  for (int a = 0; a < 3; ++a) {
+    o[a] = s->moving ? (double)s->ray_org[a * R + r] : (double)s->origin[a];
+    d[a] = s->ray_dir[a * R + r];
+  }
 }
 
 bool ray_valid(const double d[3]) { return d[0] != 0 || d[1] != 0 || d[2] != 0; }
@@ -1171,6 +1267,12 @@ int orc_sh_eval(int deg, const double* dirs, int m, double* Y) {
 }
 
 /* Single-point sensor projection (for pinning the projection functions). */
+/* pose of a (moving) sensor at frame time t: R[9] world->sensor rows, o[3] */
+int orc_pose_at(const orc_sensor* s, double t, double* R, double* o) {
+  pose_at(s, t, R, o);
+  return 0;
+}
+
 int orc_project_points(const orc_sensor* s, const double* xw, int m, double* uv, int* ok) {
   for (int i = 0; i < m; ++i) {
     double margin = 1e300;

@@ -126,6 +126,47 @@ def _to_world(R_sw, d_sensor):
     return np.ascontiguousarray(d.astype(np.float32))
 
 
+def _add_motion(desc, d_sensor, times, R_sw1, origin1, rs_iters=3):
+    """Moving sensor: pose (R_sw, origin) at frame time 0 and (R_sw1, origin1) at 1; ray i,
+    captured at times[i], gets the world direction R(t_i)^T d_i and the origin o(t_i), with the
+    origin linear in t and the rotation spherically interpolated (scipy's Slerp)."""
+    from scipy.spatial.transform import Rotation, Slerp
+    R0 = np.asarray(desc["R_sw"], np.float32).astype(np.float64)
+    R1 = np.asarray(R_sw1, np.float32).astype(np.float64)
+    o0 = np.asarray(desc["origin"], np.float32).astype(np.float64)
+    o1 = np.asarray(origin1, np.float32).astype(np.float64)
+    slerp = Slerp([0.0, 1.0], Rotation.from_matrix(np.stack([R0, R1])))
+    Rt = slerp(np.clip(times, 0.0, 1.0)).as_matrix()                 # [R,3,3] world->sensor
+    d = np.einsum("rji,jr->ir", Rt, d_sensor)                           # R^T d per ray
+    n = np.linalg.norm(d, axis=0, keepdims=True)
+    d = np.where(n > 0, d / np.where(n > 0, n, 1.0), 0.0)
+    d[:, ~np.any(d_sensor != 0, axis=0)] = 0.0
+    org = (1.0 - times)[None, :] * o0[:, None] + times[None, :] * o1[:, None]
+    desc.update(moving=1, R_sw1=np.asarray(R_sw1, np.float32), origin1=np.asarray(origin1, np.float32),
+                ray_dir=np.ascontiguousarray(d.astype(np.float32)),
+                ray_org=np.ascontiguousarray(org.astype(np.float32)), rs_iters=rs_iters)
+    return desc
+
+
+def rolling_shutter(desc, R_sw1, origin1, rs_iters=3):
+    """Camera with rolling shutter: rows read out top to bottom, row r at frame time
+    (r + 0.5) / H.  desc is a static camera from pinhole() / fisheye() holding the pose at t=0."""
+    W, H = desc["width"], desc["height"]
+    ys = np.repeat(np.arange(H), W)
+    times = (ys + 0.5) / H
+    d_sensor = np.asarray(desc["R_sw"], np.float32).astype(np.float64) @ desc["ray_dir"].astype(np.float64)
+    d_sensor[:, ~np.any(desc["ray_dir"] != 0, axis=0)] = 0.0
+    return _add_motion(dict(desc), d_sensor, times, R_sw1, origin1, rs_iters)
+
+
+def spinning(desc, R_sw1, origin1, rs_iters=3):
+    """Spinning LiDAR in motion: azimuth column a fired at frame time a / n_az."""
+    n_az = desc["n_az"]
+    times = np.tile(np.arange(n_az) / n_az, desc["n_beams"])
+    d_sensor = np.asarray(desc["R_sw"], np.float32).astype(np.float64) @ desc["ray_dir"].astype(np.float64)
+    return _add_motion(dict(desc), d_sensor, times, R_sw1, origin1, rs_iters)
+
+
 def pinhole(width, height, fx, fy, cx=None, cy=None, R_sw=None, origin=None,
             near=0.1, kind=PINHOLE):
     cx = width / 2.0 if cx is None else cx

@@ -421,3 +421,104 @@ def test_adjoint_matches_finite_differences_lidar():
     an = oracle.grads_as_rows(gr, sel)
     assert np.abs(an).max() > 0
     np.testing.assert_allclose(an, fd, atol=1e-6 * np.abs(fd).max(), rtol=1e-5)
+
+
+# ------------------------------------------------------------------ time-dependent sensors
+def _moving_pinhole(W=48, H=40, f=40.0, shift=(0.4, -0.1, 0.3), yaw=0.15):
+    R0 = synth.yaw_camera_pose(0.3)
+    R1 = synth.yaw_camera_pose(0.3 + yaw)
+    o0 = np.array([0.5, -0.2, 0.1], np.float32)
+    s = synth.pinhole(W, H, f, f, R_sw=R0, origin=o0)
+    return synth.rolling_shutter(s, R1, o0 + np.asarray(shift, np.float32))
+
+
+def test_moving_pose_matches_scipy_slerp():
+    """The oracle's pose interpolation (quaternions from the matrices, shorter-arc slerp,
+    linear origin) equals scipy's Slerp on the same float32 poses."""
+    from scipy.spatial.transform import Slerp
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        R0 = Rotation.random(random_state=rng).as_matrix().astype(np.float32)
+        R1 = Rotation.random(random_state=rng).as_matrix().astype(np.float32)
+        o0, o1 = rng.normal(size=3).astype(np.float32), rng.normal(size=3).astype(np.float32)
+        s = synth.rolling_shutter(synth.pinhole(8, 8, 8.0, 8.0, R_sw=R0, origin=o0), R1, o1)
+        sl = Slerp([0, 1], Rotation.from_matrix(np.stack([R0, R1]).astype(np.float64)))
+        for t in (0.0, 0.13, 0.5, 0.77, 1.0):
+            R, o = oracle.pose_at(s, t)
+            # the float32 matrices are orthonormal only to ~1e-8; scipy projects them onto
+            # rotations, the oracle normalises the extracted quaternion
+            np.testing.assert_allclose(R, sl([t]).as_matrix()[0], atol=5e-8)
+            np.testing.assert_allclose(o, (1 - t) * o0.astype(np.float64) + t * o1.astype(np.float64), atol=1e-14)
+
+
+def test_rolling_shutter_ray_tables_round_trip():
+    """A point on the ray of pixel (x, y), captured at t = (y + 0.5)/H from o(t), projects back
+    to that pixel centre at the fixed point of the time-dependent projection (the generator
+    builds the rays with scipy's Slerp, the oracle with its own interpolation)."""
+    s = _moving_pinhole()
+    s["rs_iters"] = 40                                  # converged fixed point
+    d = s["ray_dir"].astype(np.float64)
+    o = s["ray_org"].astype(np.float64)
+    pts = (o + 6.0 * d).T
+    uv, ok = oracle.project_points(s, pts)
+    W = s["width"]
+    idx = np.arange(d.shape[1])
+    centre = np.stack([idx % W + 0.5, idx // W + 0.5], 1)
+    assert ok.all()
+    assert np.abs(uv - centre).max() < 2e-3             # float32 ray rounding
+
+
+def test_spinning_lidar_ray_tables_round_trip():
+    """Same for a spinning LiDAR in motion: column a fires at t = a / n_az; away from the
+    sweep's seam a point on a ray projects back to its (azimuth, elevation)."""
+    rng = np.random.default_rng(4)
+    be = synth.beams_uniform(rng, 8, -15, 10)
+    s = synth.lidar(be, 64, R_sw=synth.yaw_lidar_pose(0.7), origin=[1.0, 0.5, 0.2], n_phi=2, max_per_tile=16)
+    s = synth.spinning(s, synth.yaw_lidar_pose(0.9), np.array([2.0, 0.8, 0.2], np.float32))
+    s["rs_iters"] = 40
+    d = s["ray_dir"].astype(np.float64)
+    o = s["ray_org"].astype(np.float64)
+    uv, ok = oracle.project_points(s, (o + 9.0 * d).T)
+    a = np.tile(np.arange(64), 8)
+    b = np.repeat(np.arange(8), 64)
+    keep = (a > 1) & (a < 62)
+    assert ok.all()
+    np.testing.assert_allclose(uv[keep, 0], 2 * np.pi * a[keep] / 64, atol=2e-6)
+    np.testing.assert_allclose(uv[keep, 1], np.sort(be).astype(np.float64)[b[keep]], atol=2e-6)
+
+
+def test_moving_sensor_without_motion_equals_static():
+    """A 'moving' camera whose two poses coincide renders what the static camera renders."""
+    g, s = synth.scene_pinhole_small(3, n=600)
+    m = synth.rolling_shutter(s, s["R_sw"], s["origin"])
+    _, la, a = oracle.render(g, s)
+    _, lb, b = oracle.render(g, m)
+    assert la["n_pairs"] == lb["n_pairs"] and np.array_equal(la["pair_gauss"], lb["pair_gauss"])
+    for k in ("feat", "depth", "alpha"):   # the moving table's rays differ by float32 rounding
+        np.testing.assert_allclose(a[k], b[k], rtol=2e-6, atol=1e-6)
+
+
+def test_per_ray_origin_closed_form():
+    """One isotropic particle seen by a translating rolling-shutter camera: every ray uses its
+    own origin, alpha_i = sigma exp(-|(mu - o_i) x d_i|^2 / (2 s^2)) (Eq. 1, 3D response)."""
+    s = synth.pinhole(48, 48, 45.0, 45.0)
+    s = synth.rolling_shutter(s, s["R_sw"], np.array([0.25, 0.0, 0.0], np.float32))
+    mu = np.array([[0.1], [-0.05], [3.0]])
+    g = synth.particles(np.random.default_rng(0), mu, 0.2, 0.2, 0, synth.FEAT_CAMERA,
+                        dc=synth.camera_rgb_dc(np.array([[0.9], [0.4], [0.2]])))
+    g["log_scale"][:] = np.float32(np.log(0.2))
+    g["opacity_logit"][:] = np.float32(np.log(0.3 / 0.7))
+    sigma = 1.0 / (1.0 + np.exp(-np.float64(g["opacity_logit"][0])))
+    sc = np.exp(np.float64(g["log_scale"][0, 0]))
+    _, lists, out = oracle.render(g, s)
+    d = s["ray_dir"].astype(np.float64).T
+    v = mu.ravel().astype(np.float32).astype(np.float64)[None] - s["ray_org"].astype(np.float64).T
+    dd = np.sum(d * d, axis=1)
+    tau = np.sum(v * d, axis=1) / dd
+    D2 = np.sum(np.cross(v, d) ** 2, axis=1) / (sc**2 * dd)
+    alpha = np.minimum(sigma * np.exp(-0.5 * D2), 0.99)
+    alpha = np.where(alpha < 1 / 255, 0.0, alpha)
+    hit = out["n_proc"] > 0
+    assert (alpha > 0).sum() > 100 and np.all(alpha[~hit] == 0)
+    np.testing.assert_allclose(out["alpha"], alpha, atol=1e-13)
+    np.testing.assert_allclose(out["depth"], tau * alpha, atol=1e-12)
