@@ -110,6 +110,20 @@ typedef struct {
   const float* beam_elev_host; /* host [n_beams] radians, sorted ascending (LiDAR set-up only) */
   const float* ray_dir;   /* device [3][R] */
   void* tables;           /* device, LiDAR tiling + summed-area table */
+  /* Time-dependent sensor (Sec. 3.2 and its appendix on time-dependent effects: sensor motion
+   * inside the projection, each ray at its own time).  moving = 0: a static sensor, the rest
+   * is ignored.  moving = 1: (R_sw, origin) is the pose at frame time 0 and (R_sw1, origin1)
+   * at time 1; in between the origin moves linearly and the rotation by spherical linear
+   * interpolation (shorter arc).  Camera row v is read out at t = v / height (rolling
+   * shutter), LiDAR azimuth phi at t = phi / (2 pi).  A sigma point is projected with the pose
+   * at t = 1/2, then rs_iters - 1 more times with the pose at the time of its previous
+   * projection.  ray_org (device [3][R]) holds every ray's origin o(t_i); ray_dir its
+   * direction at t_i.  Not for UT_ORTHO. */
+  int32_t moving;
+  float R_sw1[9];
+  float origin1[3];
+  const float* ray_org;   /* device [3][R], moving sensors only */
+  int32_t rs_iters;       /* 1..64 */
 } ut_sensor;
 
 /* Compositing cut-offs (Eq. 1 practice): skip alpha < alpha_min, clamp alpha at

@@ -20,6 +20,7 @@ int camera_tiles_y(const ut_sensor* s) { return (s->height + UT_CAMERA_TILE - 1)
 
 bool sensor_ok(const ut_sensor* s) {
   if (!s || !s->ray_dir) return false;
+  if (s->moving && (!s->ray_org || s->rs_iters < 1 || s->rs_iters > 64 || s->kind == UT_ORTHO)) return false;
   if (s->kind == UT_LIDAR)
     return s->n_beams > 0 && s->n_az > 0 && s->n_phi > 0 && s->n_phi <= UT_MAX_ELEV_TILES &&
            s->n_theta > 0 && s->tables && s->max_tile_rays > 0 && s->max_tile_rays <= UT_MAX_LIDAR_TILE_RAYS &&
@@ -33,6 +34,27 @@ bool gaussians_ok(const ut_gaussians* g) {
   return g && g->n >= 0 && g->sh_degree >= 0 && g->sh_degree <= 3 &&
          (g->feat_kind == UT_FEAT_CAMERA || g->feat_kind == UT_FEAT_LIDAR) &&
          (g->n == 0 || (g->mean && g->quat && g->log_scale && g->opacity_logit && g->feat));
+}
+
+// Unit quaternion (w, x, y, z) of a (float32, near-orthonormal) rotation matrix, from the
+// largest of the four diagonal combinations for conditioning.
+void rotation_quaternion(const float Rf[9], double q[4]) {
+  double m[9];
+  for (int i = 0; i < 9; ++i) m[i] = Rf[i];
+  const double tr = m[0] + m[4] + m[8];
+  const double c[4] = {1 + tr, 1 + m[0] - m[4] - m[8], 1 - m[0] + m[4] - m[8], 1 - m[0] - m[4] + m[8]};
+  int b = 0;
+  for (int i = 1; i < 4; ++i)
+    if (c[i] > c[b]) b = i;
+  const double r = std::sqrt(c[b]), h = 0.5 / r;
+  switch (b) {
+    case 0: q[0] = 0.5 * r; q[1] = (m[7] - m[5]) * h; q[2] = (m[2] - m[6]) * h; q[3] = (m[3] - m[1]) * h; break;
+    case 1: q[1] = 0.5 * r; q[0] = (m[7] - m[5]) * h; q[2] = (m[1] + m[3]) * h; q[3] = (m[2] + m[6]) * h; break;
+    case 2: q[2] = 0.5 * r; q[0] = (m[2] - m[6]) * h; q[1] = (m[1] + m[3]) * h; q[3] = (m[5] + m[7]) * h; break;
+    default: q[3] = 0.5 * r; q[0] = (m[3] - m[1]) * h; q[1] = (m[2] + m[6]) * h; q[2] = (m[5] + m[7]) * h; break;
+  }
+  const double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int i = 0; i < 4; ++i) q[i] /= n;
 }
 
 SensorK make_sensor_k(const ut_sensor* s) {
@@ -63,6 +85,22 @@ SensorK make_sensor_k(const ut_sensor* s) {
   }
   k.super_x = (k.tiles_x + kSuper - 1) / kSuper;
   k.super_y = (k.tiles_y + kSuper - 1) / kSuper;
+  if (s->moving) {
+    k.moving = 1;
+    k.rs_iters = s->rs_iters;
+    k.ray_org = s->ray_org;
+    for (int i = 0; i < 3; ++i) k.o1[i] = s->origin1[i];
+    rotation_quaternion(s->R_sw, k.q0);
+    rotation_quaternion(s->R_sw1, k.q1);
+    double dot = 0;
+    for (int i = 0; i < 4; ++i) dot += k.q0[i] * k.q1[i];
+    if (dot < 0) {   // the shorter arc
+      for (int i = 0; i < 4; ++i) k.q1[i] = -k.q1[i];
+      dot = -dot;
+    }
+    k.slerp_th = dot < 1.0 - 1e-12 ? std::acos(std::min(dot, 1.0)) : 0.0;
+    k.slerp_isin = k.slerp_th > 0 ? 1.0 / std::sin(k.slerp_th) : 0.0;
+  }
   return k;
 }
 

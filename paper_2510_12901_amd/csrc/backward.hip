@@ -22,7 +22,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int BLOCK>
+template <int BLOCK, bool MOVING>
 __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __restrict__ rec,
                                                      const uint32_t* __restrict__ gauss,
                                                      const uint32_t* __restrict__ ranges, int n_tiles,
@@ -39,7 +39,8 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
   const uint32_t start = ranges[tile];
   const long long ray = tile_ray(s, tile, threadIdx.x);
   const long long R = s.n_rays;
-  const double ox = s.o[0], oy = s.o[1], oz = s.o[2];
+  double ox = s.o[0], oy = s.o[1], oz = s.o[2];   // this ray's origin (moving sensors: its own)
+  double ex = 0, ey = 0, ez = 0;                  // ... minus the sensor origin
   double dx = 0, dy = 0, dz = 0;
   uint32_t np = 0;
   double T = 1.0, gf0 = 0, gf1 = 0, gf2 = 0, gdep = 0, gom = 0;
@@ -66,12 +67,22 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
   // the forward's tile cone, rebuilt from the same rays: entries it drops are skipped here too
   const bool has_ray = ray >= 0 && (dx != 0 || dy != 0 || dz != 0);
+  constexpr bool mv = MOVING;
+  if (mv && has_ray) {
+    ox = s.ray_org[ray];
+    oy = s.ray_org[R + ray];
+    oz = s.ray_org[2 * R + ray];
+    ex = ox - s.o[0], ey = oy - s.o[1], ez = oz - s.o[2];
+  }
+  double emax = __builtin_sqrt(__builtin_fma(ex, ex, __builtin_fma(ey, ey, ez * ez)));
   double ux, uy, uz, sn;
   {
     const double il = has_ray ? rcp_f64(__builtin_sqrt(__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)))) : 0.0;
     tile_cone_axis<BLOCK>(dx * il, dy * il, dz * il, red, wave, lane, ux, uy, uz, sn);
   }
-  tile_cone_finish<BLOCK>(has_ray ? cone_cos(ux, uy, uz, dx, dy, dz) : 1.0, sn, ux, uy, uz, red, wave, lane, cone);
+  if (mv) emax = -block_reduce<BLOCK>(-emax, true, red[0], wave, lane);
+  tile_cone_finish<BLOCK>(has_ray ? cone_cos(ux, uy, uz, dx, dy, dz) : 1.0, sn, ux, uy, uz, red, wave, lane, cone,
+                          mv ? emax : 0.0);
   const bool cull = cone.on != 0;
   if (threadIdx.x == 0) s_max = 0;
   __syncthreads();
@@ -102,8 +113,14 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
 #pragma unroll
       for (int k = 0; k < UT_ACC_FLOATS; ++k) g[k] = 0.0;
       if (j < (int)np) {
-        const PairGeom q = pair_geometry(r, dx, dy, dz);
-        const PairResp pr = pair_response(r, q);
+        double am[3];
+        const double* ac = r.a;   // whitened centre seen from this ray's origin
+        if (mv) {
+          pair_centre(r, ex, ey, ez, am);
+          ac = am;
+        }
+        const PairGeom q = pair_geometry(r, ac, dx, dy, dz);
+        const PairResp pr = pair_response(ac, q);
         const double tau = pr.tau;
         if (!pair_cut(q, cut_threshold(r.log_sigma, prm.log_alpha_min)) && tau >= s.near_) {
           const double a = pair_alpha(r, pr, kExp2Frac);
@@ -129,9 +146,9 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
             }
             // B = M^T M: B u = M^T r and B d = M^T w with u = mu - o - t* d
             const double* M = r.m;
-            const double rx = __builtin_fma(-tau, q.w[0], r.a[0]);   // M (mu - o - t* d)
-            const double ry = __builtin_fma(-tau, q.w[1], r.a[1]);
-            const double rz = __builtin_fma(-tau, q.w[2], r.a[2]);
+            const double rx = __builtin_fma(-tau, q.w[0], ac[0]);   // M (mu - o - t* d)
+            const double ry = __builtin_fma(-tau, q.w[1], ac[1]);
+            const double rz = __builtin_fma(-tau, q.w[2], ac[2]);
             const double bux = M[0] * rx + M[3] * ry + M[6] * rz;
             const double buy = M[1] * rx + M[4] * ry + M[7] * rz;
             const double buz = M[2] * rx + M[5] * ry + M[8] * rz;
@@ -294,12 +311,22 @@ hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const u
   const int n_tiles = s.tiles_x * s.tiles_y;
   const Record* rec = reinterpret_cast<const Record*>(p.records);
   if (n_tiles > 0) {
+#define UT_LAUNCH_BACKWARD(B)                                                                              \
+  do {                                                                                                     \
+    if (s.moving)                                                                                          \
+      hipLaunchKernelGGL((k_backward<B, true>), dim3(n_tiles), dim3(B), 0, st, s, rec, lists.gauss,        \
+                         lists.ranges, n_tiles, prm, fwd, up, g.mean, acc, g.n);                            \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_backward<B, false>), dim3(n_tiles), dim3(B), 0, st, s, rec, lists.gauss,       \
+                         lists.ranges, n_tiles, prm, fwd, up, g.mean, acc, g.n);                            \
+  } while (0)
     if (s.kind != UT_LIDAR || max_tile_rays > 128)
-      hipLaunchKernelGGL(k_backward<256>, dim3(n_tiles), dim3(256), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, fwd, up, g.mean, acc, g.n);
+      UT_LAUNCH_BACKWARD(256);
     else if (max_tile_rays > 64)
-      hipLaunchKernelGGL(k_backward<128>, dim3(n_tiles), dim3(128), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, fwd, up, g.mean, acc, g.n);
+      UT_LAUNCH_BACKWARD(128);
     else
-      hipLaunchKernelGGL(k_backward<64>, dim3(n_tiles), dim3(64), 0, st, s, rec, lists.gauss, lists.ranges, n_tiles, prm, fwd, up, g.mean, acc, g.n);
+      UT_LAUNCH_BACKWARD(64);
+#undef UT_LAUNCH_BACKWARD
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

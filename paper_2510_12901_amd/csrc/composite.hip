@@ -44,7 +44,7 @@ struct CompositeShared {
   TileCone cone;
 };
 
-template <int BLOCK, int RPL, int BATCH, bool STATS = false>
+template <int BLOCK, int RPL, int BATCH, bool STATS = false, bool MOVING = false>
 __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* __restrict__ rec,
                                                const uint2* __restrict__ trect,
                                                const uint32_t* __restrict__ bgauss,
@@ -58,6 +58,8 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
   const uint32_t start = branges[sid], end = branges[n_super + sid];
   long long ray[RPL];
   double dx[RPL], dy[RPL], dz[RPL], T[RPL], f0[RPL], f1[RPL], f2[RPL], dep[RPL];
+  double ex[RPL], ey[RPL], ez[RPL];   // moving sensor: ray origin minus the sensor origin
+  double emax = 0.0;
   uint32_t nproc[RPL], nvisit[RPL], npass[RPL];
   bool rdone[RPL];
   bool done = true;
@@ -73,6 +75,15 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
     }
     rdone[k] = !(ray[k] >= 0 && (dx[k] != 0 || dy[k] != 0 || dz[k] != 0));
     done = done && rdone[k];
+    ex[k] = ey[k] = ez[k] = 0;
+    if constexpr (MOVING) {
+      if (!rdone[k]) {
+        ex[k] = (double)s.ray_org[ray[k]] - s.o[0];
+        ey[k] = (double)s.ray_org[s.n_rays + ray[k]] - s.o[1];
+        ez[k] = (double)s.ray_org[2 * s.n_rays + ray[k]] - s.o[2];
+        emax = fmax(emax, __builtin_sqrt(__builtin_fma(ex[k], ex[k], __builtin_fma(ey[k], ey[k], ez[k] * ez[k]))));
+      }
+    }
     T[k] = 1.0;
     f0[k] = f1[k] = f2[k] = dep[k] = 0;
     nproc[k] = nvisit[k] = npass[k] = 0;
@@ -94,7 +105,8 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
 #pragma unroll
   for (int k = 0; k < RPL; ++k)
     if (!rdone[k]) cmin = fmin(cmin, cone_cos(ux, uy, uz, dx[k], dy[k], dz[k]));
-  tile_cone_finish<BLOCK>(cmin, sn, ux, uy, uz, sm.red, wave, lane, sm.cone);
+  if constexpr (MOVING) emax = -block_reduce<BLOCK>(-emax, true, sm.red[0], wave, lane);
+  tile_cone_finish<BLOCK>(cmin, sn, ux, uy, uz, sm.red, wave, lane, sm.cone, emax);
   const bool cull = sm.cone.on != 0;
 
   uint32_t pos = start, head = 0, n_cand = 0, n_hits = 0;   // uniform across the workgroup
@@ -147,11 +159,17 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
           if (rdone[k]) continue;
-          const PairGeom q = pair_geometry(r, dx[k], dy[k], dz[k]);
+          double am[3];
+          const double* a = r.a;
+          if constexpr (MOVING) {
+            pair_centre(r, ex[k], ey[k], ez[k], am);
+            a = am;
+          }
+          const PairGeom q = pair_geometry(r, a, dx[k], dy[k], dz[k]);
           if constexpr (STATS) ++nvisit[k];
           if (pair_cut(q, cut_threshold(r.log_sigma, prm.log_alpha_min))) continue;
           if constexpr (STATS) ++npass[k];
-          const PairResp pr = pair_response(r, q);
+          const PairResp pr = pair_response(a, q);
           const double tau = pr.tau;
           if (tau < s.near_) continue;
           const double alpha = __builtin_fmin(pair_alpha(r, pr, sm.etab), prm.alpha_max);
@@ -210,7 +228,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n_tiles) {
   return t < n_tiles ? t : -1;
 }
 
-template <int BLOCK, int RPL, int BATCH, bool STATS>
+template <int BLOCK, int RPL, int BATCH, bool STATS, bool MOVING>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void k_composite(SensorK s, const Record* __restrict__ rec,
                                                       const uint2* __restrict__ trect,
                                                       const uint32_t* __restrict__ bgauss,
@@ -219,7 +237,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
   __shared__ CompositeShared<BLOCK, RPL, BATCH> sm;
   const int tile = xcd_tile(blockIdx.x, n_tiles);
   if (tile < 0) return;
-  composite_tile<BLOCK, RPL, BATCH, STATS>(s, rec, trect, bgauss, branges, tile, s.super_x * s.super_y, prm, out, sm);
+  composite_tile<BLOCK, RPL, BATCH, STATS, MOVING>(s, rec, trect, bgauss, branges, tile, s.super_x * s.super_y, prm, out, sm);
 }
 
 // Persistent batched compositing: workgroups pull (request, tile) items from a counter.
@@ -237,8 +255,14 @@ __global__ __launch_bounds__(kCamBlock) void k_composite_batch(const BatchItemK*
     int it = 0;
     while (it + 1 < n_items && (uint32_t)items[it + 1].tile_base <= w) ++it;
     const BatchItemK& I = items[it];
-    composite_tile<kCamBlock, kCamRpl, kCamBatch>(I.s, I.rec, I.trect, I.gauss, I.ranges, (int)(w - I.tile_base),
-                        I.s.super_x * I.s.super_y, prm, I.out, sm);
+    if (I.s.moving)
+      composite_tile<kCamBlock, kCamRpl, kCamBatch, false, true>(I.s, I.rec, I.trect, I.gauss, I.ranges,
+                                                                  (int)(w - I.tile_base), I.s.super_x * I.s.super_y,
+                                                                  prm, I.out, sm);
+    else
+      composite_tile<kCamBlock, kCamRpl, kCamBatch, false, false>(I.s, I.rec, I.trect, I.gauss, I.ranges,
+                                                                   (int)(w - I.tile_base), I.s.super_x * I.s.super_y,
+                                                                   prm, I.out, sm);
   }
 }
 
@@ -253,14 +277,19 @@ hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, con
   const Record* rec = reinterpret_cast<const Record*>(p.records);
   const uint2* tr = reinterpret_cast<const uint2*>(p.trect);
   const bool stats = out.n_visit != nullptr || out.n_pass != nullptr;
-#define UT_LAUNCH_COMPOSITE(B, R, N)                                                                        \
-  do {                                                                                                    \
-    if (stats)                                                                                            \
-      hipLaunchKernelGGL((k_composite<B, R, N, true>), dim3(grid), dim3(B), 0, st, s, rec, tr, bins.gauss,  \
-                         bins.ranges, n_tiles, prm, out);                                                 \
-    else                                                                                                  \
-      hipLaunchKernelGGL((k_composite<B, R, N, false>), dim3(grid), dim3(B), 0, st, s, rec, tr, bins.gauss, \
-                         bins.ranges, n_tiles, prm, out);                                                 \
+  const bool mv = s.moving != 0;
+#define UT_LAUNCH_COMPOSITE_V(B, R, N, ST, MV)                                                                \
+  hipLaunchKernelGGL((k_composite<B, R, N, ST, MV>), dim3(grid), dim3(B), 0, st, s, rec, tr, bins.gauss,      \
+                     bins.ranges, n_tiles, prm, out)
+#define UT_LAUNCH_COMPOSITE(B, R, N)                        \
+  do {                                                      \
+    if (stats) {                                            \
+      if (mv) UT_LAUNCH_COMPOSITE_V(B, R, N, true, true);   \
+      else UT_LAUNCH_COMPOSITE_V(B, R, N, true, false);     \
+    } else {                                                \
+      if (mv) UT_LAUNCH_COMPOSITE_V(B, R, N, false, true);  \
+      else UT_LAUNCH_COMPOSITE_V(B, R, N, false, false);    \
+    }                                                       \
   } while (0)
   if (s.kind == UT_LIDAR && max_tile_rays > 256)
     UT_LAUNCH_COMPOSITE(256, 2, 256);   // LiDAR tiles of up to 512 rays: two rays per lane
@@ -271,6 +300,7 @@ hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, con
   else
     UT_LAUNCH_COMPOSITE(64, 1, 64);
 #undef UT_LAUNCH_COMPOSITE
+#undef UT_LAUNCH_COMPOSITE_V
   return hipGetLastError();
 }
 

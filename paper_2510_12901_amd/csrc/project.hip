@@ -12,13 +12,10 @@
 namespace ut {
 namespace {
 
-// Sensor map g(x) of one world point: (u, v) and validity (see utrast.h for each model).
+// Sensor map of one point in sensor axes: (u, v) and validity (see utrast.h for each model).
 template <int KIND>
-__device__ __forceinline__ bool project_point(const SensorK& s, const double xw[3], double& u, double& v) {
-  const double dx = xw[0] - s.o[0], dy = xw[1] - s.o[1], dz = xw[2] - s.o[2];
-  const double x = s.R[0] * dx + s.R[1] * dy + s.R[2] * dz;
-  const double y = s.R[3] * dx + s.R[4] * dy + s.R[5] * dz;
-  const double z = s.R[6] * dx + s.R[7] * dy + s.R[8] * dz;
+__device__ __forceinline__ bool project_sensor(const SensorK& s, double x, double y, double z, double& u,
+                                               double& v) {
   if constexpr (KIND == UT_PINHOLE) {
     if (!(z > s.near_)) return false;
     const double iz = 1.0 / z;
@@ -60,6 +57,33 @@ __device__ __forceinline__ bool project_point(const SensorK& s, const double xw[
   return true;
 }
 
+// Sensor map g(x) of one world point.  A moving sensor observes the point at the time of the
+// row (camera, t = v / height) or azimuth (LiDAR, t = phi / 2 pi) it falls on: the point is
+// projected with the pose at t = 1/2 and then rs_iters - 1 more times with the pose at the
+// time of its previous projection (see utrast.h).
+template <int KIND, bool MOVING>
+__device__ __forceinline__ bool project_point(const SensorK& s, const double xw[3], double& u, double& v) {
+  if constexpr (!MOVING) {
+    const double dx = xw[0] - s.o[0], dy = xw[1] - s.o[1], dz = xw[2] - s.o[2];
+    const double x = s.R[0] * dx + s.R[1] * dy + s.R[2] * dz;
+    const double y = s.R[3] * dx + s.R[4] * dy + s.R[5] * dz;
+    const double z = s.R[6] * dx + s.R[7] * dy + s.R[8] * dz;
+    return project_sensor<KIND>(s, x, y, z, u, v);
+  } else {
+    double t = 0.5;
+    for (int it = 0; it < s.rs_iters; ++it) {
+      double q[4], o[3], rel[3], p[3];
+      pose_at(s, t, q, o);
+      rel[0] = xw[0] - o[0], rel[1] = xw[1] - o[1], rel[2] = xw[2] - o[2];
+      quat_rotate(q, rel, p);
+      if (!project_sensor<KIND>(s, p[0], p[1], p[2], u, v)) return false;
+      if constexpr (KIND == UT_LIDAR) t = u * (0.5 / kPi);
+      else t = fmin(fmax(v / s.height, 0.0), 1.0);
+    }
+    return true;
+  }
+}
+
 // summed-area-table count over inclusive culling cells [x0,x1] x [y0,y1] (Alg. 2)
 __device__ __forceinline__ long sat_count(const SensorK& s, int x0, int x1, int y0, int y1) {
   const long W = s.cull_el + 1;
@@ -82,7 +106,7 @@ __device__ __forceinline__ uint32_t depth_key(float mx, float my, float mz, cons
 // unrolled and issued together instead of one dependent loop trip at a time.  KIND is the
 // sensor model, so each instantiation carries only its own projection code (the LiDAR and
 // fisheye arctangents would otherwise set the register count of every camera).
-template <int DEG, int KIND>
+template <int DEG, int KIND, bool MOVING>
 __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK& s, double ut_a, double ut_b,
                                             double ut_k, Record* __restrict__ rec,
                                             int32_t* __restrict__ rect, uint2* __restrict__ trect,
@@ -133,14 +157,14 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
         const double gam = sqrt(cpl);
         double gu[7], gv[7];
         const double mu[3] = {(double)mx, (double)my, (double)mz};
-        ok = project_point<KIND>(s, mu, gu[0], gv[0]);
+        ok = project_point<KIND, MOVING>(s, mu, gu[0], gv[0]);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
           if (!ok) break;
           const double e0 = gam * sc[j] * Rm[j], e1 = gam * sc[j] * Rm[3 + j], e2 = gam * sc[j] * Rm[6 + j];
           const double pp[3] = {mu[0] + e0, mu[1] + e1, mu[2] + e2};
           const double pm[3] = {mu[0] - e0, mu[1] - e1, mu[2] - e2};
-          ok = project_point<KIND>(s, pp, gu[1 + j], gv[1 + j]) && project_point<KIND>(s, pm, gu[4 + j], gv[4 + j]);
+          ok = project_point<KIND, MOVING>(s, pp, gu[1 + j], gv[1 + j]) && project_point<KIND, MOVING>(s, pm, gu[4 + j], gv[4 + j]);
         }
         if (ok) {
           if constexpr (KIND == UT_LIDAR) {
@@ -291,20 +315,20 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
 // spilling and runs best at three waves per SIMD; the camera kernels run best at two waves,
 // where the compiler keeps all (DEG+1)^2 x 3 coefficient loads in flight (left to itself it
 // trades them for a third wave, and the pinhole then takes over twice as long).
-template <int DEG, int KIND>
+template <int DEG, int KIND, bool MOVING>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_project_capped(
     ut_gaussians g, SensorK s, double ut_a, double ut_b, double ut_k, Record* __restrict__ rec,
     int32_t* __restrict__ rect, uint2* __restrict__ trect, uint32_t* __restrict__ key,
     uint32_t* __restrict__ count, float* __restrict__ moments, uint32_t* __restrict__ n_culled) {
-  project_all<DEG, KIND>(g, s, ut_a, ut_b, ut_k, rec, rect, trect, key, count, moments, n_culled);
+  project_all<DEG, KIND, MOVING>(g, s, ut_a, ut_b, ut_k, rec, rect, trect, key, count, moments, n_culled);
 }
 
-template <int DEG, int KIND>
+template <int DEG, int KIND, bool MOVING>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_project(
     ut_gaussians g, SensorK s, double ut_a, double ut_b, double ut_k, Record* __restrict__ rec,
     int32_t* __restrict__ rect, uint2* __restrict__ trect, uint32_t* __restrict__ key,
     uint32_t* __restrict__ count, float* __restrict__ moments, uint32_t* __restrict__ n_culled) {
-  project_all<DEG, KIND>(g, s, ut_a, ut_b, ut_k, rec, rect, trect, key, count, moments, n_culled);
+  project_all<DEG, KIND, MOVING>(g, s, ut_a, ut_b, ut_k, rec, rect, trect, key, count, moments, n_culled);
 }
 
 }  // namespace
@@ -317,15 +341,20 @@ hipError_t launch_project(const ut_gaussians& g, const SensorK& s, const double 
   const int blocks = std::min((g.n + 255) / 256, 2048);
   Record* rec = reinterpret_cast<Record*>(out.records);
   uint2* tr = reinterpret_cast<uint2*>(out.trect);
-#define UT_LAUNCH_PROJECT(KERNEL, D, K)                                                                \
-  hipLaunchKernelGGL((KERNEL<D, K>), dim3(blocks), dim3(256), 0, st, g, s, abk[0], abk[1], abk[2], rec, \
+#define UT_LAUNCH_PROJECT(KERNEL, D, K, MV)                                                                \
+  hipLaunchKernelGGL((KERNEL<D, K, MV>), dim3(blocks), dim3(256), 0, st, g, s, abk[0], abk[1], abk[2], rec, \
                      out.rect, tr, out.key, out.count, out.moments, out.n_culled)
-#define UT_LAUNCH_PROJECT_KIND(D)                                          \
-  switch (s.kind) {                                                        \
-    case UT_PINHOLE: UT_LAUNCH_PROJECT(k_project, D, UT_PINHOLE); break;   \
-    case UT_FISHEYE: UT_LAUNCH_PROJECT(k_project, D, UT_FISHEYE); break;   \
-    case UT_LIDAR: UT_LAUNCH_PROJECT(k_project_capped, D, UT_LIDAR); break; \
-    default: UT_LAUNCH_PROJECT(k_project, D, UT_ORTHO); break;             \
+#define UT_LAUNCH_PROJECT_MV(KERNEL, D, K)                      \
+  do {                                                          \
+    if (s.moving) UT_LAUNCH_PROJECT(KERNEL, D, K, true);        \
+    else UT_LAUNCH_PROJECT(KERNEL, D, K, false);                \
+  } while (0)
+#define UT_LAUNCH_PROJECT_KIND(D)                                                    \
+  switch (s.kind) {                                                                  \
+    case UT_PINHOLE: UT_LAUNCH_PROJECT_MV(k_project, D, UT_PINHOLE); break;          \
+    case UT_FISHEYE: UT_LAUNCH_PROJECT_MV(k_project, D, UT_FISHEYE); break;          \
+    case UT_LIDAR: UT_LAUNCH_PROJECT_MV(k_project_capped, D, UT_LIDAR); break;       \
+    default: UT_LAUNCH_PROJECT(k_project, D, UT_ORTHO, false); break;                \
   }
   switch (g.sh_degree) {
     case 0: UT_LAUNCH_PROJECT_KIND(0); break;
@@ -334,6 +363,7 @@ hipError_t launch_project(const ut_gaussians& g, const SensorK& s, const double 
     default: UT_LAUNCH_PROJECT_KIND(3); break;
   }
 #undef UT_LAUNCH_PROJECT_KIND
+#undef UT_LAUNCH_PROJECT_MV
 #undef UT_LAUNCH_PROJECT
   return hipGetLastError();
 }

@@ -16,6 +16,7 @@ namespace ut {
 struct TileCone {
   double u[3], e1[3], e2[3];
   double cos2t, sin2t;
+  double emax;   // largest distance of a ray origin from the sensor origin (moving sensors)
   int on;
 };
 
@@ -58,9 +59,11 @@ __device__ __forceinline__ void tile_cone_axis(double sx, double sy, double sz, 
 // minimum, 1 when it has no ray); thread 0 writes the cone, then the block synchronises.
 template <int BLOCK>
 __device__ __forceinline__ void tile_cone_finish(double cmin, double sn, double ux, double uy, double uz,
-                                                 double (&red)[4][BLOCK / 64], int wave, int lane, TileCone& tc) {
+                                                 double (&red)[4][BLOCK / 64], int wave, int lane, TileCone& tc,
+                                                 double emax = 0.0) {
   cmin = block_reduce<BLOCK>(cmin, true, red[3], wave, lane);
   if (threadIdx.x == 0) {
+    tc.emax = emax;
     const double ct = cmin - 1e-9;                       // widen for rounding
     tc.on = (sn > 0.0 && ct > 0.7071067811865476) ? 1 : 0;
     const double st = __builtin_sqrt(1.0 - ct * ct);
@@ -89,13 +92,25 @@ __device__ __forceinline__ void tile_cone_finish(double cmin, double sn, double 
 // form on span(e1, e2).  In psi = 2 phi this is P + Rc cos(psi) - B sin(psi), minimised over
 // psi in [0, 2 theta] in closed form.  The threshold carries 0.05 of slack over the per-ray
 // cut so that rounding cannot drop an entry that a ray would keep; the dropped entries are
-// exactly ones every ray of the tile would skip, so outputs are unchanged.
+// exactly ones every ray of the tile would skip, so outputs are unchanged.  For a moving
+// sensor the rays start from different origins; the threshold grows by their spread.
 __device__ __forceinline__ bool cone_rejects(const Record* __restrict__ rp, const TileCone& tc,
                                              double log_alpha_min) {
-  const double cut = cut_threshold(rp->log_sigma, log_alpha_min) + 0.05;
+  double cut = cut_threshold(rp->log_sigma, log_alpha_min);
   double m[9], a[3];
 #pragma unroll
   for (int i = 0; i < 9; ++i) m[i] = rp->m[i];
+  if (tc.emax > 0.0) {
+    // Rays from origins o + e, |e| <= emax: the whitened centre moves by M e, |M e| <= |M|_F emax,
+    // so the distance to each ray's line is at least the one from o minus that.
+    if (cut < 0.0) return true;   // sigma < alpha_min: no ray reaches it
+    double mf = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) mf = __builtin_fma(m[i], m[i], mf);
+    const double r = __builtin_sqrt(cut) + __builtin_sqrt(mf) * tc.emax;
+    cut = r * r;
+  }
+  cut += 0.05;
 #pragma unroll
   for (int i = 0; i < 3; ++i) a[i] = rp->a[i];
   double w[3][3], x[3][3];   // w_k = M v_k and x_k = a x w_k for v = (u, e1, e2)

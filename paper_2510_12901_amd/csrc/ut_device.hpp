@@ -51,6 +51,13 @@ struct SensorK {
   const float* ray_dir;     // [3][R]
   long long n_rays;
   int super_x, super_y;     // super-tile grid
+  // moving sensor: unit quaternions of the poses at t = 0 and 1 (shorter arc), the slerp
+  // angle and 1 / sin of it (0: the rotations coincide, interpolate linearly), end origin,
+  // per-ray origins and the fixed-point iteration count
+  int moving, rs_iters;
+  double q0[4], q1[4], slerp_th, slerp_isin;
+  double o1[3];
+  const float* ray_org;     // [3][R]
 };
 
 // Byte layout of the LiDAR device tables (bounds, beam_start, sat), 256-byte aligned parts.
@@ -109,6 +116,37 @@ __device__ __forceinline__ double rcp_f64(double x) {
   return __builtin_fma(r, e, r);
 }
 
+// Pose of a moving sensor at frame time t (the origin linear in t, the rotation slerped
+// between the unit quaternions q0 and q1): the world->sensor rotation as a unit quaternion.
+__device__ __forceinline__ void pose_at(const SensorK& s, double t, double q[4], double o[3]) {
+  double w0 = 1.0 - t, w1 = t;
+  if (s.slerp_isin > 0) {
+    w0 = sin((1.0 - t) * s.slerp_th) * s.slerp_isin;
+    w1 = sin(t * s.slerp_th) * s.slerp_isin;
+  }
+  double n = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    q[i] = __builtin_fma(w0, s.q0[i], w1 * s.q1[i]);
+    n = __builtin_fma(q[i], q[i], n);
+  }
+  const double in = 1.0 / sqrt(n);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) q[i] *= in;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) o[i] = __builtin_fma(1.0 - t, s.o[i], t * s.o1[i]);
+}
+
+// R(q) v for a unit quaternion q = (w, u): v + 2 w (u x v) + 2 u x (u x v).
+__device__ __forceinline__ void quat_rotate(const double q[4], const double v[3], double r[3]) {
+  const double w = q[0], ux = q[1], uy = q[2], uz = q[3];
+  const double cx = uy * v[2] - uz * v[1], cy = uz * v[0] - ux * v[2], cz = ux * v[1] - uy * v[0];
+  const double dx = uy * cz - uz * cy, dy = uz * cx - ux * cz, dz = ux * cy - uy * cx;
+  r[0] = v[0] + 2.0 * (w * cx + dx);
+  r[1] = v[1] + 2.0 * (w * cy + dy);
+  r[2] = v[2] + 2.0 * (w * cz + dz);
+}
+
 // Response geometry of one (ray, particle) pair in the particle's whitened frame, where the
 // particle is the unit ball: w = M d and a = M (mu - o).  The whitened ray passes the centre at
 // squared distance D^2 = |a x w|^2 / |w|^2 and reaches the maximum response at
@@ -121,14 +159,17 @@ struct PairGeom {
   double cc;     // |a x w|^2 = D^2 w.w
 };
 
-__device__ __forceinline__ PairGeom pair_geometry(const Record& c, double dx, double dy, double dz) {
+// a is the whitened centre seen from the ray's origin: the record's a = M (mu - o) for a
+// static sensor, pair_centre() for a ray with its own origin.
+__device__ __forceinline__ PairGeom pair_geometry(const Record& c, const double a[3], double dx, double dy,
+                                                  double dz) {
   PairGeom p;
   p.w[0] = __builtin_fma(c.m[0], dx, __builtin_fma(c.m[1], dy, c.m[2] * dz));
   p.w[1] = __builtin_fma(c.m[3], dx, __builtin_fma(c.m[4], dy, c.m[5] * dz));
   p.w[2] = __builtin_fma(c.m[6], dx, __builtin_fma(c.m[7], dy, c.m[8] * dz));
-  const double cx = __builtin_fma(c.a[1], p.w[2], -(c.a[2] * p.w[1]));
-  const double cy = __builtin_fma(c.a[2], p.w[0], -(c.a[0] * p.w[2]));
-  const double cz = __builtin_fma(c.a[0], p.w[1], -(c.a[1] * p.w[0]));
+  const double cx = __builtin_fma(a[1], p.w[2], -(a[2] * p.w[1]));
+  const double cy = __builtin_fma(a[2], p.w[0], -(a[0] * p.w[2]));
+  const double cz = __builtin_fma(a[0], p.w[1], -(a[1] * p.w[0]));
   p.ww = __builtin_fma(p.w[0], p.w[0], __builtin_fma(p.w[1], p.w[1], p.w[2] * p.w[2]));
   p.cc = __builtin_fma(cx, cx, __builtin_fma(cy, cy, cz * cz));
   return p;
@@ -149,13 +190,21 @@ struct PairResp {
   double D2;    // squared whitened distance
 };
 
-__device__ __forceinline__ PairResp pair_response(const Record& c, const PairGeom& q) {
+__device__ __forceinline__ PairResp pair_response(const double a[3], const PairGeom& q) {
   PairResp r;
   r.iww = rcp_f64(q.ww);
-  const double aw = __builtin_fma(c.a[0], q.w[0], __builtin_fma(c.a[1], q.w[1], c.a[2] * q.w[2]));
+  const double aw = __builtin_fma(a[0], q.w[0], __builtin_fma(a[1], q.w[1], a[2] * q.w[2]));
   r.tau = aw * r.iww;
   r.D2 = q.cc * r.iww;
   return r;
+}
+
+// Whitened centre M (mu - o_i) for a ray whose origin o_i lies e = o_i - o from the sensor
+// origin o of the record: a - M e.
+__device__ __forceinline__ void pair_centre(const Record& c, double ex, double ey, double ez, double a[3]) {
+  a[0] = c.a[0] - __builtin_fma(c.m[0], ex, __builtin_fma(c.m[1], ey, c.m[2] * ez));
+  a[1] = c.a[1] - __builtin_fma(c.m[3], ex, __builtin_fma(c.m[4], ey, c.m[5] * ez));
+  a[2] = c.a[2] - __builtin_fma(c.m[6], ex, __builtin_fma(c.m[7], ey, c.m[8] * ez));
 }
 
 // Unclamped opacity of the pair, sigma * exp(-D^2 / 2), evaluated as exp(ln sigma - D^2 / 2).

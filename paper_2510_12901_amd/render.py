@@ -79,6 +79,14 @@ class Sensor:
         c.near_ = float(desc.get("near", 0.1))
         self.ray_dir = torch.as_tensor(np.ascontiguousarray(desc["ray_dir"], np.float32), device=device)
         c.ray_dir = self.ray_dir.data_ptr()
+        self.ray_org = None
+        if desc.get("moving"):
+            self.ray_org = torch.as_tensor(np.ascontiguousarray(desc["ray_org"], np.float32), device=device)
+            c.moving = 1
+            c.R_sw1[:] = [float(x) for x in np.asarray(desc["R_sw1"], np.float32).ravel()]
+            c.origin1[:] = [float(x) for x in np.asarray(desc["origin1"], np.float32)]
+            c.ray_org = self.ray_org.data_ptr()
+            c.rs_iters = int(desc.get("rs_iters", 3))
         self._keep = []
         if c.kind == A.LIDAR:
             be = np.ascontiguousarray(desc["beam_elev"], np.float32)

@@ -52,6 +52,18 @@ def _scene(name):
         g, s = synth.scene_lidar(7, n=20000, n_beams=32, n_az=512, n_phi=4, max_per_tile=M)
         g["mean"] *= np.float32(0.2)
         return g, s
+    if name == "pinhole_rolling_shutter":              # camera translating and yawing during readout
+        g, s = _scene("pinhole_sh3_posed")
+        R1 = synth.yaw_camera_pose(0.92)
+        return g, synth.rolling_shutter(s, R1, s["origin"] + np.array([0.6, -0.3, 0.1], np.float32))
+    if name == "fisheye_rolling_shutter":
+        g, s = _scene("fisheye_small")
+        R1 = synth.yaw_camera_pose(0.12)
+        return g, synth.rolling_shutter(s, R1, s["origin"] + np.array([0.4, 0.0, 0.2], np.float32))
+    if name == "lidar_moving":                         # spinning LiDAR on a moving, turning vehicle
+        g, s = _scene("lidar_posed_m64")
+        R1 = synth.yaw_lidar_pose(2.25)
+        return g, synth.spinning(s, R1, s["origin"] + np.array([1.5, 0.4, 0.0], np.float32))
     if name == "pinhole_wide_aniso":                   # wide field of view, needle/disc particles
         rng = np.random.default_rng(6)                 # (1:1000 axis ratios) close to the camera
         n = 6000
@@ -62,7 +74,8 @@ def _scene(name):
 
 
 SCENES = ["pinhole_128x96", "pinhole_ragged", "pinhole_sh3_posed", "pinhole_wide_aniso", "fisheye_small",
-          "lidar_small", "lidar_nocull", "lidar_posed_m64", "lidar_m128", "lidar_m256", "lidar_m512"]
+          "lidar_small", "lidar_nocull", "lidar_posed_m64", "lidar_m128", "lidar_m256", "lidar_m512",
+          "pinhole_rolling_shutter", "fisheye_rolling_shutter", "lidar_moving"]
 
 
 @pytest.mark.parametrize("name", SCENES)
@@ -209,3 +222,24 @@ def test_large_lidar_tiles_rejected_by_batch_and_adjoint():
     p, bins, out = ut.render(g, s)
     with pytest.raises(A.UtError, match="unsupported"):
         ut.composite_batch([(p, bins, s, out)])
+
+
+def test_batched_composite_with_moving_and_static_sensors():
+    """The batched persistent composite handles a moving sensor's per-ray origins: every output
+    is bit-identical to the plain single-request call."""
+    import torch
+    import paper_2510_12901_amd as ut
+    items, plain = [], []
+    for name in ("pinhole_rolling_shutter", "pinhole_ragged", "lidar_moving"):
+        g_np, s_np = _scene(name)
+        g = ut.GaussianSet.from_numpy(g_np)
+        s = ut.Sensor(s_np)
+        p, bins, a = ut.render(g, s, state=True)
+        b = ut.alloc_out(s, g.mean.device, state=True)
+        items.append((p, bins, s, b))
+        plain.append(a)
+    ut.composite_batch(items)
+    torch.cuda.synchronize()
+    for (p, bins, s, b), a in zip(items, plain):
+        for k in ("feat", "depth", "alpha", "t_final", "n_proc"):
+            assert torch.equal(getattr(a, k), getattr(b, k)), k
