@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--streams", type=int, default=4, help="HIP streams the sensors of a frame are spread over")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-time-dependent", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--served-seconds", type=float, default=3.0)
     ap.add_argument("--vehicles", type=str, default="1,4,8")
@@ -347,6 +348,8 @@ def main():
 
     if not args.no_backward:
         result["backward"] = bench_backward(ut, synth, dev, args)
+    if not args.no_time_dependent:
+        result["time_dependent"] = bench_time_dependent(ut, synth, dev, args)
     if not args.no_served:
         from paper_2510_12901_amd import serve
         result["served"] = serve.bench_served(g, gl, sensors_np, sensors, dev, args, log)
@@ -380,6 +383,57 @@ def bench_backward(ut, synth, dev, args):
     ms = (time.perf_counter() - t0) * 1e3 / n
     return {"workload": "1,000,000 particles, pinhole 1920x1080, forward + adjoint of mean L1",
             "ms_per_step": round(ms, 3), "mrays_per_s": round(s.n_rays / ms / 1e3, 2), "pairs": pipe.n_pairs}
+
+
+def bench_time_dependent(ut, synth, dev, args):
+    """Static vs moving sensors on the 1,000,000-particle pinhole 1920x1080 scene (rolling
+    shutter: 0.5 m sideways and 0.01 rad of yaw during the readout, a side camera of a car at
+    15 m/s filming at 30 frames/s) and the 300,000-particle 128x2048 LiDAR (1.5 m and 0.03 rad over one sweep,
+    15 m/s at 10 Hz).  Each render (projection, binning, sort, compositing) is timed frame by
+    frame (median of K after W warm-up frames)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    out = {}
+    cam_g, cam = synth.scene_pinhole_large(args.seed)
+    lid_g, lid = synth.scene_lidar(args.seed)
+    turn = np.array([[np.cos(0.01), 0.0, -np.sin(0.01)], [0.0, 1.0, 0.0], [np.sin(0.01), 0.0, np.cos(0.01)]])
+    R_cam1 = (turn @ np.asarray(cam["R_sw"], np.float64)).astype(np.float32)   # 0.01 rad about camera y
+    cam_m = synth.rolling_shutter(cam, R_cam1, np.asarray(cam["origin"], np.float32) + np.array([0.5, 0, 0], np.float32))
+    lid_m = synth.spinning(lid, synth.yaw_lidar_pose(0.03), np.array([1.5, 0.0, 0.0], np.float32))
+    for name, g_np, descs in (("pinhole_1920x1080_1M", cam_g, (cam, cam_m)), ("lidar_128x2048_300k", lid_g, (lid, lid_m))):
+        g = ut.GaussianSet.from_numpy(g_np, dev)
+        row = {}
+        for label, d in zip(("static", "moving"), descs):
+            s = ut.Sensor(d, dev)
+            pipe = ut.SensorPipeline(g, s)
+            for _ in range(SETUP_FRAMES + args.warmup):
+                pipe.run(stream)
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(args.steps):
+                t0 = time.perf_counter()
+                pipe.run(stream)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            ms = float(np.median(times)) * 1e3
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(5):
+                pipe.composite_only(stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            o = ut.alloc_out(s, dev, state=True, counters=True)
+            pipe.composite_only(stream, o)
+            torch.cuda.synchronize()
+            row[label] = {"ms_per_frame": round(ms, 3), "mrays_per_s": round(s.n_rays / ms / 1e3, 2),
+                          "composite_ms": round(e0.elapsed_time(e1) / 5, 4), "bin_pairs": pipe.n_pairs,
+                          "evaluated_pairs": int(o.n_visit.to(torch.int64).sum().item()),
+                          "list_positions": int(o.n_proc.to(torch.int64).sum().item())}
+            del o
+            del pipe, s
+        out[name] = row
+        log(f"time-dependent {name}: {json.dumps(row)}")
+    return out
 
 
 def cpu_baseline(g_np, gl_np, sensors_np, log):

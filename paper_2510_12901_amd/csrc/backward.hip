@@ -74,15 +74,25 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
     oz = s.ray_org[2 * R + ray];
     ex = ox - s.o[0], ey = oy - s.o[1], ez = oz - s.o[2];
   }
-  double emax = __builtin_sqrt(__builtin_fma(ex, ex, __builtin_fma(ey, ey, ez * ez)));
+  double emax = 0.0, etx = 0.0, ety = 0.0, etz = 0.0;
   double ux, uy, uz, sn;
   {
     const double il = has_ray ? rcp_f64(__builtin_sqrt(__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)))) : 0.0;
     tile_cone_axis<BLOCK>(dx * il, dy * il, dz * il, red, wave, lane, ux, uy, uz, sn);
   }
-  if (mv) emax = -block_reduce<BLOCK>(-emax, true, red[0], wave, lane);
+  if constexpr (mv) {
+    // the tile's reference origin (mean ray origin) and the spread around it, as the forward
+    const double cnt = block_reduce<BLOCK>(has_ray ? 1.0 : 0.0, false, red[3], wave, lane);
+    const double cx = block_reduce<BLOCK>(ex, false, red[0], wave, lane);
+    const double cy = block_reduce<BLOCK>(ey, false, red[1], wave, lane);
+    const double cz = block_reduce<BLOCK>(ez, false, red[2], wave, lane);
+    if (cnt > 0) etx = cx / cnt, ety = cy / cnt, etz = cz / cnt;
+    const double fx = ex - etx, fy = ey - ety, fz = ez - etz;
+    emax = has_ray ? __builtin_sqrt(__builtin_fma(fx, fx, __builtin_fma(fy, fy, fz * fz))) : 0.0;
+    emax = -block_reduce<BLOCK>(-emax, true, red[0], wave, lane);
+  }
   tile_cone_finish<BLOCK>(has_ray ? cone_cos(ux, uy, uz, dx, dy, dz) : 1.0, sn, ux, uy, uz, red, wave, lane, cone,
-                          mv ? emax : 0.0);
+                          emax, etx, ety, etz);
   const bool cull = cone.on != 0;
   if (threadIdx.x == 0) s_max = 0;
   __syncthreads();
@@ -101,7 +111,7 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
       if (part == 0) sh_g[j] = g;
     }
     __syncthreads();
-    if (threadIdx.x < cnt) sh_dead[threadIdx.x] = cull && cone_rejects(sh + threadIdx.x, cone, prm.log_alpha_min);
+    if (threadIdx.x < cnt) sh_dead[threadIdx.x] = cull && cone_rejects<MOVING>(sh + threadIdx.x, cone, prm.log_alpha_min);
     __syncthreads();
     for (int jj = cnt - 1; jj >= 0; --jj) {
       const int j = lo + jj;

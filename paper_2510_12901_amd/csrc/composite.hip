@@ -81,7 +81,6 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
         ex[k] = (double)s.ray_org[ray[k]] - s.o[0];
         ey[k] = (double)s.ray_org[s.n_rays + ray[k]] - s.o[1];
         ez[k] = (double)s.ray_org[2 * s.n_rays + ray[k]] - s.o[2];
-        emax = fmax(emax, __builtin_sqrt(__builtin_fma(ex[k], ex[k], __builtin_fma(ey[k], ey[k], ez[k] * ez[k]))));
       }
     }
     T[k] = 1.0;
@@ -105,8 +104,28 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
 #pragma unroll
   for (int k = 0; k < RPL; ++k)
     if (!rdone[k]) cmin = fmin(cmin, cone_cos(ux, uy, uz, dx[k], dy[k], dz[k]));
-  if constexpr (MOVING) emax = -block_reduce<BLOCK>(-emax, true, sm.red[0], wave, lane);
-  tile_cone_finish<BLOCK>(cmin, sn, ux, uy, uz, sm.red, wave, lane, sm.cone, emax);
+  double etx = 0, ety = 0, etz = 0;
+  if constexpr (MOVING) {
+    // reference origin of the tile: the mean ray origin; spread: the largest distance from it
+    double cx = 0, cy = 0, cz = 0, cnt = 0;
+#pragma unroll
+    for (int k = 0; k < RPL; ++k)
+      if (!rdone[k]) cx += ex[k], cy += ey[k], cz += ez[k], cnt += 1.0;
+    cnt = block_reduce<BLOCK>(cnt, false, sm.red[3], wave, lane);
+    cx = block_reduce<BLOCK>(cx, false, sm.red[0], wave, lane);
+    cy = block_reduce<BLOCK>(cy, false, sm.red[1], wave, lane);
+    cz = block_reduce<BLOCK>(cz, false, sm.red[2], wave, lane);
+    if (cnt > 0) etx = cx / cnt, ety = cy / cnt, etz = cz / cnt;
+    emax = 0.0;
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+      if (rdone[k]) continue;
+      const double fx = ex[k] - etx, fy = ey[k] - ety, fz = ez[k] - etz;
+      emax = fmax(emax, __builtin_sqrt(__builtin_fma(fx, fx, __builtin_fma(fy, fy, fz * fz))));
+    }
+    emax = -block_reduce<BLOCK>(-emax, true, sm.red[0], wave, lane);
+  }
+  tile_cone_finish<BLOCK>(cmin, sn, ux, uy, uz, sm.red, wave, lane, sm.cone, emax, etx, ety, etz);
   const bool cull = sm.cone.on != 0;
 
   uint32_t pos = start, head = 0, n_cand = 0, n_hits = 0;   // uniform across the workgroup
@@ -122,7 +141,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
         g = bgauss[j];
         hit = rect_covers(trect[g], tx, ty, s);
       }
-      const bool keep = hit && !(cull && cone_rejects(rec + g, sm.cone, prm.log_alpha_min));
+      const bool keep = hit && !(cull && cone_rejects<MOVING>(rec + g, sm.cone, prm.log_alpha_min));
       const unsigned long long mh = __ballot(hit), mk = __ballot(keep);
       if (lane == 0) sm.wcnt[wave] = make_uint2((uint32_t)__popcll(mh), (uint32_t)__popcll(mk));
       __syncthreads();

@@ -16,7 +16,9 @@ namespace ut {
 struct TileCone {
   double u[3], e1[3], e2[3];
   double cos2t, sin2t;
-  double emax;   // largest distance of a ray origin from the sensor origin (moving sensors)
+  // moving sensors: the tile's reference origin relative to the sensor origin, and the
+  // largest distance of a ray origin of the tile from that reference
+  double et[3], emax;
   int on;
 };
 
@@ -60,10 +62,12 @@ __device__ __forceinline__ void tile_cone_axis(double sx, double sy, double sz, 
 template <int BLOCK>
 __device__ __forceinline__ void tile_cone_finish(double cmin, double sn, double ux, double uy, double uz,
                                                  double (&red)[4][BLOCK / 64], int wave, int lane, TileCone& tc,
-                                                 double emax = 0.0) {
+                                                 double emax = 0.0, double etx = 0.0, double ety = 0.0,
+                                                 double etz = 0.0) {
   cmin = block_reduce<BLOCK>(cmin, true, red[3], wave, lane);
   if (threadIdx.x == 0) {
     tc.emax = emax;
+    tc.et[0] = etx, tc.et[1] = ety, tc.et[2] = etz;
     const double ct = cmin - 1e-9;                       // widen for rounding
     tc.on = (sn > 0.0 && ct > 0.7071067811865476) ? 1 : 0;
     const double st = __builtin_sqrt(1.0 - ct * ct);
@@ -94,15 +98,25 @@ __device__ __forceinline__ void tile_cone_finish(double cmin, double sn, double 
 // cut so that rounding cannot drop an entry that a ray would keep; the dropped entries are
 // exactly ones every ray of the tile would skip, so outputs are unchanged.  For a moving
 // sensor the rays start from different origins; the threshold grows by their spread.
+template <bool MOVING>
 __device__ __forceinline__ bool cone_rejects(const Record* __restrict__ rp, const TileCone& tc,
                                              double log_alpha_min) {
   double cut = cut_threshold(rp->log_sigma, log_alpha_min);
   double m[9], a[3];
 #pragma unroll
   for (int i = 0; i < 9; ++i) m[i] = rp->m[i];
-  if (tc.emax > 0.0) {
-    // Rays from origins o + e, |e| <= emax: the whitened centre moves by M e, |M e| <= |M|_F emax,
-    // so the distance to each ray's line is at least the one from o minus that.
+#pragma unroll
+  for (int i = 0; i < 3; ++i) a[i] = rp->a[i];
+  if constexpr (MOVING) {
+    // seen from the tile's reference origin o + et: a - M et
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      a[i] -= __builtin_fma(m[3 * i], tc.et[0], __builtin_fma(m[3 * i + 1], tc.et[1], m[3 * i + 2] * tc.et[2]));
+  }
+  if constexpr (MOVING) {
+    // Rays from origins o + et + e, |e| <= emax: the whitened centre moves by M e, with
+    // |M e| <= |M|_F emax, so the distance to each ray's line is at least the one from the
+    // reference origin minus that.
     if (cut < 0.0) return true;   // sigma < alpha_min: no ray reaches it
     double mf = 0.0;
 #pragma unroll
@@ -111,8 +125,6 @@ __device__ __forceinline__ bool cone_rejects(const Record* __restrict__ rp, cons
     cut = r * r;
   }
   cut += 0.05;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) a[i] = rp->a[i];
   double w[3][3], x[3][3];   // w_k = M v_k and x_k = a x w_k for v = (u, e1, e2)
   const double* v[3] = {tc.u, tc.e1, tc.e2};
 #pragma unroll
