@@ -50,7 +50,7 @@ class Sensor(C.Structure):
                 ("cull", C.c_int), ("cull_az", C.c_int), ("cull_el", C.c_int),
                 ("sat", C.c_void_p), ("ray_dir", C.c_void_p),
                 ("moving", C.c_int), ("R_sw1", C.c_float * 9), ("origin1", C.c_float * 3),
-                ("ray_org", C.c_void_p), ("rs_iters", C.c_int)]
+                ("ray_org", C.c_void_p), ("rs_iters", C.c_int), ("beam_divergence", C.c_double)]
 
 
 class Params(C.Structure):
@@ -168,6 +168,7 @@ class OracleSensor:
             c.cull_az, c.cull_el = int(s["cull_az"]), int(s["cull_el"])
             self.mask, self.sat = ray_sat(self.beam_elev, c.n_az, self.bounds[0], self.bounds[-1],
                                           c.cull_az, c.cull_el)
+            c.beam_divergence = float(s.get("beam_divergence", 0.0))
             c.sat = _p(self.sat).value
             self.n_tiles = n_phi * n_theta
             self.n_rays = c.n_beams * c.n_az

@@ -56,6 +56,9 @@ typedef struct {
   float origin1[3];
   const float* ray_org;      /* [3][R] world frame, moving sensors only */
   int rs_iters;              /* fixed-point iterations of the time-dependent projection */
+  /* LiDAR beam divergence (full angle, radians; 0 = off): the 3D smoothing filter of the
+   * appendix on beam divergence (Eq. 6), without its opacity factor. */
+  double beam_divergence;
 } orc_sensor;
 
 typedef struct {
@@ -96,6 +99,8 @@ struct Particle {
   double sigma;
   double Sigma[9];
   double Binv[9]; /* Sigma^{-1} */
+  bool filtered;  /* beam-divergence filter applied: Sigma holds Sigma_hat, L its Cholesky factor */
+  double L[9];
 };
 
 void quat_to_rot(const double q[4], double R[9]) {
@@ -166,6 +171,44 @@ Particle make_particle(const orc_gaussians* g, int i) {
     }
   p.ok = inverse3(p.Sigma, p.Binv);
   return p;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Beam-divergence filter (appendix, Eq. 6).  READING: the paper names the smoothed
+ * covariance Sigma_hat without defining it; following the 3D smoothing filter it cites, the
+ * particle is widened in the plane orthogonal to d = (mu - o)/|mu - o| by the beam's variance
+ * at that range, Sigma_hat = Sigma + (r tan(theta/2))^2 (I - d d^T), r = |mu - o|, theta the
+ * full divergence angle; the response is exp(-(x-mu)^T Sigma_hat^{-1} (x-mu) / 2) with the
+ * opacity left unscaled, as the paper prescribes.  The UT's sigma points then use the
+ * Cholesky factor of Sigma_hat as the matrix square root.
+ * ---------------------------------------------------------------------------------- */
+bool cholesky3(const double A[9], double L[9]) {
+  for (int i = 0; i < 9; ++i) L[i] = 0;
+  for (int j = 0; j < 3; ++j) {
+    double d = A[j * 3 + j];
+    for (int k = 0; k < j; ++k) d -= L[j * 3 + k] * L[j * 3 + k];
+    if (!(d > 0)) return false;
+    L[j * 3 + j] = std::sqrt(d);
+    for (int i = j + 1; i < 3; ++i) {
+      double v = A[i * 3 + j];
+      for (int k = 0; k < j; ++k) v -= L[i * 3 + k] * L[j * 3 + k];
+      L[i * 3 + j] = v / L[j * 3 + j];
+    }
+  }
+  return true;
+}
+
+void apply_beam_divergence(const orc_sensor* s, Particle& p) {
+  if (!p.ok || s->kind != 2 || !(s->beam_divergence > 0)) return;
+  double v[3] = {p.mu[0] - s->origin[0], p.mu[1] - s->origin[1], p.mu[2] - s->origin[2]};
+  const double r = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  if (!(r > 0)) return;
+  for (int a = 0; a < 3; ++a) v[a] /= r;
+  const double w = r * std::tan(0.5 * s->beam_divergence);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) p.Sigma[i * 3 + j] += w * w * ((i == j ? 1.0 : 0.0) - v[i] * v[j]);
+  p.filtered = true;
+  p.ok = inverse3(p.Sigma, p.Binv) && cholesky3(p.Sigma, p.L);
 }
 
 /* ------------------------------------------------------------------------------------
@@ -445,8 +488,9 @@ bool unscented_transform(const orc_sensor* s, const Particle& p, const orc_param
   for (int d = 0; d < 3; ++d) pts[0][d] = p.mu[d];
   for (int j = 0; j < 3; ++j)
     for (int d = 0; d < 3; ++d) {
-      pts[1 + j][d] = p.mu[d] + gamma * p.s[j] * p.R[d * 3 + j];
-      pts[4 + j][d] = p.mu[d] - gamma * p.s[j] * p.R[d * 3 + j];
+      const double col = p.filtered ? p.L[d * 3 + j] : p.s[j] * p.R[d * 3 + j];   /* sqrt(Sigma) column j */
+      pts[1 + j][d] = p.mu[d] + gamma * col;
+      pts[4 + j][d] = p.mu[d] - gamma * col;
     }
   double g[7][2];
   for (int k = 0; k < 7; ++k)
@@ -588,7 +632,8 @@ int orc_project(const orc_gaussians* g, const orc_sensor* s, const orc_params* p
   const double o[3] = {s->origin[0], s->origin[1], s->origin[2]};
 #pragma omp parallel for schedule(dynamic, 256) reduction(+ : n_inv, n_cull)
   for (int i = 0; i < n; ++i) {
-    const Particle p = make_particle(g, i);
+    Particle p = make_particle(g, i);
+    apply_beam_divergence(s, p);
     double margin = 1e300, m[2] = {0, 0}, cov[3] = {0, 0, 0};
     bool ok = p.ok && unscented_transform(s, p, prm, m, cov, &margin);
     int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
@@ -757,6 +802,7 @@ PerGaussian per_gaussian(const orc_gaussians* g, const orc_sensor* s) {
 #pragma omp parallel for schedule(static)
   for (int i = 0; i < n; ++i) {
     pg.P[i] = make_particle(g, i);
+    apply_beam_divergence(s, pg.P[i]);
     double f[3] = {0, 0, 0};
     int cl[3] = {0, 0, 0};
     if (pg.P[i].ok) gaussian_features(g, i, pg.P[i].mu, o, f, cl);

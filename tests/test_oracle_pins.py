@@ -522,3 +522,67 @@ def test_per_ray_origin_closed_form():
     assert (alpha > 0).sum() > 100 and np.all(alpha[~hit] == 0)
     np.testing.assert_allclose(out["alpha"], alpha, atol=1e-13)
     np.testing.assert_allclose(out["depth"], tau * alpha, atol=1e-12)
+
+
+# ------------------------------------------------------------------ LiDAR beam divergence
+def _divergence_scene(theta):
+    rng = np.random.default_rng(8)
+    be = synth.beams_uniform(rng, 32, -3, 4)
+    s = synth.lidar(be, 2048, n_phi=2, max_per_tile=32)
+    s["beam_divergence"] = theta
+    mu = np.array([[6.0], [0.8], [0.1]])
+    g = synth.particles(rng, mu, 0.05, 0.05, 0, synth.FEAT_LIDAR)
+    g["feat"] = synth.lidar_feat(rng, 1)
+    g["quat"][:, 0] = [1, 0, 0, 0]
+    g["opacity_logit"][:] = np.float32(np.log(0.6 / 0.4))
+    return g, s
+
+
+def test_beam_divergence_response_is_numeric_maximum_of_the_smoothed_gaussian():
+    """Eq. 6 reading: Sigma_hat = Sigma + (r tan(theta/2))^2 (I - d d^T) and alpha = sigma max_t
+    exp(-q(t)/2) with no opacity factor; checked ray by ray against a bounded scalar maximisation
+    of the smoothed density built here from that definition."""
+    theta = 0.02
+    g, s = _divergence_scene(theta)
+    _, _, out = oracle.render(g, s)
+    mu = g["mean"][:, 0].astype(np.float64)
+    sc = np.exp(np.float64(g["log_scale"][0, 0]))
+    r = np.linalg.norm(mu)
+    d = mu / r
+    w2 = (r * np.tan(theta / 2)) ** 2
+    Sig = sc * sc * np.eye(3) + w2 * (np.eye(3) - np.outer(d, d))
+    B = np.linalg.inv(Sig)
+    sigma = 1 / (1 + np.exp(-np.float64(g["opacity_logit"][0])))
+    dirs = s["ray_dir"].astype(np.float64).T
+    hit = np.nonzero(out["alpha"] > 0)[0]
+    assert len(hit) > 20
+    for k in hit[:: max(1, len(hit) // 40)]:
+        e = dirs[k]
+        f = lambda t: (t * e - mu) @ B @ (t * e - mu)
+        best = minimize_scalar(f, bounds=(0.1, 20.0), method="bounded", options={"xatol": 1e-12})
+        a = min(sigma * np.exp(-0.5 * best.fun), 0.99)
+        assert abs(out["alpha"][k] - a) < 1e-9 * max(1.0, a)
+    # Coverage of the widened footprint (pins the sigma points built from the Cholesky factor):
+    # every ray whose smoothed response clearly exceeds the cut-off must be composited.
+    eb, mb = dirs @ B, B @ mu
+    ebe = np.einsum("ij,ij->i", eb, dirs)
+    qmin = mu @ mb - (eb @ mu) ** 2 / ebe
+    front = (eb @ mu) / ebe > s["near"]          # the maximising point lies ahead of the sensor
+    strong = np.nonzero(front & (sigma * np.exp(-0.5 * qmin) > 0.05))[0]
+    assert len(strong) > 20 and np.all(out["alpha"][strong] > 0)
+
+
+def test_beam_divergence_widens_without_scaling_opacity():
+    """The filter widens the footprint (more rays hit) but keeps the peak: without an opacity
+    factor the ray nearest the centre still sees alpha close to sigma (a determinant-ratio factor
+    would scale it by about 0.41 here); theta = 0 is the plain response."""
+    g, s0 = _divergence_scene(0.0)
+    _, _, a0 = oracle.render(g, s0)
+    g, s1 = _divergence_scene(0.02)
+    _, _, a1 = oracle.render(g, s1)
+    _, _, a_plain = oracle.render(g, {k: v for k, v in s0.items() if k != "beam_divergence"})
+    np.testing.assert_array_equal(a0["alpha"], a_plain["alpha"])
+    assert (a1["alpha"] > 0).sum() > 1.5 * (a0["alpha"] > 0).sum()
+    sigma = 1 / (1 + np.exp(-np.float64(g["opacity_logit"][0])))
+    assert a0["alpha"].max() <= a1["alpha"].max() <= sigma
+    assert a1["alpha"].max() > 0.9 * sigma
