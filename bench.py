@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-time-dependent", action="store_true")
+    ap.add_argument("--no-beam-divergence", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--served-seconds", type=float, default=3.0)
     ap.add_argument("--vehicles", type=str, default="1,4,8")
@@ -350,6 +351,8 @@ def main():
         result["backward"] = bench_backward(ut, synth, dev, args)
     if not args.no_time_dependent:
         result["time_dependent"] = bench_time_dependent(ut, synth, dev, args)
+    if not args.no_beam_divergence:
+        result["beam_divergence"] = bench_beam_divergence(ut, synth, dev, args)
     if not args.no_served:
         from paper_2510_12901_amd import serve
         result["served"] = serve.bench_served(g, gl, sensors_np, sensors, dev, args, log)
@@ -385,6 +388,54 @@ def bench_backward(ut, synth, dev, args):
             "ms_per_step": round(ms, 3), "mrays_per_s": round(s.n_rays / ms / 1e3, 2), "pairs": pipe.n_pairs}
 
 
+def _time_sensor(ut, g, d, dev, args, stream):
+    """Frame time of one sensor render (projection, binning, sort, compositing; median of K
+    frames after the set-up and W warm-up frames), the compositing time alone and the work
+    counters of one frame."""
+    import torch
+    s = ut.Sensor(d, dev)
+    pipe = ut.SensorPipeline(g, s)
+    for _ in range(SETUP_FRAMES + args.warmup):
+        pipe.run(stream)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        pipe.run(stream)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ms = float(np.median(times)) * 1e3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        pipe.composite_only(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    o = ut.alloc_out(s, dev, state=True, counters=True)
+    pipe.composite_only(stream, o)
+    torch.cuda.synchronize()
+    return {"ms_per_frame": round(ms, 3), "mrays_per_s": round(s.n_rays / ms / 1e3, 2),
+            "composite_ms": round(e0.elapsed_time(e1) / 5, 4), "bin_pairs": pipe.n_pairs,
+            "evaluated_pairs": int(o.n_visit.to(torch.int64).sum().item()),
+            "list_positions": int(o.n_proc.to(torch.int64).sum().item())}
+
+
+def bench_beam_divergence(ut, synth, dev, args):
+    """The 300,000-particle 128x2048 LiDAR without and with a 3 mrad beam-divergence cone
+    (the smoothing widens every particle across the beam, so tiles receive more pairs)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    g_np, lid = synth.scene_lidar(args.seed)
+    g = ut.GaussianSet.from_numpy(g_np, dev)
+    row = {}
+    for label, theta in (("off", 0.0), ("3mrad", 0.003)):
+        d = dict(lid)
+        d["beam_divergence"] = theta
+        row[label] = _time_sensor(ut, g, d, dev, args, stream)
+    log(f"beam divergence lidar_128x2048_300k: {json.dumps(row)}")
+    return {"lidar_128x2048_300k": row}
+
+
 def bench_time_dependent(ut, synth, dev, args):
     """Static vs moving sensors on the 1,000,000-particle pinhole 1920x1080 scene (rolling
     shutter: 0.5 m sideways and 0.01 rad of yaw during the readout, a side camera of a car at
@@ -404,33 +455,7 @@ def bench_time_dependent(ut, synth, dev, args):
         g = ut.GaussianSet.from_numpy(g_np, dev)
         row = {}
         for label, d in zip(("static", "moving"), descs):
-            s = ut.Sensor(d, dev)
-            pipe = ut.SensorPipeline(g, s)
-            for _ in range(SETUP_FRAMES + args.warmup):
-                pipe.run(stream)
-            torch.cuda.synchronize()
-            times = []
-            for _ in range(args.steps):
-                t0 = time.perf_counter()
-                pipe.run(stream)
-                torch.cuda.synchronize()
-                times.append(time.perf_counter() - t0)
-            ms = float(np.median(times)) * 1e3
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(5):
-                pipe.composite_only(stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            o = ut.alloc_out(s, dev, state=True, counters=True)
-            pipe.composite_only(stream, o)
-            torch.cuda.synchronize()
-            row[label] = {"ms_per_frame": round(ms, 3), "mrays_per_s": round(s.n_rays / ms / 1e3, 2),
-                          "composite_ms": round(e0.elapsed_time(e1) / 5, 4), "bin_pairs": pipe.n_pairs,
-                          "evaluated_pairs": int(o.n_visit.to(torch.int64).sum().item()),
-                          "list_positions": int(o.n_proc.to(torch.int64).sum().item())}
-            del o
-            del pipe, s
+            row[label] = _time_sensor(ut, g, d, dev, args, stream)
         out[name] = row
         log(f"time-dependent {name}: {json.dumps(row)}")
     return out

@@ -124,6 +124,15 @@ typedef struct {
   float origin1[3];
   const float* ray_org;   /* device [3][R], moving sensors only */
   int32_t rs_iters;       /* 1..64 */
+  /* LiDAR beam divergence (Sec. 3.2, LiDAR appendix: the beam is a cone, not a line).  Full
+   * cone angle in radians, 0 <= beam_divergence < pi; 0 = off.  Each particle is smoothed
+   * across the beam at its range r = |mu - origin| before projection:
+   * Sigma_hat = Sigma + (r tan(beam_divergence / 2))^2 (I - d d^T), d = (mu - origin) / r,
+   * with the opacity left unscaled; the UT's sigma points use the lower Cholesky factor L of
+   * Sigma_hat and the record holds M = L^{-1}.  origin is the frame-start origin for moving
+   * sensors.  Must be 0 for cameras (UT_ERR_ARG otherwise); the adjoint
+   * (ut_render_backward) returns UT_ERR_UNSUPPORTED when it is non-zero. */
+  double beam_divergence;
 } ut_sensor;
 
 /* Compositing cut-offs (Eq. 1 practice): skip alpha < alpha_min, clamp alpha at

@@ -30,7 +30,8 @@ class UtSensor(C.Structure):
                 ("cull_az", i32), ("cull_el", i32), ("n_theta", i32), ("max_tile_rays", i32),
                 ("beam_elev_host", P), ("ray_dir", P), ("tables", P),
                 ("moving", i32), ("R_sw1", C.c_float * 9), ("origin1", C.c_float * 3), ("ray_org", P),
-                ("rs_iters", i32)]
+                ("rs_iters", i32),
+                ("beam_divergence", C.c_double)]
 
 
 class UtRenderParams(C.Structure):

@@ -21,6 +21,8 @@ int camera_tiles_y(const ut_sensor* s) { return (s->height + UT_CAMERA_TILE - 1)
 bool sensor_ok(const ut_sensor* s) {
   if (!s || !s->ray_dir) return false;
   if (s->moving && (!s->ray_org || s->rs_iters < 1 || s->rs_iters > 64 || s->kind == UT_ORTHO)) return false;
+  if (!(s->beam_divergence >= 0 && s->beam_divergence < kPi)) return false;
+  if (s->beam_divergence > 0 && s->kind != UT_LIDAR) return false;
   if (s->kind == UT_LIDAR)
     return s->n_beams > 0 && s->n_az > 0 && s->n_phi > 0 && s->n_phi <= UT_MAX_ELEV_TILES &&
            s->n_theta > 0 && s->tables && s->max_tile_rays > 0 && s->max_tile_rays <= UT_MAX_LIDAR_TILE_RAYS &&
@@ -75,6 +77,7 @@ SensorK make_sensor_k(const ut_sensor* s) {
     k.beam_start = reinterpret_cast<const int*>(base + t.beam_start);
     k.sat = reinterpret_cast<const int*>(base + t.sat);
     k.n_rays = (long long)s->n_beams * s->n_az;
+    k.div_tan = s->beam_divergence > 0 ? std::tan(0.5 * s->beam_divergence) : 0.0;
   } else {
     k.width = s->width; k.height = s->height;
     k.tiles_x = camera_tiles_x(s); k.tiles_y = camera_tiles_y(s);
@@ -381,6 +384,7 @@ ut_status ut_composite_backward(const ut_gaussians* g, const ut_projected* p, co
     return UT_ERR_ARG;
   if (acc_ws_bytes < ut_backward_workspace_bytes(g->n)) return UT_ERR_CAPACITY;
   if (s->max_tile_rays > 256) return UT_ERR_UNSUPPORTED;   // the adjoint runs one lane per ray of a tile
+  if (s->beam_divergence > 0) return UT_ERR_UNSUPPORTED;   // no adjoint of the divergence filter
   const SensorK k = make_sensor_k(s);
   return from_hip(launch_backward(*g, *p, *lists, k, make_params(prm), *fwd, *up, static_cast<double*>(acc_ws),
                                   *grads, s->max_tile_rays, as_stream(stream)));

@@ -106,6 +106,51 @@ __device__ __forceinline__ uint32_t depth_key(float mx, float my, float mz, cons
 // unrolled and issued together instead of one dependent loop trip at a time.  KIND is the
 // sensor model, so each instantiation carries only its own projection code (the LiDAR and
 // fisheye arctangents would otherwise set the register count of every camera).
+// LiDAR beam divergence (Sec. 3.2, LiDAR appendix): the particle is smoothed across the beam
+// at its range r, Sigma_hat = Sigma + (r tan(theta/2))^2 (I - d d^T) with Sigma = L L^T on
+// entry (L = S R^T's transpose, column-scaled rotation), and the opacity is not rescaled.  On
+// return L holds the lower Cholesky factor of Sigma_hat and the record's M = L^{-1},
+// a = M (mu - o), so the compositing response is exp(-(x-mu)^T Sigma_hat^{-1} (x-mu) / 2).
+// false if Sigma_hat is not numerically positive definite.
+__device__ __forceinline__ bool beam_divergence_filter(const SensorK& s, float mx, float my, float mz,
+                                                       double L[9], Record& r) {
+  const double vx = (double)mx - s.o[0], vy = (double)my - s.o[1], vz = (double)mz - s.o[2];
+  const double range = sqrt(vx * vx + vy * vy + vz * vz);
+  if (!(range > 0)) return true;
+  const double ir = 1.0 / range, d[3] = {vx * ir, vy * ir, vz * ir};
+  const double w = range * s.div_tan, w2 = w * w;
+  double A[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      A[i * 3 + j] = L[i * 3] * L[j * 3] + L[i * 3 + 1] * L[j * 3 + 1] + L[i * 3 + 2] * L[j * 3 + 2] +
+                     w2 * ((i == j ? 1.0 : 0.0) - d[i] * d[j]);
+  // Cholesky, column by column
+  const double p00 = A[0];
+  if (!(p00 > 0)) return false;
+  const double l00 = sqrt(p00), l10 = A[3] / l00, l20 = A[6] / l00;
+  const double p11 = A[4] - l10 * l10;
+  if (!(p11 > 0)) return false;
+  const double l11 = sqrt(p11), l21 = (A[7] - l20 * l10) / l11;
+  const double p22 = A[8] - l20 * l20 - l21 * l21;
+  if (!(p22 > 0)) return false;
+  const double l22 = sqrt(p22);
+  L[0] = l00; L[1] = 0;   L[2] = 0;
+  L[3] = l10; L[4] = l11; L[5] = 0;
+  L[6] = l20; L[7] = l21; L[8] = l22;
+  // M = L^{-1}, lower triangular
+  const double i00 = 1.0 / l00, i11 = 1.0 / l11, i22 = 1.0 / l22;
+  const double i10 = -l10 * i00 * i11, i21 = -l21 * i11 * i22, i20 = -(l20 * i00 + l21 * i10) * i22;
+  r.m[0] = i00; r.m[1] = 0;   r.m[2] = 0;
+  r.m[3] = i10; r.m[4] = i11; r.m[5] = 0;
+  r.m[6] = i20; r.m[7] = i21; r.m[8] = i22;
+  r.a[0] = i00 * vx;
+  r.a[1] = __builtin_fma(i10, vx, i11 * vy);
+  r.a[2] = __builtin_fma(i20, vx, __builtin_fma(i21, vy, i22 * vz));
+  return true;
+}
+
 template <int DEG, int KIND, bool MOVING>
 __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK& s, double ut_a, double ut_b,
                                             double ut_k, Record* __restrict__ rec,
@@ -147,6 +192,17 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
     }
     r.log_sigma = ok ? -log1p(exp(-(double)lg)) : -1e30;   // ln sigmoid(logit)
 
+    // columns of the covariance square root the sigma points step along: S R^T's rows, or
+    // with LiDAR beam divergence the lower Cholesky factor of the smoothed covariance
+    double Lc[9];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Lc[d * 3 + j] = sc[j] * Rm[d * 3 + j];
+    if constexpr (KIND == UT_LIDAR) {
+      if (ok && s.div_tan > 0) ok = beam_divergence_filter(s, mx, my, mz, Lc, r);
+    }
+
     // unscented transform over 7 sigma points
     double m0 = 0, m1 = 0, c00 = 0, c01 = 0, c11 = 0;
     if (ok) {
@@ -161,7 +217,7 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
           if (!ok) break;
-          const double e0 = gam * sc[j] * Rm[j], e1 = gam * sc[j] * Rm[3 + j], e2 = gam * sc[j] * Rm[6 + j];
+          const double e0 = gam * Lc[j], e1 = gam * Lc[3 + j], e2 = gam * Lc[6 + j];
           const double pp[3] = {mu[0] + e0, mu[1] + e1, mu[2] + e2};
           const double pm[3] = {mu[0] - e0, mu[1] - e1, mu[2] - e2};
           ok = project_point<KIND, MOVING>(s, pp, gu[1 + j], gv[1 + j]) && project_point<KIND, MOVING>(s, pm, gu[4 + j], gv[4 + j]);

@@ -58,6 +58,7 @@ struct SensorK {
   double q0[4], q1[4], slerp_th, slerp_isin;
   double o1[3];
   const float* ray_org;     // [3][R]
+  double div_tan;           // LiDAR beam divergence: tan(cone angle / 2), 0 = off
 };
 
 // Byte layout of the LiDAR device tables (bounds, beam_start, sat), 256-byte aligned parts.

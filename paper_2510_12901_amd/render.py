@@ -96,6 +96,7 @@ class Sensor:
             c.n_phi, c.max_per_tile = int(desc["n_phi"]), int(desc["max_per_tile"])
             c.cull = int(bool(desc.get("cull", True)))
             c.cull_az, c.cull_el = int(desc.get("cull_az", 1600)), int(desc.get("cull_el", 8 * c.n_phi))
+            c.beam_divergence = float(desc.get("beam_divergence", 0.0))
         else:
             c.width, c.height = int(desc["width"]), int(desc["height"])
             c.fx, c.fy, c.cx, c.cy = (float(desc[k]) for k in ("fx", "fy", "cx", "cy"))

@@ -64,6 +64,14 @@ def _scene(name):
         g, s = _scene("lidar_posed_m64")
         R1 = synth.yaw_lidar_pose(2.25)
         return g, synth.spinning(s, R1, s["origin"] + np.array([1.5, 0.4, 0.0], np.float32))
+    if name == "lidar_divergence":                     # beams with a 6 mrad divergence cone
+        g, s = _scene("lidar_posed_m64")
+        s["beam_divergence"] = 0.006
+        return g, s
+    if name == "lidar_moving_divergence":
+        g, s = _scene("lidar_moving")
+        s["beam_divergence"] = 0.02
+        return g, s
     if name == "pinhole_wide_aniso":                   # wide field of view, needle/disc particles
         rng = np.random.default_rng(6)                 # (1:1000 axis ratios) close to the camera
         n = 6000
@@ -75,7 +83,8 @@ def _scene(name):
 
 SCENES = ["pinhole_128x96", "pinhole_ragged", "pinhole_sh3_posed", "pinhole_wide_aniso", "fisheye_small",
           "lidar_small", "lidar_nocull", "lidar_posed_m64", "lidar_m128", "lidar_m256", "lidar_m512",
-          "pinhole_rolling_shutter", "fisheye_rolling_shutter", "lidar_moving"]
+          "pinhole_rolling_shutter", "fisheye_rolling_shutter", "lidar_moving", "lidar_divergence",
+          "lidar_moving_divergence"]
 
 
 @pytest.mark.parametrize("name", SCENES)
@@ -243,3 +252,38 @@ def test_batched_composite_with_moving_and_static_sensors():
     for (p, bins, s, b), a in zip(items, plain):
         for k in ("feat", "depth", "alpha", "t_final", "n_proc"):
             assert torch.equal(getattr(a, k), getattr(b, k)), k
+
+
+def test_beam_divergence_records_and_adjoint_refusal():
+    """With beam divergence the record holds M = L^{-1} for the lower Cholesky factor L of
+    Sigma_hat = Sigma + (r tan(theta/2))^2 (I - d d^T) (built here with scipy's rotation), so
+    M is lower triangular with M^T M = Sigma_hat^{-1}; the adjoint refuses such a sensor."""
+    from scipy.spatial.transform import Rotation
+    import torch
+    import paper_2510_12901_amd as ut
+    from paper_2510_12901_amd import _abi as A
+    g_np, s_np = _scene("lidar_divergence")
+    gp, _ = gpu_render(g_np, s_np)
+    rec = gp["records"]
+    o = s_np["origin"].astype(np.float64)
+    vis = np.nonzero(gp["count"] > 0)[0]
+    assert len(vis) > 1000
+    for i in vis[::41]:
+        w, x, y, z = g_np["quat"][:, i].astype(np.float64)
+        R = Rotation.from_quat([x, y, z, w]).as_matrix()
+        sc = np.exp(g_np["log_scale"][:, i].astype(np.float64))
+        v = g_np["mean"][:, i].astype(np.float64) - o
+        r = np.linalg.norm(v)
+        d = v / r
+        S_hat = R @ np.diag(sc * sc) @ R.T + (r * np.tan(0.003)) ** 2 * (np.eye(3) - np.outer(d, d))
+        M = rec["m"][i].reshape(3, 3)
+        assert M[0, 1] == 0 and M[0, 2] == 0 and M[1, 2] == 0
+        B = np.linalg.inv(S_hat)
+        np.testing.assert_allclose(M.T @ M, B, rtol=1e-8, atol=1e-8 * np.abs(B).max())
+        np.testing.assert_allclose(rec["a"][i], M @ v, rtol=1e-10, atol=1e-10 * np.abs(M @ v).max())
+    g = ut.GaussianSet.from_numpy(g_np)
+    s = ut.Sensor(s_np)
+    p, lists, out = ut.render(g, s)
+    up = torch.ones_like(out.alpha)
+    with pytest.raises(A.UtError, match="unsupported"):
+        ut.backward(g, p, lists, s, out, None, None, up, None)
