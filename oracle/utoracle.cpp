@@ -1143,6 +1143,17 @@ void chain_to_params(const orc_gaussians* g, const orc_sensor* s, const PerGauss
       }
     }
     double dmu[3] = {A.dmu[0], A.dmu[1], A.dmu[2]};
+    /* beam divergence: Sigma_hat = Sigma + t^2 (|v|^2 I - v v^T), t = tan(theta/2), so GS also
+     * reaches the mean, d/dv [GS : t^2 (|v|^2 I - v v^T)] = t^2 (2 tr(GS) v - (GS + GS^T) v) */
+    if (p.filtered) {
+      const double t = std::tan(0.5 * s->beam_divergence), t2 = t * t;
+      const double tr = GS[0] + GS[4] + GS[8];
+      for (int a = 0; a < 3; ++a) {
+        double sv = 0;
+        for (int b = 0; b < 3; ++b) sv += (GS[a * 3 + b] + GS[b * 3 + a]) * v[b];
+        dmu[a] += t2 * (2 * tr * v[a] - sv);
+      }
+    }
     if (len > 0) {
       const double dd = ddir[0] * dir[0] + ddir[1] * dir[1] + ddir[2] * dir[2];
       for (int a = 0; a < 3; ++a) dmu[a] += (ddir[a] - dir[a] * dd) / len;
@@ -1266,6 +1277,7 @@ int orc_fd_grad(const orc_gaussians* g, const orc_sensor* s, const orc_params* p
       for (int side = 0; side < 2; ++side) {
         *slot = keep + (side ? -h : h);
         pg.P[gi] = make_particle(&gv, gi);
+        apply_beam_divergence(s, pg.P[gi]);
         double f[3];
         sh_features_raw(&gv, gi, pg.P[gi].mu, o, f);
         for (int c = 0; c < 3; ++c)   /* colour clamp held at its unperturbed state */

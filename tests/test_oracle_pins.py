@@ -407,9 +407,13 @@ def test_adjoint_matches_finite_differences_camera():
     np.testing.assert_allclose(an, fd, atol=1e-6 * scale.max(), rtol=1e-5)
 
 
-def test_adjoint_matches_finite_differences_lidar():
+@pytest.mark.parametrize("theta", [0.0, 0.02])
+def test_adjoint_matches_finite_differences_lidar(theta):
+    """theta > 0: with the beam-divergence filter the mean also moves the smoothing term
+    (r tan(theta/2))^2 (I - d d^T); finite differences see it through the full render."""
     g, s = synth.scene_lidar(2, n=2000, n_beams=16, n_az=128, n_phi=4, max_per_tile=32)
     g["mean"] *= np.float32(0.05)
+    s["beam_divergence"] = theta
     proj, lists, out = oracle.render(g, s)
     rng = np.random.default_rng(2)
     R = out["alpha"].shape[0]
