@@ -130,8 +130,8 @@ typedef struct {
    * Sigma_hat = Sigma + (r tan(beam_divergence / 2))^2 (I - d d^T), d = (mu - origin) / r,
    * with the opacity left unscaled; the UT's sigma points use the lower Cholesky factor L of
    * Sigma_hat and the record holds M = L^{-1}.  origin is the frame-start origin for moving
-   * sensors.  Must be 0 for cameras (UT_ERR_ARG otherwise); the adjoint
-   * (ut_render_backward) returns UT_ERR_UNSUPPORTED when it is non-zero. */
+   * sensors.  Must be 0 for cameras (UT_ERR_ARG otherwise).  The adjoint differentiates
+   * the filter too (the mean moves the smoothing term). */
   double beam_divergence;
 } ut_sensor;
 

@@ -384,7 +384,6 @@ ut_status ut_composite_backward(const ut_gaussians* g, const ut_projected* p, co
     return UT_ERR_ARG;
   if (acc_ws_bytes < ut_backward_workspace_bytes(g->n)) return UT_ERR_CAPACITY;
   if (s->max_tile_rays > 256) return UT_ERR_UNSUPPORTED;   // the adjoint runs one lane per ray of a tile
-  if (s->beam_divergence > 0) return UT_ERR_UNSUPPORTED;   // no adjoint of the divergence filter
   const SensorK k = make_sensor_k(s);
   return from_hip(launch_backward(*g, *p, *lists, k, make_params(prm), *fwd, *up, static_cast<double*>(acc_ws),
                                   *grads, s->max_tile_rays, as_stream(stream)));

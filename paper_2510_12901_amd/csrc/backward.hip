@@ -242,19 +242,56 @@ __global__ __launch_bounds__(256) void k_chain(ut_gaussians g, SensorK s, const 
     dlogit = a[3] * sigma * (1.0 - sigma);
     // unique-entry gradient of B -> full symmetric G
     const double G[9] = {a[7], 0.5 * a[10], 0.5 * a[11], 0.5 * a[10], a[8], 0.5 * a[12], 0.5 * a[11], 0.5 * a[12], a[9]};
-    // B = R D R^T, D = diag(1/s^2): dL/dR = 2 G R D, dL/dD_jj = (R^T G R)_jj
-    double GR[9];
-    for (int r = 0; r < 3; ++r)
-      for (int j = 0; j < 3; ++j) {
-        const double gr = G[r * 3] * R[j] + G[r * 3 + 1] * R[3 + j] + G[r * 3 + 2] * R[6 + j];
-        GR[r * 3 + j] = gr;
-      }
+    const double vx = mx - s.o[0], vy = my - s.o[1], vz = mz - s.o[2];
     double dR[9];
-    for (int r = 0; r < 3; ++r)
-      for (int j = 0; j < 3; ++j) dR[r * 3 + j] = 2.0 * GR[r * 3 + j] / (sc[j] * sc[j]);
-    for (int j = 0; j < 3; ++j) {
-      const double rtgr = R[j] * GR[j] + R[3 + j] * GR[3 + j] + R[6 + j] * GR[6 + j];
-      dls[j] = -2.0 * rtgr / (sc[j] * sc[j]);
+    if (s.div_tan > 0) {
+      // LiDAR beam divergence: B = Sigma_hat^{-1}, Sigma_hat = R S^2 R^T + t^2 (|v|^2 I - v v^T)
+      // (t = tan(theta/2), v = mu - o), so dL/dSigma_hat = -B G B =: GS reaches R and S as for
+      // a plain covariance, dL/dR = 2 GS R S^2, dL/dlog s_j = 2 s_j^2 (R^T GS R)_jj, and the
+      // mean through the smoothing term, t^2 (2 tr(GS) v - 2 GS v).
+      const double vv[3] = {vx, vy, vz};
+      const double t2 = s.div_tan * s.div_tan, r2 = vx * vx + vy * vy + vz * vz;
+      double A[9];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          double sig = 0;
+          for (int j = 0; j < 3; ++j) sig += R[r * 3 + j] * sc[j] * sc[j] * R[c * 3 + j];
+          A[r * 3 + c] = sig + t2 * ((r == c ? r2 : 0.0) - vv[r] * vv[c]);
+        }
+      // B by the adjugate (A is symmetric positive definite: the forward factored it)
+      const double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
+      const double idet = 1.0 / (A[0] * c00 + A[1] * c01 + A[2] * c02);
+      const double B[9] = {c00 * idet, (A[2] * A[7] - A[1] * A[8]) * idet, (A[1] * A[5] - A[2] * A[4]) * idet,
+                           c01 * idet, (A[0] * A[8] - A[2] * A[6]) * idet, (A[2] * A[3] - A[0] * A[5]) * idet,
+                           c02 * idet, (A[1] * A[6] - A[0] * A[7]) * idet, (A[0] * A[4] - A[1] * A[3]) * idet};
+      double GB[9], GS[9];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) GB[r * 3 + c] = G[r * 3] * B[c] + G[r * 3 + 1] * B[3 + c] + G[r * 3 + 2] * B[6 + c];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) GS[r * 3 + c] = -(B[r * 3] * GB[c] + B[r * 3 + 1] * GB[3 + c] + B[r * 3 + 2] * GB[6 + c]);
+      double SR[9];
+      for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 3; ++j) SR[r * 3 + j] = GS[r * 3] * R[j] + GS[r * 3 + 1] * R[3 + j] + GS[r * 3 + 2] * R[6 + j];
+      for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 3; ++j) dR[r * 3 + j] = 2.0 * SR[r * 3 + j] * sc[j] * sc[j];
+      for (int j = 0; j < 3; ++j) dls[j] = 2.0 * sc[j] * sc[j] * (R[j] * SR[j] + R[3 + j] * SR[3 + j] + R[6 + j] * SR[6 + j]);
+      const double tr = GS[0] + GS[4] + GS[8];
+      for (int r = 0; r < 3; ++r)
+        dmean[r] = 2.0 * t2 * (tr * vv[r] - (GS[r * 3] * vx + GS[r * 3 + 1] * vy + GS[r * 3 + 2] * vz));
+    } else {
+      // B = R D R^T, D = diag(1/s^2): dL/dR = 2 G R D, dL/dD_jj = (R^T G R)_jj
+      double GR[9];
+      for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 3; ++j) {
+          const double gr = G[r * 3] * R[j] + G[r * 3 + 1] * R[3 + j] + G[r * 3 + 2] * R[6 + j];
+          GR[r * 3 + j] = gr;
+        }
+      for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 3; ++j) dR[r * 3 + j] = 2.0 * GR[r * 3 + j] / (sc[j] * sc[j]);
+      for (int j = 0; j < 3; ++j) {
+        const double rtgr = R[j] * GR[j] + R[3 + j] * GR[3 + j] + R[6 + j] * GR[6 + j];
+        dls[j] = -2.0 * rtgr / (sc[j] * sc[j]);
+      }
     }
     // R(q_hat) -> q_hat
     const double dw = 2 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
@@ -267,7 +304,6 @@ __global__ __launch_bounds__(256) void k_chain(ut_gaussians g, SensorK s, const 
     dq[2] = (dyq - y * dot) * iq;
     dq[3] = (dzq - z * dot) * iq;
     // features: SH coefficients and the direction's dependence on the mean
-    const double vx = mx - s.o[0], vy = my - s.o[1], vz = mz - s.o[2];
     const double len = sqrt(vx * vx + vy * vy + vz * vz);
     double ex = 0, ey = 0, ez = 1;
     if (len > 0) { ex = vx / len; ey = vy / len; ez = vz / len; }
@@ -293,7 +329,7 @@ __global__ __launch_bounds__(256) void k_chain(ut_gaussians g, SensorK s, const 
         ddir[2] += dc * coef * GY[k][2];
       }
     }
-    dmean[0] = a[4]; dmean[1] = a[5]; dmean[2] = a[6];
+    dmean[0] += a[4]; dmean[1] += a[5]; dmean[2] += a[6];
     if (len > 0) {
       const double dd = ddir[0] * ex + ddir[1] * ey + ddir[2] * ez;
       dmean[0] += (ddir[0] - ex * dd) / len;

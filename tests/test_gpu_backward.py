@@ -70,6 +70,21 @@ def test_backward_matches_oracle_lidar_with_drop():
     _check(gpu, ref, label="lidar")
 
 
+def test_backward_matches_oracle_lidar_with_beam_divergence():
+    """The adjoint through the divergence filter: Sigma_hat and its dependence on the mean."""
+    g, s = synth.scene_lidar(2, n=4000, n_beams=16, n_az=256, n_phi=4, max_per_tile=32)
+    g["mean"] *= np.float32(0.05)
+    s["beam_divergence"] = 0.02
+    rng = np.random.default_rng(4)
+    R = 16 * 256
+    up = _as32(dict(feat=rng.standard_normal((3, R)), depth=0.1 * rng.standard_normal(R),
+                    alpha=rng.standard_normal(R), drop=rng.standard_normal(R)))
+    gpu, _ = _gpu_backward(g, s, up)
+    _, ol, _ = oracle.render(g, s)
+    ref = oracle.backward(g, s, ol, up)
+    _check(gpu, ref, label="lidar divergence")
+
+
 def test_backward_fd_on_64x64_copy_of_the_large_pinhole_scene():
     """2,000 particles as in the 1M-particle pinhole workload, 64x64 pinhole (fx=fy=40);
     upstream = gradient of mean |C - target| (target U[0,1], seed 7); 64 seeded particles
