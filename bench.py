@@ -73,7 +73,7 @@ def parse():
     return ap.parse_args()
 
 
-CAMERA_KERNEL = "k_composite<256, 1, 128, false>"
+CAMERA_KERNEL = "k_composite<256, 1, 128, false, false>"
 PROFILE_CMDS = {
     "stats": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_stats -o kt -- "
              "python -u bench.py --no-served --no-backward --no-cpu-baseline --steps 5 --warmup 1 --streams 1",
