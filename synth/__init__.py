@@ -96,6 +96,44 @@ def permute(g: dict, perm) -> dict:
     return subset(g, np.asarray(perm))
 
 
+def concat(a: dict, b: dict) -> dict:
+    """Two particle sets of the same SH degree and feature kind, one after the other."""
+    out = dict(a)
+    for k in ("mean", "quat", "log_scale"):
+        out[k] = np.ascontiguousarray(np.concatenate([a[k], b[k]], 1))
+    out["opacity_logit"] = np.concatenate([a["opacity_logit"], b["opacity_logit"]])
+    out["feat"] = np.ascontiguousarray(np.concatenate([a["feat"], b["feat"]], 2))
+    return out
+
+
+def actors(rng, g_background: dict, n_actors: int, per_actor: int, region, box=(4.5, 1.8, 1.5),
+           up_axis=2, scale=(0.02, 0.3), feat=None):
+    """Dynamic objects appended to a background set: per actor, ``per_actor`` particles in a
+    car-sized box of the object's own frame (centred on its origin), and an object-to-world
+    pose (yaw about ``up_axis``, centre uniform in ``region`` = [[lo, hi]] * 3).
+
+    Returns (particles, actor ids [N] int32 with -1 for the background, poses [n_actors, 7]
+    float32 = (qw, qx, qy, qz, tx, ty, tz)).  The background keeps its order and comes first."""
+    n = n_actors * per_actor
+    half = np.asarray(box, np.float64) / 2
+    mean = np.stack([rng.uniform(-h, h, n) for h in half])
+    if up_axis != 2:
+        mean = np.roll(mean, up_axis - 2, axis=0)
+    kind, deg = g_background["feat_kind"], g_background["sh_degree"]
+    obj = particles(rng, mean, scale[0], scale[1], deg, kind)
+    if feat is not None:
+        obj["feat"] = feat(rng, n)
+    yaw = rng.uniform(0, 2 * np.pi, n_actors)
+    q = np.zeros((n_actors, 4))
+    q[:, 0] = np.cos(yaw / 2)
+    q[:, 1 + up_axis] = np.sin(yaw / 2)
+    region = np.asarray(region, np.float64)
+    t = np.stack([rng.uniform(lo, hi, n_actors) for lo, hi in region], 1)
+    poses = np.concatenate([q, t], 1).astype(np.float32)
+    ids = np.concatenate([np.full(g_background["mean"].shape[1], -1), np.repeat(np.arange(n_actors), per_actor)])
+    return concat(g_background, obj), ids.astype(np.int32), poses
+
+
 # ----------------------------------------------------------------------------- poses
 def yaw_camera_pose(yaw: float) -> np.ndarray:
     """World (z up) -> camera axes (x right, y down, z forward) looking along yaw."""

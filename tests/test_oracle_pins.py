@@ -590,3 +590,113 @@ def test_beam_divergence_widens_without_scaling_opacity():
     sigma = 1 / (1 + np.exp(-np.float64(g["opacity_logit"][0])))
     assert a0["alpha"].max() <= a1["alpha"].max() <= sigma
     assert a1["alpha"].max() > 0.9 * sigma
+
+
+# ------------------------------------------------------------------ rigid actor transforms
+def _actor_case(seed=0, n_bg=300, n_actors=5, per_actor=40):
+    from oracle import actors as oa
+    rng = np.random.default_rng(seed)
+    g, _ = synth.scene_pinhole_small(seed, n=n_bg)
+    g, ids, poses = synth.actors(rng, g, n_actors, per_actor, [[-2, 2], [-1, 1], [3, 6]], up_axis=1)
+    poses = poses.astype(np.float64)
+    poses[:, :4] = rng.standard_normal((n_actors, 4))          # general (unnormalised) rotations
+    ids[rng.choice(len(ids), 7, replace=False)] = n_actors + 3  # out-of-range ids: background
+    return oa, g, ids, poses
+
+
+def test_actor_transform_matches_scipy_rigid_motion():
+    """mu_w = R_a mu + t and Sigma_w = R_a Sigma R_a^T, with R_a, R(q) and the composed rotation
+    all from scipy (quaternion product not used on this side)."""
+    from scipy.spatial.transform import Rotation
+    oa, g, ids, poses = _actor_case()
+    w = oa.actor_transform(g, ids, poses)
+    n = len(ids)
+    xyzw = lambda q: np.array([q[1], q[2], q[3], q[0]])
+    for i in range(n):
+        mu = g["mean"][:, i].astype(np.float64)
+        q = g["quat"][:, i].astype(np.float64)
+        S2 = np.diag(np.exp(2 * g["log_scale"][:, i].astype(np.float64)))
+        Sig = Rotation.from_quat(xyzw(q)).as_matrix() @ S2 @ Rotation.from_quat(xyzw(q)).as_matrix().T
+        Sig_w = Rotation.from_quat(xyzw(w["quat"][:, i])).as_matrix() @ S2 @ \
+            Rotation.from_quat(xyzw(w["quat"][:, i])).as_matrix().T
+        a = ids[i]
+        if 0 <= a < len(poses):
+            Ra = Rotation.from_quat(xyzw(poses[a, :4]))
+            np.testing.assert_allclose(w["mean"][:, i], Ra.apply(mu) + poses[a, 4:], rtol=0, atol=1e-12)
+            Rm = Ra.as_matrix()
+            np.testing.assert_allclose(Sig_w, Rm @ Sig @ Rm.T, rtol=0, atol=1e-12 * np.abs(Sig).max())
+            np.testing.assert_allclose(np.linalg.norm(w["quat"][:, i]), np.linalg.norm(q), rtol=1e-14)
+        else:
+            assert np.array_equal(w["mean"][:, i], mu) and np.array_equal(w["quat"][:, i], q)
+
+
+def test_actor_transform_identity_and_composition():
+    """The identity pose changes nothing; two successive poses equal their composition."""
+    from scipy.spatial.transform import Rotation
+    oa, g, ids, poses = _actor_case(1)
+    ident = np.tile([1.0, 0, 0, 0, 0, 0, 0], (len(poses), 1))
+    w = oa.actor_transform(g, ids, ident)
+    np.testing.assert_allclose(w["mean"], g["mean"], atol=1e-15)
+    np.testing.assert_allclose(w["quat"], g["quat"], atol=1e-15)
+    rng = np.random.default_rng(5)
+    p2 = np.concatenate([rng.standard_normal((len(poses), 4)), rng.standard_normal((len(poses), 3))], 1)
+    two = oa.actor_transform(oa.actor_transform(g, ids, poses), ids, p2)
+    xyzw = lambda q: np.array([q[1], q[2], q[3], q[0]])
+    comp = np.zeros_like(poses)
+    for a in range(len(poses)):
+        R1, R2 = Rotation.from_quat(xyzw(poses[a, :4])), Rotation.from_quat(xyzw(p2[a, :4]))
+        q = (R2 * R1).as_quat()
+        comp[a, :4] = [q[3], q[0], q[1], q[2]]
+        comp[a, 4:] = R2.apply(poses[a, 4:]) + p2[a, 4:]
+    one = oa.actor_transform(g, ids, comp)
+    np.testing.assert_allclose(two["mean"], one["mean"], atol=1e-12)
+    # quaternions agree up to sign (q and -q are the same rotation)
+    dots = np.abs(np.sum(two["quat"] * one["quat"], 0)) / np.sum(one["quat"] ** 2, 0)
+    np.testing.assert_allclose(dots, 1.0, atol=1e-12)
+
+
+def test_actor_transform_adjoint_matches_central_differences():
+    oa, g, ids, poses = _actor_case(2, n_bg=20, n_actors=3, per_actor=6)
+    rng = np.random.default_rng(3)
+    n = len(ids)
+    gm, gq = rng.standard_normal((3, n)), rng.standard_normal((4, n))
+    dm, dq, dp = oa.actor_transform_backward(g, ids, poses, gm, gq)
+    base = {k: np.asarray(v, np.float64) for k, v in g.items() if k in ("mean", "quat")}
+
+    def f(mean, quat, P):
+        w = oa.actor_transform(dict(g, mean=mean, quat=quat), ids, P)
+        return np.sum(w["mean"] * gm) + np.sum(w["quat"] * gq)
+    h = 1e-6
+    for name, arr, ref in (("mean", base["mean"], dm), ("quat", base["quat"], dq), ("pose", poses, dp)):
+        fd = np.zeros_like(arr)
+        for idx in np.ndindex(arr.shape):
+            ap, am = arr.copy(), arr.copy()
+            ap[idx] += h
+            am[idx] -= h
+            args = lambda x: (x, base["quat"], poses) if name == "mean" else \
+                ((base["mean"], x, poses) if name == "quat" else (base["mean"], base["quat"], x))
+            fd[idx] = (f(*args(ap)) - f(*args(am))) / (2 * h)
+        np.testing.assert_allclose(ref, fd, atol=1e-7 * np.abs(fd).max(), rtol=1e-6, err_msg=name)
+
+
+def test_actor_render_invariant_under_common_rigid_motion():
+    """Moving every particle with one actor pose and the sensor by the same motion leaves the
+    image unchanged (SH degree 0: the colour has no direction to rotate)."""
+    from oracle import actors as oa
+    from scipy.spatial.transform import Rotation
+    g, s = synth.scene_pinhole_small(4, n=800)
+    ids = np.zeros(g["mean"].shape[1], np.int32)
+    Ra = Rotation.from_rotvec([0.3, -0.5, 0.2])
+    q = Ra.as_quat()
+    pose = np.array([[q[3], q[0], q[1], q[2], 1.5, -0.5, 2.0]])
+    gw = oa.actor_transform_f32(g, ids, pose)
+    Rm = Ra.as_matrix()
+    s_w = synth.pinhole(s["width"], s["height"], s["fx"], s["fy"],
+                        R_sw=np.asarray(s["R_sw"], np.float64) @ Rm.T,
+                        origin=Rm @ np.asarray(s["origin"], np.float64) + pose[0, 4:])
+    _, _, a = oracle.render(g, s)
+    _, _, b = oracle.render(gw, s_w)
+    for k in ("feat", "depth", "alpha"):
+        d = np.abs(np.asarray(a[k]) - np.asarray(b[k])) / max(1.0, np.abs(a[k]).max())
+        assert np.mean(d) < 1e-6 and np.quantile(d, 0.995) < 1e-4, (k, d.max())
+    assert (a["alpha"] > 0).mean() > 0.3
