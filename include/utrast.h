@@ -15,7 +15,9 @@
  *                         (on per-tile lists materialised by ut_tile_lists_fill)
  *
  * plus host set-up (ut_lidar_tiling = Alg. 1, ut_sensor_build = ray mask / summed-area
- * table of Appendix B) and a batched, persistent composite for serving.
+ * table of Appendix B), a batched, persistent composite for serving, and the scene graph's
+ * rigid actor transforms (ut_actor_transform and its adjoint) that bring dynamic objects'
+ * particles to the world frame before projection.
  *
  * Conventions shared by every call
  * --------------------------------
@@ -348,6 +350,43 @@ size_t ut_batch_workspace_bytes(int32_t n_items);
 ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items,
                              const ut_render_params* prm, void* queue_ws, size_t ws_bytes,
                              int32_t n_workgroups, ut_stream stream);
+
+/* Scene graph: rigid actor transforms (Sec. 3.1, scene representation).  Every particle
+ * belongs to the static background or to one dynamic object (actor); an actor's particles
+ * keep their means and covariances in the actor's own frame, and at render time the actor's
+ * SE(3) pose for the timestamp maps them to the world:
+ *   mu_w = R_a mu + t_a,   Sigma_w = R_a Sigma R_a^T,   i.e. q_w = q_a * q (Hamilton product),
+ * with R_a = R(q_a / |q_a|).  Scale, opacity and features are not changed, so the world-frame
+ * ut_gaussians shares those arrays with the object-frame one.  A moving sensor still sees
+ * each actor at the one pose given for the frame. */
+typedef struct {
+  float q[4];     /* rotation object -> world, (w, x, y, z); normalised by the kernels */
+  float t[3];     /* translation (world position of the object's origin) */
+  float pad_;     /* unused; keeps the record 32 bytes */
+} ut_actor_pose;
+
+/* Forward: mean_world[3][n], quat_world[4][n] (device, caller-allocated, must not overlap
+ * g->mean / g->quat) receive the world-frame means and quaternions of g (object-frame
+ * particles; only mean, quat and n are read).  actor: device int32 [n], the actor of each
+ * particle; an id outside [0, n_actors) is background and is copied unchanged.  poses:
+ * device [n_actors] (may be NULL when n_actors == 0).  FP64 arithmetic, float32 results.
+ * UT_ERR_ARG: NULL pointers, n < 0 or n_actors < 0. */
+ut_status ut_actor_transform(const ut_gaussians* g, const int32_t* actor, const ut_actor_pose* poses,
+                             int32_t n_actors, float* mean_world, float* quat_world, ut_stream stream);
+
+/* Adjoint of ut_actor_transform.  d_mean_world[3][n], d_quat_world[4][n]: device gradients
+ * with respect to the world-frame means and quaternions (for instance from
+ * ut_composite_backward on the transformed set).  Writes d_mean[3][n], d_quat[4][n] (device;
+ * may be the same buffers as d_mean_world / d_quat_world) with respect to the object-frame
+ * parameters in g, and, when d_pose is not NULL, d_pose: device float64 [n_actors][7] =
+ * gradient with respect to (q_w, q_x, q_y, q_z, t_x, t_y, t_z) of each pose (raw quaternion,
+ * through its normalisation), zeroed by the call and accumulated with atomics (summation
+ * order not fixed).  Background particles pass their gradients through.  UT_ERR_ARG as for
+ * the forward. */
+ut_status ut_actor_transform_backward(const ut_gaussians* g, const int32_t* actor,
+                                      const ut_actor_pose* poses, int32_t n_actors,
+                                      const float* d_mean_world, const float* d_quat_world,
+                                      float* d_mean, float* d_quat, double* d_pose, ut_stream stream);
 
 #ifdef __cplusplus
 }

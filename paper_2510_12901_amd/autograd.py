@@ -4,7 +4,8 @@ from __future__ import annotations
 
 import torch
 
-from .render import GaussianSet, Sensor, UT_ABK, backward, render, render_params
+from .render import (GaussianSet, Sensor, UT_ABK, actor_poses, actor_transform, actor_transform_backward, backward,
+                     render, render_params)
 
 
 class UTRender(torch.autograd.Function):
@@ -33,3 +34,32 @@ def render_differentiable(g: GaussianSet, sensor: Sensor, abk=UT_ABK, params=Non
     Returns (feat [3,R], depth [R], alpha [R], drop [R] or empty)."""
     return UTRender.apply(g.mean, g.quat, g.log_scale, g.opacity_logit, g.feat, g.sh_degree, g.feat_kind,
                           sensor, abk, params)
+
+
+class ActorTransform(torch.autograd.Function):
+    """Object-frame (mean, quat) and actor poses [n_actors, 7] -> world-frame (mean, quat);
+    the adjoint runs ut_actor_transform_backward (pose gradients included)."""
+    @staticmethod
+    def forward(ctx, mean, quat, poses, actor):
+        g = GaussianSet(mean.detach().contiguous(), quat.detach().contiguous(), mean.new_empty(0), mean.new_empty(0),
+                        mean.new_empty(0), 0, 0)
+        pz = actor_poses(poses.detach()).to(mean.device)
+        w = actor_transform(g, actor, pz)
+        ctx.state = (g, actor, pz)
+        return w.mean, w.quat
+
+    @staticmethod
+    def backward(ctx, g_mean, g_quat):
+        g, actor, pz = ctx.state
+        g_mean = torch.zeros_like(g.mean) if g_mean is None else g_mean
+        g_quat = torch.zeros_like(g.quat) if g_quat is None else g_quat
+        dm, dq, dp = actor_transform_backward(g, actor, pz, g_mean, g_quat, pose_grad=ctx.needs_input_grad[2])
+        return dm, dq, (dp.float() if dp is not None else None), None
+
+
+def transform_differentiable(g: GaussianSet, actor: torch.Tensor, poses: torch.Tensor) -> GaussianSet:
+    """World-frame particle set whose mean and quaternion carry gradients back to the
+    object-frame parameters and to the poses (a float32 [n_actors, 7] tensor)."""
+    mean_w, quat_w = ActorTransform.apply(g.mean, g.quat, poses, actor)
+    return g.with_params(mean_w, quat_w, g.log_scale, g.opacity_logit, g.feat)
+

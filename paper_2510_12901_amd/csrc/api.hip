@@ -441,4 +441,22 @@ ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items, const 
   return from_hip(launch_composite_batch(dev, n_items, total, counter, make_params(prm), n_workgroups, st));
 }
 
+ut_status ut_actor_transform(const ut_gaussians* g, const int32_t* actor, const ut_actor_pose* poses,
+                             int32_t n_actors, float* mean_world, float* quat_world, ut_stream stream) {
+  if (!g || g->n < 0 || n_actors < 0 || (n_actors > 0 && !poses)) return UT_ERR_ARG;
+  if (g->n > 0 && (!g->mean || !g->quat || !actor || !mean_world || !quat_world)) return UT_ERR_ARG;
+  return from_hip(launch_actor_transform(*g, actor, poses, n_actors, mean_world, quat_world, as_stream(stream)));
+}
+
+ut_status ut_actor_transform_backward(const ut_gaussians* g, const int32_t* actor,
+                                      const ut_actor_pose* poses, int32_t n_actors,
+                                      const float* d_mean_world, const float* d_quat_world,
+                                      float* d_mean, float* d_quat, double* d_pose, ut_stream stream) {
+  if (!g || g->n < 0 || n_actors < 0 || (n_actors > 0 && !poses)) return UT_ERR_ARG;
+  if (g->n > 0 && (!g->mean || !g->quat || !actor || !d_mean_world || !d_quat_world || !d_mean || !d_quat))
+    return UT_ERR_ARG;
+  return from_hip(launch_actor_backward(*g, actor, poses, n_actors, d_mean_world, d_quat_world, d_mean, d_quat,
+                                        d_pose, as_stream(stream)));
+}
+
 }  // extern "C"

@@ -70,4 +70,10 @@ hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const u
                            const ut_upstream& up, double* acc, const ut_gaussian_grads& grads,
                            int max_tile_rays, hipStream_t st);
 
+hipError_t launch_actor_transform(const ut_gaussians& g, const int32_t* actor, const ut_actor_pose* poses,
+                                  int n_act, float* mean_w, float* quat_w, hipStream_t st);
+hipError_t launch_actor_backward(const ut_gaussians& g, const int32_t* actor, const ut_actor_pose* poses,
+                                 int n_act, const float* dmw, const float* dqw, float* dmean, float* dquat,
+                                 double* d_pose, hipStream_t st);
+
 }  // namespace ut

@@ -436,3 +436,47 @@ class SensorPipeline:
         s.synchronize()
         self.sort_and_composite(s, composite_events)
         return self.out
+
+
+# ---------------------------------------------------------------------------- scene graph
+def actor_poses(poses) -> torch.Tensor:
+    """Pose table [n_actors, 7] (qw, qx, qy, qz, tx, ty, tz) -> the device layout of
+    ut_actor_pose, float32 [n_actors, 8] (last column unused)."""
+    p = torch.as_tensor(poses, dtype=torch.float32)
+    if p.dim() != 2 or p.shape[1] not in (7, 8):
+        raise ValueError("poses must be [n_actors, 7]")
+    if p.shape[1] == 7:
+        p = torch.cat([p, torch.zeros_like(p[:, :1])], 1)
+    return p.contiguous()
+
+
+def actor_transform(g: GaussianSet, actor: torch.Tensor, poses: torch.Tensor, stream=None) -> GaussianSet:
+    """World-frame copy of an object-frame particle set (ut_actor_transform): new mean and
+    quaternion tensors, the other arrays shared.  actor: int32 [N] on the device (-1 =
+    background); poses: [n_actors, 7] or [n_actors, 8] float32 on the device."""
+    _require_cuda(actor, torch.int32, "actor")
+    poses = poses if poses.shape[-1] == 8 and poses.is_cuda else actor_poses(poses).to(g.mean.device)
+    _require_cuda(poses, torch.float32, "poses")
+    mean_w, quat_w = torch.empty_like(g.mean), torch.empty_like(g.quat)
+    gc = g.c()
+    check(lib().ut_actor_transform(ref(gc), _ptr(actor), _ptr(poses), int(poses.shape[0]), _ptr(mean_w),
+                                   _ptr(quat_w), _stream(stream)), "ut_actor_transform")
+    return g.with_params(mean_w, quat_w, g.log_scale, g.opacity_logit, g.feat)
+
+
+def actor_transform_backward(g: GaussianSet, actor: torch.Tensor, poses: torch.Tensor, d_mean_world: torch.Tensor,
+                             d_quat_world: torch.Tensor, pose_grad: bool = True, stream=None):
+    """Adjoint of actor_transform: (d_mean, d_quat) with respect to the object-frame set and
+    the pose gradient float64 [n_actors, 7] (None when pose_grad is False)."""
+    _require_cuda(actor, torch.int32, "actor")
+    poses = poses if poses.shape[-1] == 8 and poses.is_cuda else actor_poses(poses).to(g.mean.device)
+    dmw, dqw = d_mean_world.contiguous().float(), d_quat_world.contiguous().float()
+    d_mean, d_quat = torch.empty_like(g.mean), torch.empty_like(g.quat)
+    n_act = int(poses.shape[0])
+    d_pose = torch.empty((n_act, 7), dtype=torch.float64, device=g.mean.device) if pose_grad else None
+    gc = g.c()
+    check(lib().ut_actor_transform_backward(ref(gc), _ptr(actor), _ptr(poses), n_act, _ptr(dmw), _ptr(dqw),
+                                            _ptr(d_mean), _ptr(d_quat), _ptr(d_pose), _stream(stream)),
+          "ut_actor_transform_backward")
+    return d_mean, d_quat, d_pose
+
