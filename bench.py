@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-time-dependent", action="store_true")
     ap.add_argument("--no-beam-divergence", action="store_true")
+    ap.add_argument("--no-actors", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--served-seconds", type=float, default=3.0)
     ap.add_argument("--vehicles", type=str, default="1,4,8")
@@ -353,6 +354,8 @@ def main():
         result["time_dependent"] = bench_time_dependent(ut, synth, dev, args)
     if not args.no_beam_divergence:
         result["beam_divergence"] = bench_beam_divergence(ut, synth, dev, args)
+    if not args.no_actors:
+        result["actors"] = bench_actors(ut, synth, dev, args, args.particles, log)
     if not args.no_served:
         from paper_2510_12901_amd import serve
         result["served"] = serve.bench_served(g, gl, sensors_np, sensors, dev, args, log)
@@ -434,6 +437,90 @@ def bench_beam_divergence(ut, synth, dev, args):
         row[label] = _time_sensor(ut, g, d, dev, args, stream)
     log(f"beam divergence lidar_128x2048_300k: {json.dumps(row)}")
     return {"lidar_128x2048_300k": row}
+
+
+def bench_actors(ut, synth, dev, args, n_particles, log):
+    """The multisensor frame with a scene graph: the last 100,032 of the 2,000,000 particles
+    form 64 car-sized actors (1,563 particles each, object frames, yaw poses on the ground),
+    transformed to the world once per frame (ut_actor_transform) before the 7 sensors render.
+    Reports the transform kernel against HBM (60 algorithmic bytes per particle: actor id,
+    mean and quaternion in; mean and quaternion out), its adjoint, and the frame with and
+    without the transform."""
+    import torch
+    n_act, per = 64, 1563
+    g_np, gl_np, sensors_np = synth.scene_multisensor(args.seed, n=n_particles)
+    n_bg = n_particles - n_act * per
+    rng = np.random.default_rng(args.seed + 17)
+    g_obj, ids, poses = synth.actors(rng, synth.subset(g_np, np.arange(n_bg)), n_act, per,
+                                     [[-40, 40], [-40, 40], [-4, -3]], up_axis=2)
+    lid_feat = np.concatenate([gl_np["feat"][:, :, :n_bg], synth.lidar_feat(rng, n_act * per)], 2)
+    g = ut.GaussianSet.from_numpy(g_obj, dev)
+    actor = torch.as_tensor(ids, device=dev)
+    P = ut.actor_poses(poses).to(dev)
+    lfeat = torch.as_tensor(lid_feat, device=dev)
+    stream = torch.cuda.current_stream()
+    gw = ut.actor_transform(g, actor, P)
+    glw = ut.GaussianSet(gw.mean, gw.quat, gw.log_scale, gw.opacity_logit, lfeat, 0, synth.FEAT_LIDAR)
+    sensors = [ut.Sensor(s, dev) for s in sensors_np]
+    pipes = [ut.SensorPipeline(glw if s.is_lidar else gw, s) for s in sensors]
+
+    def transform():
+        ut.actor_transform(g, actor, P, out=gw, stream=stream)   # into the world set the pipelines read
+
+    def frame(with_transform):
+        if with_transform:
+            transform()
+        for p in pipes:
+            p.project_and_count(stream)
+        stream.synchronize()
+        for p in pipes:
+            p.sort_and_composite(stream)
+
+    reps = 50
+    for _ in range(5):
+        transform()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        transform()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_us = e0.elapsed_time(e1) / reps * 1e3
+    gmw = torch.randn_like(g.mean)
+    gqw = torch.randn_like(g.quat)
+    ut.actor_transform_backward(g, actor, P, gmw, gqw)
+    e0.record(stream)
+    for _ in range(reps):
+        ut.actor_transform_backward(g, actor, P, gmw, gqw)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    b_us = e0.elapsed_time(e1) / reps * 1e3
+    row = {}
+    for label, wt in (("with_transform", True), ("pre_transformed", False)):
+        for _ in range(SETUP_FRAMES + args.warmup):
+            frame(wt)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            frame(wt)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        row[label + "_ms"] = round(float(np.median(times)) * 1e3, 3)
+    n = g.n
+    n_obj = n_act * per
+    fwd_bytes = 60 * n
+    # adjoint: id, world gradients in, object gradients out for every particle (60 B); the
+    # object-frame mean and quaternion are read for actor particles only (+28 B)
+    bwd_bytes = 60 * n + 28 * n_obj
+    res = {"workload": f"{n:,} particles, {n_act} actors x {per} particles; multisensor frame (7 sensors, one stream)",
+           "transform_us": round(t_us, 2), "transform_gbps": round(fwd_bytes / t_us / 1e3, 1),
+           "transform_frac_hbm": round(fwd_bytes / t_us / 1e3 / PEAK_HBM_GBS, 3),
+           "backward_us": round(b_us, 2), "backward_gbps": round(bwd_bytes / b_us / 1e3, 1),
+           "backward_frac_hbm": round(bwd_bytes / b_us / 1e3 / PEAK_HBM_GBS, 3),
+           "bytes_per_particle": {"forward": 60, "backward": "60 (background), 88 (actor)"}, **row}
+    log(f"actors: {json.dumps(res)}")
+    return res
 
 
 def bench_time_dependent(ut, synth, dev, args):

@@ -450,18 +450,26 @@ def actor_poses(poses) -> torch.Tensor:
     return p.contiguous()
 
 
-def actor_transform(g: GaussianSet, actor: torch.Tensor, poses: torch.Tensor, stream=None) -> GaussianSet:
+def actor_transform(g: GaussianSet, actor: torch.Tensor, poses: torch.Tensor, out: GaussianSet | None = None,
+                    stream=None) -> GaussianSet:
     """World-frame copy of an object-frame particle set (ut_actor_transform): new mean and
-    quaternion tensors, the other arrays shared.  actor: int32 [N] on the device (-1 =
-    background); poses: [n_actors, 7] or [n_actors, 8] float32 on the device."""
+    quaternion tensors (or those of ``out``, rewritten), the other arrays shared.  actor:
+    int32 [N] on the device (-1 = background); poses: [n_actors, 7] or [n_actors, 8] float32."""
     _require_cuda(actor, torch.int32, "actor")
     poses = poses if poses.shape[-1] == 8 and poses.is_cuda else actor_poses(poses).to(g.mean.device)
     _require_cuda(poses, torch.float32, "poses")
-    mean_w, quat_w = torch.empty_like(g.mean), torch.empty_like(g.quat)
+    if out is not None:
+        _require_cuda(out.mean, torch.float32, "out.mean")
+        _require_cuda(out.quat, torch.float32, "out.quat")
+        if out.mean.shape != g.mean.shape or out.quat.shape != g.quat.shape:
+            raise ValueError("out must have the shape of g")
+        mean_w, quat_w = out.mean, out.quat
+    else:
+        mean_w, quat_w = torch.empty_like(g.mean), torch.empty_like(g.quat)
     gc = g.c()
     check(lib().ut_actor_transform(ref(gc), _ptr(actor), _ptr(poses), int(poses.shape[0]), _ptr(mean_w),
                                    _ptr(quat_w), _stream(stream)), "ut_actor_transform")
-    return g.with_params(mean_w, quat_w, g.log_scale, g.opacity_logit, g.feat)
+    return out if out is not None else g.with_params(mean_w, quat_w, g.log_scale, g.opacity_logit, g.feat)
 
 
 def actor_transform_backward(g: GaussianSet, actor: torch.Tensor, poses: torch.Tensor, d_mean_world: torch.Tensor,
