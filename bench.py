@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--no-time-dependent", action="store_true")
     ap.add_argument("--no-beam-divergence", action="store_true")
     ap.add_argument("--no-actors", action="store_true")
+    ap.add_argument("--host-count", action="store_true",
+                    help="read each sensor's pair total on the host before sorting (one mid-frame sync)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--served-seconds", type=float, default=3.0)
     ap.add_argument("--vehicles", type=str, default="1,4,8")
@@ -252,7 +254,17 @@ def main():
     streams = [torch.cuda.Stream(device=dev) for _ in range(min(args.streams, len(pipes)))]
     torch.cuda.synchronize()
 
+    device_count = False
+
     def frame(events=None):
+        if device_count:
+            # the pair totals stay on the GPU: each sensor's whole render is enqueued on its
+            # stream at once (capacities from the set-up frames; overflow checked afterwards)
+            for i, p in enumerate(pipes):
+                st = streams[i % len(streams)]
+                p.project_and_count(st)
+                p.sort_and_composite_device(st, None if events is None else events[i])
+            return
         # every sensor's projection + pair count first, one host synchronisation for the
         # seven pair totals, then every sensor's sort + compositing
         for i, p in enumerate(pipes):
@@ -267,6 +279,12 @@ def main():
     # before), so the pipelines are primed with SETUP_FRAMES untimed frames before the warm-up.
     for _ in range(SETUP_FRAMES):
         frame()
+    torch.cuda.synchronize()
+    if not args.host_count:
+        for p in pipes:
+            p.set_capacity(int(p.n_pairs * 1.25) + 4096)
+            p.clear_overflow()
+        device_count = True
     for _ in range(args.warmup):
         frame()
     torch.cuda.synchronize()
@@ -283,6 +301,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / K
+    if any(p.overflowed() for p in pipes):
+        raise RuntimeError("a sensor's pair total exceeded its capacity: frames incomplete")
     value = rays_per_frame * K / (t1 - t0) / 1e6
     comp_ms = np.array([[e[0].elapsed_time(e[1]) for e in evk] for evk in ev])   # [K, sensors]
     log(f"plain frame {ms_per_step:.2f} ms, {value:.1f} Mrays/s")

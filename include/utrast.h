@@ -285,6 +285,20 @@ ut_status ut_bin_and_sort(const ut_projected* p, int32_t n, const ut_sensor* s, 
                           size_t ws_bytes, ut_bin_lists* bins, uint64_t* n_pairs,
                           ut_stream stream);
 
+/* Step 2 without the host round trip: like ut_bin_sort, but the pair total P is read on the
+ * device from ws (as ut_bin_count left it), and every launch is sized for a capacity
+ * max_pairs chosen by the caller (bins->max_pairs >= max_pairs, pair_ws of at least
+ * ut_pair_workspace_bytes(max_pairs) bytes, max_pairs < 2^30).  If P > max_pairs nothing
+ * is emitted, every super-tile range is left empty (a composite then renders nothing) and
+ * *overflow (device uint32, may be NULL) is set to 1; it is never cleared by the library, so
+ * one flag can guard several calls: check it after the stream has completed and render
+ * again with a larger capacity.  The result is bit-identical to ut_bin_sort whenever P fits.
+ * Nothing is synchronised, so a whole frame (projection, count, this call, compositing) can
+ * be enqueued, or captured in a graph, without a host round trip. */
+ut_status ut_bin_sort_device(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws,
+                             size_t ws_bytes, void* pair_ws, size_t pair_ws_bytes, uint64_t max_pairs,
+                             ut_bin_lists* bins, uint32_t* overflow, ut_stream stream);
+
 /* Per-tile lists from the bins.  ut_tile_lists_count writes each tile's list length into
  * lists->ranges and turns it into [start, end) ranges; the total (the number of (tile,
  * particle) pairs) is copied to *n_pairs_host (pinned, asynchronous) if non-NULL.

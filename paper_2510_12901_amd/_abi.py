@@ -85,6 +85,7 @@ SIGNATURES = [
     ("ut_bin_count", i32, [P, i32, P, P, C.c_size_t, P, P]),
     ("ut_bin_sort", i32, [P, i32, P, P, C.c_size_t, P, C.c_size_t, C.c_uint64, P, P]),
     ("ut_bin_and_sort", i32, [P, i32, P, P, C.c_size_t, P, P, P]),
+    ("ut_bin_sort_device", i32, [P, i32, P, P, C.c_size_t, P, C.c_size_t, C.c_uint64, P, P, P]),
     ("ut_tile_lists_count", i32, [P, P, P, P, P, P]),
     ("ut_tile_lists_fill", i32, [P, P, P, P, P]),
     ("ut_composite_camera", i32, [P, P, P, P, P, P]),

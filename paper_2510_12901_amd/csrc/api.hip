@@ -316,6 +316,20 @@ ut_status ut_bin_sort(const ut_projected* p, int32_t n, const ut_sensor* s, void
   return from_hip(launch_bin_sort(*p, n, k, w, pw, n_pairs, *bins, as_stream(stream)));
 }
 
+ut_status ut_bin_sort_device(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws, size_t ws_bytes,
+                             void* pair_ws, size_t pair_ws_bytes, uint64_t max_pairs, ut_bin_lists* bins,
+                             uint32_t* overflow, ut_stream stream) {
+  if (n < 0 || !projected_ok(p, n) || !sensor_ok(s) || !ws || !bins || !bins->ranges ||
+      (max_pairs > 0 && (!bins->gauss || !pair_ws)))
+    return UT_ERR_ARG;
+  if (max_pairs > bins->max_pairs || max_pairs >= (1ull << 30)) return UT_ERR_CAPACITY;
+  CountWorkspace w = count_workspace(ws, n);
+  PairWorkspace pw = pair_workspace(pair_ws, max_pairs);
+  if (w.bytes > ws_bytes || (max_pairs > 0 && pw.bytes > pair_ws_bytes)) return UT_ERR_CAPACITY;
+  const SensorK k = make_sensor_k(s);
+  return from_hip(launch_bin_sort_device(*p, n, k, w, pw, max_pairs, *bins, overflow, as_stream(stream)));
+}
+
 ut_status ut_bin_and_sort(const ut_projected* p, int32_t n, const ut_sensor* s, void* ws, size_t ws_bytes,
                           ut_bin_lists* bins, uint64_t* n_pairs, ut_stream stream) {
   uint64_t P = 0;

@@ -435,7 +435,9 @@ __global__ void k_gather_counts(const uint32_t* __restrict__ order, const uint32
 __global__ __launch_bounds__(256) void k_duplicate(const uint32_t* __restrict__ order, const uint64_t* __restrict__ offs,
                                                     const uint32_t* __restrict__ m_dev, const uint2* __restrict__ trect,
                                                     int n, int tiles_x, int SX, int wrap,
-                                                    uint32_t* __restrict__ pair_key, uint32_t* __restrict__ pair_gauss) {
+                                                    uint32_t* __restrict__ pair_key, uint32_t* __restrict__ pair_gauss,
+                                                    const uint32_t* __restrict__ emit) {
+  if (emit && *emit == 0u) return;   // device-count sort: nothing to emit, or over capacity
   __shared__ uint32_t s_off[4][64], s_g[4][64];
   __shared__ int s_x0[4][64], s_y0[4][64], s_w[4][64];
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
@@ -483,7 +485,9 @@ __global__ __launch_bounds__(256) void k_duplicate(const uint32_t* __restrict__ 
   }
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ tiles, uint64_t P, uint32_t* __restrict__ ranges, int n_tiles) {
+__global__ void k_ranges(const uint32_t* __restrict__ tiles, uint64_t P_max, const uint32_t* __restrict__ P_dev,
+                         uint32_t* __restrict__ ranges, int n_tiles) {
+  const uint64_t P = P_dev ? (uint64_t)*P_dev : P_max;
   const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (i >= P) return;
   const uint32_t t = tiles[i];
@@ -613,6 +617,7 @@ PairWorkspace pair_workspace(void* base, uint64_t n_pairs) {
   w.tkB = reinterpret_cast<uint32_t*>(take(4 * mp));
   w.tv = reinterpret_cast<uint32_t*>(take(4 * mp));
   w.hist = reinterpret_cast<uint32_t*>(take(radix_ws_bytes(mp)));
+  w.n_dev = reinterpret_cast<uint32_t*>(take(4));
   w.bytes = o;
   return w;
 }
@@ -649,12 +654,47 @@ hipError_t launch_bin_sort(const ut_projected& p, int n, const SensorK& s, Count
   const int blocks = (n + 255) / 256;
   hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(256), 0, st, ws.dvA, ws.offs, ws.m_dev,
                      reinterpret_cast<const uint2*>(p.trect), n, s.tiles_x, s.super_x, s.kind == UT_LIDAR ? 1 : 0,
-                     pw.tkA, v_first);
+                     pw.tkA, v_first, nullptr);
   uint32_t *kr, *vr;
   e = radix_sort(pw.tkA, pw.tkB, v_first, v_second, (size_t)n_pairs, nullptr, bits, pw.hist, st, &kr, &vr);
   if (e != hipSuccess) return e;
   const unsigned rb = (unsigned)((n_pairs + 255) / 256);
-  hipLaunchKernelGGL(k_ranges, dim3(rb), dim3(256), 0, st, kr, n_pairs, bins.ranges, n_super);
+  hipLaunchKernelGGL(k_ranges, dim3(rb), dim3(256), 0, st, kr, n_pairs, nullptr, bins.ranges, n_super);
+  return hipGetLastError();
+}
+
+namespace {
+// The pair total of the count step against the capacity: the sort's device count is the
+// total when it fits, else 0 (nothing is emitted) and the overflow flag is raised.
+__global__ void k_pair_guard(const uint64_t* __restrict__ total, uint64_t max_pairs, uint32_t* __restrict__ n_dev,
+                             uint32_t* __restrict__ overflow) {
+  if (threadIdx.x != 0) return;
+  const uint64_t P = *total;
+  const bool fits = P <= max_pairs;
+  n_dev[0] = fits ? (uint32_t)P : 0u;
+  if (!fits && overflow) overflow[0] = 1u;
+}
+}  // namespace
+
+hipError_t launch_bin_sort_device(const ut_projected& p, int n, const SensorK& s, CountWorkspace& ws,
+                                  PairWorkspace& pw, uint64_t max_pairs, const ut_bin_lists& bins,
+                                  uint32_t* overflow, hipStream_t st) {
+  const int n_super = s.super_x * s.super_y;
+  hipError_t e = fill_u32(bins.ranges, 0u, 2 * (size_t)n_super, st);
+  if (e != hipSuccess || max_pairs == 0 || n == 0) return e;
+  hipLaunchKernelGGL(k_pair_guard, dim3(1), dim3(64), 0, st, ws.total, max_pairs, pw.n_dev, overflow);
+  const int bits = tile_bits(n_super);
+  uint32_t* v_first = (radix_passes(bits) % 2) ? pw.tv : bins.gauss;
+  uint32_t* v_second = (radix_passes(bits) % 2) ? bins.gauss : pw.tv;
+  const int blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(256), 0, st, ws.dvA, ws.offs, ws.m_dev,
+                     reinterpret_cast<const uint2*>(p.trect), n, s.tiles_x, s.super_x, s.kind == UT_LIDAR ? 1 : 0,
+                     pw.tkA, v_first, pw.n_dev);
+  uint32_t *kr, *vr;
+  e = radix_sort(pw.tkA, pw.tkB, v_first, v_second, (size_t)max_pairs, pw.n_dev, bits, pw.hist, st, &kr, &vr);
+  if (e != hipSuccess) return e;
+  const unsigned rb = (unsigned)((max_pairs + 255) / 256);
+  hipLaunchKernelGGL(k_ranges, dim3(rb), dim3(256), 0, st, kr, max_pairs, pw.n_dev, bins.ranges, n_super);
   return hipGetLastError();
 }
 

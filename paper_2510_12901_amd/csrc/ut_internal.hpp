@@ -29,6 +29,7 @@ struct CountWorkspace {
 struct PairWorkspace {
   uint32_t *tkA, *tkB, *tv;          // pair tile keys ping-pong, pair value scratch [P]
   uint32_t* hist;                    // the pair sort's digit offsets, look-back words, tickets
+  uint32_t* n_dev;                   // pair count on the device (the device-count sort)
   size_t bytes;
 };
 CountWorkspace count_workspace(void* base, int n);
@@ -37,6 +38,9 @@ PairWorkspace pair_workspace(void* base, uint64_t n_pairs);
 hipError_t launch_bin_count(const ut_projected& p, int n, const SensorK& s, CountWorkspace& ws, hipStream_t st);
 hipError_t launch_bin_sort(const ut_projected& p, int n, const SensorK& s, CountWorkspace& ws,
                            PairWorkspace& pw, uint64_t n_pairs, const ut_bin_lists& bins, hipStream_t st);
+hipError_t launch_bin_sort_device(const ut_projected& p, int n, const SensorK& s, CountWorkspace& ws,
+                                  PairWorkspace& pw, uint64_t max_pairs, const ut_bin_lists& bins,
+                                  uint32_t* overflow, hipStream_t st);
 hipError_t launch_tile_lists_count(const ut_projected& p, const SensorK& s, const ut_bin_lists& bins,
                                    const ut_tile_lists& lists, hipStream_t st);
 hipError_t launch_tile_lists_fill(const ut_projected& p, const SensorK& s, const ut_bin_lists& bins,

@@ -384,6 +384,8 @@ class SensorPipeline:
         self.total = torch.zeros(1, dtype=torch.int64).pin_memory()
         self.bins: BinLists | None = None
         self.n_pairs = 0
+        self.capacity = 0                 # pair capacity of the device-count path
+        self.overflow = torch.zeros(1, dtype=torch.int32, device=dev)
 
     def _ensure_bins(self, P: int):
         dev = self.g.mean.device
@@ -421,6 +423,49 @@ class SensorPipeline:
               "ut_composite")
         if composite_events is not None:
             composite_events[1].record(stream)
+
+    def set_capacity(self, max_pairs: int):
+        """Size the bins and the pair workspace for the device-count path (no host round trip
+        between counting and sorting); a frame whose pair total exceeds max_pairs raises the
+        overflow flag and renders nothing."""
+        max_pairs = int(max_pairs)
+        self.pair_ws.ensure(int(lib().ut_pair_workspace_bytes(max_pairs)))
+        self._ensure_bins(max_pairs)
+        self.capacity = max_pairs
+
+    def sort_and_composite_device(self, stream=None, composite_events=None):
+        """Sort and composite right after project_and_count on the same stream, the pair total
+        staying on the device (ut_bin_sort_device).  Check ``overflowed()`` once the stream has
+        completed."""
+        if self.capacity <= 0:
+            raise ValueError("set_capacity first")
+        L = lib()
+        st = _stream(stream)
+        buf = self.ws.buf
+        pbuf = self.pair_ws.buf
+        check(L.ut_bin_sort_device(ref(self.p.c()), self.g.n, ref(self.sensor.c), buf.data_ptr(), buf.numel(),
+                                   pbuf.data_ptr(), pbuf.numel(), self.capacity, ref(self.bins.c()),
+                                   self.overflow.data_ptr(), st), "ut_bin_sort_device")
+        if composite_events is not None:
+            composite_events[0].record(stream)
+        fn = L.ut_composite_lidar if self.sensor.is_lidar else L.ut_composite_camera
+        check(fn(ref(self.p.c()), ref(self.bins.c()), ref(self.sensor.c), ref(self.params), ref(self.out.c()), st),
+              "ut_composite")
+        if composite_events is not None:
+            composite_events[1].record(stream)
+
+    def run_device(self, stream=None, composite_events=None):
+        """One render with no host synchronisation (device-count path)."""
+        s = stream or torch.cuda.current_stream()
+        self.project_and_count(s)
+        self.sort_and_composite_device(s, composite_events)
+        return self.out
+
+    def overflowed(self) -> bool:
+        return bool(self.overflow.item())
+
+    def clear_overflow(self):
+        self.overflow.zero_()
 
     def composite_only(self, stream=None, out: RenderOut | None = None):
         L = lib()
