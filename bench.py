@@ -28,15 +28,16 @@ if ROOT not in sys.path:
 PEAK_FP64_TFLOPS = 78.6        # MI355X dense float64 vector (FMA = 2 FLOPs)
 PEAK_HBM_GBS = 8000.0
 # float64 FLOPs (FMA = 2) of the compositing's work, counted from the arithmetic of the
-# method: every (ray, list entry) pair a ray evaluates needs the whitened geometry w = M d (15),
-# c = a x w (9), c.c (5), w.w (5) and the pre-test c.c > cut * w.w (1); a pair that passes the
-# pre-test adds 1/w.w with two Newton steps (9), a.w (5), t* (1), D^2 (1), the exponent (1),
-# exp (17), alpha = min(sigma rho, alpha_max) (2), w = alpha T (1), 4 accumulations (8) and
-# T (1 - alpha) (2).  The kernel counts both kinds of pair per ray (n_visit, n_pass) in an
+# method in the record's quadric form: every (ray, list entry) pair a ray evaluates needs
+# d^T B d from the ray's six monomials (11), d^T B v (5), num = v^T B v d^T B d - (d^T B v)^2
+# (3), the cut (2) and the pre-test num > cut d^T B d (1); a pair that passes the pre-test adds
+# 1/d^T B d with two Newton steps (9), t* (1), D^2 = max(num, 0) / d^T B d (2), the exponent
+# (1), exp (17), alpha = min(sigma rho, alpha_max) (2), w = alpha T (1), 4 accumulations (8)
+# and T (1 - alpha) (2).  The kernel counts both kinds of pair per ray (n_visit, n_pass) in an
 # untimed pass; entries dropped by the tile-cone test are never evaluated and not counted.
-FLOPS_PER_VISIT = 35
+FLOPS_PER_VISIT = 22
 SETUP_FRAMES = 8
-FLOPS_PER_PASS = 47
+FLOPS_PER_PASS = 43
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "composite_traffic.json")
 
 

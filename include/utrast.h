@@ -131,7 +131,7 @@ typedef struct {
    * across the beam at its range r = |mu - origin| before projection:
    * Sigma_hat = Sigma + (r tan(beam_divergence / 2))^2 (I - d d^T), d = (mu - origin) / r,
    * with the opacity left unscaled; the UT's sigma points use the lower Cholesky factor L of
-   * Sigma_hat and the record holds M = L^{-1}.  origin is the frame-start origin for moving
+   * Sigma_hat and the compositing record holds Sigma_hat^{-1}.  origin is the frame-start origin for moving
    * sensors.  Must be 0 for cameras (UT_ERR_ARG otherwise).  The adjoint differentiates
    * the filter too (the mean moves the smoothing term). */
   double beam_divergence;

@@ -63,6 +63,7 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
     }
   }
   const double Tf = T;
+  const RayQ rq = ray_q(dx, dy, dz);
   double S = 0.0;
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
   // the forward's tile cone, rebuilt from the same rays: entries it drops are skipped here too
@@ -123,14 +124,11 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
 #pragma unroll
       for (int k = 0; k < UT_ACC_FLOATS; ++k) g[k] = 0.0;
       if (j < (int)np) {
-        double am[3];
-        const double* ac = r.a;   // whitened centre seen from this ray's origin
-        if (mv) {
-          pair_centre(r, ex, ey, ez, am);
-          ac = am;
-        }
-        const PairGeom q = pair_geometry(r, ac, dx, dy, dz);
-        const PairResp pr = pair_response(ac, q);
+        Centre cv;   // the centre seen from this ray's origin
+        if constexpr (mv) cv = pair_centre(r, ex, ey, ez);
+        else cv = record_centre(r);
+        const PairGeom q = pair_geometry(r, cv, rq);
+        const PairResp pr = pair_response(q);
         const double tau = pr.tau;
         if (!pair_cut(q, cut_threshold(r.log_sigma, prm.log_alpha_min)) && tau >= s.near_) {
           const double a = pair_alpha(r, pr, kExp2Frac);
@@ -154,22 +152,18 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
               g[3] = dalpha * (a / exp_neg(r.log_sigma, kExp2Frac));   // dL/dsigma = dL/dalpha * rho
               dD2 = -0.5 * dalpha * a;
             }
-            // B = M^T M: B u = M^T r and B d = M^T w with u = mu - o - t* d
-            const double* M = r.m;
-            const double rx = __builtin_fma(-tau, q.w[0], ac[0]);   // M (mu - o - t* d)
-            const double ry = __builtin_fma(-tau, q.w[1], ac[1]);
-            const double rz = __builtin_fma(-tau, q.w[2], ac[2]);
-            const double bux = M[0] * rx + M[3] * ry + M[6] * rz;
-            const double buy = M[1] * rx + M[4] * ry + M[7] * rz;
-            const double buz = M[2] * rx + M[5] * ry + M[8] * rz;
-            const double bdx = M[0] * q.w[0] + M[3] * q.w[1] + M[6] * q.w[2];
-            const double bdy = M[1] * q.w[0] + M[4] * q.w[1] + M[7] * q.w[2];
-            const double bdz = M[2] * q.w[0] + M[5] * q.w[1] + M[8] * q.w[2];
+            // B d from the record's quadric and B u = B v - t* B d, u = mu - o - t* d
+            double bd[3];
+            sym_apply(r.b, dx, dy, dz, bd);
+            const double bdx = bd[0], bdy = bd[1], bdz = bd[2];
+            const double bux = __builtin_fma(-tau, bdx, cv.bv[0]);
+            const double buy = __builtin_fma(-tau, bdy, cv.bv[1]);
+            const double buz = __builtin_fma(-tau, bdz, cv.bv[2]);
             const uint32_t gi = sh_g[jj];
             const double ux = ((double)mean[gi] - ox) - tau * dx;
             const double uy = ((double)mean[n + gi] - oy) - tau * dy;
             const double uz = ((double)mean[2 * n + gi] - oz) - tau * dz;
-            const double t2 = 2.0 * dD2, ti = dtau * pr.iww;
+            const double t2 = 2.0 * dD2, ti = dtau * pr.idbd;
             g[4] = t2 * bux + ti * bdx;
             g[5] = t2 * buy + ti * bdy;
             g[6] = t2 * buz + ti * bdz;

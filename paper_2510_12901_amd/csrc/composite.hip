@@ -93,6 +93,9 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
       sz = __builtin_fma(dz[k], il, sz);
     }
   }
+  RayQ rq[RPL];
+#pragma unroll
+  for (int k = 0; k < RPL; ++k) rq[k] = ray_q(dx[k], dy[k], dz[k]);
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
   const unsigned long long lt = (1ull << lane) - 1ull;
   if (threadIdx.x < 32) sm.etab[threadIdx.x] = kExp2Frac[threadIdx.x];
@@ -178,17 +181,14 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
           if (rdone[k]) continue;
-          double am[3];
-          const double* a = r.a;
-          if constexpr (MOVING) {
-            pair_centre(r, ex[k], ey[k], ez[k], am);
-            a = am;
-          }
-          const PairGeom q = pair_geometry(r, a, dx[k], dy[k], dz[k]);
+          Centre cv;
+          if constexpr (MOVING) cv = pair_centre(r, ex[k], ey[k], ez[k]);
+          else cv = record_centre(r);
+          const PairGeom q = pair_geometry(r, cv, rq[k]);
           if constexpr (STATS) ++nvisit[k];
           if (pair_cut(q, cut_threshold(r.log_sigma, prm.log_alpha_min))) continue;
           if constexpr (STATS) ++npass[k];
-          const PairResp pr = pair_response(a, q);
+          const PairResp pr = pair_response(q);
           const double tau = pr.tau;
           if (tau < s.near_) continue;
           const double alpha = __builtin_fmin(pair_alpha(r, pr, sm.etab), prm.alpha_max);
@@ -247,8 +247,11 @@ __device__ __forceinline__ int xcd_tile(int b, int n_tiles) {
   return t < n_tiles ? t : -1;
 }
 
+// Register budget: one ray per lane keeps the ray, its six quadratic monomials and the
+// accumulators in 128 VGPRs (4 waves per SIMD) with no spill in the pair loop; two rays per
+// lane take 3 waves.
 template <int BLOCK, int RPL, int BATCH, bool STATS, bool MOVING>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void k_composite(SensorK s, const Record* __restrict__ rec,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(RPL == 1 ? 4 : 3))) void k_composite(SensorK s, const Record* __restrict__ rec,
                                                       const uint2* __restrict__ trect,
                                                       const uint32_t* __restrict__ bgauss,
                                                       const uint32_t* __restrict__ branges, int n_tiles,

@@ -109,11 +109,12 @@ __device__ __forceinline__ uint32_t depth_key(float mx, float my, float mz, cons
 // LiDAR beam divergence (Sec. 3.2, LiDAR appendix): the particle is smoothed across the beam
 // at its range r, Sigma_hat = Sigma + (r tan(theta/2))^2 (I - d d^T) with Sigma = L L^T on
 // entry (L = S R^T's transpose, column-scaled rotation), and the opacity is not rescaled.  On
-// return L holds the lower Cholesky factor of Sigma_hat and the record's M = L^{-1},
-// a = M (mu - o), so the compositing response is exp(-(x-mu)^T Sigma_hat^{-1} (x-mu) / 2).
+// return L holds the lower Cholesky factor of Sigma_hat, m = L^{-1} and a = m (mu - o), so the
+// record's quadric is Sigma_hat^{-1} = m^T m and the compositing response is
+// exp(-(x-mu)^T Sigma_hat^{-1} (x-mu) / 2).
 // false if Sigma_hat is not numerically positive definite.
 __device__ __forceinline__ bool beam_divergence_filter(const SensorK& s, float mx, float my, float mz,
-                                                       double L[9], Record& r) {
+                                                       double L[9], double m[9], double a[3]) {
   const double vx = (double)mx - s.o[0], vy = (double)my - s.o[1], vz = (double)mz - s.o[2];
   const double range = sqrt(vx * vx + vy * vy + vz * vz);
   if (!(range > 0)) return true;
@@ -142,12 +143,12 @@ __device__ __forceinline__ bool beam_divergence_filter(const SensorK& s, float m
   // M = L^{-1}, lower triangular
   const double i00 = 1.0 / l00, i11 = 1.0 / l11, i22 = 1.0 / l22;
   const double i10 = -l10 * i00 * i11, i21 = -l21 * i11 * i22, i20 = -(l20 * i00 + l21 * i10) * i22;
-  r.m[0] = i00; r.m[1] = 0;   r.m[2] = 0;
-  r.m[3] = i10; r.m[4] = i11; r.m[5] = 0;
-  r.m[6] = i20; r.m[7] = i21; r.m[8] = i22;
-  r.a[0] = i00 * vx;
-  r.a[1] = __builtin_fma(i10, vx, i11 * vy);
-  r.a[2] = __builtin_fma(i20, vx, __builtin_fma(i21, vy, i22 * vz));
+  m[0] = i00; m[1] = 0;   m[2] = 0;
+  m[3] = i10; m[4] = i11; m[5] = 0;
+  m[6] = i20; m[7] = i21; m[8] = i22;
+  a[0] = i00 * vx;
+  a[1] = __builtin_fma(i10, vx, i11 * vy);
+  a[2] = __builtin_fma(i20, vx, __builtin_fma(i21, vy, i22 * vz));
   return true;
 }
 
@@ -170,6 +171,7 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
     bool ok = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(l0) && isfinite(l1) &&
               isfinite(l2) && isfinite(lg) && isfinite(qq) && qq > 0;
     Record r;
+    double M[9], A[3];   // M with M^T M = Sigma^{-1}, and A = M (mu - o)
     double Rm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, sc[3] = {1, 1, 1};
     if (ok) {
       const double inv = 1.0 / sqrt(qq);
@@ -182,13 +184,13 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
     // M = S^{-1} R^T and a = M (mu - o)
     {
       const double i0 = 1.0 / sc[0], i1 = 1.0 / sc[1], i2 = 1.0 / sc[2];
-      r.m[0] = Rm[0] * i0; r.m[1] = Rm[3] * i0; r.m[2] = Rm[6] * i0;
-      r.m[3] = Rm[1] * i1; r.m[4] = Rm[4] * i1; r.m[5] = Rm[7] * i1;
-      r.m[6] = Rm[2] * i2; r.m[7] = Rm[5] * i2; r.m[8] = Rm[8] * i2;
+      M[0] = Rm[0] * i0; M[1] = Rm[3] * i0; M[2] = Rm[6] * i0;
+      M[3] = Rm[1] * i1; M[4] = Rm[4] * i1; M[5] = Rm[7] * i1;
+      M[6] = Rm[2] * i2; M[7] = Rm[5] * i2; M[8] = Rm[8] * i2;
       const double vx = (double)mx - s.o[0], vy = (double)my - s.o[1], vz = (double)mz - s.o[2];
-      r.a[0] = __builtin_fma(r.m[0], vx, __builtin_fma(r.m[1], vy, r.m[2] * vz));
-      r.a[1] = __builtin_fma(r.m[3], vx, __builtin_fma(r.m[4], vy, r.m[5] * vz));
-      r.a[2] = __builtin_fma(r.m[6], vx, __builtin_fma(r.m[7], vy, r.m[8] * vz));
+      A[0] = __builtin_fma(M[0], vx, __builtin_fma(M[1], vy, M[2] * vz));
+      A[1] = __builtin_fma(M[3], vx, __builtin_fma(M[4], vy, M[5] * vz));
+      A[2] = __builtin_fma(M[6], vx, __builtin_fma(M[7], vy, M[8] * vz));
     }
     r.log_sigma = ok ? -log1p(exp(-(double)lg)) : -1e30;   // ln sigmoid(logit)
 
@@ -200,7 +202,7 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
 #pragma unroll
       for (int j = 0; j < 3; ++j) Lc[d * 3 + j] = sc[j] * Rm[d * 3 + j];
     if constexpr (KIND == UT_LIDAR) {
-      if (ok && s.div_tan > 0) ok = beam_divergence_filter(s, mx, my, mz, Lc, r);
+      if (ok && s.div_tan > 0) ok = beam_divergence_filter(s, mx, my, mz, Lc, M, A);
     }
 
     // unscented transform over 7 sigma points
@@ -329,6 +331,19 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
         f[c] = (g.feat_kind == UT_FEAT_CAMERA) ? (acc + 0.5 > 0 ? acc + 0.5 : 0.0) : acc;
       }
       r.feat[0] = f[0]; r.feat[1] = f[1]; r.feat[2] = f[2];
+      // the quadric form of the record: B = M^T M, B v = M^T A, v^T B v = A.A, trace(B) = |M|_F^2
+      r.b[0] = __builtin_fma(M[0], M[0], __builtin_fma(M[3], M[3], M[6] * M[6]));
+      r.b[1] = __builtin_fma(M[0], M[1], __builtin_fma(M[3], M[4], M[6] * M[7]));
+      r.b[2] = __builtin_fma(M[0], M[2], __builtin_fma(M[3], M[5], M[6] * M[8]));
+      r.b[3] = __builtin_fma(M[1], M[1], __builtin_fma(M[4], M[4], M[7] * M[7]));
+      r.b[4] = __builtin_fma(M[1], M[2], __builtin_fma(M[4], M[5], M[7] * M[8]));
+      r.b[5] = __builtin_fma(M[2], M[2], __builtin_fma(M[5], M[5], M[8] * M[8]));
+      r.bv[0] = __builtin_fma(M[0], A[0], __builtin_fma(M[3], A[1], M[6] * A[2]));
+      r.bv[1] = __builtin_fma(M[1], A[0], __builtin_fma(M[4], A[1], M[7] * A[2]));
+      r.bv[2] = __builtin_fma(M[2], A[0], __builtin_fma(M[5], A[1], M[8] * A[2]));
+      r.vbv = __builtin_fma(A[0], A[0], __builtin_fma(A[1], A[1], A[2] * A[2]));
+      r.trb = r.b[0] + r.b[3] + r.b[5];
+      r.pad = 0.0;
       const uint4* src = reinterpret_cast<const uint4*>(&r);
       uint4* dst = reinterpret_cast<uint4*>(rec + i);
 #pragma unroll

@@ -89,7 +89,8 @@ __device__ __forceinline__ void tile_cone_finish(double cmin, double sn, double 
 }
 
 // Conservative tile-cone test: true when no unit direction d within the cone can bring the
-// particle's response to alpha_min, i.e. h(d) = |a x Md|^2 - cut |Md|^2 > 0 on the whole cone.
+// particle's response to alpha_min, i.e. h(d) = |a x Md|^2 - cut |Md|^2 > 0 on the whole cone
+// (M^T M = Sigma^{-1}, a = M (mu - o); the record's quadric gives h without M).
 // With d = cos(phi) u + sin(phi) e, e a unit vector in span(e1, e2) and phi <= theta,
 //   h >= cos^2(phi) A - 2 sin(phi) cos(phi) B + sin^2(phi) C,
 // where A = h(u), B bounds the mixed term over all e and C is the smallest eigenvalue of the
@@ -102,44 +103,34 @@ template <bool MOVING>
 __device__ __forceinline__ bool cone_rejects(const Record* __restrict__ rp, const TileCone& tc,
                                              double log_alpha_min) {
   double cut = cut_threshold(rp->log_sigma, log_alpha_min);
-  double m[9], a[3];
+  double b[6];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) m[i] = rp->m[i];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) a[i] = rp->a[i];
+  for (int i = 0; i < 6; ++i) b[i] = rp->b[i];
+  Centre c = record_centre(*rp);
   if constexpr (MOVING) {
-    // seen from the tile's reference origin o + et: a - M et
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      a[i] -= __builtin_fma(m[3 * i], tc.et[0], __builtin_fma(m[3 * i + 1], tc.et[1], m[3 * i + 2] * tc.et[2]));
-  }
-  if constexpr (MOVING) {
+    // seen from the tile's reference origin o + et
+    c = pair_centre(*rp, tc.et[0], tc.et[1], tc.et[2]);
     // Rays from origins o + et + e, |e| <= emax: the whitened centre moves by M e, with
-    // |M e| <= |M|_F emax, so the distance to each ray's line is at least the one from the
-    // reference origin minus that.
+    // |M e| <= |M|_F emax and |M|_F^2 = trace(B), so the distance to each ray's line is at
+    // least the one from the reference origin minus that.
     if (cut < 0.0) return true;   // sigma < alpha_min: no ray reaches it
-    double mf = 0.0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) mf = __builtin_fma(m[i], m[i], mf);
-    const double r = __builtin_sqrt(cut) + __builtin_sqrt(mf) * tc.emax;
+    const double r = __builtin_sqrt(cut) + __builtin_sqrt(rp->trb) * tc.emax;
     cut = r * r;
   }
   cut += 0.05;
-  double w[3][3], x[3][3];   // w_k = M v_k and x_k = a x w_k for v = (u, e1, e2)
+  // h(d) = d^T Q d with Q = (v^T B v - cut) B - (B v)(B v)^T, i.e. |a x Md|^2 - cut |Md|^2
+  // for any M with M^T M = B and a = M v; H(i, j) = v_i^T Q v_j over v = (u, e1, e2)
   const double* v[3] = {tc.u, tc.e1, tc.e2};
+  double bvk[3][3], p[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      w[k][i] = __builtin_fma(m[3 * i], v[k][0], __builtin_fma(m[3 * i + 1], v[k][1], m[3 * i + 2] * v[k][2]));
-    x[k][0] = __builtin_fma(a[1], w[k][2], -(a[2] * w[k][1]));
-    x[k][1] = __builtin_fma(a[2], w[k][0], -(a[0] * w[k][2]));
-    x[k][2] = __builtin_fma(a[0], w[k][1], -(a[1] * w[k][0]));
+    sym_apply(b, v[k][0], v[k][1], v[k][2], bvk[k]);
+    p[k] = __builtin_fma(c.bv[0], v[k][0], __builtin_fma(c.bv[1], v[k][1], c.bv[2] * v[k][2]));
   }
+  const double s = c.vbv - cut;
   auto H = [&](int i, int j) {
-    const double xx = __builtin_fma(x[i][0], x[j][0], __builtin_fma(x[i][1], x[j][1], x[i][2] * x[j][2]));
-    const double ww = __builtin_fma(w[i][0], w[j][0], __builtin_fma(w[i][1], w[j][1], w[i][2] * w[j][2]));
-    return __builtin_fma(-cut, ww, xx);
+    const double q = __builtin_fma(v[i][0], bvk[j][0], __builtin_fma(v[i][1], bvk[j][1], v[i][2] * bvk[j][2]));
+    return __builtin_fma(s, q, -(p[i] * p[j]));
   };
   const double A = H(0, 0), H01 = H(0, 1), H02 = H(0, 2);
   const double H11 = H(1, 1), H12 = H(1, 2), H22 = H(2, 2);

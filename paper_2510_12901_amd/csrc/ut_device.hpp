@@ -22,14 +22,19 @@ constexpr int kSuper = UT_SUPER_TILE;
 
 // Per-particle compositing record written by the projection for one sensor, read
 // (gathered) by the compositing and adjoint kernels.  128 bytes = eight 16-byte chunks.
-// With M = S^{-1} R^T (so Sigma^{-1} = M^T M) and a = M (mu - o) fixed per particle and
-// sensor, a ray d gives w = M d, t* = a.w / w.w, r = a - t* w and D^2 = r.r: the distance
-// of maximum response and the squared Mahalanobis distance there.
+// The response along a ray o + t d is a quadric in t: with B = Sigma^{-1} and v = mu - o,
+// (t d - v)^T B (t d - v) is smallest at t* = d^T B v / d^T B d, where it equals
+// D^2 = (v^T B v d^T B d - (d^T B v)^2) / d^T B d.  B, B v and v^T B v are fixed per particle
+// and sensor, so a pair costs the two ray products d^T B d (from the ray's six quadratic
+// monomials) and d^T B v.
 struct alignas(16) Record {
-  double m[9];       // M, row-major: row j = R[:, j]^T / s_j
-  double a[3];       // M (mu - o), o = sensor origin
+  double b[6];       // B = Sigma^{-1}: b00, b01, b02, b11, b12, b22
+  double bv[3];      // B (mu - o), o = sensor origin
+  double vbv;        // (mu - o)^T B (mu - o)
   double log_sigma;  // ln(opacity): alpha = exp(ln sigma - D^2 / 2), and the pre-test threshold
   double feat[3];    // colour or LiDAR features evaluated at the particle's SH direction
+  double trb;        // trace(B) = |M|_F^2 for every M with M^T M = B
+  double pad;
 };
 static_assert(sizeof(Record) == UT_RECORD_BYTES, "record size must match the ABI");
 constexpr int kRecordChunks = UT_RECORD_BYTES / 16;
@@ -148,31 +153,70 @@ __device__ __forceinline__ void quat_rotate(const double q[4], const double v[3]
   r[2] = v[2] + 2.0 * (w * cz + dz);
 }
 
-// Response geometry of one (ray, particle) pair in the particle's whitened frame, where the
-// particle is the unit ball: w = M d and a = M (mu - o).  The whitened ray passes the centre at
-// squared distance D^2 = |a x w|^2 / |w|^2 and reaches the maximum response at
-// t* = (a . w) / |w|^2 (Sec. 3, the 3D response replacing the 2D splat).  The compositing and
-// the adjoint evaluate it through the same functions, so both take identical skip / clamp /
-// stop decisions.
-struct PairGeom {
-  double w[3];   // M d
-  double ww;     // w.w = d^T Sigma^{-1} d
-  double cc;     // |a x w|^2 = D^2 w.w
+// A ray direction with its quadratic monomials (the cross terms doubled), so that
+// d^T B d = b00 xx + b11 yy + b22 zz + b01 xy + b02 xz + b12 yz.
+struct RayQ {
+  double x, y, z;
+  double xx, yy, zz, xy, xz, yz;
 };
 
-// a is the whitened centre seen from the ray's origin: the record's a = M (mu - o) for a
+__device__ __forceinline__ RayQ ray_q(double x, double y, double z) {
+  RayQ r;
+  r.x = x; r.y = y; r.z = z;
+  r.xx = x * x; r.yy = y * y; r.zz = z * z;
+  r.xy = 2.0 * x * y; r.xz = 2.0 * x * z; r.yz = 2.0 * y * z;
+  return r;
+}
+
+// B s for a symmetric B stored as its six unique entries.
+__device__ __forceinline__ void sym_apply(const double b[6], double sx, double sy, double sz, double o[3]) {
+  o[0] = __builtin_fma(b[0], sx, __builtin_fma(b[1], sy, b[2] * sz));
+  o[1] = __builtin_fma(b[1], sx, __builtin_fma(b[3], sy, b[4] * sz));
+  o[2] = __builtin_fma(b[2], sx, __builtin_fma(b[4], sy, b[5] * sz));
+}
+
+// Response geometry of one (ray, particle) pair (Sec. 3, the 3D response replacing the 2D
+// splat).  The compositing and the adjoint evaluate it through the same functions, so both
+// take identical skip / clamp / stop decisions.
+struct PairGeom {
+  double dbd;   // d^T B d
+  double dbv;   // d^T B v
+  double num;   // v^T B v d^T B d - (d^T B v)^2 = D^2 d^T B d
+};
+
+// The particle's centre seen from the ray's origin: (B v, v^T B v) from the record for a
 // static sensor, pair_centre() for a ray with its own origin.
-__device__ __forceinline__ PairGeom pair_geometry(const Record& c, const double a[3], double dx, double dy,
-                                                  double dz) {
+struct Centre {
+  double bv[3];
+  double vbv;
+};
+
+__device__ __forceinline__ Centre record_centre(const Record& c) {
+  Centre q;
+  q.bv[0] = c.bv[0]; q.bv[1] = c.bv[1]; q.bv[2] = c.bv[2];
+  q.vbv = c.vbv;
+  return q;
+}
+
+// Centre for a ray whose origin lies e = o_i - o from the record's sensor origin o:
+// v_i = v - e, so B v_i = B v - B e and v_i^T B v_i = v^T B v - e^T (2 B v - B e).
+__device__ __forceinline__ Centre pair_centre(const Record& c, double ex, double ey, double ez) {
+  double be[3];
+  sym_apply(c.b, ex, ey, ez, be);
+  Centre q;
+  q.bv[0] = c.bv[0] - be[0]; q.bv[1] = c.bv[1] - be[1]; q.bv[2] = c.bv[2] - be[2];
+  const double s0 = __builtin_fma(2.0, c.bv[0], -be[0]), s1 = __builtin_fma(2.0, c.bv[1], -be[1]),
+               s2 = __builtin_fma(2.0, c.bv[2], -be[2]);
+  q.vbv = c.vbv - __builtin_fma(ex, s0, __builtin_fma(ey, s1, ez * s2));
+  return q;
+}
+
+__device__ __forceinline__ PairGeom pair_geometry(const Record& c, const Centre& v, const RayQ& d) {
   PairGeom p;
-  p.w[0] = __builtin_fma(c.m[0], dx, __builtin_fma(c.m[1], dy, c.m[2] * dz));
-  p.w[1] = __builtin_fma(c.m[3], dx, __builtin_fma(c.m[4], dy, c.m[5] * dz));
-  p.w[2] = __builtin_fma(c.m[6], dx, __builtin_fma(c.m[7], dy, c.m[8] * dz));
-  const double cx = __builtin_fma(a[1], p.w[2], -(a[2] * p.w[1]));
-  const double cy = __builtin_fma(a[2], p.w[0], -(a[0] * p.w[2]));
-  const double cz = __builtin_fma(a[0], p.w[1], -(a[1] * p.w[0]));
-  p.ww = __builtin_fma(p.w[0], p.w[0], __builtin_fma(p.w[1], p.w[1], p.w[2] * p.w[2]));
-  p.cc = __builtin_fma(cx, cx, __builtin_fma(cy, cy, cz * cz));
+  p.dbd = __builtin_fma(c.b[0], d.xx, __builtin_fma(c.b[3], d.yy, __builtin_fma(c.b[5], d.zz,
+          __builtin_fma(c.b[1], d.xy, __builtin_fma(c.b[2], d.xz, c.b[4] * d.yz)))));
+  p.dbv = __builtin_fma(v.bv[0], d.x, __builtin_fma(v.bv[1], d.y, v.bv[2] * d.z));
+  p.num = __builtin_fma(v.vbv, p.dbd, -(p.dbv * p.dbv));
   return p;
 }
 
@@ -182,30 +226,21 @@ __device__ __forceinline__ double cut_threshold(double log_sigma, double log_alp
   return __builtin_fma(2.0, log_sigma, 1e-3 - 2.0 * log_alpha_min);
 }
 
-// True when the pair cannot reach alpha_min: D^2 > cut, tested as |a x w|^2 > cut w.w.
-__device__ __forceinline__ bool pair_cut(const PairGeom& q, double cut) { return q.cc > q.ww * cut; }
+// True when the pair cannot reach alpha_min: D^2 > cut, tested as num > cut d^T B d.
+__device__ __forceinline__ bool pair_cut(const PairGeom& q, double cut) { return q.num > q.dbd * cut; }
 
 struct PairResp {
-  double iww;   // 1 / (w.w)
+  double idbd;  // 1 / d^T B d
   double tau;   // t*
-  double D2;    // squared whitened distance
+  double D2;    // squared Mahalanobis distance at t*
 };
 
-__device__ __forceinline__ PairResp pair_response(const double a[3], const PairGeom& q) {
+__device__ __forceinline__ PairResp pair_response(const PairGeom& q) {
   PairResp r;
-  r.iww = rcp_f64(q.ww);
-  const double aw = __builtin_fma(a[0], q.w[0], __builtin_fma(a[1], q.w[1], a[2] * q.w[2]));
-  r.tau = aw * r.iww;
-  r.D2 = q.cc * r.iww;
+  r.idbd = rcp_f64(q.dbd);
+  r.tau = q.dbv * r.idbd;
+  r.D2 = __builtin_fmax(q.num, 0.0) * r.idbd;
   return r;
-}
-
-// Whitened centre M (mu - o_i) for a ray whose origin o_i lies e = o_i - o from the sensor
-// origin o of the record: a - M e.
-__device__ __forceinline__ void pair_centre(const Record& c, double ex, double ey, double ez, double a[3]) {
-  a[0] = c.a[0] - __builtin_fma(c.m[0], ex, __builtin_fma(c.m[1], ey, c.m[2] * ez));
-  a[1] = c.a[1] - __builtin_fma(c.m[3], ex, __builtin_fma(c.m[4], ey, c.m[5] * ez));
-  a[2] = c.a[2] - __builtin_fma(c.m[6], ex, __builtin_fma(c.m[7], ey, c.m[8] * ez));
 }
 
 // Unclamped opacity of the pair, sigma * exp(-D^2 / 2), evaluated as exp(ln sigma - D^2 / 2).

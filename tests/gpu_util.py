@@ -9,7 +9,14 @@ import oracle
 AMBIG = 1e-9          # decisions closer than this to their threshold are ambiguous
 TOL = 1e-4            # max-abs bound on feat / depth / alpha / drop
 
-REC_DTYPE = np.dtype([("m", "<f8", 9), ("a", "<f8", 3), ("log_sigma", "<f8"), ("feat", "<f8", 3)])
+REC_DTYPE = np.dtype([("b", "<f8", 6), ("bv", "<f8", 3), ("vbv", "<f8"), ("log_sigma", "<f8"), ("feat", "<f8", 3),
+                      ("trb", "<f8"), ("pad", "<f8")])
+
+
+def rec_B(rec, i):
+    """The symmetric 3x3 B of record i from its six unique entries."""
+    b = rec["b"][i]
+    return np.array([[b[0], b[1], b[2]], [b[1], b[3], b[4]], [b[2], b[4], b[5]]])
 
 
 def to_np(t):

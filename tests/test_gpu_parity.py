@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import AMBIG, TOL, full_parity, gpu_render, to_np
+from gpu_util import AMBIG, TOL, full_parity, gpu_render, rec_B, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -98,8 +98,8 @@ def test_render_parity(name):
 
 
 def test_records_match_particle_definition():
-    """Record contents: exp(log opacity) = sigmoid(logit); M^T M = Sigma^{-1} with Sigma from
-    scipy's rotation; a = M (mu - o)."""
+    """Record contents: exp(log opacity) = sigmoid(logit); B = Sigma^{-1} with Sigma from
+    scipy's rotation; B v, v^T B v (v = mu - o) and trace(B)."""
     from scipy.spatial.transform import Rotation
     g, s = _scene("pinhole_sh3_posed")
     gp, _ = gpu_render(g, s)
@@ -112,10 +112,12 @@ def test_records_match_particle_definition():
         R = Rotation.from_quat([x, y, z, w]).as_matrix()
         sc = np.exp(g["log_scale"][:, i].astype(np.float64))
         B = np.linalg.inv(R @ np.diag(sc * sc) @ R.T)
-        M = rec["m"][i].reshape(3, 3)
-        np.testing.assert_allclose(M.T @ M, B, rtol=1e-9, atol=1e-9 * np.abs(B).max())
+        Bg = rec_B(rec, i)
+        np.testing.assert_allclose(Bg, B, rtol=1e-9, atol=1e-9 * np.abs(B).max())
         v = g["mean"][:, i].astype(np.float64) - o
-        np.testing.assert_allclose(rec["a"][i], M @ v, rtol=1e-12, atol=1e-12 * np.abs(M @ v).max())
+        np.testing.assert_allclose(rec["bv"][i], B @ v, rtol=1e-9, atol=1e-9 * np.abs(B @ v).max())
+        np.testing.assert_allclose(rec["vbv"][i], v @ B @ v, rtol=1e-9)
+        np.testing.assert_allclose(rec["trb"][i], np.trace(B), rtol=1e-9)
         np.testing.assert_allclose(np.exp(rec["log_sigma"][i]), 1 / (1 + np.exp(-np.float64(g["opacity_logit"][i]))),
                                    rtol=1e-14)
 
@@ -255,9 +257,8 @@ def test_batched_composite_with_moving_and_static_sensors():
 
 
 def test_beam_divergence_records():
-    """With beam divergence the record holds M = L^{-1} for the lower Cholesky factor L of
-    Sigma_hat = Sigma + (r tan(theta/2))^2 (I - d d^T) (built here with scipy's rotation), so
-    M is lower triangular with M^T M = Sigma_hat^{-1}."""
+    """With beam divergence the record's quadric is B = Sigma_hat^{-1} for
+    Sigma_hat = Sigma + (r tan(theta/2))^2 (I - d d^T) (built here with scipy's rotation)."""
     from scipy.spatial.transform import Rotation
     g_np, s_np = _scene("lidar_divergence")
     gp, _ = gpu_render(g_np, s_np)
@@ -273,8 +274,7 @@ def test_beam_divergence_records():
         r = np.linalg.norm(v)
         d = v / r
         S_hat = R @ np.diag(sc * sc) @ R.T + (r * np.tan(0.003)) ** 2 * (np.eye(3) - np.outer(d, d))
-        M = rec["m"][i].reshape(3, 3)
-        assert M[0, 1] == 0 and M[0, 2] == 0 and M[1, 2] == 0
         B = np.linalg.inv(S_hat)
-        np.testing.assert_allclose(M.T @ M, B, rtol=1e-8, atol=1e-8 * np.abs(B).max())
-        np.testing.assert_allclose(rec["a"][i], M @ v, rtol=1e-10, atol=1e-10 * np.abs(M @ v).max())
+        np.testing.assert_allclose(rec_B(rec, i), B, rtol=1e-8, atol=1e-8 * np.abs(B).max())
+        np.testing.assert_allclose(rec["bv"][i], B @ v, rtol=1e-8, atol=1e-8 * np.abs(B @ v).max())
+        np.testing.assert_allclose(rec["vbv"][i], v @ B @ v, rtol=1e-8)
