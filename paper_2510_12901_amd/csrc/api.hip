@@ -435,24 +435,34 @@ ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items, const 
       return UT_ERR_ARG;
     if (it.sensor->max_tile_rays > 256) return UT_ERR_UNSUPPORTED;   // one lane per ray of a 256-lane group
   }
-  for (int i = 0; i < n_items; ++i) {
-    const ut_batch_item& it = items[i];
-    BatchItemK k;
-    std::memset(&k, 0, sizeof k);
-    k.s = make_sensor_k(it.sensor);
-    k.rec = reinterpret_cast<const Record*>(it.proj->records);
-    k.trect = reinterpret_cast<const uint2*>(it.proj->trect);
-    k.gauss = it.bins->gauss;
-    k.ranges = it.bins->ranges;
-    k.out = *it.out;
-    k.n_tiles = ut_sensor_tiles(it.sensor);
-    k.tile_base = total;
-    total += k.n_tiles;
-    hipLaunchKernelGGL(k_write_item, dim3(1), dim3(64), 0, st, k, dev + i);
+  // static sensors first, then moving ones: each group runs in its own persistent launch (the
+  // per-ray origins of a moving sensor would otherwise cost every static pair registers)
+  int slot = 0, n_static = 0, static_tiles = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    total = 0;
+    for (int i = 0; i < n_items; ++i) {
+      const ut_batch_item& it = items[i];
+      if ((it.sensor->moving != 0) != (pass == 1)) continue;
+      BatchItemK k;
+      std::memset(&k, 0, sizeof k);
+      k.s = make_sensor_k(it.sensor);
+      k.rec = reinterpret_cast<const Record*>(it.proj->records);
+      k.trect = reinterpret_cast<const uint2*>(it.proj->trect);
+      k.gauss = it.bins->gauss;
+      k.ranges = it.bins->ranges;
+      k.out = *it.out;
+      k.n_tiles = ut_sensor_tiles(it.sensor);
+      k.tile_base = total;
+      total += k.n_tiles;
+      hipLaunchKernelGGL(k_write_item, dim3(1), dim3(64), 0, st, k, dev + slot);
+      ++slot;
+    }
+    if (pass == 0) { n_static = slot; static_tiles = total; }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return UT_ERR_DEVICE;
-  return from_hip(launch_composite_batch(dev, n_items, total, counter, make_params(prm), n_workgroups, st));
+  return from_hip(launch_composite_batch(dev, n_static, static_tiles, n_items - n_static, total, counter,
+                                         make_params(prm), n_workgroups, st));
 }
 
 ut_status ut_actor_transform(const ut_gaussians* g, const int32_t* actor, const ut_actor_pose* poses,

@@ -262,29 +262,27 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(RPL == 1 
   composite_tile<BLOCK, RPL, BATCH, STATS, MOVING>(s, rec, trect, bgauss, branges, tile, s.super_x * s.super_y, prm, out, sm);
 }
 
-// Persistent batched compositing: workgroups pull (request, tile) items from a counter.
-__global__ __launch_bounds__(kCamBlock) void k_composite_batch(const BatchItemK* __restrict__ items, int n_items,
-                                                          int total_tiles, uint32_t* counter,
-                                                          RenderParamsK prm) {
+// Persistent batched compositing: workgroups pull (request, tile) items from a counter.  Static
+// and moving sensors run in separate launches (MOVING), so each keeps the register budget of
+// its single-request kernel.
+template <bool MOVING>
+__global__ __launch_bounds__(kCamBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_composite_batch(
+    const BatchItemK* __restrict__ items, int n_items, int total_tiles, uint32_t* counter, RenderParamsK prm) {
   __shared__ CompositeShared<kCamBlock, kCamRpl, kCamBatch> sm;
   __shared__ uint32_t s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
     __syncthreads();
-    const uint32_t w = s_item;
+    // uniform by construction; saying so lets the item's sensor description live in SGPRs
+    const uint32_t w = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (w >= (uint32_t)total_tiles) break;
     int it = 0;
     while (it + 1 < n_items && (uint32_t)items[it + 1].tile_base <= w) ++it;
     const BatchItemK& I = items[it];
-    if (I.s.moving)
-      composite_tile<kCamBlock, kCamRpl, kCamBatch, false, true>(I.s, I.rec, I.trect, I.gauss, I.ranges,
+    composite_tile<kCamBlock, kCamRpl, kCamBatch, false, MOVING>(I.s, I.rec, I.trect, I.gauss, I.ranges,
                                                                   (int)(w - I.tile_base), I.s.super_x * I.s.super_y,
                                                                   prm, I.out, sm);
-    else
-      composite_tile<kCamBlock, kCamRpl, kCamBatch, false, false>(I.s, I.rec, I.trect, I.gauss, I.ranges,
-                                                                   (int)(w - I.tile_base), I.s.super_x * I.s.super_y,
-                                                                   prm, I.out, sm);
   }
 }
 
@@ -326,13 +324,17 @@ hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, con
   return hipGetLastError();
 }
 
-hipError_t launch_composite_batch(const BatchItemK* items_dev, int n_items, int total_tiles,
-                                  uint32_t* counter, const RenderParamsK& prm, int n_workgroups,
+hipError_t launch_composite_batch(const BatchItemK* items_dev, int n_static, int static_tiles, int n_moving,
+                                  int moving_tiles, uint32_t* counter, const RenderParamsK& prm, int n_workgroups,
                                   hipStream_t st) {
-  hipError_t e = fill_u32(counter, 0u, 1, st);
-  if (e != hipSuccess || total_tiles == 0) return e;
-  hipLaunchKernelGGL(k_composite_batch, dim3(n_workgroups), dim3(kCamBlock), 0, st, items_dev, n_items, total_tiles,
-                     counter, prm);
+  hipError_t e = fill_u32(counter, 0u, 2, st);
+  if (e != hipSuccess) return e;
+  if (static_tiles > 0)
+    hipLaunchKernelGGL(k_composite_batch<false>, dim3(n_workgroups), dim3(kCamBlock), 0, st, items_dev, n_static,
+                       static_tiles, counter, prm);
+  if (moving_tiles > 0)
+    hipLaunchKernelGGL(k_composite_batch<true>, dim3(n_workgroups), dim3(kCamBlock), 0, st, items_dev + n_static,
+                       n_moving, moving_tiles, counter + 1, prm);
   return hipGetLastError();
 }
 

@@ -65,8 +65,8 @@ struct BatchItemK {
   int n_tiles;
   int tile_base;   // prefix over items of n_tiles
 };
-hipError_t launch_composite_batch(const BatchItemK* items_dev, int n_items, int total_tiles,
-                                  uint32_t* counter, const RenderParamsK& prm, int n_workgroups,
+hipError_t launch_composite_batch(const BatchItemK* items_dev, int n_static, int static_tiles, int n_moving,
+                                  int moving_tiles, uint32_t* counter, const RenderParamsK& prm, int n_workgroups,
                                   hipStream_t st);
 
 hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const ut_tile_lists& lists,
