@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--particles", type=int, default=2_000_000)
-    ap.add_argument("--streams", type=int, default=4, help="HIP streams the sensors of a frame are spread over")
+    ap.add_argument("--streams", type=int, default=7, help="HIP streams the sensors of a frame are spread over")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-time-dependent", action="store_true")
