@@ -483,6 +483,44 @@ class SensorPipeline:
         return self.out
 
 
+class FrameGraph:
+    """One frame of several sensor renders captured in a HIP graph (device-count path: no host
+    round trip inside the frame).  Each pipeline runs on its own stream forked from the
+    capture stream; replay() re-runs projection, binning, sort and compositing of every
+    sensor into the pipelines' own output buffers.  Every pipeline must have its capacity set
+    (SensorPipeline.set_capacity) and have run once eagerly (buffers sized); check the
+    pipelines' overflowed() after a replay has completed."""
+
+    def __init__(self, pipes, stream=None):
+        if any(p.capacity <= 0 for p in pipes):
+            raise ValueError("set_capacity on every pipeline before capturing")
+        self.pipes = list(pipes)
+        self.main = stream or torch.cuda.Stream()
+        self.side = [torch.cuda.Stream() for _ in self.pipes]
+        self.graph = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(self.graph, stream=self.main):
+            fork = torch.cuda.Event()
+            fork.record(self.main)
+            joins = []
+            for p, st in zip(self.pipes, self.side):
+                st.wait_event(fork)
+                p.project_and_count(st)
+                p.sort_and_composite_device(st)
+                e = torch.cuda.Event()
+                e.record(st)
+                joins.append(e)
+            for e in joins:
+                self.main.wait_event(e)
+        torch.cuda.synchronize()
+
+    def replay(self):
+        self.graph.replay()
+
+    def overflowed(self) -> bool:
+        return any(p.overflowed() for p in self.pipes)
+
+
 # ---------------------------------------------------------------------------- scene graph
 def actor_poses(poses) -> torch.Tensor:
     """Pose table [n_actors, 7] (qw, qx, qy, qz, tx, ty, tz) -> the device layout of
