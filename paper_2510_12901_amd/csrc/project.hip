@@ -102,6 +102,21 @@ __device__ __forceinline__ uint32_t depth_key(float mx, float my, float mz, cons
   return __float_as_uint(k);
 }
 
+// Image-axis interval [lo, hi] that contains the pinhole projection f * a / z + c of every point
+// of a ball of radius rho around camera-frame (a, z) seen in the (a, z) plane, z > rho: the
+// tangents of the viewing angle plus / minus the ball's angular radius.  False when the ball
+// reaches 90 degrees off axis (no finite bound).
+__device__ __forceinline__ bool pinhole_ball_range(double a, double z, double rho, double f, double c, double& lo,
+                                                   double& hi) {
+  const double t = a / z;
+  const double td = rho / sqrt(fmax(a * a + z * z - rho * rho, 0.0));
+  const double dp = 1.0 - t * td, dm = 1.0 + t * td;
+  if (!(dp > 0.0) || !(dm > 0.0) || !isfinite(td)) return false;
+  lo = f * ((t - td) / dm) + c;
+  hi = f * ((t + td) / dp) + c;
+  return true;
+}
+
 // DEG is the SH degree as a compile-time constant, so the (DEG+1)^2 x 3 coefficient loads are
 // unrolled and issued together instead of one dependent loop trip at a time.  KIND is the
 // sensor model, so each instantiation carries only its own projection code (the LiDAR and
@@ -152,7 +167,7 @@ __device__ __forceinline__ bool beam_divergence_filter(const SensorK& s, float m
   return true;
 }
 
-template <int DEG, int KIND, bool MOVING>
+template <int DEG, int KIND, bool MOVING, bool DIV = false>
 __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK& s, double ut_a, double ut_b,
                                             double ut_k, Record* __restrict__ rec,
                                             int32_t* __restrict__ rect, uint2* __restrict__ trect,
@@ -181,8 +196,9 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
       Rm[6] = 2 * (x * z - w * y);     Rm[7] = 2 * (y * z + w * x);     Rm[8] = 1 - 2 * (x * x + y * y);
       sc[0] = exp((double)l0); sc[1] = exp((double)l1); sc[2] = exp((double)l2);
     }
-    // M = S^{-1} R^T and a = M (mu - o)
-    {
+    // M = S^{-1} R^T and a = M (mu - o); formed where the record is written (so they are not
+    // live through the UT), except with beam divergence, whose filter replaces them here
+    auto form_m = [&]() {
       const double i0 = 1.0 / sc[0], i1 = 1.0 / sc[1], i2 = 1.0 / sc[2];
       M[0] = Rm[0] * i0; M[1] = Rm[3] * i0; M[2] = Rm[6] * i0;
       M[3] = Rm[1] * i1; M[4] = Rm[4] * i1; M[5] = Rm[7] * i1;
@@ -191,23 +207,58 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
       A[0] = __builtin_fma(M[0], vx, __builtin_fma(M[1], vy, M[2] * vz));
       A[1] = __builtin_fma(M[3], vx, __builtin_fma(M[4], vy, M[5] * vz));
       A[2] = __builtin_fma(M[6], vx, __builtin_fma(M[7], vy, M[8] * vz));
-    }
+    };
+    if constexpr (DIV) form_m();
     r.log_sigma = ok ? -log1p(exp(-(double)lg)) : -1e30;   // ln sigmoid(logit)
 
-    // columns of the covariance square root the sigma points step along: S R^T's rows, or
-    // with LiDAR beam divergence the lower Cholesky factor of the smoothed covariance
-    double Lc[9];
+    // columns of the covariance square root the sigma points step along: column j of R S, or
+    // with LiDAR beam divergence the lower Cholesky factor of the smoothed covariance (kept
+    // in registers only in that variant)
+    double Lc[DIV ? 9 : 1];
+    if constexpr (KIND == UT_LIDAR && DIV) {   // launched only for a LiDAR with beam divergence
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+      for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) Lc[d * 3 + j] = sc[j] * Rm[d * 3 + j];
-    if constexpr (KIND == UT_LIDAR) {
-      if (ok && s.div_tan > 0) ok = beam_divergence_filter(s, mx, my, mz, Lc, M, A);
+        for (int j = 0; j < 3; ++j) Lc[d * 3 + j] = sc[j] * Rm[d * 3 + j];
+      if (ok) ok = beam_divergence_filter(s, mx, my, mz, Lc, M, A);
+    }
+    auto col = [&](int d, int j) -> double {
+      if constexpr (DIV) return Lc[d * 3 + j];
+      else return sc[j] * Rm[d * 3 + j];
+    };
+
+    // Static pinhole, no moments requested: a particle whose sigma points all lie in front of
+    // the camera and whose 3-sigma rect certainly misses the image needs no UT.  The sigma
+    // points lie within rho = sqrt(3 + lambda) max(s) of the mean, so their projections fall in
+    // the interval [lo, hi] of the ball; the UT mean lies in it too and each variance is at most
+    // (|W_c0| + 6 W_i) (hi - lo)^2, which bounds the rect's half-extent.  Culling then matches
+    // the full path exactly (count 0, empty rect) with a pixel of slack for rounding.
+    bool off_image = false;
+    if constexpr (KIND == UT_PINHOLE && !MOVING) {
+      const double lam = ut_a * ut_a * (3.0 + ut_k) - 3.0;
+      const double cpl = 3.0 + lam;
+      // convex mean weights (lambda >= 0) and positive focal lengths keep the bound valid
+      if (ok && moments == nullptr && lam >= 0.0 && s.fx > 0.0 && s.fy > 0.0) {
+        const double rho = sqrt(cpl) * fmax(sc[0], fmax(sc[1], sc[2]));
+        const double dx = (double)mx - s.o[0], dy = (double)my - s.o[1], dz = (double)mz - s.o[2];
+        const double xc = s.R[0] * dx + s.R[1] * dy + s.R[2] * dz;
+        const double yc = s.R[3] * dx + s.R[4] * dy + s.R[5] * dz;
+        const double zc = s.R[6] * dx + s.R[7] * dy + s.R[8] * dz;
+        double ulo, uhi, vlo, vhi;
+        if (zc - rho > s.near_ && pinhole_ball_range(xc, zc, rho, s.fx, s.cx, ulo, uhi) &&
+            pinhole_ball_range(yc, zc, rho, s.fy, s.cy, vlo, vhi)) {
+          const double wsum = fabs(lam / cpl + 1.0 - ut_a * ut_a + ut_b) + 3.0 / cpl;
+          const double k = 3.0 * sqrt(wsum);
+          const double eu = k * (uhi - ulo) + 1.0, ev = k * (vhi - vlo) + 1.0;
+          const double W = (double)s.tiles_x * UT_CAMERA_TILE, H = (double)s.tiles_y * UT_CAMERA_TILE;
+          off_image = uhi + eu < 0.0 || ulo - eu >= W || vhi + ev < 0.0 || vlo - ev >= H;
+        }
+      }
     }
 
     // unscented transform over 7 sigma points
     double m0 = 0, m1 = 0, c00 = 0, c01 = 0, c11 = 0;
-    if (ok) {
+    if (ok && !off_image) {
       const double lam = ut_a * ut_a * (3.0 + ut_k) - 3.0;
       const double cpl = 3.0 + lam;
       ok = cpl > 0;
@@ -219,7 +270,7 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
           if (!ok) break;
-          const double e0 = gam * Lc[j], e1 = gam * Lc[3 + j], e2 = gam * Lc[6 + j];
+          const double e0 = gam * col(0, j), e1 = gam * col(1, j), e2 = gam * col(2, j);
           const double pp[3] = {mu[0] + e0, mu[1] + e1, mu[2] + e2};
           const double pm[3] = {mu[0] - e0, mu[1] - e1, mu[2] - e2};
           ok = project_point<KIND, MOVING>(s, pp, gu[1 + j], gv[1 + j]) && project_point<KIND, MOVING>(s, pm, gu[4 + j], gv[4 + j]);
@@ -253,7 +304,7 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
 
     int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
     uint32_t cnt = 0;
-    if (ok) {
+    if (ok && !off_image) {
       const double eu = 3.0 * sqrt(c00), ev = 3.0 * sqrt(c11);
       if constexpr (KIND != UT_LIDAR) {
         const double T = UT_CAMERA_TILE;
@@ -331,6 +382,7 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
         f[c] = (g.feat_kind == UT_FEAT_CAMERA) ? (acc + 0.5 > 0 ? acc + 0.5 : 0.0) : acc;
       }
       r.feat[0] = f[0]; r.feat[1] = f[1]; r.feat[2] = f[2];
+      if constexpr (!DIV) form_m();
       // the quadric form of the record: B = M^T M, B v = M^T A, v^T B v = A.A, trace(B) = |M|_F^2
       r.b[0] = __builtin_fma(M[0], M[0], __builtin_fma(M[3], M[3], M[6] * M[6]));
       r.b[1] = __builtin_fma(M[0], M[1], __builtin_fma(M[3], M[4], M[6] * M[7]));
@@ -386,12 +438,12 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
 // spilling and runs best at three waves per SIMD; the camera kernels run best at two waves,
 // where the compiler keeps all (DEG+1)^2 x 3 coefficient loads in flight (left to itself it
 // trades them for a third wave, and the pinhole then takes over twice as long).
-template <int DEG, int KIND, bool MOVING>
+template <int DEG, int KIND, bool MOVING, bool DIV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_project_capped(
     ut_gaussians g, SensorK s, double ut_a, double ut_b, double ut_k, Record* __restrict__ rec,
     int32_t* __restrict__ rect, uint2* __restrict__ trect, uint32_t* __restrict__ key,
     uint32_t* __restrict__ count, float* __restrict__ moments, uint32_t* __restrict__ n_culled) {
-  project_all<DEG, KIND, MOVING>(g, s, ut_a, ut_b, ut_k, rec, rect, trect, key, count, moments, n_culled);
+  project_all<DEG, KIND, MOVING, DIV>(g, s, ut_a, ut_b, ut_k, rec, rect, trect, key, count, moments, n_culled);
 }
 
 template <int DEG, int KIND, bool MOVING>
@@ -415,6 +467,17 @@ hipError_t launch_project(const ut_gaussians& g, const SensorK& s, const double 
 #define UT_LAUNCH_PROJECT(KERNEL, D, K, MV)                                                                \
   hipLaunchKernelGGL((KERNEL<D, K, MV>), dim3(blocks), dim3(256), 0, st, g, s, abk[0], abk[1], abk[2], rec, \
                      out.rect, tr, out.key, out.count, out.moments, out.n_culled)
+#define UT_LAUNCH_LIDAR(D, MV)                                                                               \
+  do {                                                                                                    \
+    if (s.div_tan > 0)                                                                                    \
+      hipLaunchKernelGGL((k_project_capped<D, UT_LIDAR, MV, true>), dim3(blocks), dim3(256), 0, st, g, s,  \
+                         abk[0], abk[1], abk[2], rec, out.rect, tr, out.key, out.count, out.moments,      \
+                         out.n_culled);                                                                   \
+    else                                                                                                  \
+      hipLaunchKernelGGL((k_project_capped<D, UT_LIDAR, MV, false>), dim3(blocks), dim3(256), 0, st, g, s, \
+                         abk[0], abk[1], abk[2], rec, out.rect, tr, out.key, out.count, out.moments,      \
+                         out.n_culled);                                                                   \
+  } while (0)
 #define UT_LAUNCH_PROJECT_MV(KERNEL, D, K)                      \
   do {                                                          \
     if (s.moving) UT_LAUNCH_PROJECT(KERNEL, D, K, true);        \
@@ -424,7 +487,10 @@ hipError_t launch_project(const ut_gaussians& g, const SensorK& s, const double 
   switch (s.kind) {                                                                  \
     case UT_PINHOLE: UT_LAUNCH_PROJECT_MV(k_project, D, UT_PINHOLE); break;          \
     case UT_FISHEYE: UT_LAUNCH_PROJECT_MV(k_project, D, UT_FISHEYE); break;          \
-    case UT_LIDAR: UT_LAUNCH_PROJECT_MV(k_project_capped, D, UT_LIDAR); break;       \
+    case UT_LIDAR:                                                                   \
+      if (s.moving) UT_LAUNCH_LIDAR(D, true);                                        \
+      else UT_LAUNCH_LIDAR(D, false);                                                \
+      break;                                                                         \
     default: UT_LAUNCH_PROJECT(k_project, D, UT_ORTHO, false); break;                \
   }
   switch (g.sh_degree) {
@@ -435,6 +501,7 @@ hipError_t launch_project(const ut_gaussians& g, const SensorK& s, const double 
   }
 #undef UT_LAUNCH_PROJECT_KIND
 #undef UT_LAUNCH_PROJECT_MV
+#undef UT_LAUNCH_LIDAR
 #undef UT_LAUNCH_PROJECT
   return hipGetLastError();
 }

@@ -278,3 +278,38 @@ def test_beam_divergence_records():
         np.testing.assert_allclose(rec_B(rec, i), B, rtol=1e-8, atol=1e-8 * np.abs(B).max())
         np.testing.assert_allclose(rec["bv"][i], B @ v, rtol=1e-8, atol=1e-8 * np.abs(B @ v).max())
         np.testing.assert_allclose(rec["vbv"][i], v @ B @ v, rtol=1e-8)
+
+
+@pytest.mark.parametrize("abk", [(1.0, 2.0, 0.0), (1.0, 0.0, 1.0)])
+def test_offscreen_precull_matches_full_projection(abk):
+    """Without moments the static pinhole projection skips the UT of particles whose 3-sigma
+    rect certainly misses the image; every output must equal the full path (moments
+    requested), on a scene with particles all around a posed camera, some huge, some at the
+    image border."""
+    import torch
+    import paper_2510_12901_amd as ut
+    rng = np.random.default_rng(21)
+    n = 60000
+    mean = np.stack([rng.uniform(-30, 30, n), rng.uniform(-30, 30, n), rng.uniform(-4, 4, n)])
+    g_np = synth.particles(rng, mean, 0.01, 3.0, 3, synth.FEAT_CAMERA)
+    s_np = synth.pinhole(200, 150, 160.0, 150.0, cx=97.0, cy=71.0, R_sw=synth.yaw_camera_pose(0.7),
+                         origin=np.array([0.5, -1.0, 0.2], np.float32))
+    g = ut.GaussianSet.from_numpy(g_np)
+    s = ut.Sensor(s_np)
+    full = ut.project(g, s, abk=abk, moments=True)
+    fast = ut.project(g, s, abk=abk, moments=False)
+    torch.cuda.synchronize()
+    for k in ("rect", "key", "count", "trect", "n_culled"):
+        assert torch.equal(getattr(full, k), getattr(fast, k)), k
+    vis = torch.nonzero(full.count > 0).flatten()
+    from paper_2510_12901_amd import _abi as A
+    rb = A.RECORD_BYTES
+    fr = full.records.view(-1, rb)[vis]
+    qr = fast.records.view(-1, rb)[vis]
+    assert torch.equal(fr, qr)
+    # the scene exercises the skip: many particles lie well in front of the camera yet project
+    # far outside the image
+    v = np.asarray(s_np["R_sw"], np.float64) @ (mean - np.asarray(s_np["origin"], np.float64)[:, None])
+    u = 160.0 * v[0] / v[2] + 97.0
+    far_off = (v[2] > 2.0) & ((u < -150) | (u > 350))
+    assert far_off.sum() > n // 10
