@@ -6,8 +6,8 @@
 // T_i = T_{i+1} / (1 - alpha_i) from the stored final transmittance, and keeps the suffix
 // sum S = sum_{j>i} w_j a_j.  Per pair it forms 13 partials (colour 3, opacity, mean 3,
 // the 6 unique entries of B = Sigma^{-1}); wavefronts whose lanes touched the particle
-// reduce them across 64 lanes and lane 0 adds them atomically (float64) into SoA
-// accumulators acc[13][n].
+// reduce all 13 across 64 lanes in one reduce-scatter (17 exchanges) and 13 lanes add them
+// atomically (float64) into SoA accumulators acc[13][n].
 // k_chain: one lane per particle, chain rule to (mean, quat, log_scale, logit, SH).
 #include "ut_cone.hpp"
 #include "ut_internal.hpp"
@@ -16,10 +16,34 @@
 namespace ut {
 namespace {
 
-__device__ __forceinline__ double wave_sum(double v) {
+// Sums 16 per-lane values over the 64 lanes of a wavefront with 17 exchanges instead of
+// 16 x 6: at each step a lane keeps half of its partial sums and trades the other half with
+// the lane whose index differs in one bit.  Afterwards lane l holds the total of value
+// idx = 8 b5 + 4 b4 + 2 b3 + b2 (b_k = bit k of l), the same on the 4 lanes that differ only
+// in bits 0 and 1.  Every lane of the wavefront must be active.
+__device__ __forceinline__ double wave_reduce_scatter16(const double v[16], int lane, int& idx) {
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+  double w[8], x[4], y[2];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  for (int k = 0; k < 8; ++k) {
+    const double send = b5 ? v[k] : v[k + 8], keep = b5 ? v[k + 8] : v[k];
+    w[k] = keep + __shfl_xor(send, 32);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double send = b4 ? w[k] : w[k + 4], keep = b4 ? w[k + 4] : w[k];
+    x[k] = keep + __shfl_xor(send, 16);
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double send = b3 ? x[k] : x[k + 2], keep = b3 ? x[k + 2] : x[k];
+    y[k] = keep + __shfl_xor(send, 8);
+  }
+  double z = (b2 ? y[1] : y[0]) + __shfl_xor(b2 ? y[0] : y[1], 4);
+  z += __shfl_xor(z, 2);
+  z += __shfl_xor(z, 1);
+  idx = (b5 ? 8 : 0) + (b4 ? 4 : 0) + (b3 ? 2 : 0) + (b2 ? 1 : 0);
+  return z;
 }
 
 template <int BLOCK, bool MOVING>
@@ -177,12 +201,14 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
         }
       }
       if (__ballot(contrib)) {
+        // one reduction for all 13 partials, then one atomic instruction: lane 4k adds sum k
         const uint32_t gi = sh_g[jj];
+        double v16[16];
 #pragma unroll
-        for (int k = 0; k < UT_ACC_FLOATS; ++k) {
-          const double v = wave_sum(g[k]);
-          if (lane == 0 && v != 0.0) unsafeAtomicAdd(acc + (size_t)k * n + gi, v);
-        }
+        for (int k = 0; k < 16; ++k) v16[k] = k < UT_ACC_FLOATS ? g[k] : 0.0;
+        int idx;
+        const double tot = wave_reduce_scatter16(v16, lane, idx);
+        if ((lane & 3) == 0 && idx < UT_ACC_FLOATS && tot != 0.0) unsafeAtomicAdd(acc + (size_t)idx * n + gi, tot);
       }
     }
   }
