@@ -12,7 +12,7 @@
  *   ut_composite_camera   front-to-back compositing of the 3D response (Eq. 1)
  *   ut_composite_lidar    the same over azimuth-elevation tiles, plus LiDAR outputs
  *   ut_composite_backward adjoint of the above with respect to every particle parameter
- *                         (on per-tile lists materialised by ut_tile_lists_fill)
+ *                         (walking the super-tile bins backwards)
  *
  * plus host set-up (ut_lidar_tiling = Alg. 1, ut_sensor_build = ray mask / summed-area
  * table of Appendix B), a batched, persistent composite for serving, and the scene graph's
@@ -188,7 +188,11 @@ typedef struct {
  * n_visit[R], n_pass[R] (optional, may be NULL; written by ut_composite_camera/_lidar, not by
  * ut_composite_batch): work counters -- list entries the ray actually evaluated (entries that
  * no ray of the tile can reach are dropped before the rays see them) and, of those, entries
- * that passed the alpha_min pre-test. */
+ * that passed the alpha_min pre-test.
+ * tile_end[n_tiles] (optional, adjoint state, may be NULL; written by ut_composite_camera/_lidar
+ * and ut_composite_batch): per tile, the index in the super-tile bin (bins->gauss) just past
+ * the last entry any ray of the tile processed, so the adjoint can walk the bin backwards from
+ * there without materialised per-tile lists. */
 typedef struct {
   float* feat;
   float* depth;
@@ -198,6 +202,7 @@ typedef struct {
   uint32_t* n_proc;
   uint32_t* n_visit;
   uint32_t* n_pass;
+  uint32_t* tile_end;
 } ut_render_out;
 
 /* Upstream gradients dL/d(output), device float32 arrays shaped like ut_render_out;
@@ -330,17 +335,18 @@ size_t ut_backward_workspace_bytes(int32_t n_gaussians);
 
 /* Adjoint of ut_composite_* with the discrete structure of the forward held fixed (lists,
  * culls, alpha_min skips, alpha_max clamps, colour clamps, the termination index).
- * lists: per-tile lists from ut_tile_lists_count / ut_tile_lists_fill of the forward's bins.
- * Replays each ray's list in reverse from fwd->n_proc, recovering T_i = T_{i+1}/(1 -
- * alpha_i) from fwd->t_final; per-pair gradients are reduced per wavefront and added
- * atomically into per-particle float64 accumulators (acc_ws, zeroed by the call), then a
- * per-particle kernel applies the chain rule to (mean, quat, log_scale, opacity_logit,
- * feat) including the SH direction's dependence on the mean.  fwd must hold feat,
- * t_final and n_proc of the forward call with the same arguments.  Gradients are
+ * bins: the forward's super-tile bins.  Each tile walks its super-tile bin backwards from
+ * fwd->tile_end, keeping the entries whose rect covers the tile (and that the tile's ray cone
+ * can reach), and replays each ray's list in reverse from fwd->n_proc, recovering
+ * T_i = T_{i+1}/(1 - alpha_i) from fwd->t_final; per-pair gradients are reduced per wavefront
+ * and added atomically into per-particle float64 accumulators (acc_ws, zeroed by the call),
+ * then a per-particle kernel applies the chain rule to (mean, quat, log_scale, opacity_logit,
+ * feat) including the SH direction's dependence on the mean.  fwd must hold feat, t_final,
+ * n_proc and tile_end of the forward call with the same arguments.  Gradients are
  * accumulated in float64 but their summation order is not fixed (atomics).  Sensors whose
  * tiles hold more than 256 rays (LiDAR with large M) return UT_ERR_UNSUPPORTED. */
 ut_status ut_composite_backward(const ut_gaussians* g, const ut_projected* p,
-                                const ut_tile_lists* lists, const ut_sensor* s,
+                                const ut_bin_lists* bins, const ut_sensor* s,
                                 const ut_render_params* prm, const ut_render_out* fwd,
                                 const ut_upstream* up, void* acc_ws, size_t acc_ws_bytes,
                                 ut_gaussian_grads* grads, ut_stream stream);

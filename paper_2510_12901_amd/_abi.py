@@ -53,7 +53,7 @@ class UtTileLists(C.Structure):
 
 class UtRenderOut(C.Structure):
     _fields_ = [("feat", P), ("depth", P), ("alpha", P), ("drop", P), ("t_final", P), ("n_proc", P),
-                ("n_visit", P), ("n_pass", P)]
+                ("n_visit", P), ("n_pass", P), ("tile_end", P)]
 
 
 class UtUpstream(C.Structure):

@@ -388,18 +388,18 @@ size_t ut_backward_workspace_bytes(int32_t n_gaussians) {
   return (size_t)UT_ACC_FLOATS * sizeof(double) * (size_t)(n_gaussians > 0 ? n_gaussians : 1);
 }
 
-ut_status ut_composite_backward(const ut_gaussians* g, const ut_projected* p, const ut_tile_lists* lists,
+ut_status ut_composite_backward(const ut_gaussians* g, const ut_projected* p, const ut_bin_lists* bins,
                                 const ut_sensor* s, const ut_render_params* prm, const ut_render_out* fwd,
                                 const ut_upstream* up, void* acc_ws, size_t acc_ws_bytes,
                                 ut_gaussian_grads* grads, ut_stream stream) {
-  if (!gaussians_ok(g) || !p || !p->records || !lists || !lists->ranges || !sensor_ok(s) || !params_ok(prm) ||
-      !fwd || !fwd->feat || !fwd->t_final || !fwd->n_proc || !up || !acc_ws || !grads || !grads->mean ||
+  if (!gaussians_ok(g) || !p || !p->records || !p->trect || !bins_ok(bins) || !sensor_ok(s) || !params_ok(prm) ||
+      !fwd || !fwd->feat || !fwd->t_final || !fwd->n_proc || !fwd->tile_end || !up || !acc_ws || !grads || !grads->mean ||
       !grads->quat || !grads->log_scale || !grads->opacity_logit || !grads->feat)
     return UT_ERR_ARG;
   if (acc_ws_bytes < ut_backward_workspace_bytes(g->n)) return UT_ERR_CAPACITY;
   if (s->max_tile_rays > 256) return UT_ERR_UNSUPPORTED;   // the adjoint runs one lane per ray of a tile
   const SensorK k = make_sensor_k(s);
-  return from_hip(launch_backward(*g, *p, *lists, k, make_params(prm), *fwd, *up, static_cast<double*>(acc_ws),
+  return from_hip(launch_backward(*g, *p, *bins, k, make_params(prm), *fwd, *up, static_cast<double*>(acc_ws),
                                   *grads, s->max_tile_rays, as_stream(stream)));
 }
 

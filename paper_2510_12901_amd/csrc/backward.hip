@@ -48,19 +48,22 @@ __device__ __forceinline__ double wave_reduce_scatter16(const double v[16], int 
 
 template <int BLOCK, bool MOVING>
 __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __restrict__ rec,
-                                                     const uint32_t* __restrict__ gauss,
-                                                     const uint32_t* __restrict__ ranges, int n_tiles,
+                                                     const uint2* __restrict__ trect,
+                                                     const uint32_t* __restrict__ bgauss,
+                                                     const uint32_t* __restrict__ branges, int n_super,
                                                      RenderParamsK prm, ut_render_out fwd, ut_upstream up,
                                                      const float* __restrict__ mean, double* __restrict__ acc,
                                                      int n) {
   __shared__ Record sh[BLOCK];
-  __shared__ uint32_t sh_g[BLOCK];
-  __shared__ uint32_t sh_dead[BLOCK];   // 1: no ray of the tile can reach alpha_min on the entry
+  __shared__ uint32_t sh_g[BLOCK];   // kept entries of one step: particle ...
+  __shared__ uint32_t sh_j[BLOCK];   // ... and its position in the tile's list
+  __shared__ uint2 s_wc[BLOCK / 64];
   __shared__ uint32_t s_max;
   __shared__ double red[4][BLOCK / 64];
   __shared__ TileCone cone;
   const int tile = blockIdx.x;
-  const uint32_t start = ranges[tile];
+  const int tx = tile % s.tiles_x, ty = tile / s.tiles_x;
+  const uint32_t bstart = branges[super_of_tile(tile, s)];
   const long long ray = tile_ray(s, tile, threadIdx.x);
   const long long R = s.n_rays;
   double ox = s.o[0], oy = s.o[1], oz = s.o[2];   // this ray's origin (moving sensors: its own)
@@ -123,24 +126,52 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
   __syncthreads();
   atomicMax(&s_max, np);
   __syncthreads();
-  const int jmax = (int)s_max;
+  const uint32_t jmax = s_max;
+  const unsigned long long lt = (1ull << lane) - 1ull;
 
-  for (int hi = jmax; hi > 0; hi -= BLOCK) {
-    const int lo = hi > BLOCK ? hi - BLOCK : 0;
-    const int cnt = hi - lo;
+  // Walk the super-tile bin backwards from the forward's end for this tile.  Entries whose rect
+  // covers the tile form the tile's list; the first jmax of them lie in [bstart, tile_end), so
+  // a step's covering entries take the positions just below those of the later steps.  Entries
+  // the tile cone rules out are dropped before their records are staged.
+  uint32_t cur = jmax > 0 ? fwd.tile_end[tile] : bstart;   // exclusive bin index
+  uint32_t top = jmax;                                     // list positions below this remain
+  while (cur > bstart && top > 0) {
+    const uint32_t lo = cur - bstart > (uint32_t)BLOCK ? cur - BLOCK : bstart;
+    const uint32_t b = lo + threadIdx.x;
+    uint32_t g = 0;
+    bool hit = false;
+    if (b < cur) {
+      g = bgauss[b];
+      hit = rect_covers(trect[g], tx, ty, s);
+    }
+    const bool keep = hit && !(cull && cone_rejects<MOVING>(rec + g, cone, prm.log_alpha_min));
+    const unsigned long long mh = __ballot(hit), mk = __ballot(keep);
+    __syncthreads();   // the previous step's records are no longer read
+    if (lane == 0) s_wc[wave] = make_uint2((uint32_t)__popcll(mh), (uint32_t)__popcll(mk));
     __syncthreads();
-    for (int c = threadIdx.x; c < cnt * kRecordChunks; c += BLOCK) {
-      const int j = c / kRecordChunks, part = c - j * kRecordChunks;
-      const uint32_t g = gauss[start + lo + j];
-      reinterpret_cast<uint4*>(sh + j)[part] = reinterpret_cast<const uint4*>(rec + g)[part];
-      if (part == 0) sh_g[j] = g;
+    uint32_t hb = 0, kb = 0, ht = 0, kt = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) {
+      const uint2 c = s_wc[w];
+      if (w < wave) hb += c.x, kb += c.y;
+      ht += c.x, kt += c.y;
+    }
+    if (keep) {
+      const uint32_t slot = kb + (uint32_t)__popcll(mk & lt);
+      sh_g[slot] = g;
+      sh_j[slot] = top - ht + hb + (uint32_t)__popcll(mh & lt);   // position in the tile's list
     }
     __syncthreads();
-    if (threadIdx.x < cnt) sh_dead[threadIdx.x] = cull && cone_rejects<MOVING>(sh + threadIdx.x, cone, prm.log_alpha_min);
+    const int cnt = (int)kt;
+    for (int c = threadIdx.x; c < cnt * kRecordChunks; c += BLOCK) {
+      const int j = c / kRecordChunks, part = c - j * kRecordChunks;
+      reinterpret_cast<uint4*>(sh + j)[part] = reinterpret_cast<const uint4*>(rec + sh_g[j])[part];
+    }
     __syncthreads();
+    top -= ht;
+    cur = lo;
     for (int jj = cnt - 1; jj >= 0; --jj) {
-      const int j = lo + jj;
-      if (sh_dead[jj]) continue;                      // every ray of the tile skips this entry
+      const int j = (int)sh_j[jj];
       if (__ballot(j < (int)np) == 0ull) continue;   // no lane of this wave visited entry j
       const Record& r = sh[jj];
       bool contrib = false;
@@ -368,7 +399,7 @@ __global__ __launch_bounds__(256) void k_chain(ut_gaussians g, SensorK s, const 
 
 }  // namespace
 
-hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const ut_tile_lists& lists,
+hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const ut_bin_lists& bins,
                            const SensorK& s, const RenderParamsK& prm, const ut_render_out& fwd,
                            const ut_upstream& up, double* acc, const ut_gaussian_grads& grads,
                            int max_tile_rays, hipStream_t st) {
@@ -376,15 +407,17 @@ hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const u
   if (e != hipSuccess || g.n == 0) return e;
   const int n_tiles = s.tiles_x * s.tiles_y;
   const Record* rec = reinterpret_cast<const Record*>(p.records);
+  const uint2* tr = reinterpret_cast<const uint2*>(p.trect);
+  const int n_super = s.super_x * s.super_y;
   if (n_tiles > 0) {
 #define UT_LAUNCH_BACKWARD(B)                                                                              \
   do {                                                                                                     \
     if (s.moving)                                                                                          \
-      hipLaunchKernelGGL((k_backward<B, true>), dim3(n_tiles), dim3(B), 0, st, s, rec, lists.gauss,        \
-                         lists.ranges, n_tiles, prm, fwd, up, g.mean, acc, g.n);                            \
+      hipLaunchKernelGGL((k_backward<B, true>), dim3(n_tiles), dim3(B), 0, st, s, rec, tr, bins.gauss,     \
+                         bins.ranges, n_super, prm, fwd, up, g.mean, acc, g.n);                             \
     else                                                                                                   \
-      hipLaunchKernelGGL((k_backward<B, false>), dim3(n_tiles), dim3(B), 0, st, s, rec, lists.gauss,       \
-                         lists.ranges, n_tiles, prm, fwd, up, g.mean, acc, g.n);                            \
+      hipLaunchKernelGGL((k_backward<B, false>), dim3(n_tiles), dim3(B), 0, st, s, rec, tr, bins.gauss,    \
+                         bins.ranges, n_super, prm, fwd, up, g.mean, acc, g.n);                             \
   } while (0)
     if (s.kind != UT_LIDAR || max_tile_rays > 128)
       UT_LAUNCH_BACKWARD(256);

@@ -36,8 +36,11 @@ struct CompositeShared {
   static_assert(BATCH + BLOCK <= (int)kRing, "ring must hold a batch plus one refill step");
   Record rec[BATCH];
   uint32_t rpos[BATCH];    // position of each staged record in the tile's list
+  uint32_t rbin[BATCH];    // ... and in the super-tile bin
   uint32_t cand[kRing];    // ring of candidate particle indices ...
-  uint32_t cpos[kRing];    // ... and their positions in the tile's list
+  uint32_t cpos[kRing];    // ... their positions in the tile's list ...
+  uint32_t cbin[kRing];    // ... and in the super-tile bin
+  uint32_t tend;           // the tile's bin end for the adjoint
   uint2 wcnt[BLOCK / 64];  // per wavefront: (rect hits, kept entries) of one refill step
   double red[4][BLOCK / 64];
   double etab[32];         // LDS copy of kExp2Frac for the response's exponential
@@ -60,7 +63,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
   double dx[RPL], dy[RPL], dz[RPL], T[RPL], f0[RPL], f1[RPL], f2[RPL], dep[RPL];
   double ex[RPL], ey[RPL], ez[RPL];   // moving sensor: ray origin minus the sensor origin
   double emax = 0.0;
-  uint32_t nproc[RPL], nvisit[RPL], npass[RPL];
+  uint32_t nproc[RPL], nbin[RPL], nvisit[RPL], npass[RPL];
   bool rdone[RPL];
   bool done = true;
   double sx = 0, sy = 0, sz = 0;
@@ -85,7 +88,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
     }
     T[k] = 1.0;
     f0[k] = f1[k] = f2[k] = dep[k] = 0;
-    nproc[k] = nvisit[k] = npass[k] = 0;
+    nproc[k] = nbin[k] = nvisit[k] = npass[k] = 0;
     if (!rdone[k]) {
       const double il = rcp_f64(__builtin_sqrt(__builtin_fma(dx[k], dx[k], __builtin_fma(dy[k], dy[k], dz[k] * dz[k]))));
       sx = __builtin_fma(dx[k], il, sx);
@@ -159,6 +162,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
         const uint32_t slot = (head + n_cand + kb + (uint32_t)__popcll(mk & lt)) & kRing;
         sm.cand[slot] = g;
         sm.cpos[slot] = n_hits + hb + (uint32_t)__popcll(mh & lt);
+        sm.cbin[slot] = j;
       }
       n_cand += kt;
       n_hits += ht;
@@ -172,7 +176,10 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
       const uint32_t slot = (head + j) & kRing;
       const uint32_t g = sm.cand[slot];
       reinterpret_cast<uint4*>(sm.rec + j)[part] = reinterpret_cast<const uint4*>(rec + g)[part];
-      if (part == 0) sm.rpos[j] = sm.cpos[slot];
+      if (part == 0) {
+        sm.rpos[j] = sm.cpos[slot];
+        sm.rbin[j] = sm.cbin[slot];
+      }
     }
     __syncthreads();
     if (!done) {
@@ -202,6 +209,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
           if (T[k] < prm.t_min) {
             rdone[k] = true;
             nproc[k] = sm.rpos[j] + 1;   // list entries up to and including the terminating one
+            nbin[k] = sm.rbin[j] + 1;    // bin entries up to and including it
           }
         }
         bool all = true;
@@ -219,7 +227,17 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
   // a ray still open here has visited the whole list of its tile
 #pragma unroll
   for (int k = 0; k < RPL; ++k)
-    if (!rdone[k]) nproc[k] = n_hits;
+    if (!rdone[k]) nproc[k] = n_hits, nbin[k] = end;
+  if (out.tile_end) {   // uniform: the adjoint walks the bin back from the largest end
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) m = nproc[k] > 0 && nbin[k] > m ? nbin[k] : m;
+    if (threadIdx.x == 0) sm.tend = 0;
+    __syncthreads();
+    if (m > 0) atomicMax(&sm.tend, m);
+    __syncthreads();
+    if (threadIdx.x == 0) out.tile_end[tile] = sm.tend;
+  }
 #pragma unroll
   for (int k = 0; k < RPL; ++k) {
     if (ray[k] < 0) continue;

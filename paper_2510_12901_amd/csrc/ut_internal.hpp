@@ -69,7 +69,7 @@ hipError_t launch_composite_batch(const BatchItemK* items_dev, int n_static, int
                                   int moving_tiles, uint32_t* counter, const RenderParamsK& prm, int n_workgroups,
                                   hipStream_t st);
 
-hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const ut_tile_lists& lists,
+hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const ut_bin_lists& bins,
                            const SensorK& s, const RenderParamsK& prm, const ut_render_out& fwd,
                            const ut_upstream& up, double* acc, const ut_gaussian_grads& grads,
                            int max_tile_rays, hipStream_t st);

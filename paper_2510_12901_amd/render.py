@@ -287,13 +287,14 @@ class RenderOut:
     n_proc: torch.Tensor | None
     n_visit: torch.Tensor | None = None     # work counters (optional)
     n_pass: torch.Tensor | None = None
+    tile_end: torch.Tensor | None = None    # adjoint state: per tile, the bin index past its last entry
     _c: A.UtRenderOut = field(default=None, repr=False)
 
     def c(self) -> A.UtRenderOut:
         if self._c is None:
             self._c = A.UtRenderOut(self.feat.data_ptr(), self.depth.data_ptr(), self.alpha.data_ptr(),
                                     _ptr(self.drop), _ptr(self.t_final), _ptr(self.n_proc),
-                                    _ptr(self.n_visit), _ptr(self.n_pass))
+                                    _ptr(self.n_visit), _ptr(self.n_pass), _ptr(self.tile_end))
         return self._c
 
 
@@ -306,7 +307,8 @@ def alloc_out(sensor: Sensor, device="cuda", state=True, counters=False) -> Rend
                      torch.empty(R, dtype=torch.float64, device=device) if state else None,
                      torch.empty(R, dtype=torch.int32, device=device) if state else None,
                      torch.empty(R, dtype=torch.int32, device=device) if counters else None,
-                     torch.empty(R, dtype=torch.int32, device=device) if counters else None)
+                     torch.empty(R, dtype=torch.int32, device=device) if counters else None,
+                     torch.empty(max(sensor.n_tiles, 1), dtype=torch.int32, device=device) if state else None)
 
 
 def composite(p: Projection, bins: BinLists, sensor: Sensor, params=None, out: RenderOut | None = None,
@@ -326,13 +328,15 @@ def render(g: GaussianSet, sensor: Sensor, abk=UT_ABK, params=None, state=True, 
     return p, bins, out
 
 
-def backward(g: GaussianSet, p: Projection, lists, sensor: Sensor, fwd: RenderOut,
+def backward(g: GaussianSet, p: Projection, bins: BinLists, sensor: Sensor, fwd: RenderOut,
              up_feat=None, up_depth=None, up_alpha=None, up_drop=None, params=None, stream=None) -> dict:
     """Adjoint: gradients of sum(upstream * outputs) with respect to the particle parameters.
-    ``lists`` are the forward's bins (materialised here) or already materialised TileLists."""
+    ``bins`` are the forward's super-tile bins; ``fwd`` its outputs with the adjoint state."""
     dev = g.mean.device
-    if isinstance(lists, BinLists):
-        lists = tile_lists(p, sensor, lists, stream=stream)
+    if not isinstance(bins, BinLists):
+        raise TypeError("backward takes the forward's BinLists")
+    if fwd.t_final is None or fwd.n_proc is None or fwd.tile_end is None:
+        raise ValueError("the forward must be rendered with state=True")
     prm = params or render_params()
     acc = torch.empty(int(lib().ut_backward_workspace_bytes(g.n)), dtype=torch.uint8, device=dev)
     grads = dict(mean=torch.empty_like(g.mean), quat=torch.empty_like(g.quat),
@@ -342,7 +346,7 @@ def backward(g: GaussianSet, p: Projection, lists, sensor: Sensor, fwd: RenderOu
     keep = [t.contiguous().float() if t is not None else None for t in (up_feat, up_depth, up_alpha, up_drop)]
     up = A.UtUpstream(*(_ptr(t) for t in keep))
     gc = g.c()
-    check(lib().ut_composite_backward(ref(gc), ref(p.c()), ref(lists.c()), ref(sensor.c), ref(prm), ref(fwd.c()),
+    check(lib().ut_composite_backward(ref(gc), ref(p.c()), ref(bins.c()), ref(sensor.c), ref(prm), ref(fwd.c()),
                                       ref(up), acc.data_ptr(), acc.numel(), ref(gg), _stream(stream)),
           "ut_composite_backward")
     return grads
