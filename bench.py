@@ -80,11 +80,14 @@ def parse():
 CAMERA_KERNEL = "k_composite<256, 1, 128, false, false>"
 PROFILE_CMDS = {
     "stats": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_stats -o kt -- "
-             "python -u bench.py --no-served --no-backward --no-cpu-baseline --steps 5 --warmup 1 --streams 1",
+             "python -u bench.py --no-served --no-backward --no-cpu-baseline --no-time-dependent --no-beam-divergence "
+             "--no-actors --steps 5 --warmup 1 --streams 1",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- "
-             "python -u bench.py --no-served --no-backward --no-cpu-baseline --steps 2 --warmup 1 --streams 1 --calib-copy",
+             "python -u bench.py --no-served --no-backward --no-cpu-baseline --no-time-dependent --no-beam-divergence "
+             "--no-actors --steps 2 --warmup 1 --streams 1 --calib-copy",
     "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o w -- "
-             "python -u bench.py --no-served --no-backward --no-cpu-baseline --steps 2 --warmup 1 --streams 1 --calib-copy",
+             "python -u bench.py --no-served --no-backward --no-cpu-baseline --no-time-dependent --no-beam-divergence "
+             "--no-actors --steps 2 --warmup 1 --streams 1 --calib-copy",
 }
 
 
