@@ -47,7 +47,9 @@ struct CompositeShared {
   TileCone cone;
 };
 
-template <int BLOCK, int RPL, int BATCH, bool STATS = false, bool MOVING = false>
+// TILE_END: track each ray's bin end and write the tile's (adjoint state); the batched serving
+// path, which never feeds an adjoint, leaves it out and keeps those registers.
+template <int BLOCK, int RPL, int BATCH, bool STATS = false, bool MOVING = false, bool TILE_END = true>
 __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* __restrict__ rec,
                                                const uint2* __restrict__ trect,
                                                const uint32_t* __restrict__ bgauss,
@@ -162,7 +164,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
         const uint32_t slot = (head + n_cand + kb + (uint32_t)__popcll(mk & lt)) & kRing;
         sm.cand[slot] = g;
         sm.cpos[slot] = n_hits + hb + (uint32_t)__popcll(mh & lt);
-        sm.cbin[slot] = j;
+        if constexpr (TILE_END) sm.cbin[slot] = j;
       }
       n_cand += kt;
       n_hits += ht;
@@ -178,7 +180,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
       reinterpret_cast<uint4*>(sm.rec + j)[part] = reinterpret_cast<const uint4*>(rec + g)[part];
       if (part == 0) {
         sm.rpos[j] = sm.cpos[slot];
-        sm.rbin[j] = sm.cbin[slot];
+        if constexpr (TILE_END) sm.rbin[j] = sm.cbin[slot];
       }
     }
     __syncthreads();
@@ -209,7 +211,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
           if (T[k] < prm.t_min) {
             rdone[k] = true;
             nproc[k] = sm.rpos[j] + 1;   // list entries up to and including the terminating one
-            nbin[k] = sm.rbin[j] + 1;    // bin entries up to and including it
+            if constexpr (TILE_END) nbin[k] = sm.rbin[j] + 1;   // bin entries up to and including it
           }
         }
         bool all = true;
@@ -228,7 +230,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
 #pragma unroll
   for (int k = 0; k < RPL; ++k)
     if (!rdone[k]) nproc[k] = n_hits, nbin[k] = end;
-  if (out.tile_end) {   // uniform: the adjoint walks the bin back from the largest end
+  if (TILE_END && out.tile_end) {   // uniform: the adjoint walks the bin back from the largest end
     uint32_t m = 0;
 #pragma unroll
     for (int k = 0; k < RPL; ++k) m = nproc[k] > 0 && nbin[k] > m ? nbin[k] : m;
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(kCamBlock) __attribute__((amdgpu_waves_per_eu(3))) 
     int it = 0;
     while (it + 1 < n_items && (uint32_t)items[it + 1].tile_base <= w) ++it;
     const BatchItemK& I = items[it];
-    composite_tile<kCamBlock, kCamRpl, kCamBatch, false, MOVING>(I.s, I.rec, I.trect, I.gauss, I.ranges,
+    composite_tile<kCamBlock, kCamRpl, kCamBatch, false, MOVING, false>(I.s, I.rec, I.trect, I.gauss, I.ranges,
                                                                   (int)(w - I.tile_base), I.s.super_x * I.s.super_y,
                                                                   prm, I.out, sm);
   }
