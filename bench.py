@@ -5,8 +5,10 @@ Workload (the multi-sensor simulation frame): 2,000,000 particles resident in HB
 = 4 pinhole cameras 1920x1080 + 2 fisheye cameras 1920x1280 + 1 spinning LiDAR 128x2048
 (13,471,744 rays).  A timed step renders one frame through the whole hot path for every
 sensor: sigma-point projection (+ LiDAR ray culling), depth and super-tile radix sorts,
-compositing (with on-chip per-tile list compaction).  Inputs are seeded and synthetic and already resident when timing
-starts.  Prints ONE JSON line (see the design doc for every field).
+compositing (with on-chip per-tile list compaction).  Inputs are seeded and synthetic and
+already resident when timing starts.  Prints ONE JSON line: the frame throughput, the
+compositing kernel against its float64 roofline, the oracle timed on the host, and the
+adjoint, time-dependent, beam-divergence, actor and serving measurements beside them.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 """

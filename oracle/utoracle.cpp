@@ -13,7 +13,7 @@
  * Build: -O2 -fno-fast-math -ffp-contract=off (no FMA contraction), OpenMP over
  * independent rays / tiles only.
  *
- * Readings of passages the paper leaves open are marked READING and listed in the design doc.
+ * Readings of passages the paper leaves open are marked READING where they are applied.
  */
 #include <algorithm>
 #include <cmath>
