@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--no-time-dependent", action="store_true")
     ap.add_argument("--no-beam-divergence", action="store_true")
     ap.add_argument("--no-actors", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the per-configuration stage timings")
     ap.add_argument("--host-count", action="store_true",
                     help="read each sensor's pair total on the host before sorting (one mid-frame sync)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -83,13 +84,13 @@ CAMERA_KERNEL = "k_composite<256, 1, 128, false, false>"
 PROFILE_CMDS = {
     "stats": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_stats -o kt -- "
              "python -u bench.py --no-served --no-backward --no-cpu-baseline --no-time-dependent --no-beam-divergence "
-             "--no-actors --steps 5 --warmup 1 --streams 1",
+             "--no-actors --no-configs --steps 5 --warmup 1 --streams 1",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- "
              "python -u bench.py --no-served --no-backward --no-cpu-baseline --no-time-dependent --no-beam-divergence "
-             "--no-actors --steps 2 --warmup 1 --streams 1 --calib-copy",
+             "--no-actors --no-configs --steps 2 --warmup 1 --streams 1 --calib-copy",
     "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o w -- "
              "python -u bench.py --no-served --no-backward --no-cpu-baseline --no-time-dependent --no-beam-divergence "
-             "--no-actors --steps 2 --warmup 1 --streams 1 --calib-copy",
+             "--no-actors --no-configs --steps 2 --warmup 1 --streams 1 --calib-copy",
 }
 
 
@@ -376,6 +377,8 @@ def main():
 
     if not args.no_backward:
         result["backward"] = bench_backward(ut, synth, dev, args)
+    if not args.no_configs:
+        result["configs"] = bench_configs(ut, synth, dev, args)
     if not args.no_time_dependent:
         result["time_dependent"] = bench_time_dependent(ut, synth, dev, args)
     if not args.no_beam_divergence:
@@ -547,6 +550,81 @@ def bench_actors(ut, synth, dev, args, n_particles, log):
            "bytes_per_particle": {"forward": 60, "backward": "60 (background), 88 (actor)"}, **row}
     log(f"actors: {json.dumps(res)}")
     return res
+
+
+def bench_configs(ut, synth, dev, args):
+    """Each single-sensor workload on its own (plain path, one stream): frame time (median of K
+    renders, host-count path) and per-stage GPU time from HIP events around projection,
+    depth sort + pair count, pair emission + super-tile sort, and compositing (median of K,
+    pair totals kept on the GPU so the stages run back to back).  Projection and binning are
+    priced against HBM with their algorithmic bytes:
+      projection: 76 B per particle (11 floats in; rects, packed rect, key, count out) plus
+                  12 K + 128 B per particle that reaches a tile (K SH coefficients per channel
+                  in, the record out);
+      depth sort: per visible particle 4 radix passes of 16 B (key and value in and out) plus
+                  4 B for the digit histogram, and 16 B per particle for the compaction;
+      pair sort:  per super-tile pair 8 B emitted, 16 B per radix pass, 4 B for the ranges."""
+    import torch
+    stream = torch.cuda.current_stream()
+    K = args.steps
+    cases = [("cfg0 pinhole 128x96, 1,000 particles", synth.scene_pinhole_small(args.seed)),
+             ("cfg1 fisheye 1920x1280, 500,000 particles", synth.scene_fisheye(args.seed)),
+             ("cfg2 LiDAR 128x2048, 300,000 particles", synth.scene_lidar(args.seed)),
+             ("cfg3 pinhole 1920x1080, 1,000,000 particles", synth.scene_pinhole_large(args.seed))]
+    rows = {}
+    for name, (g_np, s_np) in cases:
+        g = ut.GaussianSet.from_numpy(g_np, dev)
+        s = ut.Sensor(s_np, dev)
+        pipe = ut.SensorPipeline(g, s)
+        for _ in range(SETUP_FRAMES + args.warmup):
+            pipe.run(stream)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(K):
+            t0 = time.perf_counter()
+            pipe.run(stream)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        frame_ms = float(np.median(times)) * 1e3
+        P = pipe.n_pairs
+        V = int((pipe.p.count > 0).sum().item())
+        pipe.set_capacity(int(P * 1.25) + 4096)
+        pipe.clear_overflow()
+        st_ms = {k: [] for k in ("project", "depth_sort", "pair_sort", "composite")}
+        for _ in range(K):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            ev[0].record(stream)
+            pipe.project(stream)
+            ev[1].record(stream)
+            pipe.count(stream)
+            ev[2].record(stream)
+            pipe.sort_device(stream)
+            ev[3].record(stream)
+            pipe.composite_only(stream)
+            ev[4].record(stream)
+            torch.cuda.synchronize()
+            for i, k in enumerate(st_ms):
+                st_ms[k].append(ev[i].elapsed_time(ev[i + 1]))
+        if pipe.overflowed():
+            raise RuntimeError(f"{name}: pair capacity exceeded")
+        med = {k: float(np.median(v)) for k, v in st_ms.items()}
+        n, Kc = g.n, (g.sh_degree + 1) ** 2
+        n_super = int(s.n_super)
+        pair_passes = (max(int(np.ceil(np.log2(max(n_super, 2)))), 1) + 7) // 8
+        b_proj = 76 * n + (12 * Kc + 128) * V
+        b_depth = 16 * n + (4 * 16 + 4) * V
+        b_pair = (8 + 16 * pair_passes + 4) * P
+        gbps = lambda b, ms: b / (ms * 1e-3) / 1e9
+        rows[name] = {
+            "rays": s.n_rays, "frame_ms": round(frame_ms, 4), "mrays_per_s": round(s.n_rays / frame_ms / 1e3, 2),
+            "frames_per_s": round(1e3 / frame_ms, 1), "visible": V, "bin_pairs": P,
+            "stage_ms": {k: round(v, 4) for k, v in med.items()},
+            "hbm_frac": {"project": round(gbps(b_proj, med["project"]) / PEAK_HBM_GBS, 3),
+                         "depth_sort": round(gbps(b_depth, med["depth_sort"]) / PEAK_HBM_GBS, 3),
+                         "pair_sort": round(gbps(b_pair, med["pair_sort"]) / PEAK_HBM_GBS, 3)}}
+        log(f"{name}: {json.dumps(rows[name])}")
+        del pipe, s, g
+    return rows
 
 
 def bench_time_dependent(ut, synth, dev, args):

@@ -398,16 +398,23 @@ class SensorPipeline:
                                  torch.empty((2, self.sensor.n_super), dtype=torch.int32, device=dev), P)
         self.bins.n_pairs = P
 
-    def project_and_count(self, stream=None):
-        L = lib()
-        st = _stream(stream)
+    def project(self, stream=None):
+        """Stage a1 (+ a2): ut_project into the pipeline's projection buffers."""
         gc = self.g.c()
         abk_arr = (C.c_double * 3)(*self.abk)
-        check(L.ut_project(ref(gc), ref(self.sensor.c), C.cast(abk_arr, C.c_void_p), ref(self.p.c()), st),
-              "ut_project")
+        check(lib().ut_project(ref(gc), ref(self.sensor.c), C.cast(abk_arr, C.c_void_p), ref(self.p.c()),
+                               _stream(stream)), "ut_project")
+
+    def count(self, stream=None):
+        """First half of binning: depth sort of the visible particles and the pair total."""
+        L = lib()
         buf = self.ws.ensure(int(L.ut_count_workspace_bytes(self.g.n)))
         check(L.ut_bin_count(ref(self.p.c()), self.g.n, ref(self.sensor.c), buf.data_ptr(), buf.numel(),
-                             self.total.data_ptr(), st), "ut_bin_count")
+                             self.total.data_ptr(), _stream(stream)), "ut_bin_count")
+
+    def project_and_count(self, stream=None):
+        self.project(stream)
+        self.count(stream)
 
     def sort_and_composite(self, stream=None, composite_events=None):
         """Call after the count has completed on the host (stream synchronised)."""
@@ -441,22 +448,22 @@ class SensorPipeline:
         """Sort and composite right after project_and_count on the same stream, the pair total
         staying on the device (ut_bin_sort_device).  Check ``overflowed()`` once the stream has
         completed."""
-        if self.capacity <= 0:
-            raise ValueError("set_capacity first")
-        L = lib()
-        st = _stream(stream)
-        buf = self.ws.buf
-        pbuf = self.pair_ws.buf
-        check(L.ut_bin_sort_device(ref(self.p.c()), self.g.n, ref(self.sensor.c), buf.data_ptr(), buf.numel(),
-                                   pbuf.data_ptr(), pbuf.numel(), self.capacity, ref(self.bins.c()),
-                                   self.overflow.data_ptr(), st), "ut_bin_sort_device")
+        self.sort_device(stream)
         if composite_events is not None:
             composite_events[0].record(stream)
-        fn = L.ut_composite_lidar if self.sensor.is_lidar else L.ut_composite_camera
-        check(fn(ref(self.p.c()), ref(self.bins.c()), ref(self.sensor.c), ref(self.params), ref(self.out.c()), st),
-              "ut_composite")
+        self.composite_only(stream)
         if composite_events is not None:
             composite_events[1].record(stream)
+
+    def sort_device(self, stream=None):
+        """Second half of binning with the pair total kept on the GPU (ut_bin_sort_device)."""
+        if self.capacity <= 0:
+            raise ValueError("set_capacity first")
+        buf = self.ws.buf
+        pbuf = self.pair_ws.buf
+        check(lib().ut_bin_sort_device(ref(self.p.c()), self.g.n, ref(self.sensor.c), buf.data_ptr(), buf.numel(),
+                                       pbuf.data_ptr(), pbuf.numel(), self.capacity, ref(self.bins.c()),
+                                       self.overflow.data_ptr(), _stream(stream)), "ut_bin_sort_device")
 
     def run_device(self, stream=None, composite_events=None):
         """One render with no host synchronisation (device-count path)."""
