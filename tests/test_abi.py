@@ -77,3 +77,22 @@ def test_workspace_sizes_monotone(L):
     assert b > a > 0
     assert L.ut_backward_workspace_bytes(1000) == 13 * 8 * 1000
     assert L.ut_batch_workspace_bytes(7) > 256
+
+
+def test_argument_errors_of_the_later_entry_points(L):
+    """Host-side checks of the device-count sort, the adjoint, the batch and the actor
+    transforms return before anything is enqueued (no GPU needed)."""
+    from paper_2510_12901_amd import _abi as A
+    assert L.ut_bin_sort_device(None, 0, None, None, 0, None, 0, 0, None, None, None) == A.UT_ERR_ARG
+    assert L.ut_composite_backward(None, None, None, None, None, None, None, None, 0, None, None) == A.UT_ERR_ARG
+    assert L.ut_composite_batch(None, 0, None, None, 0, 1, None) == A.UT_ERR_ARG
+    g = A.UtGaussians(None, None, None, None, None, 0, 0, 0)
+    assert L.ut_actor_transform(None, None, None, 0, None, None, None) == A.UT_ERR_ARG
+    assert L.ut_actor_transform(A.ref(g), None, None, -1, None, None, None) == A.UT_ERR_ARG
+    assert L.ut_actor_transform(A.ref(g), None, None, 2, None, None, None) == A.UT_ERR_ARG   # poses missing
+    g.n = 5
+    assert L.ut_actor_transform(A.ref(g), None, None, 0, None, None, None) == A.UT_ERR_ARG   # arrays missing
+    assert L.ut_actor_transform_backward(A.ref(g), None, None, 0, None, None, None, None, None, None) == A.UT_ERR_ARG
+    # an empty set with no actors is a valid no-op that touches no device memory
+    g.n = 0
+    assert L.ut_actor_transform(A.ref(g), None, None, 0, None, None, None) == A.UT_OK
