@@ -189,8 +189,8 @@ typedef struct {
  * ut_composite_batch): work counters -- list entries the ray actually evaluated (entries that
  * no ray of the tile can reach are dropped before the rays see them) and, of those, entries
  * that passed the alpha_min pre-test.
- * tile_end[n_tiles] (optional, adjoint state, may be NULL; written by ut_composite_camera/_lidar
- * and ut_composite_batch): per tile, the index in the super-tile bin (bins->gauss) just past
+ * tile_end[n_tiles] (optional, adjoint state, may be NULL; written by ut_composite_camera/_lidar,
+ * not by ut_composite_batch): per tile, the index in the super-tile bin (bins->gauss) just past
  * the last entry any ray of the tile processed, so the adjoint can walk the bin backwards from
  * there without materialised per-tile lists. */
 typedef struct {
@@ -358,7 +358,7 @@ ut_status ut_composite_backward(const ut_gaussians* g, const ut_projected* p,
  * same as ut_composite_camera / ut_composite_lidar, so every ray's output is bit-identical
  * to the single-request call.  items: host array [n_items]; queue_ws: device workspace of
  * ut_batch_workspace_bytes(n_items) bytes.  Sensors whose tiles hold more than 256 rays
- * return UT_ERR_UNSUPPORTED (n_visit / n_pass are not written on this path). */
+ * return UT_ERR_UNSUPPORTED (n_visit, n_pass and tile_end are not written on this path). */
 typedef struct {
   const ut_projected* proj;
   const ut_bin_lists* bins;

@@ -63,7 +63,8 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
   __shared__ TileCone cone;
   const int tile = blockIdx.x;
   const int tx = tile % s.tiles_x, ty = tile / s.tiles_x;
-  const uint32_t bstart = branges[super_of_tile(tile, s)];
+  const int sid = super_of_tile(tile, s);
+  const uint32_t bstart = branges[sid], bend = branges[n_super + sid];
   const long long ray = tile_ray(s, tile, threadIdx.x);
   const long long R = s.n_rays;
   double ox = s.o[0], oy = s.o[1], oz = s.o[2];   // this ray's origin (moving sensors: its own)
@@ -133,7 +134,8 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
   // covers the tile form the tile's list; the first jmax of them lie in [bstart, tile_end), so
   // a step's covering entries take the positions just below those of the later steps.  Entries
   // the tile cone rules out are dropped before their records are staged.
-  uint32_t cur = jmax > 0 ? fwd.tile_end[tile] : bstart;   // exclusive bin index
+  // exclusive bin index; clamped to the bin so that a stale state cannot read past it
+  uint32_t cur = jmax > 0 ? min(max(fwd.tile_end[tile], bstart), bend) : bstart;
   uint32_t top = jmax;                                     // list positions below this remain
   while (cur > bstart && top > 0) {
     const uint32_t lo = cur - bstart > (uint32_t)BLOCK ? cur - BLOCK : bstart;
