@@ -371,6 +371,24 @@ ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items,
                              const ut_render_params* prm, void* queue_ws, size_t ws_bytes,
                              int32_t n_workgroups, ut_stream stream);
 
+/* Spatial order of a resident particle set.  Results never depend on the particles' order
+ * (every list is ordered by depth key, ties by index), but memory traffic does: stored along a
+ * Z-order curve of their means, the particles one view sees share cache lines.  A one-time
+ * reorder for a resident scene:
+ *   ut_spatial_order   perm (device uint32 [n], caller-allocated) = the particle indices in
+ *                      order of the 30-bit Morton code of the mean inside the bounding box of
+ *                      the finite means (10 bits per axis; non-finite means last; ties by
+ *                      index).  ws: device, ut_spatial_order_workspace_bytes(n) bytes.
+ *   ut_gather_gaussians writes the reordered set, dst[:, j] = src[:, perm[j]], into caller
+ *                      arrays of the source's shapes (must not overlap the source).
+ * A reordered set renders the same images; its gradients are in the new order (row j belongs
+ * to source particle perm[j]).  UT_ERR_ARG for NULL pointers or n < 0; UT_ERR_CAPACITY for a
+ * short workspace. */
+size_t ut_spatial_order_workspace_bytes(int32_t n_gaussians);
+ut_status ut_spatial_order(const ut_gaussians* g, uint32_t* perm, void* ws, size_t ws_bytes, ut_stream stream);
+ut_status ut_gather_gaussians(const ut_gaussians* src, const uint32_t* perm, float* mean, float* quat,
+                              float* log_scale, float* opacity_logit, float* feat, ut_stream stream);
+
 /* Scene graph: rigid actor transforms (Sec. 3.1, scene representation).  Every particle
  * belongs to the static background or to one dynamic object (actor); an actor's particles
  * keep their means and covariances in the actor's own frame, and at render time the actor's

@@ -95,6 +95,9 @@ SIGNATURES = [
     ("ut_batch_workspace_bytes", C.c_size_t, [i32]),
     ("ut_composite_batch", i32, [P, i32, P, P, C.c_size_t, i32, P]),
     ("ut_actor_transform", i32, [P, P, P, i32, P, P, P]),
+    ("ut_spatial_order_workspace_bytes", C.c_size_t, [i32]),
+    ("ut_spatial_order", i32, [P, P, P, C.c_size_t, P]),
+    ("ut_gather_gaussians", i32, [P, P, P, P, P, P, P, P]),
     ("ut_actor_transform_backward", i32, [P, P, P, i32, P, P, P, P, P, P]),
 ]
 

@@ -483,4 +483,27 @@ ut_status ut_actor_transform_backward(const ut_gaussians* g, const int32_t* acto
                                         d_pose, as_stream(stream)));
 }
 
+size_t ut_spatial_order_workspace_bytes(int32_t n_gaussians) { return spatial_order_ws_bytes(n_gaussians); }
+
+ut_status ut_spatial_order(const ut_gaussians* g, uint32_t* perm, void* ws, size_t ws_bytes, ut_stream stream) {
+  if (!g || g->n < 0 || (g->n > 0 && (!g->mean || !perm || !ws))) return UT_ERR_ARG;
+  if (g->n > 0 && ws_bytes < spatial_order_ws_bytes(g->n)) return UT_ERR_CAPACITY;
+  return from_hip(launch_spatial_order(*g, perm, ws, as_stream(stream)));
+}
+
+ut_status ut_gather_gaussians(const ut_gaussians* src, const uint32_t* perm, float* mean, float* quat,
+                              float* log_scale, float* opacity_logit, float* feat, ut_stream stream) {
+  if (!gaussians_ok(src)) return UT_ERR_ARG;
+  const int n = src->n;
+  if (n > 0 && (!perm || !mean || !quat || !log_scale || !opacity_logit || !feat)) return UT_ERR_ARG;
+  const int K = (src->sh_degree + 1) * (src->sh_degree + 1);
+  hipStream_t st = as_stream(stream);
+  hipError_t e = launch_gather_rows(src->mean, perm, mean, 3, n, st);
+  if (e == hipSuccess) e = launch_gather_rows(src->quat, perm, quat, 4, n, st);
+  if (e == hipSuccess) e = launch_gather_rows(src->log_scale, perm, log_scale, 3, n, st);
+  if (e == hipSuccess) e = launch_gather_rows(src->opacity_logit, perm, opacity_logit, 1, n, st);
+  if (e == hipSuccess) e = launch_gather_rows(src->feat, perm, feat, 3 * K, n, st);
+  return from_hip(e);
+}
+
 }  // extern "C"

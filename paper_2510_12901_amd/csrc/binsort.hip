@@ -336,14 +336,14 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
   }
 }
 
+}  // namespace
+
 // Bytes of the sort's own workspace for up to n_max keys: per-pass digit offsets, per-pass
 // look-back words and tickets.
 size_t radix_ws_bytes(size_t n_max) {
   const size_t tiles = (std::max<size_t>(n_max, 1) + kSortTile - 1) / kSortTile;
   return 4 * ((size_t)kMaxPasses * kRadix + (size_t)kMaxPasses * tiles * kRadix + kMaxPasses);
 }
-
-}  // namespace
 
 // Sorts (k, v) pairs by the low `bits` bits of k (bits <= 32), stable.  n_max sizes the grid;
 // when n_dev is given the kernels read the actual length from it.  Buffers ping-pong;

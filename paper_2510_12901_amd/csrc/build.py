@@ -14,7 +14,7 @@ PKG = os.path.dirname(CSRC)
 ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libutrast.so")
-SOURCES = ["api.hip", "project.hip", "binsort.hip", "composite.hip", "backward.hip", "actors.hip"]
+SOURCES = ["api.hip", "project.hip", "binsort.hip", "composite.hip", "backward.hip", "actors.hip", "layout.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

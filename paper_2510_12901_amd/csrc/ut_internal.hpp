@@ -74,6 +74,16 @@ hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const u
                            const ut_upstream& up, double* acc, const ut_gaussian_grads& grads,
                            int max_tile_rays, hipStream_t st);
 
+// Radix sort of (key, value) pairs, shared by the binning and the spatial order.
+size_t radix_ws_bytes(size_t n_max);
+hipError_t radix_sort(uint32_t* kA, uint32_t* kB, uint32_t* vA, uint32_t* vB, size_t n_max,
+                      const uint32_t* n_dev, int bits, uint32_t* ws, hipStream_t st,
+                      uint32_t** k_res, uint32_t** v_res);
+
+size_t spatial_order_ws_bytes(int n);
+hipError_t launch_spatial_order(const ut_gaussians& g, uint32_t* perm, void* ws, hipStream_t st);
+hipError_t launch_gather_rows(const float* src, const uint32_t* perm, float* dst, int rows, int n, hipStream_t st);
+
 hipError_t launch_actor_transform(const ut_gaussians& g, const int32_t* actor, const ut_actor_pose* poses,
                                   int n_act, float* mean_w, float* quat_w, hipStream_t st);
 hipError_t launch_actor_backward(const ut_gaussians& g, const int32_t* actor, const ut_actor_pose* poses,

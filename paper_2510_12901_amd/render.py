@@ -532,6 +532,30 @@ class FrameGraph:
         return any(p.overflowed() for p in self.pipes)
 
 
+# ---------------------------------------------------------------------------- spatial order
+def spatial_order(g: GaussianSet, stream=None) -> torch.Tensor:
+    """int32 [N] permutation: the particle indices along the Z-order curve of their means
+    (ut_spatial_order).  Reordering a resident scene once makes the projection's reads of the
+    particles one view sees share cache lines."""
+    dev = g.mean.device
+    perm = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)
+    ws = torch.empty(int(lib().ut_spatial_order_workspace_bytes(g.n)), dtype=torch.uint8, device=dev)
+    gc = g.c()
+    check(lib().ut_spatial_order(ref(gc), _ptr(perm), _ptr(ws), ws.numel(), _stream(stream)), "ut_spatial_order")
+    return perm[: g.n]
+
+
+def gather(g: GaussianSet, perm: torch.Tensor, stream=None) -> GaussianSet:
+    """The set reordered by perm (row j = source particle perm[j]), ut_gather_gaussians."""
+    _require_cuda(perm, torch.int32, "perm")
+    out = GaussianSet(torch.empty_like(g.mean), torch.empty_like(g.quat), torch.empty_like(g.log_scale),
+                      torch.empty_like(g.opacity_logit), torch.empty_like(g.feat), g.sh_degree, g.feat_kind)
+    gc = g.c()
+    check(lib().ut_gather_gaussians(ref(gc), _ptr(perm), _ptr(out.mean), _ptr(out.quat), _ptr(out.log_scale),
+                                    _ptr(out.opacity_logit), _ptr(out.feat), _stream(stream)), "ut_gather_gaussians")
+    return out
+
+
 # ---------------------------------------------------------------------------- scene graph
 def actor_poses(poses) -> torch.Tensor:
     """Pose table [n_actors, 7] (qw, qx, qy, qz, tx, ty, tz) -> the device layout of
