@@ -19,6 +19,8 @@ bit-identical to plain renders.
 """
 from __future__ import annotations
 
+import contextlib
+import gc
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -32,6 +34,22 @@ from .render import (BinLists, GaussianSet, RenderOut, Sensor, SensorPipeline, _
                      render_params)
 
 ALIGN = 256
+
+
+@contextlib.contextmanager
+def _collector_paused():
+    """Keep Python's cyclic garbage collector out of a serving loop.  A full (oldest
+    generation) collection walks every object the process holds -- with torch and the scene
+    loaded that is a pause of tens of milliseconds, long enough to stall every request in
+    flight.  The loops create no reference cycles (their objects are freed by reference
+    counting), so the collector is paused for the run and its previous state restored."""
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
 
 
 class DevicePool:
@@ -81,6 +99,10 @@ class Request:
     sensor: int
     arrival: float
     t_done: float = -1.0
+    t_start: float = -1.0      # slot taken, projection enqueued
+    t_counted: float = -1.0    # pair total seen on the host
+    t_sort: float = -1.0       # pool memory granted, sort enqueued
+    t_batch: float = -1.0      # compositing launch enqueued
     n_pairs: int = 0
     slot: "Slot" = None
     mem: tuple = None
@@ -190,6 +212,10 @@ class Server:
     def run(self, trace, on_done=None, max_batch=None):
         """trace: list of (arrival_seconds, frame_id, sensor_index) sorted by arrival.
         on_done(request) is called (outputs still valid) before the slot is reused."""
+        with _collector_paused():
+            return self._run(trace, on_done, max_batch)
+
+    def _run(self, trace, on_done, max_batch):
         reqs = [Request(i, int(f), int(si), float(t)) for i, (t, f, si) in enumerate(trace)]
         waiting, counting, counted, sorting, batches = deque(), [], deque(), [], []
         free_slots = list(self.slots)
@@ -208,6 +234,7 @@ class Server:
             while waiting and free_slots:
                 r = waiting.popleft()
                 r.slot = free_slots.pop()
+                r.t_start = now()
                 self._start(r)
                 counting.append(r)
                 progressed = True
@@ -215,6 +242,7 @@ class Server:
                 if r.slot.ev_count.query():
                     counting.remove(r)
                     r.n_pairs = int(r.slot.total.item())
+                    r.t_counted = now()
                     counted.append(r)
                     progressed = True
             max_mem_wait = max(max_mem_wait, len(counted))
@@ -229,6 +257,7 @@ class Server:
                     break
                 counted.popleft()
                 r.mem = blk
+                r.t_sort = now()
                 self._sort(r)
                 sorting.append(r)
                 progressed = True
@@ -237,8 +266,10 @@ class Server:
                 if max_batch:
                     ready = ready[:max_batch]
                 if ready:
+                    tb = now()
                     for r in ready:
                         sorting.remove(r)
+                        r.t_batch = tb
                     k = free_comp.pop(0)
                     ev = self._composite(ready, k)
                     batches.append((ev, ready, k))
@@ -261,8 +292,13 @@ class Server:
                     progressed = True
             if not progressed:
                 time.sleep(20e-6)
+        stage = lambda a, b: round(float(np.mean([getattr(r, b) - getattr(r, a) for r in reqs])) * 1e3, 3)
         self.stats = {"batches": n_batches, "mean_batch": float(np.mean(batch_sizes)) if batch_sizes else 0.0,
-                      "pool_peak_bytes": self.pool.peak, "max_waiting_for_memory": max_mem_wait}
+                      "pool_peak_bytes": self.pool.peak, "max_waiting_for_memory": max_mem_wait,
+                      # mean milliseconds a request spends between consecutive stages
+                      "stage_ms": {"slot_wait": stage("arrival", "t_start"), "count": stage("t_start", "t_counted"),
+                                   "memory_wait": stage("t_counted", "t_sort"), "sort": stage("t_sort", "t_batch"),
+                                   "composite": stage("t_batch", "t_done")}}
         return reqs
 
 
@@ -271,6 +307,11 @@ def run_plain(g_cam, g_lidar, sensors, trace, pipes=None, on_done=None):
     the single-request path (no overlap between requests)."""
     if pipes is None:
         pipes = [SensorPipeline(g_lidar if s.is_lidar else g_cam, s) for s in sensors]
+    with _collector_paused():
+        return _run_plain(pipes, trace, on_done)
+
+
+def _run_plain(pipes, trace, on_done):
     reqs = [Request(i, int(f), int(si), float(t)) for i, (t, f, si) in enumerate(trace)]
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()

@@ -7,6 +7,24 @@ import pytest
 from paper_2510_12901_amd import serve
 
 
+def test_collector_paused_inside_a_loop_and_restored():
+    import gc
+    was = gc.isenabled()
+    try:
+        for start in (True, False):
+            (gc.enable if start else gc.disable)()
+            with serve._collector_paused():
+                assert not gc.isenabled()
+            assert gc.isenabled() == start
+        gc.enable()
+        with pytest.raises(ValueError):
+            with serve._collector_paused():
+                raise ValueError("request failed")
+        assert gc.isenabled()   # restored on the error path too
+    finally:
+        (gc.enable if was else gc.disable)()
+
+
 def test_pool_first_fit_and_merge():
     pool = serve.DevicePool(4096, device="cpu")
     a = pool.alloc(1000)          # rounds to 1024
@@ -83,6 +101,10 @@ def test_served_results_bit_identical_to_plain_under_memory_pressure():
     assert server.stats["pool_peak_bytes"] <= server.pool.nbytes
     assert server.stats["mean_batch"] >= 1.0
     assert all(r.t_done >= r.arrival for r in reqs)
+    # every request passed the stages in order
+    assert all(r.arrival <= r.t_start <= r.t_counted <= r.t_sort <= r.t_batch <= r.t_done for r in reqs)
+    assert set(server.stats["stage_ms"]) == {"slot_wait", "count", "memory_wait", "sort", "composite"}
+    assert server.stats["stage_ms"]["memory_wait"] > 0.0
 
 
 @pytest.mark.gpu
