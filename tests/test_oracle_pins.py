@@ -71,6 +71,97 @@ def test_ut_close_to_monte_carlo_pinhole():
         np.testing.assert_allclose([proj["cov2"][0, i], proj["cov2"][2, i]], [mc_c[0, 0], mc_c[1, 1]], rtol=0.05)
 
 
+# Nonlinear sensor maps.  A particle stretched along one axis only (the other two scales
+# 1e-5 of it) makes the projection a function of one Gaussian scalar t ~ N(0, s^2); the
+# exact moments of that function follow from the Gaussian's moments E[t^2k] = (2k-1)!! s^2k,
+# expanded in s.  The 7-point UT, whose axis points sit at mu +- sqrt(c) L_i with
+# c = alpha^2 (3 + kappa), reproduces the Gaussian's moments up to the fourth only when
+# c = 3, so its mean and variance agree with the exact ones through s^4 there and differ at
+# s^4 by terms that depend on (alpha, beta, kappa) otherwise.  Each check compares the
+# normalised s^4 coefficient, (value - lower orders) / s^4, at s = 0.005 (s^6 terms < 0.02).
+def _stretched(mean, axis, sigma):
+    rng = np.random.default_rng(0)
+    g = synth.particles(rng, np.asarray(mean, np.float64).reshape(3, 1), 1.0, 1.0, 0, synth.FEAT_CAMERA)
+    g["quat"] = np.array([[1.0], [0.0], [0.0], [0.0]], np.float32)
+    ls = np.full((3, 1), np.log(1e-5 * sigma), np.float32)
+    ls[axis, 0] = np.log(sigma)
+    g["log_scale"] = ls
+    return g, float(np.exp(np.float64(ls[axis, 0])))
+
+
+@pytest.mark.parametrize("abk", [(1.0, 0.0, 0.0), (1.0, 2.0, 0.0), (0.5, 2.0, 1.0), (1.3, 0.0, 2.0)])
+def test_ut_pinhole_depth_stretched_series(abk):
+    """Sec. 3.2 UT through the pinhole map.  A particle at (x0, y0, z0) stretched along the
+    optical axis projects to u - cx = f x0 / z, v - cy = f y0 / z with z = z0 (1 + t).
+    Exact Gaussian moments: E[1/(1+t)] = 1 + s^2 + 3 s^4, Var[1/(1+t)] = s^2 + 8 s^4 (+O(s^6)).
+    The UT gives 1 + s^2 + c s^4 and s^2 + (3c - alpha^2 + beta) s^4 (expansion of its seven
+    points: four collapse onto the mean, two sit at z0 (1 +- sqrt(c) s)); with
+    (alpha, beta, kappa) = (1, 0, 0) both equal the exact moments, and beta enters the
+    variance only through the centre point, one-for-one."""
+    a, b, k = abk
+    c = a * a * (3.0 + k)
+    s_cam = synth.pinhole(64, 48, 90.0, 80.0, cx=30.0, cy=20.0)
+    for z0 in (8.0, 20.0):
+        g, sigma = _stretched([0.6 * z0, -0.4 * z0, z0], 2, 0.005 * z0)
+        x0, y0, zz = (float(v) for v in g["mean"][:, 0].astype(np.float64))
+        s = sigma / zz
+        pr = oracle.project(g, s_cam, abk)
+        assert pr["valid"][0]
+        mu = (pr["mean2"][0, 0] - 30.0) / (90.0 * x0 / zz)
+        mv = (pr["mean2"][1, 0] - 20.0) / (80.0 * y0 / zz)
+        for m in (mu, mv):
+            assert abs((m - 1.0 - s * s) / s**4 - c) < 0.005 * c + 0.005
+        var = np.array([pr["cov2"][0, 0] / (90.0 * x0 / zz) ** 2,
+                        pr["cov2"][1, 0] / (90.0 * 80.0 * x0 * y0 / zz**2),
+                        pr["cov2"][2, 0] / (80.0 * y0 / zz) ** 2])
+        c4 = (var - s * s) / s**4
+        np.testing.assert_allclose(c4, 3 * c - a * a + b, atol=0.01 + 0.002 * (3 * c))
+        if abk == (1.0, 0.0, 0.0):
+            np.testing.assert_allclose(c4, 8.0, atol=0.01)      # exact Var[1/(1+t)]
+
+
+@pytest.mark.parametrize("where, axis", [((0.0, 1.0, 0.0), 0), ((0.0, 1.0, 0.0), 2), ((1.0, 0.0, 0.0), 1)])
+def test_ut_lidar_angles_stretched_series(where, axis):
+    """Eq. 3 map through the UT.  A particle at distance r0 stretched across the line of
+    sight moves one angle by atan(t): along the horizontal the azimuth, along z the
+    elevation, asin(z / r) = atan(t).  Exact: mean unchanged by symmetry, Var[atan t] =
+    s^2 - 2 s^4 + O(s^6); the UT (c = 3) agrees through s^4.  The particle on the +x axis
+    has sigma azimuths on both sides of 0 = 2 pi (they must be unwrapped around the mean's)."""
+    ls = synth.lidar(np.deg2rad(np.linspace(-20.0, 20.0, 16)), 256)
+    r0 = 15.0
+    g, sigma = _stretched(r0 * np.array(where), axis, 0.005 * r0)
+    s = sigma / r0
+    pr = oracle.project(g, ls)
+    assert pr["valid"][0]
+    moved = 1 if axis == 2 else 0
+    centre = np.arctan2(where[1], where[0]) if moved == 0 else 0.0
+    d = (pr["mean2"][moved, 0] - centre + np.pi) % (2 * np.pi) - np.pi
+    assert abs(d) < 1e-14
+    var = pr["cov2"][0 if moved == 0 else 2, 0]
+    assert abs((var - s * s) / s**4 - (-2.0)) < 0.01
+    # the other angle sees only the 1e-5 side scales: variance ~(1e-5 s)^2, no s^2 term
+    assert pr["cov2"][2 if moved == 0 else 0, 0] < 1e-5 * s * s
+    assert abs(pr["cov2"][1, 0]) < 1e-5 * s * s
+
+
+def test_ut_fisheye_axis_stretched_series():
+    """Equidistant fisheye through the UT.  A particle on the optical axis at depth z0
+    stretched along x maps to u - cx = f d(atan t), d(theta) = theta (1 + k1 theta^2 + ...).
+    Exact: mean cx by symmetry, Var = f^2 (s^2 + (6 k1 - 2) s^4 + O(s^6)); the UT agrees
+    through s^4."""
+    k = [0.04, -0.01, 0.005, 0.0]
+    fe = synth.fisheye(96, 64, k)
+    f = fe["fx"]
+    z0 = 12.0
+    g, sigma = _stretched([0.0, 0.0, z0], 0, 0.005 * z0)
+    s = sigma / z0
+    pr = oracle.project(g, fe)
+    assert pr["valid"][0]
+    assert abs(pr["mean2"][0, 0] - fe["cx"]) < 1e-12 * f
+    var = pr["cov2"][0, 0] / (f * f)
+    assert abs((var - s * s) / s**4 - (6 * k[0] - 2.0)) < 0.01
+
+
 # ------------------------------------------------------------------ projections
 def test_projection_round_trip_of_ray_tables():
     """Every camera ray of the generator's table, pushed out to 7 m, projects back to its
