@@ -1088,34 +1088,56 @@ void chain_to_params(const orc_gaussians* g, const orc_sensor* s, const PerGauss
     if (!p.ok) continue;
     /* opacity */
     d_logit[i] = A.dsigma * p.sigma * (1 - p.sigma);
-    /* B = Sigma^{-1}: dL/dSigma = -B G B */
-    double GB[9], GS[9];
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
-        double v = 0;
-        for (int k = 0; k < 3; ++k) v += A.dB[a * 3 + k] * p.Binv[k * 3 + b];
-        GB[a * 3 + b] = v;
-      }
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
-        double v = 0;
-        for (int k = 0; k < 3; ++k) v += p.Binv[a * 3 + k] * GB[k * 3 + b];
-        GS[a * 3 + b] = -v;
-      }
-    /* Sigma = R diag(s^2) R^T with GS symmetric: dL/dR = (GS + GS^T) R diag(s^2),
-     * dL/ds_j = 2 s_j (R^T GS R)_jj, dL/dlog_scale_j = s_j dL/ds_j */
+    /* dL/dR and dL/dlog_scale from G = dL/dB (Sec. 3.2: Sigma = R S S^T R^T) */
+    double GS[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     double GR[9];
-    for (int a = 0; a < 3; ++a)
+    if (!p.filtered) {
+      /* B = R diag(1/s^2) R^T: dL/dR = (G + G^T) R diag(1/s^2), dL/dlog_scale_j =
+       * -2 (R^T G R)_jj / s_j^2.  The same derivative as the route through Sigma below, taken
+       * without forming -B G B, whose entries reach (1/s_min^2)^2 |G| and leave the rotation
+       * gradient of a thin particle to cancellation. */
+      for (int a = 0; a < 3; ++a)
+        for (int j = 0; j < 3; ++j) {
+          double v = 0;
+          for (int k = 0; k < 3; ++k) v += (A.dB[a * 3 + k] + A.dB[k * 3 + a]) * p.R[k * 3 + j];
+          GR[a * 3 + j] = v / (p.s[j] * p.s[j]);
+        }
       for (int j = 0; j < 3; ++j) {
         double v = 0;
-        for (int k = 0; k < 3; ++k) v += (GS[a * 3 + k] + GS[k * 3 + a]) * p.R[k * 3 + j];
-        GR[a * 3 + j] = v * p.s[j] * p.s[j];
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) v += p.R[a * 3 + j] * A.dB[a * 3 + b] * p.R[b * 3 + j];
+        d_log_scale[j * n + i] = -2 * v / (p.s[j] * p.s[j]);
       }
-    for (int j = 0; j < 3; ++j) {
-      double v = 0;
+    } else {
+      /* B = Sigma_hat^{-1}: dL/dSigma_hat = -B G B */
+      double GB[9];
       for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) v += p.R[a * 3 + j] * GS[a * 3 + b] * p.R[b * 3 + j];
-      d_log_scale[j * n + i] = 2 * p.s[j] * v * p.s[j];
+        for (int b = 0; b < 3; ++b) {
+          double v = 0;
+          for (int k = 0; k < 3; ++k) v += A.dB[a * 3 + k] * p.Binv[k * 3 + b];
+          GB[a * 3 + b] = v;
+        }
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          double v = 0;
+          for (int k = 0; k < 3; ++k) v += p.Binv[a * 3 + k] * GB[k * 3 + b];
+          GS[a * 3 + b] = -v;
+        }
+      /* Sigma_hat = R diag(s^2) R^T + (smoothing, free of R and s) with GS symmetric:
+       * dL/dR = (GS + GS^T) R diag(s^2), dL/ds_j = 2 s_j (R^T GS R)_jj,
+       * dL/dlog_scale_j = s_j dL/ds_j */
+      for (int a = 0; a < 3; ++a)
+        for (int j = 0; j < 3; ++j) {
+          double v = 0;
+          for (int k = 0; k < 3; ++k) v += (GS[a * 3 + k] + GS[k * 3 + a]) * p.R[k * 3 + j];
+          GR[a * 3 + j] = v * p.s[j] * p.s[j];
+        }
+      for (int j = 0; j < 3; ++j) {
+        double v = 0;
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) v += p.R[a * 3 + j] * GS[a * 3 + b] * p.R[b * 3 + j];
+        d_log_scale[j * n + i] = 2 * p.s[j] * v * p.s[j];
+      }
     }
     double J[4][9], dqn[4];
     quat_to_rot_jacobian(p.qn, J);
