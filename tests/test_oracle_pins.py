@@ -498,6 +498,36 @@ def test_adjoint_matches_finite_differences_camera():
     np.testing.assert_allclose(an, fd, atol=1e-6 * scale.max(), rtol=1e-5)
 
 
+def _thin_disc_scene(seed, n=500):
+    """Discs 1e-3 to 1e-4 as thick as they are wide, 10-30 m in front of a 48x40 pinhole."""
+    rng = np.random.default_rng(seed)
+    mean = np.stack([rng.uniform(-4, 4, n), rng.uniform(-3, 3, n), rng.uniform(10, 30, n)])
+    g = synth.particles(rng, mean, 0.3, 1.2, 0, synth.FEAT_CAMERA)
+    w = rng.uniform(np.log(0.3), np.log(1.2), n)
+    g["log_scale"] = np.stack([w, w + rng.uniform(-0.5, 0.5, n),
+                               w + rng.uniform(np.log(1e-4), np.log(1e-3), n)]).astype(np.float32)
+    return g, synth.pinhole(48, 40, 60.0, 60.0), rng
+
+
+def test_adjoint_matches_finite_differences_thin_discs():
+    """Thin particles: B's largest eigenvalue is 1e6-1e8 times its smallest, so the chain from
+    dL/dB to rotation and scales must not pass through dL/dSigma = -B G B (whose entries reach
+    (1/s_min^2)^2 |G|): that route is off by ~1% in the quaternion gradient here."""
+    g, s, rng = _thin_disc_scene(11)
+    R = s["width"] * s["height"]
+    up = dict(feat=rng.standard_normal((3, R)), depth=0.1 * rng.standard_normal(R),
+              alpha=rng.standard_normal(R))
+    proj, lists, out = oracle.render(g, s)
+    gr = oracle.backward(g, s, lists, up)
+    sel = np.argsort(np.abs(gr["quat"]).sum(0))[-40:]
+    fd = oracle.fd_grad(g, s, lists, up, sel, h=1e-5)
+    an = oracle.grads_as_rows(gr, sel)
+    geo = slice(0, 10)                               # mean, quat, log_scale
+    scale = np.abs(fd[:, geo]).max()
+    assert scale > 1.0
+    np.testing.assert_allclose(an[:, geo], fd[:, geo], atol=1e-4 * scale, rtol=1e-4)
+
+
 @pytest.mark.parametrize("theta", [0.0, 0.02])
 def test_adjoint_matches_finite_differences_lidar(theta):
     """theta > 0: with the beam-divergence filter the mean also moves the smoothing term
