@@ -623,7 +623,7 @@ def bench_configs(ut, synth, dev, args):
         n, Kc = g.n, (g.sh_degree + 1) ** 2
         n_super = int(s.n_super)
         pair_passes = (max(int(np.ceil(np.log2(max(n_super, 2)))), 1) + 7) // 8
-        b_proj = 76 * n + (12 * Kc + 128) * V
+        b_proj = 76 * n + (12 * Kc + int(ut.lib().ut_record_bytes())) * V
         b_depth = 16 * n + (4 * 16 + 4) * V
         b_pair = (8 + 16 * pair_passes + 4) * P
         gbps = lambda b, ms: b / (ms * 1e-3) / 1e9

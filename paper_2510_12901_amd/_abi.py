@@ -13,7 +13,7 @@ f64 = C.c_double
 UT_OK, UT_ERR_ARG, UT_ERR_CAPACITY, UT_ERR_DEVICE, UT_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 PINHOLE, FISHEYE, LIDAR, ORTHO = 0, 1, 2, 3
 FEAT_CAMERA, FEAT_LIDAR = 0, 1
-RECORD_BYTES = 128
+RECORD_BYTES = 128   # UT_RECORD_BYTES; lib() refuses a library built with another size
 ACC_FLOATS = 13
 
 
@@ -120,6 +120,10 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        if L.ut_record_bytes() != RECORD_BYTES:
+            # buffers sized here would not hold the library's records
+            raise ImportError(f"{LIB_PATH} writes {L.ut_record_bytes()}-byte records, the binding "
+                              f"allocates {RECORD_BYTES}: rebuild the library")
         _lib = L
     return _lib
 

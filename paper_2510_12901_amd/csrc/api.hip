@@ -446,7 +446,7 @@ ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items, const 
       BatchItemK k;
       std::memset(&k, 0, sizeof k);
       k.s = make_sensor_k(it.sensor);
-      k.rec = reinterpret_cast<const Record*>(it.proj->records);
+      k.rec = reinterpret_cast<const RecordG*>(it.proj->records);
       k.trect = reinterpret_cast<const uint2*>(it.proj->trect);
       k.gauss = it.bins->gauss;
       k.ranges = it.bins->ranges;

@@ -47,7 +47,7 @@ __device__ __forceinline__ double wave_reduce_scatter16(const double v[16], int 
 }
 
 template <int BLOCK, bool MOVING>
-__global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __restrict__ rec,
+__global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const RecordG* __restrict__ rec,
                                                      const uint2* __restrict__ trect,
                                                      const uint32_t* __restrict__ bgauss,
                                                      const uint32_t* __restrict__ branges, int n_super,
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
     const int cnt = (int)kt;
     for (int c = threadIdx.x; c < cnt * kRecordChunks; c += BLOCK) {
       const int j = c / kRecordChunks, part = c - j * kRecordChunks;
-      reinterpret_cast<uint4*>(sh + j)[part] = reinterpret_cast<const uint4*>(rec + sh_g[j])[part];
+      stage_record_chunk(rec + sh_g[j], sh + j, part);
     }
     __syncthreads();
     top -= ht;
@@ -184,10 +184,10 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
         Centre cv;   // the centre seen from this ray's origin
         if constexpr (mv) cv = pair_centre(r, ex, ey, ez);
         else cv = record_centre(r);
-        const PairGeom q = pair_geometry(r, cv, rq);
-        const PairResp pr = pair_response(q);
+        PairResp pr;
+        const bool pass = pair_eval(r, cv, rq, ex, ey, ez, cut_threshold(r.log_sigma, prm.log_alpha_min), pr);
         const double tau = pr.tau;
-        if (!pair_cut(q, cut_threshold(r.log_sigma, prm.log_alpha_min)) && tau >= s.near_) {
+        if (pass && tau >= s.near_) {
           const double a = pair_alpha(r, pr, kExp2Frac);
           const bool clamped = a > prm.alpha_max;
           const double alpha = clamped ? prm.alpha_max : a;
@@ -209,17 +209,25 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const Record* __r
               g[3] = dalpha * (a / exp_neg(r.log_sigma, kExp2Frac));   // dL/dsigma = dL/dalpha * rho
               dD2 = -0.5 * dalpha * a;
             }
-            // B d from the record's quadric and B u = B v - t* B d, u = mu - o - t* d
+            // B d from the record's quadric and B u = B v - t* B d, u = mu - o - t* d (for thin
+            // records B u from u itself: the difference cancels like the forward's num)
             double bd[3];
             sym_apply(r.b, dx, dy, dz, bd);
             const double bdx = bd[0], bdy = bd[1], bdz = bd[2];
-            const double bux = __builtin_fma(-tau, bdx, cv.bv[0]);
-            const double buy = __builtin_fma(-tau, bdy, cv.bv[1]);
-            const double buz = __builtin_fma(-tau, bdz, cv.bv[2]);
             const uint32_t gi = sh_g[jj];
             const double ux = ((double)mean[gi] - ox) - tau * dx;
             const double uy = ((double)mean[n + gi] - oy) - tau * dy;
             const double uz = ((double)mean[2 * n + gi] - oz) - tau * dz;
+            double bux, buy, buz;
+            if (record_thin(r)) {
+              double bu[3];
+              sym_apply(r.b, ux, uy, uz, bu);
+              bux = bu[0]; buy = bu[1]; buz = bu[2];
+            } else {
+              bux = __builtin_fma(-tau, bdx, cv.bv[0]);
+              buy = __builtin_fma(-tau, bdy, cv.bv[1]);
+              buz = __builtin_fma(-tau, bdz, cv.bv[2]);
+            }
             const double t2 = 2.0 * dD2, ti = dtau * pr.idbd;
             g[4] = t2 * bux + ti * bdx;
             g[5] = t2 * buy + ti * bdy;
@@ -408,7 +416,7 @@ hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const u
   hipError_t e = fill_f64(acc, 0.0, (size_t)UT_ACC_FLOATS * g.n, st);
   if (e != hipSuccess || g.n == 0) return e;
   const int n_tiles = s.tiles_x * s.tiles_y;
-  const Record* rec = reinterpret_cast<const Record*>(p.records);
+  const RecordG* rec = reinterpret_cast<const RecordG*>(p.records);
   const uint2* tr = reinterpret_cast<const uint2*>(p.trect);
   const int n_super = s.super_x * s.super_y;
   if (n_tiles > 0) {

@@ -50,7 +50,7 @@ struct CompositeShared {
 // TILE_END: track each ray's bin end and write the tile's (adjoint state); the batched serving
 // path, which never feeds an adjoint, leaves it out and keeps those registers.
 template <int BLOCK, int RPL, int BATCH, bool STATS = false, bool MOVING = false, bool TILE_END = true>
-__device__ __forceinline__ void composite_tile(const SensorK& s, const Record* __restrict__ rec,
+__device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* __restrict__ rec,
                                                const uint2* __restrict__ trect,
                                                const uint32_t* __restrict__ bgauss,
                                                const uint32_t* __restrict__ branges, int tile, int n_super,
@@ -177,7 +177,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
       const uint32_t j = c / kRecordChunks, part = c - j * kRecordChunks;
       const uint32_t slot = (head + j) & kRing;
       const uint32_t g = sm.cand[slot];
-      reinterpret_cast<uint4*>(sm.rec + j)[part] = reinterpret_cast<const uint4*>(rec + g)[part];
+      stage_record_chunk(rec + g, sm.rec + j, (int)part);
       if (part == 0) {
         sm.rpos[j] = sm.cpos[slot];
         if constexpr (TILE_END) sm.rbin[j] = sm.cbin[slot];
@@ -193,11 +193,12 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const Record* _
           Centre cv;
           if constexpr (MOVING) cv = pair_centre(r, ex[k], ey[k], ez[k]);
           else cv = record_centre(r);
-          const PairGeom q = pair_geometry(r, cv, rq[k]);
           if constexpr (STATS) ++nvisit[k];
-          if (pair_cut(q, cut_threshold(r.log_sigma, prm.log_alpha_min))) continue;
+          PairResp pr;
+          if (!pair_eval(r, cv, rq[k], MOVING ? ex[k] : 0.0, MOVING ? ey[k] : 0.0, MOVING ? ez[k] : 0.0,
+                         cut_threshold(r.log_sigma, prm.log_alpha_min), pr))
+            continue;
           if constexpr (STATS) ++npass[k];
-          const PairResp pr = pair_response(q);
           const double tau = pr.tau;
           if (tau < s.near_) continue;
           const double alpha = __builtin_fmin(pair_alpha(r, pr, sm.etab), prm.alpha_max);
@@ -271,7 +272,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n_tiles) {
 // accumulators in 128 VGPRs (4 waves per SIMD) with no spill in the pair loop; two rays per
 // lane take 3 waves.
 template <int BLOCK, int RPL, int BATCH, bool STATS, bool MOVING>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(RPL == 1 ? 4 : 3))) void k_composite(SensorK s, const Record* __restrict__ rec,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(RPL == 1 ? 4 : 3))) void k_composite(SensorK s, const RecordG* __restrict__ rec,
                                                       const uint2* __restrict__ trect,
                                                       const uint32_t* __restrict__ bgauss,
                                                       const uint32_t* __restrict__ branges, int n_tiles,
@@ -314,7 +315,7 @@ hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, con
   const int n_tiles = s.tiles_x * s.tiles_y;
   if (n_tiles == 0) return hipSuccess;
   const int grid = 8 * ((n_tiles + 7) / 8);
-  const Record* rec = reinterpret_cast<const Record*>(p.records);
+  const RecordG* rec = reinterpret_cast<const RecordG*>(p.records);
   const uint2* tr = reinterpret_cast<const uint2*>(p.trect);
   const bool stats = out.n_visit != nullptr || out.n_pass != nullptr;
   const bool mv = s.moving != 0;

@@ -169,7 +169,7 @@ __device__ __forceinline__ bool beam_divergence_filter(const SensorK& s, float m
 
 template <int DEG, int KIND, bool MOVING, bool DIV = false>
 __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK& s, double ut_a, double ut_b,
-                                            double ut_k, Record* __restrict__ rec,
+                                            double ut_k, RecordG* __restrict__ rec,
                                             int32_t* __restrict__ rect, uint2* __restrict__ trect,
                                             uint32_t* __restrict__ key,
                                             uint32_t* __restrict__ count, float* __restrict__ moments,
@@ -185,7 +185,7 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
     const double qq = (double)q0 * q0 + (double)q1 * q1 + (double)q2 * q2 + (double)q3 * q3;
     bool ok = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(l0) && isfinite(l1) &&
               isfinite(l2) && isfinite(lg) && isfinite(qq) && qq > 0;
-    Record r;
+    RecordG r;
     double M[9], A[3];   // M with M^T M = Sigma^{-1}, and A = M (mu - o)
     double Rm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, sc[3] = {1, 1, 1};
     if (ok) {
@@ -381,9 +381,10 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
         for (int k = 0; k < K; ++k) acc += (double)g.feat[(size_t)(k * 3 + c) * n + i] * Y[k];
         f[c] = (g.feat_kind == UT_FEAT_CAMERA) ? (acc + 0.5 > 0 ? acc + 0.5 : 0.0) : acc;
       }
-      r.feat[0] = f[0]; r.feat[1] = f[1]; r.feat[2] = f[2];
+      r.feat[0] = (float)f[0]; r.feat[1] = (float)f[1]; r.feat[2] = (float)f[2];
+      r.pad = 0.0f;
       if constexpr (!DIV) form_m();
-      // the quadric form of the record: B = M^T M, B v = M^T A, v^T B v = A.A, trace(B) = |M|_F^2
+      // the quadric form of the record: B = M^T M, B v = M^T A, v^T B v = A.A
       r.b[0] = __builtin_fma(M[0], M[0], __builtin_fma(M[3], M[3], M[6] * M[6]));
       r.b[1] = __builtin_fma(M[0], M[1], __builtin_fma(M[3], M[4], M[6] * M[7]));
       r.b[2] = __builtin_fma(M[0], M[2], __builtin_fma(M[3], M[5], M[6] * M[8]));
@@ -394,8 +395,7 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
       r.bv[1] = __builtin_fma(M[1], A[0], __builtin_fma(M[4], A[1], M[7] * A[2]));
       r.bv[2] = __builtin_fma(M[2], A[0], __builtin_fma(M[5], A[1], M[8] * A[2]));
       r.vbv = __builtin_fma(A[0], A[0], __builtin_fma(A[1], A[1], A[2] * A[2]));
-      r.trb = r.b[0] + r.b[3] + r.b[5];
-      r.pad = 0.0;
+      r.v[0] = vx; r.v[1] = vy; r.v[2] = vz;
       const uint4* src = reinterpret_cast<const uint4*>(&r);
       uint4* dst = reinterpret_cast<uint4*>(rec + i);
 #pragma unroll
@@ -440,7 +440,7 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
 // trades them for a third wave, and the pinhole then takes over twice as long).
 template <int DEG, int KIND, bool MOVING, bool DIV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_project_capped(
-    ut_gaussians g, SensorK s, double ut_a, double ut_b, double ut_k, Record* __restrict__ rec,
+    ut_gaussians g, SensorK s, double ut_a, double ut_b, double ut_k, RecordG* __restrict__ rec,
     int32_t* __restrict__ rect, uint2* __restrict__ trect, uint32_t* __restrict__ key,
     uint32_t* __restrict__ count, float* __restrict__ moments, uint32_t* __restrict__ n_culled) {
   project_all<DEG, KIND, MOVING, DIV>(g, s, ut_a, ut_b, ut_k, rec, rect, trect, key, count, moments, n_culled);
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 
 template <int DEG, int KIND, bool MOVING>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_project(
-    ut_gaussians g, SensorK s, double ut_a, double ut_b, double ut_k, Record* __restrict__ rec,
+    ut_gaussians g, SensorK s, double ut_a, double ut_b, double ut_k, RecordG* __restrict__ rec,
     int32_t* __restrict__ rect, uint2* __restrict__ trect, uint32_t* __restrict__ key,
     uint32_t* __restrict__ count, float* __restrict__ moments, uint32_t* __restrict__ n_culled) {
   project_all<DEG, KIND, MOVING>(g, s, ut_a, ut_b, ut_k, rec, rect, trect, key, count, moments, n_culled);
@@ -462,7 +462,7 @@ hipError_t launch_project(const ut_gaussians& g, const SensorK& s, const double 
   if (e != hipSuccess) return e;
   if (g.n == 0) return hipSuccess;
   const int blocks = std::min((g.n + 255) / 256, 2048);
-  Record* rec = reinterpret_cast<Record*>(out.records);
+  RecordG* rec = reinterpret_cast<RecordG*>(out.records);
   uint2* tr = reinterpret_cast<uint2*>(out.trect);
 #define UT_LAUNCH_PROJECT(KERNEL, D, K, MV)                                                                \
   hipLaunchKernelGGL((KERNEL<D, K, MV>), dim3(blocks), dim3(256), 0, st, g, s, abk[0], abk[1], abk[2], rec, \

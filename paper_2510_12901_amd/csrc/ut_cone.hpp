@@ -100,7 +100,7 @@ __device__ __forceinline__ void tile_cone_finish(double cmin, double sn, double 
 // exactly ones every ray of the tile would skip, so outputs are unchanged.  For a moving
 // sensor the rays start from different origins; the threshold grows by their spread.
 template <bool MOVING>
-__device__ __forceinline__ bool cone_rejects(const Record* __restrict__ rp, const TileCone& tc,
+__device__ __forceinline__ bool cone_rejects(const RecordG* __restrict__ rp, const TileCone& tc,
                                              double log_alpha_min) {
   double cut = cut_threshold(rp->log_sigma, log_alpha_min);
   double b[6];
@@ -114,7 +114,7 @@ __device__ __forceinline__ bool cone_rejects(const Record* __restrict__ rp, cons
     // |M e| <= |M|_F emax and |M|_F^2 = trace(B), so the distance to each ray's line is at
     // least the one from the reference origin minus that.
     if (cut < 0.0) return true;   // sigma < alpha_min: no ray reaches it
-    const double r = __builtin_sqrt(cut) + __builtin_sqrt(rp->trb) * tc.emax;
+    const double r = __builtin_sqrt(cut) + __builtin_sqrt(b[0] + b[3] + b[5]) * tc.emax;   // trace(B) = |M|_F^2
     cut = r * r;
   }
   cut += 0.05;
@@ -146,7 +146,10 @@ __device__ __forceinline__ bool cone_rejects(const Record* __restrict__ rp, cons
     const double f1 = __builtin_fma(Rc, tc.cos2t, P) - B * tc.sin2t;
     fmin = A < f1 ? A : f1;
   }
-  return fmin > 0.0;
+  // the cone's quadric (v^T B v - cut) B - B v (B v)^T cancels like num does: thin records
+  // are never dropped here (their pairs are decided by the residual form).  Tested last, so
+  // the record's loads are not held behind a branch.
+  return fmin > 0.0 && !record_thin(*rp);
 }
 
 }  // namespace ut

@@ -8,6 +8,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "utrast.h"
@@ -21,23 +22,55 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kSuper = UT_SUPER_TILE;
 
 // Per-particle compositing record written by the projection for one sensor, read
-// (gathered) by the compositing and adjoint kernels.  128 bytes = eight 16-byte chunks.
+// (gathered) by the compositing and adjoint kernels.  128 bytes = eight 16-byte chunks, so a
+// gathered record is one cache line.
 // The response along a ray o + t d is a quadric in t: with B = Sigma^{-1} and v = mu - o,
 // (t d - v)^T B (t d - v) is smallest at t* = d^T B v / d^T B d, where it equals
 // D^2 = (v^T B v d^T B d - (d^T B v)^2) / d^T B d.  B, B v and v^T B v are fixed per particle
 // and sensor, so a pair costs the two ray products d^T B d (from the ray's six quadratic
 // monomials) and d^T B v.
-struct alignas(16) Record {
+struct alignas(16) RecordG {
   double b[6];       // B = Sigma^{-1}: b00, b01, b02, b11, b12, b22
   double bv[3];      // B (mu - o), o = sensor origin
   double vbv;        // (mu - o)^T B (mu - o)
   double log_sigma;  // ln(opacity): alpha = exp(ln sigma - D^2 / 2), and the pre-test threshold
-  double feat[3];    // colour or LiDAR features evaluated at the particle's SH direction
-  double trb;        // trace(B) = |M|_F^2 for every M with M^T M = B
+  double v[3];       // mu - o itself, for the residual form of thin records (record_thin)
+  float feat[3];     // colour or LiDAR features at the particle's SH direction (the outputs' precision)
+  float pad;
+};
+static_assert(sizeof(RecordG) == UT_RECORD_BYTES, "record size must match the ABI");
+constexpr int kRecordChunks = UT_RECORD_BYTES / 16;
+constexpr int kFeatChunk = 7;   // the chunk holding feat; the seven before it are float64 fields
+
+// The record as the compositing and adjoint kernels keep it in LDS: the same fields with the
+// features widened to float64 once, when the record is staged.
+struct alignas(16) Record {
+  double b[6];
+  double bv[3];
+  double vbv;
+  double log_sigma;
+  double v[3];
+  double feat[3];
   double pad;
 };
-static_assert(sizeof(Record) == UT_RECORD_BYTES, "record size must match the ABI");
-constexpr int kRecordChunks = UT_RECORD_BYTES / 16;
+static_assert(sizeof(Record) == UT_RECORD_BYTES + 16, "staged record layout");
+
+static_assert(offsetof(RecordG, feat) == kFeatChunk * 16, "chunk map of the record");
+
+// Records whose v^T B v exceeds kThinVbv take the residual form of D^2 (pair_eval).
+constexpr double kThinVbv = 1e7;
+
+// Stage chunk `part` of a gathered record into its LDS copy.
+__device__ __forceinline__ void stage_record_chunk(const RecordG* __restrict__ src, Record* dst, int part) {
+  const uint4 x = reinterpret_cast<const uint4*>(src)[part];
+  if (part < kFeatChunk) {
+    reinterpret_cast<uint4*>(dst)[part] = x;
+  } else {
+    dst->feat[0] = (double)__uint_as_float(x.x);
+    dst->feat[1] = (double)__uint_as_float(x.y);
+    dst->feat[2] = (double)__uint_as_float(x.z);
+  }
+}
 
 // Sensor description passed to kernels by value.
 struct SensorK {
@@ -191,7 +224,8 @@ struct Centre {
   double vbv;
 };
 
-__device__ __forceinline__ Centre record_centre(const Record& c) {
+template <class Rec>
+__device__ __forceinline__ Centre record_centre(const Rec& c) {
   Centre q;
   q.bv[0] = c.bv[0]; q.bv[1] = c.bv[1]; q.bv[2] = c.bv[2];
   q.vbv = c.vbv;
@@ -200,7 +234,8 @@ __device__ __forceinline__ Centre record_centre(const Record& c) {
 
 // Centre for a ray whose origin lies e = o_i - o from the record's sensor origin o:
 // v_i = v - e, so B v_i = B v - B e and v_i^T B v_i = v^T B v - e^T (2 B v - B e).
-__device__ __forceinline__ Centre pair_centre(const Record& c, double ex, double ey, double ez) {
+template <class Rec>
+__device__ __forceinline__ Centre pair_centre(const Rec& c, double ex, double ey, double ez) {
   double be[3];
   sym_apply(c.b, ex, ey, ez, be);
   Centre q;
@@ -241,6 +276,40 @@ __device__ __forceinline__ PairResp pair_response(const PairGeom& q) {
   r.tau = q.dbv * r.idbd;
   r.D2 = __builtin_fmax(q.num, 0.0) * r.idbd;
   return r;
+}
+
+// Records whose v^T B v exceeds kThinVbv (particles very thin, or small and far, relative to
+// their distance) lose about ulp(v^T B v) of D^2 to the cancellation in
+// num = v^T B v d^T B d - (d^T B v)^2: 2e-3 in alpha for a disc 1e-4 as thick as it is wide
+// at 50 m.  For them D^2 comes from the residual u = v_i - t* d instead, D^2 = u^T B u, whose
+// error stays near ulp(|v|) in the whitened frame.  The test reads the record, so it is
+// uniform across a wavefront; fewer than 1 in 10^4 records of a typical scene take it.
+template <class Rec>
+__device__ __forceinline__ bool record_thin(const Rec& c) { return c.vbv > kThinVbv; }
+
+// Response of one (ray, record) pair for a ray whose origin lies e from the record's sensor
+// origin (cv = pair_centre(c, e), or record_centre(c) with e = 0).  Returns false when the
+// pair cannot reach alpha_min (D^2 > cut); otherwise pr holds 1/d^T B d, t* and D^2.  The
+// compositing and the adjoint both evaluate pairs here, so their alphas are bit-identical.
+// Every active lane of a wavefront evaluates the same record, so the thin test is taken from
+// the first active lane as a scalar branch.
+__device__ __forceinline__ bool pair_eval(const Record& c, const Centre& cv, const RayQ& d, double ex, double ey,
+                                          double ez, double cut, PairResp& pr) {
+  const PairGeom q = pair_geometry(c, cv, d);
+  if (__builtin_expect(__builtin_amdgcn_readfirstlane((int)record_thin(c)), 0)) {
+    pr.idbd = rcp_f64(q.dbd);
+    pr.tau = q.dbv * pr.idbd;
+    const double ux = __builtin_fma(-pr.tau, d.x, c.v[0] - ex);
+    const double uy = __builtin_fma(-pr.tau, d.y, c.v[1] - ey);
+    const double uz = __builtin_fma(-pr.tau, d.z, c.v[2] - ez);
+    const double cross = __builtin_fma(c.b[1], ux * uy, __builtin_fma(c.b[2], ux * uz, c.b[4] * (uy * uz)));
+    const double diag = __builtin_fma(c.b[0], ux * ux, __builtin_fma(c.b[3], uy * uy, c.b[5] * (uz * uz)));
+    pr.D2 = __builtin_fmax(__builtin_fma(2.0, cross, diag), 0.0);
+    return !(pr.D2 > cut);
+  }
+  if (pair_cut(q, cut)) return false;
+  pr = pair_response(q);
+  return true;
 }
 
 // Unclamped opacity of the pair, sigma * exp(-D^2 / 2), evaluated as exp(ln sigma - D^2 / 2).

@@ -57,7 +57,7 @@ hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, con
 // Batched persistent compositing over several requests.
 struct BatchItemK {
   SensorK s;
-  const Record* rec;
+  const RecordG* rec;
   const uint2* trect;
   const uint32_t* gauss;    // super-tile bins
   const uint32_t* ranges;

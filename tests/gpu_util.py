@@ -9,8 +9,8 @@ import oracle
 AMBIG = 1e-9          # decisions closer than this to their threshold are ambiguous
 TOL = 1e-4            # max-abs bound on feat / depth / alpha / drop
 
-REC_DTYPE = np.dtype([("b", "<f8", 6), ("bv", "<f8", 3), ("vbv", "<f8"), ("log_sigma", "<f8"), ("feat", "<f8", 3),
-                      ("trb", "<f8"), ("pad", "<f8")])
+REC_DTYPE = np.dtype([("b", "<f8", 6), ("bv", "<f8", 3), ("vbv", "<f8"), ("log_sigma", "<f8"), ("v", "<f8", 3),
+                      ("feat", "<f4", 3), ("pad", "<f4")])
 
 
 def rec_B(rec, i):
@@ -94,7 +94,21 @@ def compare_projection(gp, op, lidar):
     return int((~ok).sum())
 
 
-def compare_outputs(go, oo, exclude_rays=None, tol=TOL):
+def d2_representation_error(g_np):
+    """Bound on the difference of two float64 evaluations of D^2 = u^T B u that start from
+    different roundings of B.  An entry of B is rounded at its largest eigenvalue, 1/s_min^2,
+    and a pair that reaches alpha_min has |u| <= 3.3 s_max (D^2 <= 2 ln(1/alpha_min) ~ 11), so
+    the two D^2 differ by at most ~9 |u|^2 * 2 ulp(1/s_min^2) = 16 eps (3.3 s_max / s_min)^2
+    (rounded up).  Negligible for ordinary particles, it is what separates two correct
+    renders of particles 1e-4 as thick as they are wide."""
+    sc = np.exp(np.asarray(g_np["log_scale"], np.float64))
+    k = (3.3 * sc.max(axis=0) / sc.min(axis=0)) ** 2
+    return float(16.0 * np.finfo(np.float64).eps * k.max())
+
+
+def compare_outputs(go, oo, exclude_rays=None, tol=TOL, eps_d2=0.0):
+    """eps_d2: per-pair D^2 difference allowed by the arithmetic (d2_representation_error);
+    a composited pair moves ln T by alpha/(1-alpha) * eps_d2 / 2 <= 49.5 eps_d2."""
     keep = oo["margin"] >= AMBIG
     if exclude_rays is not None:
         keep &= ~exclude_rays
@@ -107,12 +121,15 @@ def compare_outputs(go, oo, exclude_rays=None, tol=TOL):
         errs[k] = float(d.max(initial=0))
         assert errs[k] <= tol, (k, errs[k])
     assert np.array_equal(go["n_proc"][keep], oo["n_proc"][keep])
-    assert np.all(np.abs(go["t_final"][keep] - oo["t_final"][keep]) <= 1e-9 + 1e-9 * oo["t_final"][keep])
+    t_ref = oo["t_final"][keep]
+    t_tol = 1e-9 + (1e-9 + 49.5 * eps_d2 * oo["n_proc"][keep]) * t_ref
+    assert np.all(np.abs(go["t_final"][keep] - t_ref) <= t_tol)
     return errs, int((~keep).sum())
 
 
-def full_parity(g_np, s_np):
-    """GPU pipeline vs oracle pipeline on a small scene; returns (errors, excluded rays)."""
+def full_parity(g_np, s_np, eps_d2=0.0):
+    """GPU pipeline vs oracle pipeline on a small scene; returns (errors, excluded rays).
+    eps_d2 widens the t_final check for scenes of very thin particles (compare_outputs)."""
     gp, handles = gpu_render(g_np, s_np)
     os_ = oracle.OracleSensor(s_np)
     op, ol, oo = oracle.render(g_np, os_)
@@ -128,5 +145,5 @@ def full_parity(g_np, s_np):
         excl = np.isin(ray_tiles(os_), list(tiles))
     else:
         assert gp["n_pairs"] == ol["n_pairs"]
-    errs, n_ex = compare_outputs(gp, oo, excl)
+    errs, n_ex = compare_outputs(gp, oo, excl, eps_d2=eps_d2)
     return errs, n_ex, gp, oo, handles

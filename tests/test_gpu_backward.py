@@ -143,3 +143,23 @@ def test_backward_matches_oracle_rolling_shutter_camera():
     _, ol, _ = oracle.render(g, s)
     ref = oracle.backward(g, s, ol, up)
     _check(gpu, ref, label="rolling shutter")
+
+
+def test_backward_matches_oracle_thin_discs():
+    """Adjoint for discs 1e-3 to 1e-4 as thick as they are wide, 10-30 m away (v^T B v up to
+    ~1e11): pairs evaluated by the residual form of D^2, B u taken from u itself."""
+    rng = np.random.default_rng(11)
+    n = 500
+    mean = np.stack([rng.uniform(-4, 4, n), rng.uniform(-3, 3, n), rng.uniform(10, 30, n)])
+    g = synth.particles(rng, mean, 0.3, 1.2, 0, synth.FEAT_CAMERA)
+    w = rng.uniform(np.log(0.3), np.log(1.2), n)
+    g["log_scale"] = np.stack([w, w + rng.uniform(-0.5, 0.5, n),
+                               w + rng.uniform(np.log(1e-4), np.log(1e-3), n)]).astype(np.float32)
+    s = synth.pinhole(48, 40, 60.0, 60.0)
+    R = 48 * 40
+    up = _as32(dict(feat=rng.standard_normal((3, R)), depth=0.1 * rng.standard_normal(R),
+                    alpha=rng.standard_normal(R)))
+    gpu, _ = _gpu_backward(g, s, up)
+    _, ol, _ = oracle.render(g, s)
+    ref = oracle.backward(g, s, ol, up)
+    _check(gpu, ref, label="thin discs")
