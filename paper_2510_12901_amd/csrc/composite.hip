@@ -173,15 +173,22 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* 
     }
     if (n_cand == 0) break;
     const uint32_t cnt = min(n_cand, (uint32_t)kBatch);
-    for (uint32_t c = threadIdx.x; c < cnt * kRecordChunks; c += BLOCK) {
-      const uint32_t j = c / kRecordChunks, part = c - j * kRecordChunks;
+    // stage the batch: the float64 chunks as plain copies, then per record its features
+    // widened to float64 (two uniform loops instead of one with a divergent chunk)
+    for (uint32_t c = threadIdx.x; c < cnt * kFeatChunk; c += BLOCK) {
+      const uint32_t j = c / kFeatChunk, part = c - j * kFeatChunk;
+      const uint32_t g = sm.cand[(head + j) & kRing];
+      reinterpret_cast<uint4*>(sm.rec + j)[part] = reinterpret_cast<const uint4*>(rec + g)[part];
+    }
+    for (uint32_t j = threadIdx.x; j < cnt; j += BLOCK) {
       const uint32_t slot = (head + j) & kRing;
       const uint32_t g = sm.cand[slot];
-      stage_record_chunk(rec + g, sm.rec + j, (int)part);
-      if (part == 0) {
-        sm.rpos[j] = sm.cpos[slot];
-        if constexpr (TILE_END) sm.rbin[j] = sm.cbin[slot];
-      }
+      const uint4 x = reinterpret_cast<const uint4*>(rec + g)[kFeatChunk];
+      sm.rec[j].feat[0] = (double)__uint_as_float(x.x);
+      sm.rec[j].feat[1] = (double)__uint_as_float(x.y);
+      sm.rec[j].feat[2] = (double)__uint_as_float(x.z);
+      sm.rpos[j] = sm.cpos[slot];
+      if constexpr (TILE_END) sm.rbin[j] = sm.cbin[slot];
     }
     __syncthreads();
     if (!done) {
