@@ -145,9 +145,11 @@ def test_backward_matches_oracle_rolling_shutter_camera():
     _check(gpu, ref, label="rolling shutter")
 
 
-def test_backward_matches_oracle_thin_discs():
+@pytest.mark.parametrize("moving", [False, True])
+def test_backward_matches_oracle_thin_discs(moving):
     """Adjoint for discs 1e-3 to 1e-4 as thick as they are wide, 10-30 m away (v^T B v up to
-    ~1e11): pairs evaluated by the residual form of D^2, B u taken from u itself."""
+    ~1e11): pairs evaluated by the residual form of D^2, B u taken from u itself.  moving: a
+    rolling-shutter camera, every ray with its own origin (u = v - e - t* d)."""
     rng = np.random.default_rng(11)
     n = 500
     mean = np.stack([rng.uniform(-4, 4, n), rng.uniform(-3, 3, n), rng.uniform(10, 30, n)])
@@ -156,10 +158,14 @@ def test_backward_matches_oracle_thin_discs():
     g["log_scale"] = np.stack([w, w + rng.uniform(-0.5, 0.5, n),
                                w + rng.uniform(np.log(1e-4), np.log(1e-3), n)]).astype(np.float32)
     s = synth.pinhole(48, 40, 60.0, 60.0)
+    if moving:
+        c, sn = np.cos(0.03), np.sin(0.03)
+        R1 = np.array([[c, 0, -sn], [0, 1, 0], [sn, 0, c]], np.float32)
+        s = synth.rolling_shutter(s, R1, np.array([0.4, -0.1, 0.3], np.float32))
     R = 48 * 40
     up = _as32(dict(feat=rng.standard_normal((3, R)), depth=0.1 * rng.standard_normal(R),
                     alpha=rng.standard_normal(R)))
     gpu, _ = _gpu_backward(g, s, up)
     _, ol, _ = oracle.render(g, s)
     ref = oracle.backward(g, s, ol, up)
-    _check(gpu, ref, label="thin discs")
+    _check(gpu, ref, label="thin discs, moving" if moving else "thin discs")
