@@ -45,7 +45,7 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "composite_traffic.json")
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("composite.hip", "ut_device.hpp"):
+    for f in ("composite.hip", "ut_cone.hpp", "ut_internal.hpp", "ut_device.hpp"):   # the kernel and its headers
         h.update(open(os.path.join(ROOT, "paper_2510_12901_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -153,7 +153,8 @@ def summarize_profiles(stats_csv: str, fetch_csv: str, write_csv: str):
           "|---|---|---|---|---|",
           f"| FETCH_SIZE | {f_kib:.1f} | {f_ref:.1f} | {f_fac:.4f} | {fetch_b / 1e6:.1f} MB |",
           f"| WRITE_SIZE | {w_kib:.1f} | {w_ref:.1f} | {w_fac:.4f} | {write_b / 1e6:.1f} MB |", "",
-          f"Traffic per launch: {(fetch_b + write_b) / 1e6:.1f} MB (kernel source hash {traffic['kernel_source_hash']}; "
+          f"Traffic per launch: {(fetch_b + write_b) / 1e6:.1f} MB (kernel source hash {traffic['kernel_source_hash']}, "
+          "over composite.hip and the headers it includes; "
           "bench.py reports it only while the hash matches)."]
     open(os.path.join(ROOT, "profiles", "composite_traffic_multisensor.md"), "w").write("\n".join(md) + "\n")
     print(json.dumps(traffic))
