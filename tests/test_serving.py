@@ -118,3 +118,38 @@ def test_request_larger_than_pool_is_rejected():
     server = serve.Server(g, g, [s], pool_bytes=4096, n_slots=2)
     with pytest.raises(RuntimeError, match="whole pool"):
         server.run([(0.0, 0, 0)])
+
+
+@pytest.mark.gpu
+def test_served_thin_discs_bit_identical_to_plain():
+    """The batched compositing kernel on records that take the residual form of D^2 (discs
+    1e-3 to 1e-5 as thick as they are wide): every served result equals the plain render."""
+    import torch
+    import paper_2510_12901_amd as ut
+    import synth
+    rng = np.random.default_rng(8)
+    n = 4000
+    mean = np.stack([rng.uniform(-10, 10, n), rng.uniform(-7, 7, n), rng.uniform(15, 60, n)])
+    g_np = synth.particles(rng, mean, 0.3, 1.5, 0, synth.FEAT_CAMERA)
+    w = rng.uniform(np.log(0.3), np.log(1.5), n)
+    g_np["log_scale"] = np.stack([w, w + rng.uniform(-0.5, 0.5, n),
+                                  w + rng.uniform(np.log(1e-5), np.log(1e-3), n)]).astype(np.float32)
+    g = ut.GaussianSet.from_numpy(g_np)
+    sensors = [ut.Sensor(synth.pinhole(160, 120, 220.0, 220.0)), ut.Sensor(synth.pinhole(128, 96, 150.0, 150.0))]
+    ref = []
+    for s in sensors:
+        _, _, out = ut.render(g, s, state=False)
+        ref.append({k: getattr(out, k).cpu().numpy() for k in ("feat", "depth", "alpha")})
+    assert (ref[0]["alpha"] > 0).mean() > 0.5
+    server = serve.Server(g, g, sensors, pool_bytes=64 << 20, n_slots=4, n_workgroups=512)
+    trace = serve.poisson_trace(1000.0, 0.03, len(sensors), seed=2)
+    seen = []
+
+    def check(r):
+        for k in ("feat", "depth", "alpha"):
+            assert np.array_equal(getattr(r.out, k).cpu().numpy(), ref[r.sensor][k]), (r.rid, k)
+        seen.append(r.rid)
+
+    server.run(trace, on_done=check)
+    torch.cuda.synchronize()
+    assert sorted(seen) == list(range(len(trace))) and len(seen) >= 10
