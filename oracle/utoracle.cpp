@@ -1189,7 +1189,8 @@ struct Frozen {
 };
 
 Frozen forward_record(const orc_gaussians* g, const orc_sensor* s, const orc_params* prm,
-                      const PerGaussian& pg, const uint32_t* pair_gauss, const uint32_t* ranges) {
+                      const PerGaussian& pg, const uint32_t* pair_gauss, const uint32_t* ranges,
+                      const std::vector<char>& active) {
   const int TX = sensor_tiles_x(s), TY = sensor_tiles_y(s), NT = TX * TY;
   const long R = (s->kind == 2) ? (long)s->n_beams * s->n_az : (long)s->width * s->height;
   Frozen fz;
@@ -1199,12 +1200,25 @@ Frozen forward_record(const orc_gaussians* g, const orc_sensor* s, const orc_par
     std::vector<int> rays;
     tile_rays(s, t, rays);
     for (int r : rays) {
+      if (!active[r]) continue;   /* no upstream on this ray: it adds nothing to the gradient */
       double o[3], d[3];
       ray_geometry(s, r, R, o, d);
       composite_ray(pg, g->n, prm, s->near_, o, d, pair_gauss + ranges[t], ranges[NT + t] - ranges[t], &fz.seq[r]);
     }
   }
   return fz;
+}
+
+/* Rays with a non-zero upstream gradient.  The functional is a sum over rays of upstream
+ * times outputs, so a ray whose upstream is all zero contributes exactly zero: the adjoint
+ * and the finite differences skip its forward sequence. */
+std::vector<char> upstream_active(long R, const double* g_feat, const double* g_depth, const double* g_omega,
+                                  const double* g_drop) {
+  std::vector<char> a(R);
+  for (long r = 0; r < R; ++r)
+    a[r] = g_feat[r] != 0 || g_feat[R + r] != 0 || g_feat[2 * R + r] != 0 || g_depth[r] != 0 ||
+           g_omega[r] != 0 || (g_drop && g_drop[r] != 0);
+  return a;
 }
 
 /* value of the linear-in-outputs functional (plus the LiDAR drop term) on one ray, with
@@ -1241,8 +1255,9 @@ int orc_backward(const orc_gaussians* g, const orc_sensor* s, const orc_params* 
                  double* d_logit, double* d_feat) {
   const int n = g->n;
   const PerGaussian pg = per_gaussian(g, s);
-  const Frozen fz = forward_record(g, s, prm, pg, pair_gauss, ranges);
-  const long R = (long)fz.seq.size();
+  const long R = (s->kind == 2) ? (long)s->n_beams * s->n_az : (long)s->width * s->height;
+  const Frozen fz = forward_record(g, s, prm, pg, pair_gauss, ranges,
+                                   upstream_active(R, g_feat, g_depth, g_omega, g_drop));
   std::vector<GradAcc> acc(n);
   std::memset(acc.data(), 0, sizeof(GradAcc) * n);
   for (long r = 0; r < R; ++r) {   /* serial: accumulation order fixed */
@@ -1267,8 +1282,9 @@ int orc_fd_grad(const orc_gaussians* g, const orc_sensor* s, const orc_params* p
   const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
   const int NPAR = 11 + 3 * K;
   const PerGaussian pg0 = per_gaussian(g, s);
-  const Frozen fz = forward_record(g, s, prm, pg0, pair_gauss, ranges);
-  const long R = (long)fz.seq.size();
+  const long R = (s->kind == 2) ? (long)s->n_beams * s->n_az : (long)s->width * s->height;
+  const Frozen fz = forward_record(g, s, prm, pg0, pair_gauss, ranges,
+                                   upstream_active(R, g_feat, g_depth, g_omega, g_drop));
   std::vector<std::vector<int>> rays_of(n);
   for (long r = 0; r < R; ++r)
     for (const Contrib& c : fz.seq[r])
