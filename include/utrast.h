@@ -23,7 +23,8 @@
  * --------------------------------
  * - Pointers marked "device" are HIP device pointers (hipMalloc or torch CUDA tensors);
  *   "host" pointers are ordinary CPU memory.  The caller owns every buffer; the library
- *   never allocates or frees device memory and keeps no mutable global state, so calls on
+ *   never allocates or frees device memory and keeps no mutable global state (the one
+ *   exception is the fixed per-GPU queue of ut_composite_batch_noalloc), so calls on
  *   different streams with disjoint buffers are independent.
  * - All work is enqueued on the given stream (ut_stream = hipStream_t, NULL = the null
  *   stream).  Only ut_bin_and_sort with a non-NULL n_pairs pointer synchronises that stream.
@@ -370,6 +371,19 @@ size_t ut_batch_workspace_bytes(int32_t n_items);
 ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items,
                              const ut_render_params* prm, void* queue_ws, size_t ws_bytes,
                              int32_t n_workgroups, ut_stream stream);
+
+/* ut_composite_batch without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * The queue lives in a library-owned device array of fixed size, one per GPU, held until the
+ * process ends; the call allocates nothing.  Same items, arithmetic and outputs as
+ * ut_composite_batch (bit-identical).  n_items > UT_BATCH_NOALLOC_MAX_ITEMS returns
+ * UT_ERR_CAPACITY before anything is enqueued.  Every call on one GPU uses that GPU's single
+ * queue, which keeps the last call's contents (the counters are cleared at the start of each
+ * call): calls that overlap on one GPU (different streams, or a graph replayed while another
+ * call runs) race and must be serialised by the caller. */
+#define UT_BATCH_NOALLOC_MAX_ITEMS 64
+ut_status ut_composite_batch_noalloc(const ut_batch_item* items, int32_t n_items,
+                                     const ut_render_params* prm, int32_t n_workgroups, ut_stream stream);
 
 /* Spatial order of a resident particle set.  Results never depend on the particles' order
  * (every list is ordered by depth key, ties by index), but memory traffic does: stored along a

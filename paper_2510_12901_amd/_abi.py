@@ -15,6 +15,7 @@ PINHOLE, FISHEYE, LIDAR, ORTHO = 0, 1, 2, 3
 FEAT_CAMERA, FEAT_LIDAR = 0, 1
 RECORD_BYTES = 128   # UT_RECORD_BYTES; lib() refuses a library built with another size
 ACC_FLOATS = 13
+BATCH_NOALLOC_MAX_ITEMS = 64   # UT_BATCH_NOALLOC_MAX_ITEMS
 
 
 class UtGaussians(C.Structure):
@@ -94,6 +95,7 @@ SIGNATURES = [
     ("ut_composite_backward", i32, [P, P, P, P, P, P, P, P, C.c_size_t, P, P]),
     ("ut_batch_workspace_bytes", C.c_size_t, [i32]),
     ("ut_composite_batch", i32, [P, i32, P, P, C.c_size_t, i32, P]),
+    ("ut_composite_batch_noalloc", i32, [P, i32, P, i32, P]),
     ("ut_actor_transform", i32, [P, P, P, i32, P, P, P]),
     ("ut_spatial_order_workspace_bytes", C.c_size_t, [i32]),
     ("ut_spatial_order", i32, [P, P, P, C.c_size_t, P]),

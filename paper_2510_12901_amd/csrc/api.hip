@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "ut_internal.hpp"
@@ -412,22 +413,14 @@ __global__ void k_write_item(BatchItemK item, BatchItemK* dst) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = item;
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t ut_batch_workspace_bytes(int32_t n_items) {
-  return 256 + sizeof(BatchItemK) * (size_t)(n_items > 0 ? n_items : 1);
-}
-
-ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items, const ut_render_params* prm,
-                             void* queue_ws, size_t ws_bytes, int32_t n_workgroups, ut_stream stream) {
-  if (!items || n_items <= 0 || !params_ok(prm) || !queue_ws || n_workgroups <= 0) return UT_ERR_ARG;
-  if (ws_bytes < ut_batch_workspace_bytes(n_items)) return UT_ERR_CAPACITY;
+// The batch queue (two work counters, then the device copies of the items) at the start of
+// a workspace of ut_batch_workspace_bytes(n_items) bytes.  The items are written by small
+// kernels and the counters cleared by a fill kernel, so the whole call stays graph-capturable.
+ut_status enqueue_batch(const ut_batch_item* items, int32_t n_items, const ut_render_params* prm, void* queue_ws,
+                        int32_t n_workgroups, hipStream_t st) {
   uint32_t* counter = static_cast<uint32_t*>(queue_ws);
   BatchItemK* dev = reinterpret_cast<BatchItemK*>(static_cast<char*>(queue_ws) + 256);
   int total = 0;
-  hipStream_t st = as_stream(stream);
   for (int i = 0; i < n_items; ++i) {
     const ut_batch_item& it = items[i];
     if (!it.proj || !it.proj->records || !it.proj->trect || !bins_ok(it.bins) || !sensor_ok(it.sensor) || !it.out ||
@@ -463,6 +456,57 @@ ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items, const 
   if (e != hipSuccess) return UT_ERR_DEVICE;
   return from_hip(launch_composite_batch(dev, n_static, static_tiles, n_items - n_static, total, counter,
                                          make_params(prm), n_workgroups, st));
+}
+
+// Library-owned queue memory of ut_composite_batch_noalloc: one copy per device, for up to
+// UT_BATCH_NOALLOC_MAX_ITEMS items, alive until the process ends.  In host code the array's
+// name stands for a host-side shadow, not a device address: its device address is looked up
+// once per device (hipGetSymbolAddress with that device current) and only that address is
+// handed to kernels.
+constexpr size_t kBatchScratchBytes = 256 + sizeof(BatchItemK) * (size_t)UT_BATCH_NOALLOC_MAX_ITEMS;
+static __device__ __align__(256) unsigned char scratch[kBatchScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+ut_status batch_scratch_ptr(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return UT_ERR_DEVICE;
+  if (dev >= kMaxDevices) return UT_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return UT_ERR_DEVICE;
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return UT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ut_batch_workspace_bytes(int32_t n_items) {
+  return 256 + sizeof(BatchItemK) * (size_t)(n_items > 0 ? n_items : 1);
+}
+
+ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items, const ut_render_params* prm,
+                             void* queue_ws, size_t ws_bytes, int32_t n_workgroups, ut_stream stream) {
+  if (!items || n_items <= 0 || !params_ok(prm) || !queue_ws || n_workgroups <= 0) return UT_ERR_ARG;
+  if (ws_bytes < ut_batch_workspace_bytes(n_items)) return UT_ERR_CAPACITY;
+  return enqueue_batch(items, n_items, prm, queue_ws, n_workgroups, as_stream(stream));
+}
+
+ut_status ut_composite_batch_noalloc(const ut_batch_item* items, int32_t n_items, const ut_render_params* prm,
+                                     int32_t n_workgroups, ut_stream stream) {
+  if (!items || n_items <= 0 || !params_ok(prm) || n_workgroups <= 0) return UT_ERR_ARG;
+  if (n_items > UT_BATCH_NOALLOC_MAX_ITEMS) return UT_ERR_CAPACITY;
+  void* ws = nullptr;
+  const ut_status st = batch_scratch_ptr(&ws);
+  if (st != UT_OK) return st;
+  return enqueue_batch(items, n_items, prm, ws, n_workgroups, as_stream(stream));
 }
 
 ut_status ut_actor_transform(const ut_gaussians* g, const int32_t* actor, const ut_actor_pose* poses,

@@ -373,6 +373,21 @@ def composite_batch(items, params=None, n_workgroups=None, ws: torch.Tensor | No
     return ws
 
 
+def composite_batch_noalloc(items, params=None, n_workgroups=None, stream=None):
+    """composite_batch on the library's fixed per-GPU queue (ut_composite_batch_noalloc): no
+    workspace, no device allocation.  Calls that overlap on one GPU race on that queue."""
+    n = len(items)
+    prm = params or render_params()
+    arr = (A.UtBatchItem * n)()
+    keep = []
+    for i, (p, bins, sensor, out) in enumerate(items):
+        pc, lc, oc = p.c(), bins.c(), out.c()
+        keep += [pc, lc, oc]
+        arr[i] = A.UtBatchItem(ref(pc), ref(lc), ref(sensor.c), ref(oc))
+    check(lib().ut_composite_batch_noalloc(C.cast(arr, C.c_void_p), n, ref(prm), n_workgroups or 256 * 4,
+                                           _stream(stream)), "ut_composite_batch_noalloc")
+
+
 class SensorPipeline:
     """Preallocated per-sensor render path: projection, two-phase binning and compositing
     with buffers reused across calls (no device allocation once the list capacity fits)."""
