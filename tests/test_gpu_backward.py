@@ -169,3 +169,26 @@ def test_backward_matches_oracle_thin_discs(moving):
     _, ol, _ = oracle.render(g, s)
     ref = oracle.backward(g, s, ol, up)
     _check(gpu, ref, label="thin discs, moving" if moving else "thin discs")
+
+
+def test_backward_matches_oracle_across_many_super_tiles():
+    """All parameter groups on a 480x270 pinhole (30 x 17 tiles = 4 x 3 super-tiles of 8 x 8
+    tiles) with 200,000 particles of the 1M-particle workload's distribution (same field of
+    view, fx = fy = 300): ~1,400 list entries per tile, three quarters of the rays stop on
+    transmittance and the rest walk their whole list, so the adjoint's backward walk over long
+    super-tile bins and its float64 atomics under contention are both exercised.  Upstream:
+    gradient of mean |C - target|; rays whose forward decisions sit within 1e-9 of a threshold
+    in the oracle (its margin) get a zero upstream on both sides."""
+    W, H = 480, 270
+    g, s = synth.scene_pinhole_large(0, n=200_000, width=W, height=H, f=300.0)
+    op, ol, oo = oracle.render(g, s)
+    R = W * H
+    target = synth.l1_target(7, (3, R)).astype(np.float64)
+    up_feat = np.sign(oo["feat"] - target) / (3 * R)
+    up_feat[:, oo["margin"] < 1e-9] = 0.0
+    up = _as32(dict(feat=up_feat))
+    gpu, out = _gpu_backward(g, s, up)
+    assert int((to_np(out.t_final) < 1e-4).sum()) > R // 2          # early termination is common
+    assert ol["n_pairs"] > 500 * 30 * 17                             # long lists
+    ref = oracle.backward(g, s, ol, up)
+    _check(gpu, ref, label="480x270, 12 super-tiles")
