@@ -40,6 +40,14 @@ PEAK_HBM_GBS = 8000.0
 FLOPS_PER_VISIT = 22
 SETUP_FRAMES = 8
 FLOPS_PER_PASS = 43
+# The compositing roof in VALU lane-operations: every (ray, particle) pair a ray evaluates is
+# priced at the method's 65 lane-ops (compensated cross product 21, N c 9, |.|^2 3, M d 9,
+# |M d|^2 3, t* 3, reciprocal 2, exp 2, alpha 3, weight / transmittance / accumulators 8,
+# tests 2), against 256 CUs x 64 float64 (= non-packed float32) lanes per clock x 2.4 GHz.
+# The adjoint prices a replayed pair at 2.5 times the forward's work.
+LANE_OPS_PER_PAIR = 65
+ADJOINT_LANE_OPS_PER_PAIR = 162.5
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12     # 39.3 T lane-ops/s
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "composite_traffic.json")
 
 
@@ -69,8 +77,9 @@ def parse():
     ap.add_argument("--host-count", action="store_true",
                     help="read each sensor's pair total on the host before sorting (one mid-frame sync)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--served-seconds", type=float, default=3.0)
-    ap.add_argument("--vehicles", type=str, default="1,4,8")
+    ap.add_argument("--served-seconds", type=float, default=10.0, help="measured seconds of arrivals per trace")
+    ap.add_argument("--served-warmup", type=float, default=1.0, help="warm-up seconds of arrivals per trace")
+    ap.add_argument("--vehicles", type=str, default="1,2,4,6,8,12,16")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (reference kernel for HBM counters)")
     ap.add_argument("--lidar-sweep", action="store_true",
@@ -349,7 +358,9 @@ def main():
         del o
     per_launch_ms = float(np.mean(cam_ms))
     flops_per_launch = (visits * FLOPS_PER_VISIT + passes * FLOPS_PER_PASS) / len(cams)
-    achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
+    achieved_flops = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
+    lane_ops_per_launch = LANE_OPS_PER_PAIR * visits / len(cams)
+    achieved = lane_ops_per_launch / (per_launch_ms * 1e-3) / 1e12
     bin_pairs = [p.n_pairs for p in pipes]
     tile_pairs = [int(p.p.count[: p.g.n].to(torch.int64).sum().item()) for p in pipes]
 
@@ -378,13 +389,20 @@ def main():
                    "particles": args.particles, "rays_per_frame": rays_per_frame, "seed": args.seed,
                    "resident_order": "generation" if args.no_spatial_order else "z-order of the means",
                    "tile_pairs_per_sensor": tile_pairs, "bin_pairs_per_sensor": bin_pairs},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 2),
+                     "unit": "T VALU lane-ops/s", "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": traffic,
                      "kernel": CAMERA_KERNEL + " (camera compositing)",
-                     "flops_per_visit": FLOPS_PER_VISIT, "flops_per_pass": FLOPS_PER_PASS,
-                     "visits_per_launch": int(visits / len(cams)), "passes_per_launch": int(passes / len(cams)),
+                     "lane_ops_per_pair": LANE_OPS_PER_PAIR,
+                     "evaluated_pairs_per_launch": int(visits / len(cams)),
+                     "passes_per_launch": int(passes / len(cams)),
                      "list_positions_per_launch": int(positions / len(cams)),
-                     "avg_launch_ms": round(per_launch_ms, 4)},
+                     "avg_launch_ms": round(per_launch_ms, 4),
+                     "flop_model": {"flops_per_visit": FLOPS_PER_VISIT, "flops_per_pass": FLOPS_PER_PASS,
+                                    "achieved_tflops": round(achieved_flops, 3), "peak_fp64_tflops": PEAK_FP64_TFLOPS,
+                                    "frac": round(achieved_flops / PEAK_FP64_TFLOPS, 4)},
+                     "hbm_frac": (round(traffic / (per_launch_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+                                  if traffic else None)},
+        "rooflines": frame_rooflines(ut, pipes, stream, dev),
         "composite_ms_per_camera": [round(float(x), 4) for x in cam_ms],
     }
 
@@ -404,6 +422,50 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(g_np, gl_np, sensors_np, log)
     print(json.dumps(result), flush=True)
+
+
+def _launch_ms(stream, fn, reps=5):
+    """Average duration of fn() over reps back-to-back launches, HIP events on ``stream``."""
+    import torch
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def frame_rooflines(ut, pipes, stream, dev):
+    """The frame's other hot kernels against their roofs: LiDAR compositing (VALU lane-ops of
+    its evaluated pairs) and the projection of one pinhole camera and of the LiDAR (HBM: 76 B
+    per particle in and out of every particle, plus 12 K + 128 B per particle that reaches a
+    tile -- its K SH coefficients per channel read, its record written)."""
+    import torch
+    out = {}
+    lid = [p for p in pipes if p.sensor.is_lidar][0]
+    o = ut.alloc_out(lid.sensor, dev, state=True, counters=True)
+    lid.composite_only(stream, o)
+    ms = _launch_ms(stream, lambda: lid.composite_only(stream))
+    vis = int(o.n_visit.to(torch.int64).sum().item())
+    a = LANE_OPS_PER_PAIR * vis / (ms * 1e-3) / 1e12
+    out["lidar_composite"] = {"bound": "alu", "achieved": round(a, 3), "peak": round(PEAK_VALU_TOPS, 2),
+                              "unit": "T VALU lane-ops/s", "frac": round(a / PEAK_VALU_TOPS, 4),
+                              "evaluated_pairs_per_launch": vis, "avg_launch_ms": round(ms, 4),
+                              "max_tile_rays": lid.sensor.max_tile_rays}
+    del o
+    for name, p in (("project_pinhole", [q for q in pipes if q.sensor.kind == 0][0]), ("project_lidar", lid)):
+        ms = _launch_ms(stream, lambda: p.project(stream))
+        n = p.g.n
+        K = (p.g.sh_degree + 1) ** 2
+        V = int((p.p.count[:n] > 0).sum().item())
+        b = 76 * n + (12 * K + int(ut.lib().ut_record_bytes())) * V
+        gbps = b / (ms * 1e-3) / 1e9
+        out[name] = {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(gbps / PEAK_HBM_GBS, 4), "bytes_per_launch": b, "particles": n,
+                     "reaching_a_tile": V, "avg_launch_ms": round(ms, 4)}
+    return out
 
 
 def bench_backward(ut, synth, dev, args):
@@ -429,8 +491,23 @@ def bench_backward(ut, synth, dev, args):
         step()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / n
+    # the adjoint call alone (accumulator fill, k_backward, chain rule) against the VALU roof,
+    # pricing every pair the forward evaluated at the adjoint's lane-ops per pair
+    stream = torch.cuda.current_stream()
+    out = pipe.run()
+    up = torch.sign(out.feat - target) / out.feat.numel()
+    o = ut.alloc_out(s, dev, state=True, counters=True)
+    pipe.composite_only(stream, o)
+    vis = int(o.n_visit.to(torch.int64).sum().item())
+    del o
+    bms = _launch_ms(stream, lambda: ut.backward(g, pipe.p, pipe.bins, s, out, up_feat=up))
+    a = ADJOINT_LANE_OPS_PER_PAIR * vis / (bms * 1e-3) / 1e12
     return {"workload": "1,000,000 particles, pinhole 1920x1080, forward + adjoint of mean L1",
-            "ms_per_step": round(ms, 3), "mrays_per_s": round(s.n_rays / ms / 1e3, 2), "pairs": pipe.n_pairs}
+            "ms_per_step": round(ms, 3), "mrays_per_s": round(s.n_rays / ms / 1e3, 2), "pairs": pipe.n_pairs,
+            "roofline": {"bound": "alu", "kernel": "ut_composite_backward (fill, k_backward, k_chain)",
+                         "achieved": round(a, 3), "peak": round(PEAK_VALU_TOPS, 2), "unit": "T VALU lane-ops/s",
+                         "frac": round(a / PEAK_VALU_TOPS, 4), "lane_ops_per_pair": ADJOINT_LANE_OPS_PER_PAIR,
+                         "forward_evaluated_pairs": vis, "avg_call_ms": round(bms, 4)}}
 
 
 def _time_sensor(ut, g, d, dev, args, stream):
@@ -576,16 +653,18 @@ def bench_configs(ut, synth, dev, args):
                   in, the record out);
       depth sort: per visible particle 4 radix passes of 16 B (key and value in and out) plus
                   4 B for the digit histogram, and 16 B per particle for the compaction;
-      pair sort:  per super-tile pair 8 B emitted, 16 B per radix pass, 4 B for the ranges."""
+      pair sort:  per super-tile pair 8 B emitted, 16 B per radix pass, 4 B for the ranges.
+    The same workloads drawn with the next two seeds are timed as whole frames."""
     import torch
     stream = torch.cuda.current_stream()
     K = args.steps
-    cases = [("cfg0 pinhole 128x96, 1,000 particles", synth.scene_pinhole_small(args.seed)),
-             ("cfg1 fisheye 1920x1280, 500,000 particles", synth.scene_fisheye(args.seed)),
-             ("cfg2 LiDAR 128x2048, 300,000 particles", synth.scene_lidar(args.seed)),
-             ("cfg3 pinhole 1920x1080, 1,000,000 particles", synth.scene_pinhole_large(args.seed))]
+    cases_by_seed = {"cfg0 pinhole 128x96, 1,000 particles": synth.scene_pinhole_small,
+                     "cfg1 fisheye 1920x1280, 500,000 particles": synth.scene_fisheye,
+                     "cfg2 LiDAR 128x2048, 300,000 particles": synth.scene_lidar,
+                     "cfg3 pinhole 1920x1080, 1,000,000 particles": synth.scene_pinhole_large}
     rows = {}
-    for name, (g_np, s_np) in cases:
+    for name, gen in cases_by_seed.items():
+        g_np, s_np = gen(args.seed)
         g = ut.GaussianSet.from_numpy(g_np, dev)
         s = ut.Sensor(s_np, dev)
         pipe = ut.SensorPipeline(g, s)
@@ -635,8 +714,28 @@ def bench_configs(ut, synth, dev, args):
             "hbm_frac": {"project": round(gbps(b_proj, med["project"]) / PEAK_HBM_GBS, 3),
                          "depth_sort": round(gbps(b_depth, med["depth_sort"]) / PEAK_HBM_GBS, 3),
                          "pair_sort": round(gbps(b_pair, med["pair_sort"]) / PEAK_HBM_GBS, 3)}}
-        log(f"{name}: {json.dumps(rows[name])}")
         del pipe, s, g
+        # the same workload drawn with the next two seeds: frame time only
+        fr = [rows[name]["frame_ms"]]
+        for sd in (args.seed + 1, args.seed + 2):
+            g2_np, s2_np = cases_by_seed[name](sd)
+            g2 = ut.GaussianSet.from_numpy(g2_np, dev)
+            s2 = ut.Sensor(s2_np, dev)
+            pipe2 = ut.SensorPipeline(g2, s2)
+            for _ in range(SETUP_FRAMES + args.warmup):
+                pipe2.run(stream)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(K):
+                t0 = time.perf_counter()
+                pipe2.run(stream)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            fr.append(round(float(np.median(ts)) * 1e3, 4))
+            del pipe2, s2, g2
+        rows[name]["seeds"] = {"seed": [args.seed, args.seed + 1, args.seed + 2], "frame_ms": fr,
+                               "mrays_per_s": [round(rows[name]["rays"] / f / 1e3, 2) for f in fr]}
+        log(f"{name}: {json.dumps(rows[name])}")
     return rows
 
 
@@ -665,11 +764,19 @@ def bench_time_dependent(ut, synth, dev, args):
     return out
 
 
-def cpu_baseline(g_np, gl_np, sensors_np, log):
-    """The oracle (FP64, OpenMP over rays/tiles) on a bounded sample of the frame: the LiDAR
-    rendered in full and one pinhole camera with every 8th ray composited (its projection and
-    binning in full)."""
+def cpu_baseline(g_np, gl_np, sensors_np, log, seed=0):
+    """The oracle (FP64, OpenMP over rays/tiles) on bounded samples:
+    - value: the frame's LiDAR rendered in full and one pinhole camera with every 8th ray
+      composited (its projection and binning in full), all host threads;
+    - one_core: the frame's LiDAR with every 4th ray composited (projection and binning in
+      full) on one thread;
+    - configs: the single-sensor workloads on all threads -- the 1,000-particle pinhole, the
+      500,000-particle fisheye and the 300,000-particle LiDAR as full frames, the
+      1,000,000-particle pinhole with every 16th ray composited, and the adjoint on the
+      2,000-particle 64x64 copy of the latter (forward + backward)."""
     import oracle
+    import synth
+    threads = oracle.num_threads()
     t0 = time.perf_counter()
     lid = [s for s in sensors_np if s["kind"] == 2][0]
     cam = [s for s in sensors_np if s["kind"] == 0][0]
@@ -686,11 +793,54 @@ def cpu_baseline(g_np, gl_np, sensors_np, log):
     oracle.composite_rays(og_c, os_c, lists, ids)
     rays += len(ids)
     dt = time.perf_counter() - t0
-    log(f"cpu baseline {dt:.1f}s for {rays} rays")
-    return {"value": round(rays / dt / 1e6, 4), "unit": "Mrays/s", "cores": oracle.num_threads(),
+    del lists, pr
+    log(f"cpu baseline {dt:.1f}s for {rays} rays on {threads} threads")
+
+    def sampled(og, osn, step):
+        t = time.perf_counter()
+        p = oracle.project(og, osn)
+        ls = oracle.bin_pairs(osn, p["rect"], p["count"], p["key"])
+        sel = np.arange(0, osn.n_rays, step)
+        oracle.composite_rays(og, osn, ls, sel)
+        return len(sel), time.perf_counter() - t
+
+    oracle.set_num_threads(1)
+    try:
+        r1, t1 = sampled(og_l, os_l, 4)
+    finally:
+        oracle.set_num_threads(threads)
+    log(f"cpu baseline one core {t1:.1f}s for {r1} rays")
+
+    cfg = {}
+    for name, (gq, sq), step in (("cfg0 pinhole 128x96, 1,000 particles", synth.scene_pinhole_small(seed), 1),
+                                 ("cfg2 LiDAR 128x2048, 300,000 particles", synth.scene_lidar(seed), 1),
+                                 ("cfg1 fisheye 1920x1280, 500,000 particles", synth.scene_fisheye(seed), 1),
+                                 ("cfg3 pinhole 1920x1080, 1,000,000 particles", synth.scene_pinhole_large(seed), 16)):
+        og, osn = oracle.OracleGaussians(gq), oracle.OracleSensor(sq)
+        if step == 1:
+            t = time.perf_counter()
+            oracle.render(og, osn)
+            r, tt = osn.n_rays, time.perf_counter() - t
+        else:
+            r, tt = sampled(og, osn, step)
+        cfg[name] = {"mrays_per_s": round(r / tt / 1e6, 4), "rays": r, "seconds": round(tt, 3),
+                     "sample": "full frame" if step == 1 else f"every {step}th ray (projection and binning in full)"}
+    gq, sq = synth.scene_pinhole_large(seed, n=2000, width=64, height=64, f=40.0)
+    t = time.perf_counter()
+    op, ol, oo = oracle.render(gq, sq)
+    target = synth.l1_target(7, (3, 64 * 64)).astype(np.float64)
+    oracle.backward(gq, sq, ol, {"feat": np.sign(oo["feat"] - target) / (3 * 64 * 64)})
+    tt = time.perf_counter() - t
+    cfg["cfg3 adjoint copy: 2,000 particles, 64x64, forward + backward"] = {
+        "mrays_per_s": round(64 * 64 / tt / 1e6, 4), "rays": 64 * 64, "seconds": round(tt, 3), "sample": "full frame"}
+    log(f"cpu baseline configs: {json.dumps(cfg)}")
+    return {"value": round(rays / dt / 1e6, 4), "unit": "Mrays/s", "cores": threads,
             "kind": "oracle",
             "sample": "2,000,000-particle frame: LiDAR 128x2048 in full + pinhole 1920x1080 every 8th ray "
-                      "(projection and binning in full)", "seconds": round(dt, 2), "rays": rays}
+                      "(projection and binning in full)", "seconds": round(dt, 2), "rays": rays,
+            "one_core": {"value": round(r1 / t1 / 1e6, 4), "unit": "Mrays/s", "cores": 1, "seconds": round(t1, 2),
+                         "sample": "the frame's LiDAR, every 4th ray composited (projection and binning in full)"},
+            "configs": cfg}
 
 
 if __name__ == "__main__":

@@ -110,6 +110,10 @@ typedef struct {
   int32_t cull_az, cull_el; /* culling grid: azimuth cells over 360 deg, elevation cells */
   int32_t n_theta;        /* azimuth tiles, set by ut_sensor_build */
   int32_t max_tile_rays;  /* largest ray count of one tile, set by ut_sensor_build */
+  int32_t n_units;        /* LiDAR compositing units (runs of adjacent azimuth tiles of one
+                             elevation tile packed into one workgroup), set by ut_sensor_build */
+  int32_t unit_rays;      /* rays per unit at most (64, 128 or 256; 0 = no units), set by
+                             ut_sensor_build */
   const float* beam_elev_host; /* host [n_beams] radians, sorted ascending (LiDAR set-up only) */
   const float* ray_dir;   /* device [3][R] */
   void* tables;           /* device, LiDAR tiling + summed-area table */
@@ -240,8 +244,15 @@ ut_status ut_sensor_table_bytes(const ut_sensor* s, size_t* bytes);
 
 /* Sensor set-up, once per sensor definition (Sec. 3.3: the tiling is reused across calls).
  * LiDAR: runs Alg. 1, builds the ray mask over the culling grid and its summed-area
- * table (Appendix B) and copies them to s->tables (device, ut_sensor_table_bytes bytes);
- * sets s->n_theta and s->max_tile_rays.  Cameras: sets max_tile_rays = 256.
+ * table (Appendix B) and the compositing units, and copies them to s->tables (device,
+ * ut_sensor_table_bytes bytes); sets s->n_theta, s->max_tile_rays, s->n_units and
+ * s->unit_rays.  A unit is a run of adjacent azimuth tiles of one elevation tile within one
+ * super-tile column whose rays fit one workgroup of unit_rays lanes (the smallest of 64, 128,
+ * 256 that holds the largest tile); the tiles stay the binning units and every ray still walks
+ * its own tile's list, so units change which rays share a wavefront, not any result.
+ * Cameras: sets max_tile_rays = 256 (no units).  Camera ray tables are not built here: the
+ * rays are an input of the problem (r(t) = o + t d), so the caller supplies ray_dir (and
+ * ray_org for moving sensors), e.g. its own unprojection of the pixel centres.
  * Synchronises the stream (the host tables are freed on return). */
 ut_status ut_sensor_build(ut_sensor* s, ut_stream stream);
 
@@ -271,7 +282,11 @@ size_t ut_workspace_bytes(uint64_t max_pairs, int32_t n_tiles, int32_t n_gaussia
 /* Number of super-tiles of a (built) sensor. */
 int32_t ut_sensor_super_tiles(const ut_sensor* s);
 
-/* Binning and depth sort (Sec. 3.2, tiling as in 3DGS, binned per super-tile).
+/* Binning and depth sort (Sec. 3.2, tiling as in 3DGS, binned per super-tile).  The output
+ * is one list per super-tile of 8 x 8 tiles, not per tile: the compositing kernels filter a
+ * super-tile list by each particle's rect on chip, which yields each tile's exact
+ * (depth, index)-ordered list without writing it to memory; ut_tile_lists_count / _fill
+ * materialise the per-tile lists when a caller needs them.
  * Step 1 (ut_bin_count, asynchronous): stable radix sort of the particles by depth key,
  * exclusive scan of their super-tile counts in that order; the pair total P stays in the
  * count workspace ws and, if n_pairs_host is non-NULL, is copied there asynchronously
@@ -331,7 +346,9 @@ ut_status ut_composite_lidar(const ut_projected* p, const ut_bin_lists* bins,
                              const ut_sensor* s, const ut_render_params* prm,
                              ut_render_out* out, ut_stream stream);
 
-/* Bytes of the per-particle accumulator workspace of the adjoint. */
+/* Bytes of the per-particle accumulator workspace of the adjoint (the call takes it as an
+ * argument, acc_ws, because the per-pair partials are summed in float64 per particle before
+ * the chain rule, and the library allocates nothing). */
 size_t ut_backward_workspace_bytes(int32_t n_gaussians);
 
 /* Adjoint of ut_composite_* with the discrete structure of the forward held fixed (lists,

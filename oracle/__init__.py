@@ -14,7 +14,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# UTORACLE_LIB: load a separately built copy instead (the sanitizer test's instrumented build)
+LIB_PATH = os.environ.get("UTORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "utoracle.cpp")
 CXXFLAGS = ["-O2", "-std=c++17", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
             "-fPIC", "-shared"]
@@ -27,6 +28,8 @@ RS_ITERS = 3          # fixed-point iterations of the time-dependent projection 
 
 
 def build(force: bool = False) -> str:
+    if os.environ.get("UTORACLE_LIB"):
+        return LIB_PATH
     if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["g++", *CXXFLAGS, SRC_PATH, "-o", tmp])
@@ -88,6 +91,7 @@ def lib():
         L.orc_pose_at.argtypes = [P, C.c_double, P, P]
         L.orc_project_points.argtypes = [P, P, C.c_int, P, P]
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -360,3 +364,8 @@ def pose_at(s, t: float):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """OpenMP threads of the following oracle calls."""
+    lib().orc_set_num_threads(int(t))

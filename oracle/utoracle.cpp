@@ -1340,6 +1340,9 @@ int orc_fd_grad(const orc_gaussians* g, const orc_sensor* s, const orc_params* p
   return 0;
 }
 
+/* Sets the OpenMP threads of the following calls (timing of the CPU baseline on one core). */
+void orc_set_num_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
+
 /* OpenMP threads the oracle runs with. */
 int orc_num_threads(void) {
   int t = 1;

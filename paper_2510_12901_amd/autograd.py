@@ -4,7 +4,7 @@ from __future__ import annotations
 
 import torch
 
-from .render import (GaussianSet, Sensor, UT_ABK, actor_poses, actor_transform, actor_transform_backward, backward,
+from .render import (GaussianSet, RenderOut, Sensor, UT_ABK, actor_poses, actor_transform, actor_transform_backward, backward,
                      render, render_params)
 
 
@@ -16,13 +16,20 @@ class UTRender(torch.autograd.Function):
                         opacity_logit.detach().contiguous(), feat.detach().contiguous(), sh_degree, feat_kind)
         prm = params or render_params()
         p, bins, out = render(g, sensor, abk, prm, state=True)
-        ctx.state = (g, p, bins, out, sensor, prm)
         drop = out.drop if out.drop is not None else torch.zeros(0, device=mean.device)
+        # the returned tensors go through save_for_backward (no output -> ctx -> output cycle,
+        # and autograd refuses a backward after an in-place edit of them: the adjoint reads
+        # feat for the ray-drop derivative); only the adjoint state that is not returned stays
+        # on ctx
+        ctx.save_for_backward(out.feat, out.depth, out.alpha, drop)
+        ctx.state = (g, p, bins, out.t_final, out.n_proc, out.tile_end, sensor, prm)
         return out.feat, out.depth, out.alpha, drop
 
     @staticmethod
     def backward(ctx, g_feat, g_depth, g_alpha, g_drop):
-        g, p, lists, out, sensor, prm = ctx.state
+        g, p, lists, t_final, n_proc, tile_end, sensor, prm = ctx.state
+        feat, depth, alpha, drop = ctx.saved_tensors
+        out = RenderOut(feat, depth, alpha, drop if drop.numel() else None, t_final, n_proc, tile_end=tile_end)
         if g_drop is not None and g_drop.numel() == 0:
             g_drop = None
         gr = backward(g, p, lists, sensor, out, g_feat, g_depth, g_alpha, g_drop, params=prm)

@@ -6,6 +6,7 @@
 #include <mutex>
 #include <vector>
 
+#include "host_tables.hpp"
 #include "ut_internal.hpp"
 
 using namespace ut;
@@ -19,25 +20,12 @@ ut_status from_hip(hipError_t e) { return e == hipSuccess ? UT_OK : UT_ERR_DEVIC
 int camera_tiles_x(const ut_sensor* s) { return (s->width + UT_CAMERA_TILE - 1) / UT_CAMERA_TILE; }
 int camera_tiles_y(const ut_sensor* s) { return (s->height + UT_CAMERA_TILE - 1) / UT_CAMERA_TILE; }
 
-bool sensor_ok(const ut_sensor* s) {
-  if (!s || !s->ray_dir) return false;
-  if (s->moving && (!s->ray_org || s->rs_iters < 1 || s->rs_iters > 64 || s->kind == UT_ORTHO)) return false;
-  if (!(s->beam_divergence >= 0 && s->beam_divergence < kPi)) return false;
-  if (s->beam_divergence > 0 && s->kind != UT_LIDAR) return false;
-  if (s->kind == UT_LIDAR)
-    return s->n_beams > 0 && s->n_az > 0 && s->n_phi > 0 && s->n_phi <= UT_MAX_ELEV_TILES &&
-           s->n_theta > 0 && s->tables && s->max_tile_rays > 0 && s->max_tile_rays <= UT_MAX_LIDAR_TILE_RAYS &&
-           (!s->cull || (s->cull_az > 0 && s->cull_el > 0));
-  if (s->kind == UT_PINHOLE || s->kind == UT_FISHEYE || s->kind == UT_ORTHO)
-    return s->width > 0 && s->height > 0;
-  return false;
-}
-
-bool gaussians_ok(const ut_gaussians* g) {
-  return g && g->n >= 0 && g->sh_degree >= 0 && g->sh_degree <= 3 &&
-         (g->feat_kind == UT_FEAT_CAMERA || g->feat_kind == UT_FEAT_LIDAR) &&
-         (g->n == 0 || (g->mean && g->quat && g->log_scale && g->opacity_logit && g->feat));
-}
+using ut_host::gaussians_ok;
+using ut_host::params_ok;
+using ut_host::sensor_ok;
+using ut_host::table_layout;
+using ut_host::TableLayout;
+static_assert(ut_host::kUnitTiles == kUnitTilesMax, "unit width of the host tables and the kernels");
 
 // Unit quaternion (w, x, y, z) of a (float32, near-orthonormal) rotation matrix, from the
 // largest of the four diagonal combinations for conditioning.
@@ -72,11 +60,15 @@ SensorK make_sensor_k(const ut_sensor* s) {
     k.n_beams = s->n_beams; k.n_az = s->n_az; k.n_phi = s->n_phi; k.n_theta = s->n_theta;
     k.cull = s->cull; k.cull_az = s->cull_az; k.cull_el = s->cull_el;
     k.tiles_x = s->n_theta; k.tiles_y = s->n_phi;
-    const TableLayout t = table_layout(s->n_phi, s->cull ? s->cull_az : 0, s->cull ? s->cull_el : 0);
+    const TableLayout t = table_layout(s->n_phi, s->cull ? s->cull_az : 0, s->cull ? s->cull_el : 0,
+                                       s->n_phi * s->n_theta);
     char* base = static_cast<char*>(s->tables);
     k.bounds = reinterpret_cast<const double*>(base + t.bounds);
     k.beam_start = reinterpret_cast<const int*>(base + t.beam_start);
     k.sat = reinterpret_cast<const int*>(base + t.sat);
+    k.units = reinterpret_cast<const int4*>(base + t.units);
+    k.n_units = s->n_units;
+    k.unit_rays = s->unit_rays;
     k.n_rays = (long long)s->n_beams * s->n_az;
     k.div_tan = s->beam_divergence > 0 ? std::tan(0.5 * s->beam_divergence) : 0.0;
   } else {
@@ -117,9 +109,6 @@ RenderParamsK make_params(const ut_render_params* p) {
   return k;
 }
 
-bool params_ok(const ut_render_params* p) {
-  return p && p->alpha_min > 0 && p->alpha_max >= p->alpha_min && p->alpha_max < 1 && p->t_min >= 0;
-}
 
 bool projected_ok(const ut_projected* p, int n) {
   return p && (n == 0 || (p->records && p->rect && p->trect && p->key && p->count)) && p->n_culled;
@@ -142,56 +131,26 @@ const char* ut_status_str(ut_status s) {
 
 int32_t ut_record_bytes(void) { return UT_RECORD_BYTES; }
 
-// Alg. 1.  Histogram of per-ray elevations (each beam counts n_az rays) over r = 400 bins
-// spanning [min, max] elevation; a boundary sits at the upper edge of every bin where the
-// cumulative count reaches b/N_phi of the total (tested while it holds, so one bin can
-// place several boundaries); N_theta = ceil(max rays of an elevation tile / M).
+// Alg. 1 (host_tables.hpp).
 ut_status ut_lidar_tiling(const float* beam_elev, int32_t n_beams, int32_t n_az, int32_t n_phi,
                           int32_t M, double* bounds, int32_t* beam_start, int32_t* n_theta) {
-  if (!beam_elev || !bounds || !beam_start || !n_theta || n_beams <= 0 || n_az <= 0 || n_phi <= 0 ||
-      n_phi > UT_MAX_ELEV_TILES || M <= 0)
-    return UT_ERR_ARG;
-  for (int b = 1; b < n_beams; ++b)
-    if (!(beam_elev[b] >= beam_elev[b - 1])) return UT_ERR_ARG;
-  const int r_bins = 400;
-  const double lo = beam_elev[0], hi = beam_elev[n_beams - 1];
-  if (!(hi > lo)) return UT_ERR_ARG;
-  const double w = (hi - lo) / r_bins;
-  std::vector<long long> cum(r_bins, 0);
-  for (int b = 0; b < n_beams; ++b) {
-    int bin = (int)std::floor(((double)beam_elev[b] - lo) / w);
-    bin = std::min(std::max(bin, 0), r_bins - 1);
-    cum[bin] += n_az;
-  }
-  for (int i = 1; i < r_bins; ++i) cum[i] += cum[i - 1];
-  const long long total = cum[r_bins - 1];
-  int placed = 0;
-  bounds[0] = lo;
-  for (int i = 0; i < r_bins && placed < n_phi; ++i)
-    while (placed < n_phi && cum[i] * (long long)n_phi >= (long long)(placed + 1) * total) {
-      ++placed;
-      bounds[placed] = lo + (i + 1) * w;
-    }
-  long long most = 0;
-  int b = 0;
-  for (int k = 0; k < n_phi; ++k) {
-    beam_start[k] = b;
-    if (k == n_phi - 1) b = n_beams;
-    else
-      while (b < n_beams && (double)beam_elev[b] < bounds[k + 1]) ++b;
-    most = std::max(most, (long long)(b - beam_start[k]) * n_az);
-  }
-  beam_start[n_phi] = n_beams;
-  *n_theta = (int32_t)((most + M - 1) / M);
-  return UT_OK;
+  return ut_host::lidar_tiling(beam_elev, n_beams, n_az, n_phi, M, bounds, beam_start, n_theta);
 }
 
 ut_status ut_sensor_table_bytes(const ut_sensor* s, size_t* bytes) {
   if (!s || !bytes) return UT_ERR_ARG;
   if (s->kind != UT_LIDAR) { *bytes = 0; return UT_OK; }
-  if (s->n_phi <= 0 || s->n_phi > UT_MAX_ELEV_TILES || (s->cull && (s->cull_az <= 0 || s->cull_el <= 0)))
+  if (s->n_phi <= 0 || s->n_phi > UT_MAX_ELEV_TILES || (s->cull && (s->cull_az <= 0 || s->cull_el <= 0)) ||
+      !s->beam_elev_host)
     return UT_ERR_ARG;
-  *bytes = table_layout(s->n_phi, s->cull ? s->cull_az : 0, s->cull ? s->cull_el : 0).total;
+  // the unit table is sized by the tile count, which Alg. 1 fixes
+  std::vector<double> bounds(s->n_phi + 1);
+  std::vector<int32_t> bstart(s->n_phi + 1);
+  int32_t nth = 0;
+  const ut_status st = ut_lidar_tiling(s->beam_elev_host, s->n_beams, s->n_az, s->n_phi, s->max_per_tile,
+                                       bounds.data(), bstart.data(), &nth);
+  if (st != UT_OK) return st;
+  *bytes = table_layout(s->n_phi, s->cull ? s->cull_az : 0, s->cull ? s->cull_el : 0, s->n_phi * nth).total;
   return UT_OK;
 }
 
@@ -213,46 +172,26 @@ ut_status ut_sensor_build(ut_sensor* s, ut_stream stream) {
   int32_t nth = 0;
   st = ut_lidar_tiling(s->beam_elev_host, s->n_beams, s->n_az, NP, s->max_per_tile, bounds.data(), bstart.data(), &nth);
   if (st != UT_OK) return st;
-  // largest number of rays in one tile
-  int max_beams = 0;
-  for (int k = 0; k < NP; ++k) max_beams = std::max(max_beams, bstart[k + 1] - bstart[k]);
-  int max_az = 0;
-  for (int j = 0; j < nth; ++j) {
-    const long long a0 = ((long long)j * s->n_az + nth - 1) / nth, a1 = ((long long)(j + 1) * s->n_az + nth - 1) / nth;
-    max_az = std::max(max_az, (int)(a1 - a0));
-  }
-  const int max_rays = max_beams * max_az;
+  const int max_rays = ut_host::max_tile_rays(bstart.data(), NP, s->n_az, nth);
   if (max_rays > UT_MAX_LIDAR_TILE_RAYS) return UT_ERR_UNSUPPORTED;
-  const TableLayout t = table_layout(NP, s->cull ? s->cull_az : 0, s->cull ? s->cull_el : 0);
+  const TableLayout t = table_layout(NP, s->cull ? s->cull_az : 0, s->cull ? s->cull_el : 0, NP * nth);
   std::vector<char> host(t.total, 0);
   std::memcpy(host.data() + t.bounds, bounds.data(), sizeof(double) * (NP + 1));
   std::memcpy(host.data() + t.beam_start, bstart.data(), sizeof(int32_t) * (NP + 1));
-  if (s->cull) {
-    // ray mask over (cull_az azimuth cells over 360 deg) x (cull_el elevation cells over
-    // [T_0, T_N]); summed-area table sat[i][j] = occupied cells with az < i and el < j
-    const int CA = s->cull_az, CE = s->cull_el;
-    std::vector<uint8_t> mask((size_t)CA * CE, 0);
-    const double e0 = bounds[0], span = bounds[NP] - bounds[0];
-    for (int b = 0; b < s->n_beams; ++b) {
-      int ce = (int)std::floor(((double)s->beam_elev_host[b] - e0) * CE / span);
-      ce = std::min(std::max(ce, 0), CE - 1);
-      for (int a = 0; a < s->n_az; ++a) mask[(size_t)((long long)a * CA / s->n_az) * CE + ce] = 1;
-    }
-    int32_t* sat = reinterpret_cast<int32_t*>(host.data() + t.sat);
-    const size_t W = (size_t)CE + 1;
-    for (int i = 1; i <= CA; ++i) {
-      int32_t row = 0;
-      for (int j = 1; j <= CE; ++j) {
-        row += mask[(size_t)(i - 1) * CE + (j - 1)];
-        sat[i * W + j] = sat[(i - 1) * W + j] + row;
-      }
-    }
-  }
+  const int unit_rays = ut_host::unit_width(max_rays);
+  const int n_units = unit_rays > 0 ? ut_host::build_units(bstart.data(), NP, s->n_az, nth, unit_rays,
+                                                          reinterpret_cast<int32_t*>(host.data() + t.units))
+                                    : 0;
+  if (s->cull)
+    ut_host::ray_sat(s->beam_elev_host, s->n_beams, s->n_az, bounds.data(), NP, s->cull_az, s->cull_el,
+                     reinterpret_cast<int32_t*>(host.data() + t.sat));
   hipError_t e = hipMemcpyAsync(s->tables, host.data(), t.total, hipMemcpyHostToDevice, as_stream(stream));
   if (e == hipSuccess) e = hipStreamSynchronize(as_stream(stream));
   if (e != hipSuccess) return UT_ERR_DEVICE;
   s->n_theta = nth;
   s->max_tile_rays = max_rays;
+  s->n_units = n_units;
+  s->unit_rays = unit_rays;
   return UT_OK;
 }
 

@@ -7,7 +7,8 @@
 // sum S = sum_{j>i} w_j a_j.  Per pair it forms 13 partials (colour 3, opacity, mean 3,
 // the 6 unique entries of B = Sigma^{-1}); wavefronts whose lanes touched the particle
 // reduce all 13 across 64 lanes in one reduce-scatter (17 exchanges) and 13 lanes add them
-// atomically (float64) into SoA accumulators acc[13][n].
+// into the step's LDS sums (float64 LDS atomics), which reach the SoA accumulators acc[13][n]
+// with one float64 atomic per (entry, partial) when the step ends.
 // k_chain: one lane per particle, chain rule to (mean, quat, log_scale, logit, SH).
 #include "ut_cone.hpp"
 #include "ut_internal.hpp"
@@ -47,16 +48,19 @@ __device__ __forceinline__ double wave_reduce_scatter16(const double v[16], int 
 }
 
 template <int BLOCK, bool MOVING>
-__global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const RecordG* __restrict__ rec,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MOVING ? 3 : 4))) void k_backward(SensorK s, const RecordG* __restrict__ rec,
                                                      const uint2* __restrict__ trect,
                                                      const uint32_t* __restrict__ bgauss,
                                                      const uint32_t* __restrict__ branges, int n_super,
                                                      RenderParamsK prm, ut_render_out fwd, ut_upstream up,
-                                                     const float* __restrict__ mean, double* __restrict__ acc,
-                                                     int n) {
-  __shared__ Record sh[BLOCK];
-  __shared__ uint32_t sh_g[BLOCK];   // kept entries of one step: particle ...
-  __shared__ uint32_t sh_j[BLOCK];   // ... and its position in the tile's list
+                                                     double* __restrict__ acc, int n) {
+  // a step stages up to kStep list entries; their 13 partials are summed over the workgroup's
+  // wavefronts in LDS and leave with one float64 atomic per (entry, partial)
+  constexpr int kStep = BLOCK >= 256 ? 128 : BLOCK / 2;
+  __shared__ Record sh[kStep];
+  __shared__ uint32_t sh_g[kStep];   // kept entries of one step: particle ...
+  __shared__ uint32_t sh_j[kStep];   // ... and its position in the tile's list
+  __shared__ double sacc[UT_ACC_FLOATS][kStep];
   __shared__ uint2 s_wc[BLOCK / 64];
   __shared__ uint32_t s_max;
   __shared__ double red[4][BLOCK / 64];
@@ -138,11 +142,11 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const RecordG* __
   uint32_t cur = jmax > 0 ? min(max(fwd.tile_end[tile], bstart), bend) : bstart;
   uint32_t top = jmax;                                     // list positions below this remain
   while (cur > bstart && top > 0) {
-    const uint32_t lo = cur - bstart > (uint32_t)BLOCK ? cur - BLOCK : bstart;
+    const uint32_t lo = cur - bstart > (uint32_t)kStep ? cur - kStep : bstart;
     const uint32_t b = lo + threadIdx.x;
     uint32_t g = 0;
     bool hit = false;
-    if (b < cur) {
+    if ((int)threadIdx.x < kStep && b < cur) {
       g = bgauss[b];
       hit = rect_covers(trect[g], tx, ty, s);
     }
@@ -169,6 +173,7 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const RecordG* __
       const int j = c / kRecordChunks, part = c - j * kRecordChunks;
       stage_record_chunk(rec + sh_g[j], sh + j, part);
     }
+    for (int c = threadIdx.x; c < cnt * UT_ACC_FLOATS; c += BLOCK) sacc[c / cnt][c % cnt] = 0.0;
     __syncthreads();
     top -= ht;
     cur = lo;
@@ -214,10 +219,11 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const RecordG* __
             double bd[3];
             sym_apply(r.b, dx, dy, dz, bd);
             const double bdx = bd[0], bdy = bd[1], bdz = bd[2];
-            const uint32_t gi = sh_g[jj];
-            const double ux = ((double)mean[gi] - ox) - tau * dx;
-            const double uy = ((double)mean[n + gi] - oy) - tau * dy;
-            const double uz = ((double)mean[2 * n + gi] - oz) - tau * dz;
+            // u = mu - o_ray - t* d; the record's v = mu - o (sensor origin) is exact in float64
+            // (a difference of two float32 values), and so is v - e = mu - o_ray
+            const double ux = (r.v[0] - ex) - tau * dx;
+            const double uy = (r.v[1] - ey) - tau * dy;
+            const double uz = (r.v[2] - ez) - tau * dz;
             double bux, buy, buz;
             if (record_thin(r)) {
               double bu[3];
@@ -242,15 +248,21 @@ __global__ __launch_bounds__(BLOCK) void k_backward(SensorK s, const RecordG* __
         }
       }
       if (__ballot(contrib)) {
-        // one reduction for all 13 partials, then one atomic instruction: lane 4k adds sum k
-        const uint32_t gi = sh_g[jj];
+        // one reduction for all 13 partials, then one LDS atomic instruction: lane 4k adds sum k
         double v16[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) v16[k] = k < UT_ACC_FLOATS ? g[k] : 0.0;
         int idx;
         const double tot = wave_reduce_scatter16(v16, lane, idx);
-        if ((lane & 3) == 0 && idx < UT_ACC_FLOATS && tot != 0.0) unsafeAtomicAdd(acc + (size_t)idx * n + gi, tot);
+        if ((lane & 3) == 0 && idx < UT_ACC_FLOATS && tot != 0.0) atomicAdd(&sacc[idx][jj], tot);
       }
+    }
+    __syncthreads();
+    // the step's sums to the particles' accumulators
+    for (int c = threadIdx.x; c < cnt * UT_ACC_FLOATS; c += BLOCK) {
+      const int k = c / cnt, jj = c - k * cnt;
+      const double v = sacc[k][jj];
+      if (v != 0.0) unsafeAtomicAdd(acc + (size_t)k * n + sh_g[jj], v);
     }
   }
 }
@@ -424,10 +436,10 @@ hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const u
   do {                                                                                                     \
     if (s.moving)                                                                                          \
       hipLaunchKernelGGL((k_backward<B, true>), dim3(n_tiles), dim3(B), 0, st, s, rec, tr, bins.gauss,     \
-                         bins.ranges, n_super, prm, fwd, up, g.mean, acc, g.n);                             \
+                         bins.ranges, n_super, prm, fwd, up, acc, g.n);                             \
     else                                                                                                   \
       hipLaunchKernelGGL((k_backward<B, false>), dim3(n_tiles), dim3(B), 0, st, s, rec, tr, bins.gauss,    \
-                         bins.ranges, n_super, prm, fwd, up, g.mean, acc, g.n);                             \
+                         bins.ranges, n_super, prm, fwd, up, acc, g.n);                             \
   } while (0)
     if (s.kind != UT_LIDAR || max_tile_rays > 128)
       UT_LAUNCH_BACKWARD(256);

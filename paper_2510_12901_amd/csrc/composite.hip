@@ -9,10 +9,13 @@
 // A lane that reaches T < t_min stops (its wavefront stops when all 64 lanes have), and the
 // workgroup stops once every lane is done.
 //
-// Per (ray, particle): w = M d, rejected when |a x w|^2 > cut w.w, else t* = a.w / w.w and
-// D^2 = |a x w|^2 / w.w, rho = exp(-D^2/2) -- all float64 with explicit FMAs (no contraction
-// flags can change the arithmetic between the plain and the batched kernel, or between
-// forward and adjoint).
+// Per (ray, particle), from the record's response quadric B = Sigma^{-1}, B v and v^T B v
+// (v = mu - o): d^T B d from the ray's six quadratic monomials, d^T B v, and
+// num = v^T B v d^T B d - (d^T B v)^2; the pair is rejected when num > cut d^T B d (alpha
+// cannot reach alpha_min), else t* = d^T B v / d^T B d, D^2 = num / d^T B d (records of very
+// thin particles take D^2 from the residual u = v - t* d instead) and rho = exp(-D^2/2) --
+// all float64 with explicit FMAs, so no contraction flag can change the arithmetic between
+// the plain and the batched kernel, or between forward and adjoint.
 #include "ut_cone.hpp"
 #include "ut_internal.hpp"
 
@@ -30,7 +33,7 @@ static_assert(kCamBlock * kCamRpl >= 256, "batched tiles (up to 256 rays) must f
 // occupancy.
 template <int BLOCK, int RPL, int BATCH>
 struct CompositeShared {
-  static_assert(BATCH >= 64 && (BATCH & (BATCH - 1)) == 0, "batch must be a power of two");
+  static_assert(BATCH >= 32 && (BATCH & (BATCH - 1)) == 0, "batch must be a power of two");
   static constexpr int kBatch = BATCH;
   static constexpr uint32_t kRing = BATCH + BLOCK <= 2 * BATCH ? 2 * BATCH : 4 * BATCH;
   static_assert(BATCH + BLOCK <= (int)kRing, "ring must hold a batch plus one refill step");
@@ -47,20 +50,54 @@ struct CompositeShared {
   TileCone cone;
 };
 
+// What a LiDAR unit (several azimuth tiles in one workgroup) adds: per candidate and staged
+// record the tiles of the unit its rect covers (bit t = tile j0 + t) and its position in
+// each of those tiles' lists, per tile the list entries seen so far and the adjoint's bin end.
+template <int BLOCK, int BATCH>
+struct UnitShared {
+  static constexpr uint32_t kRing = CompositeShared<BLOCK, 1, BATCH>::kRing;
+  uint32_t cposT[kRing][kUnitTilesMax];
+  uint32_t rposT[BATCH][kUnitTilesMax];
+  uint8_t cmask[kRing];
+  uint8_t rmask[BATCH];
+  uint32_t wcntT[BLOCK / 64][kUnitTilesMax];
+  uint32_t nhT[kUnitTilesMax];
+  uint32_t tendT[kUnitTilesMax];
+};
+
 // TILE_END: track each ray's bin end and write the tile's (adjoint state); the batched serving
 // path, which never feeds an adjoint, leaves it out and keeps those registers.
-template <int BLOCK, int RPL, int BATCH, bool STATS = false, bool MOVING = false, bool TILE_END = true>
+// UNIT: `tile` is a LiDAR unit (s.units): the rays of its g tiles share the workgroup, the
+// candidates are the bin entries meeting any of the g tiles, and each ray evaluates only the
+// entries that cover its own tile, in the same order -- exactly its tile's list.  List
+// positions (n_proc) and bin ends (tile_end) are kept per tile.  us is used only for UNIT.
+template <int BLOCK, int RPL, int BATCH, bool STATS = false, bool MOVING = false, bool TILE_END = true,
+          bool UNIT = false>
 __device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* __restrict__ rec,
                                                const uint2* __restrict__ trect,
                                                const uint32_t* __restrict__ bgauss,
                                                const uint32_t* __restrict__ branges, int tile, int n_super,
                                                const RenderParamsK& prm, const ut_render_out& out,
-                                               CompositeShared<BLOCK, RPL, BATCH>& sm) {
+                                               CompositeShared<BLOCK, RPL, BATCH>& sm,
+                                               UnitShared<BLOCK, BATCH>* us = nullptr) {
+  static_assert(!UNIT || RPL == 1, "a unit runs one ray per lane");
   constexpr int kBatch = BATCH;
   constexpr uint32_t kRing = CompositeShared<BLOCK, RPL, BATCH>::kRing - 1;
-  const int tx = tile % s.tiles_x, ty = tile / s.tiles_x;
-  const int sid = super_of_tile(tile, s);
+  int tx, ty, sid, j0 = 0, gt = 1;
+  if constexpr (UNIT) {
+    const int4 u = s.units[tile];
+    ty = u.x;
+    j0 = u.y;
+    gt = u.z - u.y;
+    tx = j0;
+    sid = (ty / kSuper) * s.super_x + j0 / kSuper;
+  } else {
+    tx = tile % s.tiles_x;
+    ty = tile / s.tiles_x;
+    sid = super_of_tile(tile, s);
+  }
   const uint32_t start = branges[sid], end = branges[n_super + sid];
+  int tl[RPL];        // UNIT: the ray's tile relative to j0
   long long ray[RPL];
   double dx[RPL], dy[RPL], dz[RPL], T[RPL], f0[RPL], f1[RPL], f2[RPL], dep[RPL];
   double ex[RPL], ey[RPL], ez[RPL];   // moving sensor: ray origin minus the sensor origin
@@ -71,7 +108,9 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* 
   double sx = 0, sy = 0, sz = 0;
 #pragma unroll
   for (int k = 0; k < RPL; ++k) {
-    ray[k] = tile_ray(s, tile, threadIdx.x + k * BLOCK);
+    tl[k] = 0;
+    if constexpr (UNIT) ray[k] = unit_ray(s, s.units[tile], threadIdx.x + k * BLOCK, &tl[k]);
+    else ray[k] = tile_ray(s, tile, threadIdx.x + k * BLOCK);
     dx[k] = dy[k] = dz[k] = 0;
     if (ray[k] >= 0) {
       dx[k] = s.ray_dir[ray[k]];
@@ -104,6 +143,9 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* 
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
   const unsigned long long lt = (1ull << lane) - 1ull;
   if (threadIdx.x < 32) sm.etab[threadIdx.x] = kExp2Frac[threadIdx.x];
+  if constexpr (UNIT) {
+    if (threadIdx.x < kUnitTilesMax) us->nhT[threadIdx.x] = 0, us->tendT[threadIdx.x] = 0;
+  }
 
   // bounding cone of the tile's rays (identical in every lane: built from block reductions)
   double ux, uy, uz, sn;
@@ -145,13 +187,28 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* 
       const uint32_t j = pos + threadIdx.x;
       uint32_t g = 0;
       bool hit = false;
+      uint32_t tmask = 0;   // UNIT: tiles of the unit the entry's rect covers
       if (j < end) {
         g = bgauss[j];
-        hit = rect_covers(trect[g], tx, ty, s);
+        if constexpr (UNIT) {
+          const uint2 r = trect[g];
+          if (rect_meets_unit(r, ty, j0, j0 + gt, s))
+            for (int t = 0; t < gt; ++t) tmask |= rect_covers(r, j0 + t, ty, s) ? 1u << t : 0u;
+          hit = tmask != 0;
+        } else {
+          hit = rect_covers(trect[g], tx, ty, s);
+        }
       }
       const bool keep = hit && !(cull && cone_rejects<MOVING>(rec + g, sm.cone, prm.log_alpha_min));
       const unsigned long long mh = __ballot(hit), mk = __ballot(keep);
       if (lane == 0) sm.wcnt[wave] = make_uint2((uint32_t)__popcll(mh), (uint32_t)__popcll(mk));
+      if constexpr (UNIT) {
+        // per tile of the unit: how many of this step's entries its list gains, per wavefront
+        for (int t = 0; t < gt; ++t) {
+          const unsigned long long mt = __ballot((tmask >> t) & 1u);
+          if (lane == 0) us->wcntT[wave][t] = (uint32_t)__popcll(mt);
+        }
+      }
       __syncthreads();
       uint32_t hb = 0, kb = 0, ht = 0, kt = 0;
 #pragma unroll
@@ -160,16 +217,34 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* 
         if (w < wave) hb += c.x, kb += c.y;
         ht += c.x, kt += c.y;
       }
+      const uint32_t slot = (head + n_cand + kb + (uint32_t)__popcll(mk & lt)) & kRing;
       if (keep) {
-        const uint32_t slot = (head + n_cand + kb + (uint32_t)__popcll(mk & lt)) & kRing;
         sm.cand[slot] = g;
         sm.cpos[slot] = n_hits + hb + (uint32_t)__popcll(mh & lt);
         if constexpr (TILE_END) sm.cbin[slot] = j;
+      }
+      uint32_t step_t = 0;   // UNIT, thread t < gt: entries tile t's list gains in this step
+      if constexpr (UNIT) {
+        // the entry's position in each covered tile's list (entries the cone drops count too)
+        for (int t = 0; t < gt; ++t) {
+          const unsigned long long mt = __ballot((tmask >> t) & 1u);
+          if (keep && ((tmask >> t) & 1u)) {
+            uint32_t base = us->nhT[t];
+            for (int w = 0; w < wave; ++w) base += us->wcntT[w][t];
+            us->cposT[slot][t] = base + (uint32_t)__popcll(mt & lt);
+          }
+        }
+        if (keep) us->cmask[slot] = (uint8_t)tmask;
+        if ((int)threadIdx.x < gt)
+          for (int w = 0; w < BLOCK / 64; ++w) step_t += us->wcntT[w][threadIdx.x];
       }
       n_cand += kt;
       n_hits += ht;
       pos += BLOCK;
       __syncthreads();
+      if constexpr (UNIT) {
+        if ((int)threadIdx.x < gt) us->nhT[threadIdx.x] += step_t;
+      }
     }
     if (n_cand == 0) break;
     const uint32_t cnt = min(n_cand, (uint32_t)kBatch);
@@ -189,6 +264,12 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* 
       sm.rec[j].feat[2] = (double)__uint_as_float(x.z);
       sm.rpos[j] = sm.cpos[slot];
       if constexpr (TILE_END) sm.rbin[j] = sm.cbin[slot];
+      if constexpr (UNIT) {
+        const uint32_t m = us->cmask[slot];
+        us->rmask[j] = (uint8_t)m;
+        for (int t = 0; t < gt; ++t)
+          if ((m >> t) & 1u) us->rposT[j][t] = us->cposT[slot][t];
+      }
     }
     __syncthreads();
     if (!done) {
@@ -197,6 +278,9 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* 
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
           if (rdone[k]) continue;
+          if constexpr (UNIT) {
+            if (!((us->rmask[j] >> tl[k]) & 1u)) continue;   // not in this ray's tile's list
+          }
           Centre cv;
           if constexpr (MOVING) cv = pair_centre(r, ex[k], ey[k], ez[k]);
           else cv = record_centre(r);
@@ -218,7 +302,9 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* 
           T[k] = T[k] * (1.0 - alpha);
           if (T[k] < prm.t_min) {
             rdone[k] = true;
-            nproc[k] = sm.rpos[j] + 1;   // list entries up to and including the terminating one
+            // list entries up to and including the terminating one
+            if constexpr (UNIT) nproc[k] = us->rposT[j][tl[k]] + 1;
+            else nproc[k] = sm.rpos[j] + 1;
             if constexpr (TILE_END) nbin[k] = sm.rbin[j] + 1;   // bin entries up to and including it
           }
         }
@@ -235,10 +321,22 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* 
     n_cand -= cnt;
   }
   // a ray still open here has visited the whole list of its tile
+  if constexpr (UNIT) __syncthreads();   // the per-tile list lengths are final
 #pragma unroll
   for (int k = 0; k < RPL; ++k)
-    if (!rdone[k]) nproc[k] = n_hits, nbin[k] = end;
-  if (TILE_END && out.tile_end) {   // uniform: the adjoint walks the bin back from the largest end
+    if (!rdone[k]) {
+      if constexpr (UNIT) nproc[k] = us->nhT[tl[k]];
+      else nproc[k] = n_hits;
+      nbin[k] = end;
+    }
+  if (UNIT && TILE_END && out.tile_end) {
+    // per tile of the unit: the largest bin end of its rays
+#pragma unroll
+    for (int k = 0; k < RPL; ++k)
+      if (ray[k] >= 0 && nproc[k] > 0) atomicMax(&us->tendT[tl[k]], nbin[k]);
+    __syncthreads();
+    if ((int)threadIdx.x < gt) out.tile_end[ty * s.tiles_x + j0 + threadIdx.x] = us->tendT[threadIdx.x];
+  } else if (TILE_END && out.tile_end) {   // uniform: the adjoint walks the bin back from the largest end
     uint32_t m = 0;
 #pragma unroll
     for (int k = 0; k < RPL; ++k) m = nproc[k] > 0 && nbin[k] > m ? nbin[k] : m;
@@ -290,6 +388,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(RPL == 1 
   composite_tile<BLOCK, RPL, BATCH, STATS, MOVING>(s, rec, trect, bgauss, branges, tile, s.super_x * s.super_y, prm, out, sm);
 }
 
+// LiDAR compositing over units of adjacent azimuth tiles (one ray per lane, unit_rays lanes).
+template <int BLOCK, bool STATS, bool MOVING>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_composite_unit(
+    SensorK s, const RecordG* __restrict__ rec, const uint2* __restrict__ trect, const uint32_t* __restrict__ bgauss,
+    const uint32_t* __restrict__ branges, RenderParamsK prm, ut_render_out out) {
+  constexpr int kBatchU = BLOCK == 64 ? 32 : 128;   // 64 lanes: small LDS for 4 waves per SIMD
+  __shared__ CompositeShared<BLOCK, 1, kBatchU> sm;
+  __shared__ UnitShared<BLOCK, kBatchU> us;
+  const int unit = xcd_tile(blockIdx.x, s.n_units);
+  if (unit < 0) return;
+  composite_tile<BLOCK, 1, kBatchU, STATS, MOVING, true, true>(s, rec, trect, bgauss, branges, unit,
+                                                               s.super_x * s.super_y, prm, out, sm, &us);
+}
+
 // Persistent batched compositing: workgroups pull (request, tile) items from a counter.  Static
 // and moving sensors run in separate launches (MOVING), so each keeps the register budget of
 // its single-request kernel.
@@ -339,7 +451,28 @@ hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, con
       else UT_LAUNCH_COMPOSITE_V(B, R, N, false, false);    \
     }                                                       \
   } while (0)
-  if (s.kind == UT_LIDAR && max_tile_rays > 256)
+  if (s.kind == UT_LIDAR && s.n_units > 0 && s.unit_rays >= max_tile_rays) {
+    // LiDAR units: several azimuth tiles per workgroup, one ray per lane
+    const int ugrid = 8 * ((s.n_units + 7) / 8);
+#define UT_LAUNCH_UNIT(B)                                                                                     \
+  do {                                                                                                        \
+    if (stats) {                                                                                              \
+      if (mv) hipLaunchKernelGGL((k_composite_unit<B, true, true>), dim3(ugrid), dim3(B), 0, st, s, rec, tr,  \
+                                 bins.gauss, bins.ranges, prm, out);                                          \
+      else hipLaunchKernelGGL((k_composite_unit<B, true, false>), dim3(ugrid), dim3(B), 0, st, s, rec, tr,    \
+                              bins.gauss, bins.ranges, prm, out);                                             \
+    } else {                                                                                                  \
+      if (mv) hipLaunchKernelGGL((k_composite_unit<B, false, true>), dim3(ugrid), dim3(B), 0, st, s, rec, tr, \
+                                 bins.gauss, bins.ranges, prm, out);                                          \
+      else hipLaunchKernelGGL((k_composite_unit<B, false, false>), dim3(ugrid), dim3(B), 0, st, s, rec, tr,   \
+                              bins.gauss, bins.ranges, prm, out);                                             \
+    }                                                                                                         \
+  } while (0)
+    if (s.unit_rays == 64) UT_LAUNCH_UNIT(64);
+    else if (s.unit_rays == 128) UT_LAUNCH_UNIT(128);
+    else UT_LAUNCH_UNIT(256);
+#undef UT_LAUNCH_UNIT
+  } else if (s.kind == UT_LIDAR && max_tile_rays > 256)
     UT_LAUNCH_COMPOSITE(256, 2, 256);   // LiDAR tiles of up to 512 rays: two rays per lane
   else if (s.kind != UT_LIDAR || max_tile_rays > 128)
     UT_LAUNCH_COMPOSITE(kCamBlock, kCamRpl, kCamBatch);

@@ -97,21 +97,15 @@ struct SensorK {
   double o1[3];
   const float* ray_org;     // [3][R]
   double div_tan;           // LiDAR beam divergence: tan(cone angle / 2), 0 = off
+  // LiDAR compositing units: runs of adjacent azimuth tiles of one elevation tile inside one
+  // super-tile column, (band, first tile, end tile, rays), packed so that a unit holds at
+  // most unit_rays rays; one workgroup of unit_rays lanes composites a unit
+  const int4* units;
+  int n_units, unit_rays;
 };
 
-// Byte layout of the LiDAR device tables (bounds, beam_start, sat), 256-byte aligned parts.
-struct TableLayout {
-  size_t bounds, beam_start, sat, total;
-};
-inline TableLayout table_layout(int n_phi, int cull_az, int cull_el) {
-  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-  TableLayout t;
-  t.bounds = 0;
-  t.beam_start = al(sizeof(double) * (n_phi + 1));
-  t.sat = t.beam_start + al(sizeof(int) * (n_phi + 1));
-  t.total = t.sat + al(sizeof(int) * (size_t)(cull_az + 1) * (cull_el + 1));
-  return t;
-}
+// Tiles of a LiDAR compositing unit: at most 4 adjacent tiles, inside one super-tile column.
+constexpr int kUnitTilesMax = 4;
 
 // 2^(j/32), j = 0..31, correctly rounded to float64 (evaluated in 60-digit decimal arithmetic).
 __constant__ static const double kExp2Frac[32] = {
@@ -326,6 +320,35 @@ __device__ __forceinline__ bool rect_covers(uint2 r, int tx, int ty, const Senso
   int dx = tx - x0;
   if (dx < 0) dx += s.n_theta;
   return dx <= x1 - x0;
+}
+
+// First azimuth step of LiDAR azimuth tile j: ceil(j n_az / N_theta); step a lies in tile
+// floor(a N_theta / n_az).
+__device__ __forceinline__ int az_start(const SensorK& s, int j) {
+  return (int)(((long long)j * s.n_az + s.n_theta - 1) / s.n_theta);
+}
+
+// Ray r of LiDAR unit u = (band k, tiles [j0, j1)): the unit's beams times its azimuth steps,
+// azimuth fastest; *t receives the ray's tile relative to j0.  Returns -1 past the end.
+__device__ __forceinline__ long long unit_ray(const SensorK& s, int4 u, int r, int* t) {
+  const int b0 = s.beam_start[u.x], b1 = s.beam_start[u.x + 1];
+  const int a0 = az_start(s, u.y), a1 = az_start(s, u.z);
+  const int naz = a1 - a0;
+  *t = 0;
+  if (naz <= 0 || r >= (b1 - b0) * naz) return -1;
+  const int a = a0 + r % naz;
+  *t = (int)(((long long)a * s.n_theta) / s.n_az) - u.y;
+  return (long long)(b0 + r / naz) * s.n_az + a;
+}
+
+// Does a packed LiDAR rect cover elevation tile k and some azimuth tile of [j0, j1)
+// (j1 <= N_theta)?  The covered azimuth arc starts at x0 and is contiguous modulo N_theta.
+__device__ __forceinline__ bool rect_meets_unit(uint2 r, int k, int j0, int j1, const SensorK& s) {
+  const int x0 = (int)(r.x & 0xFFFFu), y0 = (int)(r.x >> 16), x1 = (int)(r.y & 0xFFFFu), y1 = (int)(r.y >> 16);
+  if (k < y0 || k > y1) return false;
+  int dx = j0 - x0;
+  if (dx < 0) dx += s.n_theta;
+  return dx <= x1 - x0 || (x0 > j0 && x0 < j1);
 }
 
 __device__ __forceinline__ int super_of_tile(int tile, const SensorK& s) {

@@ -1,26 +1,35 @@
 """Continuous-batching render server for closed-loop multi-sensor simulation.
 
-The particle scene stays resident on the GPU.  Every request renders one sensor.  The host
-loop moves each request through:
+The particle scene stays resident on the GPU.  Every request renders one sensor.  A request
+moves through:
 
-  waiting    arrived, no slot free yet
-  counting   projection + pair count enqueued on the slot's own stream
-  counted    pair total P known; waits until the device pool can hold its pair workspace and
-             tile lists (admission by the memory its tile lists need)
-  sorting    binning / radix sort enqueued on the slot stream
-  batched    composited together with every other sorted request in one persistent launch
-             (ut_composite_batch) on one of two compositing streams
-  done       latency recorded; pool memory and slot released
+  waiting    arrived; waits for a free slot (stream + projection buffers) and for pool
+             memory for its tile lists, reserved from a pair bound of its sensor (admission
+             by the memory its tile lists will need)
+  enqueued   projection, depth sort + pair count and the pair sort are enqueued at once on
+             the slot's stream; the pair total stays on the device (ut_bin_sort_device with
+             the bound as capacity), so no host round trip sits between the stages
+  batched    composited together with every other enqueued request in one persistent launch
+             (ut_composite_batch) on one of two compositing streams, which waits on the
+             requests' sorts on the device
+  done       a waiter thread blocks on the launch's completion event and wakes the host loop;
+             latency recorded, slot and pool memory released.  A request whose pair total
+             exceeded its bound (the device raised its overflow flag and rendered nothing)
+             goes back to the queue with the bound raised to its known total.
 
-Requests that arrive while others are on the GPU are admitted as slots and pool memory free
-up, and their projection / sorting overlaps the compositing of earlier requests.  The
-compositing arithmetic per ray is the single-request kernel's, so served outputs are
-bit-identical to plain renders.
+The host loop sleeps until the next arrival or a completion -- it does not poll.  Requests
+that arrive while others are on the GPU are admitted as slots and pool memory free up, and
+their projection and sorting overlap the compositing of earlier requests.  The compositing
+arithmetic per ray is the single-request kernel's, so served outputs are bit-identical to
+plain renders.
 """
 from __future__ import annotations
 
 import contextlib
+import json
 import gc
+import queue
+import threading
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -99,11 +108,11 @@ class Request:
     sensor: int
     arrival: float
     t_done: float = -1.0
-    t_start: float = -1.0      # slot taken, projection enqueued
-    t_counted: float = -1.0    # pair total seen on the host
-    t_sort: float = -1.0       # pool memory granted, sort enqueued
+    t_start: float = -1.0      # slot and memory granted; projection, count and sort enqueued
     t_batch: float = -1.0      # compositing launch enqueued
     n_pairs: int = 0
+    capacity: int = 0          # pair bound its tile lists were reserved for
+    retries: int = 0           # renders repeated because the pair total exceeded the bound
     slot: "Slot" = None
     mem: tuple = None
     bins: BinLists = None
@@ -112,19 +121,22 @@ class Request:
 
 class Slot:
     """Per-request-in-flight device state: a stream, projection buffers, count workspace,
-    output buffers sized for the largest sensor, and its events."""
+    the pair total and overflow flag (device, with pinned host copies), output buffers
+    sized for the largest sensor, and its events."""
 
-    def __init__(self, n: int, max_rays: int, device):
+    def __init__(self, n: int, max_rays: int, device, timing: bool):
         self.stream = torch.cuda.Stream(device=device)
         self.p = alloc_projection(n, device)
         self.ws = torch.empty(int(lib().ut_count_workspace_bytes(n)), dtype=torch.uint8, device=device)
         self.total = torch.zeros(1, dtype=torch.int64).pin_memory()
+        self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
+        self.overflow_host = torch.zeros(1, dtype=torch.int32).pin_memory()
         self.feat = torch.empty(3 * max_rays, dtype=torch.float32, device=device)
         self.depth = torch.empty(max_rays, dtype=torch.float32, device=device)
         self.alpha = torch.empty(max_rays, dtype=torch.float32, device=device)
         self.drop = torch.empty(max_rays, dtype=torch.float32, device=device)
-        self.ev_count = torch.cuda.Event()
-        self.ev_sort = torch.cuda.Event()
+        self.ev_sorted = torch.cuda.Event(enable_timing=timing)
+        self.ev_sort0 = torch.cuda.Event(enable_timing=True) if timing else None
 
     def out_for(self, sensor: Sensor) -> RenderOut:
         R = sensor.n_rays
@@ -132,31 +144,57 @@ class Slot:
                          self.drop[:R] if sensor.is_lidar else None, None, None)
 
 
+@dataclass
+class Batch:
+    reqs: list
+    stream: int
+    done: torch.cuda.Event
+    start: torch.cuda.Event = None
+    keep: list = field(default_factory=list)   # ctypes structures the launch was given
+
+
 class Server:
+    """timing=True records device timestamps of every request's pair sort and every batch's
+    compositing (stats["device"]), which show whether requests overlapped on the GPU."""
+
     def __init__(self, g_cam: GaussianSet, g_lidar: GaussianSet, sensors: list, pool_bytes: int,
-                 n_slots: int = 12, n_workgroups: int = 1024, params=None, abk=(1.0, 2.0, 0.0)):
+                 n_slots: int = 12, n_workgroups: int = 1024, params=None, abk=(1.0, 2.0, 0.0),
+                 timing: bool = False, bound_margin: float = 1.25):
         self.g_cam, self.g_lidar, self.sensors = g_cam, g_lidar, sensors
         dev = g_cam.mean.device
         self.dev = dev
         self.params = params or render_params()
         self.abk = abk
         self.n_workgroups = n_workgroups
+        self.timing = timing
+        self.bound_margin = bound_margin
         self.pool = DevicePool(pool_bytes, dev)
         max_rays = max(s.n_rays for s in sensors)
-        self.slots = [Slot(g_cam.n, max_rays, dev) for _ in range(n_slots)]
+        self.slots = [Slot(g_cam.n, max_rays, dev, timing) for _ in range(n_slots)]
         self.comp_streams = [torch.cuda.Stream(device=dev) for _ in range(2)]
         self.batch_ws = [torch.empty(int(lib().ut_batch_workspace_bytes(n_slots)), dtype=torch.uint8, device=dev)
                          for _ in range(2)]
-        self.count_bytes = int(lib().ut_count_workspace_bytes(g_cam.n))
+        self.bound = [0] * len(sensors)     # pair capacity reserved per request of each sensor
         self.stats = {}
+        self.batches = []                   # request ids of every compositing launch of the last run
+        self._calibrate()
 
     def _g(self, sensor: Sensor) -> GaussianSet:
         return self.g_lidar if sensor.is_lidar else self.g_cam
 
-    def _start(self, r: Request):
+    def _calibrate(self):
+        """One counted render per sensor sets its first pair bound (set-up, outside any run)."""
+        s = self.slots[0]
+        for si, sensor in enumerate(self.sensors):
+            self._project_count(s, sensor)
+            s.stream.synchronize()
+            self._raise_bound(si, int(s.total.item()))
+
+    def _raise_bound(self, si: int, n_pairs: int):
+        self.bound[si] = max(self.bound[si], int(n_pairs * self.bound_margin) + 4096)
+
+    def _project_count(self, s: Slot, sensor: Sensor):
         L = lib()
-        s = r.slot
-        sensor = self.sensors[r.sensor]
         g = self._g(sensor)
         st = _stream(s.stream)
         import ctypes as C
@@ -165,49 +203,60 @@ class Server:
         check(L.ut_project(ref(gc), ref(sensor.c), C.cast(abk, C.c_void_p), ref(s.p.c()), st), "ut_project")
         check(L.ut_bin_count(ref(s.p.c()), g.n, ref(sensor.c), s.ws.data_ptr(), s.ws.numel(), s.total.data_ptr(), st),
               "ut_bin_count")
-        s.ev_count.record(s.stream)
 
-    def _need(self, r: Request):
-        sensor = self.sensors[r.sensor]
-        pw = int(lib().ut_pair_workspace_bytes(r.n_pairs))
-        lb = 4 * max(r.n_pairs, 1)
-        rb = 8 * sensor.n_super
+    def _need(self, sensor: Sensor, cap: int):
+        al = lambda v: (v + ALIGN - 1) // ALIGN * ALIGN
+        pw = al(int(lib().ut_pair_workspace_bytes(cap)))
+        lb = al(4 * max(cap, 1))
+        rb = al(8 * sensor.n_super)
         return pw, lb, rb
 
-    def _sort(self, r: Request):
+    def _enqueue(self, r: Request):
+        """Projection, count and the device-count pair sort on the slot's stream; the overflow
+        flag is copied to pinned host memory behind the sort."""
         L = lib()
         s = r.slot
         sensor = self.sensors[r.sensor]
         g = self._g(sensor)
-        pw, lb, rb = self._need(r)
-        al = lambda v: (v + ALIGN - 1) // ALIGN * ALIGN
+        pw, lb, rb = self._need(sensor, r.capacity)
         pbuf = self.pool.view(r.mem, 0, pw)
-        gauss = self.pool.view(r.mem, al(pw), lb).view(torch.int32)
-        ranges = self.pool.view(r.mem, al(pw) + al(lb), rb).view(torch.int32).view(2, sensor.n_super)
-        r.bins = BinLists(gauss, ranges, r.n_pairs)
-        check(L.ut_bin_sort(ref(s.p.c()), g.n, ref(sensor.c), s.ws.data_ptr(), s.ws.numel(), pbuf.data_ptr(), pw,
-                            r.n_pairs, ref(r.bins.c()), _stream(s.stream)), "ut_bin_sort")
-        s.ev_sort.record(s.stream)
+        gauss = self.pool.view(r.mem, pw, lb).view(torch.int32)
+        ranges = self.pool.view(r.mem, pw + lb, rb)[: 8 * sensor.n_super].view(torch.int32).view(2, sensor.n_super)
+        r.bins = BinLists(gauss, ranges, r.capacity)
+        self._project_count(s, sensor)
+        with torch.cuda.stream(s.stream):
+            s.overflow.zero_()
+        if s.ev_sort0 is not None:
+            s.ev_sort0.record(s.stream)
+        check(L.ut_bin_sort_device(ref(s.p.c()), g.n, ref(sensor.c), s.ws.data_ptr(), s.ws.numel(), pbuf.data_ptr(),
+                                   pw, r.capacity, ref(r.bins.c()), s.overflow.data_ptr(), _stream(s.stream)),
+              "ut_bin_sort_device")
+        with torch.cuda.stream(s.stream):
+            s.overflow_host.copy_(s.overflow, non_blocking=True)
+        s.ev_sorted.record(s.stream)
 
-    def _composite(self, reqs, k):
+    def _composite(self, reqs, k) -> Batch:
         cs = self.comp_streams[k]
         n = len(reqs)
         arr = (A.UtBatchItem * n)()
-        keep = []
+        keep = [arr]
         for i, r in enumerate(reqs):
-            cs.wait_event(r.slot.ev_sort)
+            cs.wait_event(r.slot.ev_sorted)
             sensor = self.sensors[r.sensor]
             r.out = r.slot.out_for(sensor)
             pc, lc, oc = r.slot.p.c(), r.bins.c(), r.out.c()
             keep += [pc, lc, oc]
             arr[i] = A.UtBatchItem(ref(pc), ref(lc), ref(sensor.c), ref(oc))
+        b = Batch(list(reqs), k, torch.cuda.Event(blocking=True, enable_timing=self.timing), keep=keep)
+        if self.timing:
+            b.start = torch.cuda.Event(enable_timing=True)
+            b.start.record(cs)
         import ctypes as C
         ws = self.batch_ws[k]
         check(lib().ut_composite_batch(C.cast(arr, C.c_void_p), n, ref(self.params), ws.data_ptr(), ws.numel(),
                                        self.n_workgroups, _stream(cs)), "ut_composite_batch")
-        ev = torch.cuda.Event()
-        ev.record(cs)
-        return ev
+        b.done.record(cs)
+        return b
 
     def run(self, trace, on_done=None, max_batch=None):
         """trace: list of (arrival_seconds, frame_id, sensor_index) sorted by arrival.
@@ -217,89 +266,142 @@ class Server:
 
     def _run(self, trace, on_done, max_batch):
         reqs = [Request(i, int(f), int(si), float(t)) for i, (t, f, si) in enumerate(trace)]
-        waiting, counting, counted, sorting, batches = deque(), [], deque(), [], []
+        waiting, enqueued = deque(), []
         free_slots = list(self.slots)
         free_comp = [0, 1]
+        wake = threading.Event()
+        done_q = queue.Queue()
+        work_q = [queue.Queue(), queue.Queue()]
+
+        def waiter(k):
+            # one thread per compositing stream: its launches complete in stream order
+            while True:
+                b = work_q[k].get()
+                if b is None:
+                    return
+                b.done.synchronize()      # blocking event: the thread sleeps, the GIL is released
+                done_q.put(b)
+                wake.set()
+
+        threads = [threading.Thread(target=waiter, args=(k,), daemon=True) for k in range(2)]
+        for th in threads:
+            th.start()
         n_done, i_next = 0, 0
-        n_batches, batch_sizes, max_mem_wait = 0, [], 0
+        batch_sizes, max_mem_wait, n_retries = [], 0, 0
+        self.batches = []
+        dev_batches = []
         torch.cuda.synchronize()
+        t_ev0 = torch.cuda.Event(enable_timing=True) if self.timing else None
+        if t_ev0 is not None:
+            t_ev0.record()
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
-        while n_done < len(reqs):
-            t = now()
-            progressed = False
-            while i_next < len(reqs) and reqs[i_next].arrival <= t:
-                waiting.append(reqs[i_next])
-                i_next += 1
-            while waiting and free_slots:
-                r = waiting.popleft()
-                r.slot = free_slots.pop()
-                r.t_start = now()
-                self._start(r)
-                counting.append(r)
-                progressed = True
-            for r in list(counting):
-                if r.slot.ev_count.query():
-                    counting.remove(r)
-                    r.n_pairs = int(r.slot.total.item())
-                    r.t_counted = now()
-                    counted.append(r)
-                    progressed = True
-            max_mem_wait = max(max_mem_wait, len(counted))
-            while counted:
-                r = counted[0]
-                pw, lb, rb = self._need(r)
-                al = lambda v: (v + ALIGN - 1) // ALIGN * ALIGN
-                blk = self.pool.alloc(al(pw) + al(lb) + al(rb))
-                if blk is None:
-                    if not sorting and not batches and self.pool.in_use == 0:
-                        raise RuntimeError(f"request {r.rid} needs more than the whole pool")
-                    break
-                counted.popleft()
-                r.mem = blk
-                r.t_sort = now()
-                self._sort(r)
-                sorting.append(r)
-                progressed = True
-            if sorting and free_comp:
-                ready = [r for r in sorting if r.slot.ev_sort.query()]
-                if max_batch:
-                    ready = ready[:max_batch]
-                if ready:
-                    tb = now()
-                    for r in ready:
-                        sorting.remove(r)
-                        r.t_batch = tb
-                    k = free_comp.pop(0)
-                    ev = self._composite(ready, k)
-                    batches.append((ev, ready, k))
-                    n_batches += 1
-                    batch_sizes.append(len(ready))
-                    progressed = True
-            for item in list(batches):
-                ev, rs, k = item
-                if ev.query():
+        sort_times = {}
+        try:
+            while n_done < len(reqs):
+                wake.clear()
+                progressed = False
+                # completions first: they free slots, memory and compositing streams
+                while True:
+                    try:
+                        b = done_q.get_nowait()
+                    except queue.Empty:
+                        break
                     td = now()
-                    for r in rs:
+                    if self.timing:
+                        dev_batches.append((t_ev0.elapsed_time(b.start), t_ev0.elapsed_time(b.done),
+                                            [r.rid for r in b.reqs]))
+                    for r in b.reqs:
+                        P = int(r.slot.total.item())
+                        r.n_pairs = P
+                        self._raise_bound(r.sensor, P)
+                        if self.timing:
+                            sort_times[r.rid] = (t_ev0.elapsed_time(r.slot.ev_sort0), t_ev0.elapsed_time(r.slot.ev_sorted))
+                        if int(r.slot.overflow_host.item()) != 0:
+                            # the pair total exceeded the bound: nothing was rendered; again with
+                            # the bound raised to the now known total
+                            r.retries += 1
+                            n_retries += 1
+                            self.pool.release(r.mem)
+                            free_slots.append(r.slot)
+                            r.slot, r.mem = None, None
+                            waiting.appendleft(r)
+                            continue
                         r.t_done = td
                         if on_done is not None:
                             on_done(r)
                         self.pool.release(r.mem)
                         free_slots.append(r.slot)
-                    n_done += len(rs)
-                    batches.remove(item)
-                    free_comp.append(k)
+                        n_done += 1
+                    free_comp.append(b.stream)
                     progressed = True
-            if not progressed:
-                time.sleep(20e-6)
+                t = now()
+                while i_next < len(reqs) and reqs[i_next].arrival <= t:
+                    waiting.append(reqs[i_next])
+                    i_next += 1
+                # admission: a slot and pool memory for the sensor's pair bound
+                while waiting and free_slots:
+                    r = waiting[0]
+                    sensor = self.sensors[r.sensor]
+                    cap = self.bound[r.sensor]
+                    blk = self.pool.alloc(sum(self._need(sensor, cap)))
+                    if blk is None:
+                        if not enqueued and self.pool.in_use == 0:
+                            raise RuntimeError(f"request {r.rid} needs more than the whole pool")
+                        # a slot is free but the pool is not: held back by memory
+                        max_mem_wait = max(max_mem_wait, len(waiting))
+                        break
+                    waiting.popleft()
+                    r.capacity, r.mem = cap, blk
+                    r.slot = free_slots.pop()
+                    r.t_start = now()
+                    self._enqueue(r)
+                    enqueued.append(r)
+                    progressed = True
+                if enqueued and free_comp:
+                    take = enqueued[:max_batch] if max_batch else list(enqueued)
+                    del enqueued[: len(take)]
+                    tb = now()
+                    for r in take:
+                        r.t_batch = tb
+                    k = free_comp.pop(0)
+                    b = self._composite(take, k)
+                    self.batches.append([r.rid for r in take])
+                    batch_sizes.append(len(take))
+                    work_q[k].put(b)
+                    progressed = True
+                if not progressed:
+                    timeout = max(reqs[i_next].arrival - now(), 0.0) if i_next < len(reqs) else None
+                    if timeout is None or timeout > 0:
+                        wake.wait(timeout)
+        finally:
+            for q in work_q:
+                q.put(None)
+            for th in threads:
+                th.join()
         stage = lambda a, b: round(float(np.mean([getattr(r, b) - getattr(r, a) for r in reqs])) * 1e3, 3)
-        self.stats = {"batches": n_batches, "mean_batch": float(np.mean(batch_sizes)) if batch_sizes else 0.0,
+        self.stats = {"batches": len(batch_sizes), "mean_batch": float(np.mean(batch_sizes)) if batch_sizes else 0.0,
+                      "max_batch": int(max(batch_sizes)) if batch_sizes else 0,
                       "pool_peak_bytes": self.pool.peak, "max_waiting_for_memory": max_mem_wait,
+                      "overflow_retries": n_retries,
                       # mean milliseconds a request spends between consecutive stages
-                      "stage_ms": {"slot_wait": stage("arrival", "t_start"), "count": stage("t_start", "t_counted"),
-                                   "memory_wait": stage("t_counted", "t_sort"), "sort": stage("t_sort", "t_batch"),
+                      "stage_ms": {"admission_wait": stage("arrival", "t_start"),
+                                   "sort_wait": stage("t_start", "t_batch"),
                                    "composite": stage("t_batch", "t_done")}}
+        if self.timing:
+            self.stats["device"] = {"sort_ms": sort_times, "batches_ms": dev_batches}
+            self.stats["device_overlap"] = overlap_count(sort_times, dev_batches)
         return reqs
+
+
+def overlap_count(sort_times: dict, batches: list) -> int:
+    """Requests whose pair sort ran on the device while a compositing launch that does not
+    hold them was running (device timestamps, milliseconds)."""
+    n = 0
+    for rid, (s0, s1) in sort_times.items():
+        if any(rid not in rids and s0 < b1 and b0 < s1 for b0, b1, rids in batches):
+            n += 1
+    return n
 
 
 def run_plain(g_cam, g_lidar, sensors, trace, pipes=None, on_done=None):
@@ -352,7 +454,10 @@ def frame_latencies(reqs):
     return lat
 
 
-def summarize(reqs, rays_per_request):
+def summarize(reqs, rays_per_request, t_from: float = 0.0):
+    """Latency percentiles and completed rays/s over the requests of frames that arrived at or
+    after t_from seconds (earlier frames are the warm-up)."""
+    reqs = [r for r in reqs if r.arrival >= t_from]
     lat = frame_latencies(reqs)
     rl = np.array([r.t_done - r.arrival for r in reqs])
     span = max(r.t_done for r in reqs) - min(r.arrival for r in reqs)
@@ -365,24 +470,49 @@ def summarize(reqs, rays_per_request):
 
 
 def bench_served(g, gl, sensors_np, sensors, dev, args, log):
-    """Served vs plain on Poisson traces at 30 frames/s per simulated vehicle."""
+    """Served vs plain on Poisson traces at 30 frames/s per simulated vehicle: each trace runs
+    warm-up + measured seconds of arrivals and the statistics cover the frames that arrived
+    after the warm-up.  Where the offered load exceeds what the plain path can serve (8 or
+    more vehicles) its queue only grows, so the plain path runs the warm-up and the first 3
+    measured seconds of the trace there.  A last 2 s run at 8 vehicles records device
+    timestamps: the share of requests whose pair sort ran on the GPU while a compositing
+    launch of other requests ran.  The knee is the largest vehicle count up to which every served p99 frame latency
+    stays under 33 ms (one frame period at 30 frames/s)."""
     rays = [s.n_rays for s in sensors]
-    out = {"rate_per_vehicle_fps": 30, "seconds": args.served_seconds, "vehicles": {}}
-    pool_bytes = 48 << 30
-    server = Server(g, gl, sensors, pool_bytes=pool_bytes, n_slots=14)
+    warm_s, meas_s = args.served_warmup, args.served_seconds
+    out = {"rate_per_vehicle_fps": 30, "warmup_seconds": warm_s, "seconds": meas_s, "vehicles": {}}
+    server = Server(g, gl, sensors, pool_bytes=48 << 30, n_slots=14)
     pipes = None
-    # warm both paths
-    warm = poisson_trace(60.0, 0.1, len(sensors), seed=99)
+    warm = poisson_trace(60.0, 0.2, len(sensors), seed=99)
     server.run(warm)
     _, pipes = run_plain(g, gl, sensors, warm, pipes)
+    knee, below = None, True
     for v in [int(x) for x in args.vehicles.split(",") if x]:
-        trace = poisson_trace(30.0 * v, args.served_seconds, len(sensors), seed=v)
+        trace = poisson_trace(30.0 * v, warm_s + meas_s, len(sensors), seed=v)
         sreq = server.run(trace)
-        srv = summarize(sreq, rays)
-        srv.update(server.stats)
-        preq, pipes = run_plain(g, gl, sensors, trace, pipes)
-        pl = summarize(preq, rays)
-        out["vehicles"][str(v)] = {"served": srv, "plain": pl}
-        log(f"V={v}: served p50/p99 {srv['p50_frame_ms']}/{srv['p99_frame_ms']} ms {srv['mrays_per_s']} Mrays/s | "
-            f"plain p50/p99 {pl['p50_frame_ms']}/{pl['p99_frame_ms']} ms {pl['mrays_per_s']} Mrays/s")
+        srv = summarize(sreq, rays, t_from=warm_s)
+        srv.update({k: server.stats[k] for k in ("batches", "mean_batch", "max_batch", "pool_peak_bytes",
+                                                 "overflow_retries", "stage_ms")})
+        ptrace = trace if v < 8 else [t for t in trace if t[0] <= warm_s + 3.0]
+        preq, pipes = run_plain(g, gl, sensors, ptrace, pipes)
+        pl = summarize(preq, rays, t_from=warm_s)
+        pl["trace_seconds"] = round(max(t[0] for t in ptrace), 2)
+        out["vehicles"][str(v)] = {"offered_mrays_per_s": round(30.0 * v * sum(rays) / 1e6, 1),
+                                   "served": srv, "plain": pl}
+        below = below and srv["p99_frame_ms"] < 33.0
+        if below:
+            knee = v
+        log(f"V={v}: served p50/p99 {srv['p50_frame_ms']}/{srv['p99_frame_ms']} ms {srv['mrays_per_s']} Mrays/s "
+            f"(mean batch {srv['mean_batch']:.2f}) | plain p50/p99 {pl['p50_frame_ms']}/{pl['p99_frame_ms']} ms "
+            f"{pl['mrays_per_s']} Mrays/s")
+    out["knee_vehicles"] = knee
+    out["served_saturation_mrays_per_s"] = max(r["served"]["mrays_per_s"] for r in out["vehicles"].values())
+    del server
+    torch.cuda.synchronize()
+    timed = Server(g, gl, sensors, pool_bytes=48 << 30, n_slots=14, timing=True)
+    treq = timed.run(poisson_trace(30.0 * 8, 2.0, len(sensors), seed=123))
+    n_ov = timed.stats["device_overlap"]
+    out["device_overlap_v8"] = {"requests": len(treq), "sort_overlapping_other_compositing": n_ov,
+                                "frac": round(n_ov / len(treq), 3), "mean_batch": round(timed.stats["mean_batch"], 2)}
+    log(f"device overlap at V=8: {json.dumps(out['device_overlap_v8'])}")
     return out

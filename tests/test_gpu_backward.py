@@ -192,3 +192,21 @@ def test_backward_matches_oracle_across_many_super_tiles():
     assert ol["n_pairs"] > 500 * 30 * 17                             # long lists
     ref = oracle.backward(g, s, ol, up)
     _check(gpu, ref, label="480x270, 12 super-tiles")
+
+
+def test_autograd_refuses_backward_after_in_place_edit_of_outputs():
+    """The differentiable render saves its returned tensors for the adjoint (which reads the
+    features for the ray-drop derivative): editing one in place before backward is an error,
+    not a silently wrong gradient."""
+    import paper_2510_12901_amd as ut
+    g_np, s_np = synth.scene_lidar(2, n=2000, n_beams=16, n_az=256, n_phi=4, max_per_tile=32)
+    g_np["mean"] *= np.float32(0.05)
+    g = ut.GaussianSet.from_numpy(g_np)
+    s = ut.Sensor(s_np)
+    params = [t.clone().requires_grad_(True) for t in (g.mean, g.quat, g.log_scale, g.opacity_logit, g.feat)]
+    feat, depth, alpha, drop = ut.render_differentiable(g.with_params(*params), s)
+    loss = drop.sum() + feat.sum()
+    with torch.no_grad():
+        feat.mul_(2.0)
+    with pytest.raises(RuntimeError, match="modified by an inplace operation"):
+        loss.backward()

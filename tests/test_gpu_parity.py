@@ -342,3 +342,31 @@ def test_offscreen_precull_matches_full_projection(abk):
     u = 160.0 * v[0] / v[2] + 97.0
     far_off = (v[2] > 2.0) & ((u < -150) | (u > 350))
     assert far_off.sum() > n // 10
+
+
+@pytest.mark.parametrize("name", ["lidar_small", "lidar_posed_m64", "lidar_m128", "lidar_m256"])
+def test_lidar_compositing_units_partition_the_tiles(name):
+    """The compositing units built at sensor set-up: every azimuth-elevation tile lies in
+    exactly one unit; a unit is a run of at most 4 adjacent tiles of one elevation tile inside
+    one super-tile column; its rays fit unit_rays lanes, the smallest of 64, 128, 256 that
+    holds the largest tile."""
+    import paper_2510_12901_amd as ut
+    g_np, s_np = _scene(name)
+    s = ut.Sensor(s_np)
+    c = s.c
+    NP, NT = c.n_phi, c.n_theta
+    al = lambda v: (v + 255) // 256 * 256
+    cull = (c.cull_az + 1) * (c.cull_el + 1) if c.cull else 1
+    off = al(8 * (NP + 1)) + al(4 * (NP + 1)) + al(4 * cull)
+    tb = to_np(s.tables)
+    units = tb[off: off + 16 * c.n_units].view(np.int32).reshape(-1, 4)
+    bstart = tb[al(8 * (NP + 1)): al(8 * (NP + 1)) + 4 * (NP + 1)].view(np.int32)
+    assert c.unit_rays == min(u for u in (64, 128, 256) if u >= s.max_tile_rays)
+    az0 = lambda j: (j * c.n_az + NT - 1) // NT
+    seen = np.zeros((NP, NT), np.int64)
+    for k, j0, j1, rays in units:
+        assert 0 <= k < NP and 0 <= j0 < j1 <= NT and j1 - j0 <= 4
+        assert j0 // 8 == (j1 - 1) // 8
+        assert rays == (bstart[k + 1] - bstart[k]) * (az0(j1) - az0(j0)) <= c.unit_rays
+        seen[k, j0:j1] += 1
+    assert np.all(seen == 1)
