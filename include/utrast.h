@@ -114,6 +114,8 @@ typedef struct {
                              elevation tile packed into one workgroup), set by ut_sensor_build */
   int32_t unit_rays;      /* rays per unit at most (64, 128 or 256; 0 = no units), set by
                              ut_sensor_build */
+  int32_t n_units_wide;   /* units of up to 256 rays for the batched composite (0 = none), set
+                             by ut_sensor_build */
   const float* beam_elev_host; /* host [n_beams] radians, sorted ascending (LiDAR set-up only) */
   const float* ray_dir;   /* device [3][R] */
   void* tables;           /* device, LiDAR tiling + summed-area table */
@@ -245,8 +247,9 @@ ut_status ut_sensor_table_bytes(const ut_sensor* s, size_t* bytes);
 /* Sensor set-up, once per sensor definition (Sec. 3.3: the tiling is reused across calls).
  * LiDAR: runs Alg. 1, builds the ray mask over the culling grid and its summed-area
  * table (Appendix B) and the compositing units, and copies them to s->tables (device,
- * ut_sensor_table_bytes bytes); sets s->n_theta, s->max_tile_rays, s->n_units and
- * s->unit_rays.  A unit is a run of adjacent azimuth tiles of one elevation tile within one
+ * ut_sensor_table_bytes bytes); sets s->n_theta, s->max_tile_rays, s->n_units,
+ * s->unit_rays and s->n_units_wide (a second packing of up to 256 rays per unit, which
+ * ut_composite_batch uses).  A unit is a run of adjacent azimuth tiles of one elevation tile within one
  * super-tile column whose rays fit one workgroup of unit_rays lanes (the smallest of 64, 128,
  * 256 that holds the largest tile); the tiles stay the binning units and every ray still walks
  * its own tile's list, so units change which rays share a wavefront, not any result.

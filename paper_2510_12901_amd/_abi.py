@@ -29,7 +29,7 @@ class UtSensor(C.Structure):
                 ("fx", f64), ("fy", f64), ("cx", f64), ("cy", f64), ("k", f64 * 4), ("theta_max", f64),
                 ("n_beams", i32), ("n_az", i32), ("n_phi", i32), ("max_per_tile", i32), ("cull", i32),
                 ("cull_az", i32), ("cull_el", i32), ("n_theta", i32), ("max_tile_rays", i32),
-                ("n_units", i32), ("unit_rays", i32),
+                ("n_units", i32), ("unit_rays", i32), ("n_units_wide", i32),
                 ("beam_elev_host", P), ("ray_dir", P), ("tables", P),
                 ("moving", i32), ("R_sw1", C.c_float * 9), ("origin1", C.c_float * 3), ("ray_org", P),
                 ("rs_iters", i32),

@@ -69,6 +69,8 @@ SensorK make_sensor_k(const ut_sensor* s) {
     k.units = reinterpret_cast<const int4*>(base + t.units);
     k.n_units = s->n_units;
     k.unit_rays = s->unit_rays;
+    k.units_wide = k.units + (size_t)s->n_phi * s->n_theta;
+    k.n_units_wide = s->n_units_wide;
     k.n_rays = (long long)s->n_beams * s->n_az;
     k.div_tan = s->beam_divergence > 0 ? std::tan(0.5 * s->beam_divergence) : 0.0;
   } else {
@@ -79,8 +81,9 @@ SensorK make_sensor_k(const ut_sensor* s) {
     k.theta_max = s->theta_max;
     k.n_rays = (long long)s->width * s->height;
   }
+  k.super_h = ut_host::super_rows(s->kind);
   k.super_x = (k.tiles_x + kSuper - 1) / kSuper;
-  k.super_y = (k.tiles_y + kSuper - 1) / kSuper;
+  k.super_y = (k.tiles_y + k.super_h - 1) / k.super_h;
   if (s->moving) {
     k.moving = 1;
     k.rs_iters = s->rs_iters;
@@ -179,9 +182,10 @@ ut_status ut_sensor_build(ut_sensor* s, ut_stream stream) {
   std::memcpy(host.data() + t.bounds, bounds.data(), sizeof(double) * (NP + 1));
   std::memcpy(host.data() + t.beam_start, bstart.data(), sizeof(int32_t) * (NP + 1));
   const int unit_rays = ut_host::unit_width(max_rays);
-  const int n_units = unit_rays > 0 ? ut_host::build_units(bstart.data(), NP, s->n_az, nth, unit_rays,
-                                                          reinterpret_cast<int32_t*>(host.data() + t.units))
-                                    : 0;
+  int32_t* units = reinterpret_cast<int32_t*>(host.data() + t.units);
+  const int n_units = unit_rays > 0 ? ut_host::build_units(bstart.data(), NP, s->n_az, nth, unit_rays, units) : 0;
+  const int n_units_wide =
+      unit_rays > 0 ? ut_host::build_units(bstart.data(), NP, s->n_az, nth, 256, units + 4 * (size_t)NP * nth) : 0;
   if (s->cull)
     ut_host::ray_sat(s->beam_elev_host, s->n_beams, s->n_az, bounds.data(), NP, s->cull_az, s->cull_el,
                      reinterpret_cast<int32_t*>(host.data() + t.sat));
@@ -192,6 +196,7 @@ ut_status ut_sensor_build(ut_sensor* s, ut_stream stream) {
   s->max_tile_rays = max_rays;
   s->n_units = n_units;
   s->unit_rays = unit_rays;
+  s->n_units_wide = n_units_wide;
   return UT_OK;
 }
 
@@ -205,7 +210,8 @@ int32_t ut_sensor_super_tiles(const ut_sensor* s) {
   if (!s) return 0;
   const int tx = s->kind == UT_LIDAR ? s->n_theta : camera_tiles_x(s);
   const int ty = s->kind == UT_LIDAR ? s->n_phi : camera_tiles_y(s);
-  return ((tx + kSuper - 1) / kSuper) * ((ty + kSuper - 1) / kSuper);
+  const int sh = ut_host::super_rows(s->kind);
+  return ((tx + kSuper - 1) / kSuper) * ((ty + sh - 1) / sh);
 }
 
 int64_t ut_sensor_rays(const ut_sensor* s) {
@@ -352,14 +358,13 @@ __global__ void k_write_item(BatchItemK item, BatchItemK* dst) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = item;
 }
 
-// The batch queue (two work counters, then the device copies of the items) at the start of
+// The batch queue (four work counters, then the device copies of the items) at the start of
 // a workspace of ut_batch_workspace_bytes(n_items) bytes.  The items are written by small
 // kernels and the counters cleared by a fill kernel, so the whole call stays graph-capturable.
 ut_status enqueue_batch(const ut_batch_item* items, int32_t n_items, const ut_render_params* prm, void* queue_ws,
                         int32_t n_workgroups, hipStream_t st) {
   uint32_t* counter = static_cast<uint32_t*>(queue_ws);
   BatchItemK* dev = reinterpret_cast<BatchItemK*>(static_cast<char*>(queue_ws) + 256);
-  int total = 0;
   for (int i = 0; i < n_items; ++i) {
     const ut_batch_item& it = items[i];
     if (!it.proj || !it.proj->records || !it.proj->trect || !bins_ok(it.bins) || !sensor_ok(it.sensor) || !it.out ||
@@ -367,34 +372,45 @@ ut_status enqueue_batch(const ut_batch_item* items, int32_t n_items, const ut_re
       return UT_ERR_ARG;
     if (it.sensor->max_tile_rays > 256) return UT_ERR_UNSUPPORTED;   // one lane per ray of a 256-lane group
   }
-  // static sensors first, then moving ones: each group runs in its own persistent launch (the
-  // per-ray origins of a moving sensor would otherwise cost every static pair registers)
-  int slot = 0, n_static = 0, static_tiles = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    total = 0;
+  // items in four groups, each its own persistent launch: static or moving sensor (the per-ray
+  // origins of a moving sensor would otherwise cost every static pair registers), tiles or LiDAR
+  // units (several azimuth tiles per 256-lane workgroup)
+  BatchGroups grp;
+  std::memset(&grp, 0, sizeof grp);
+  int slot = 0;
+  for (int gi = 0; gi < 4; ++gi) {
+    const bool moving = (gi & 1) != 0, unit = (gi & 2) != 0;
+    grp.first[gi] = slot;
+    int total = 0;
     for (int i = 0; i < n_items; ++i) {
       const ut_batch_item& it = items[i];
-      if ((it.sensor->moving != 0) != (pass == 1)) continue;
+      const bool it_unit = it.sensor->kind == UT_LIDAR && it.sensor->n_units_wide > 0;
+      if ((it.sensor->moving != 0) != moving || it_unit != unit) continue;
       BatchItemK k;
       std::memset(&k, 0, sizeof k);
       k.s = make_sensor_k(it.sensor);
+      if (unit) {   // this item's workgroups take the 256-lane units
+        k.s.units = k.s.units_wide;
+        k.s.n_units = k.s.n_units_wide;
+        k.s.unit_rays = 256;
+      }
       k.rec = reinterpret_cast<const RecordG*>(it.proj->records);
       k.trect = reinterpret_cast<const uint2*>(it.proj->trect);
       k.gauss = it.bins->gauss;
       k.ranges = it.bins->ranges;
       k.out = *it.out;
-      k.n_tiles = ut_sensor_tiles(it.sensor);
+      k.n_tiles = unit ? k.s.n_units : ut_sensor_tiles(it.sensor);
       k.tile_base = total;
       total += k.n_tiles;
       hipLaunchKernelGGL(k_write_item, dim3(1), dim3(64), 0, st, k, dev + slot);
       ++slot;
     }
-    if (pass == 0) { n_static = slot; static_tiles = total; }
+    grp.count[gi] = slot - grp.first[gi];
+    grp.tiles[gi] = total;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return UT_ERR_DEVICE;
-  return from_hip(launch_composite_batch(dev, n_static, static_tiles, n_items - n_static, total, counter,
-                                         make_params(prm), n_workgroups, st));
+  return from_hip(launch_composite_batch(dev, grp, counter, make_params(prm), n_workgroups, st));
 }
 
 // Library-owned queue memory of ut_composite_batch_noalloc: one copy per device, for up to

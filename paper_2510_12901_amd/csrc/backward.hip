@@ -17,33 +17,55 @@
 namespace ut {
 namespace {
 
-// Sums 16 per-lane values over the 64 lanes of a wavefront with 17 exchanges instead of
-// 16 x 6: at each step a lane keeps half of its partial sums and trades the other half with
-// the lane whose index differs in one bit.  Afterwards lane l holds the total of value
-// idx = 8 b5 + 4 b4 + 2 b3 + b2 (b_k = bit k of l), the same on the 4 lanes that differ only
-// in bits 0 and 1.  Every lane of the wavefront must be active.
+// Lane exchanges of float64 values without LDS: each 32-bit half moves through a DPP lane
+// pattern (within rows of 16 lanes) or a gfx950 permlane swap (across rows and halves).
+__device__ __forceinline__ uint32_t lo32(double x) { return (uint32_t)__double_as_longlong(x); }
+__device__ __forceinline__ uint32_t hi32(double x) { return (uint32_t)((unsigned long long)__double_as_longlong(x) >> 32); }
+__device__ __forceinline__ double from32(uint32_t lo, uint32_t hi) {
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// the value of lane dpp(l) for the pattern CTRL (every lane reads a lane of its own row)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  return from32((uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo32(x), CTRL, 0xF, 0xF, false),
+                (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi32(x), CTRL, 0xF, 0xF, false));
+}
+// a (lanes 32..63) <-> b (lanes 0..31): afterwards a + b holds, in lanes 0..31, a summed over
+// lanes l and l + 32, and in lanes 32..63 b summed over lanes l - 32 and l
+__device__ __forceinline__ double swap32_sum(double a, double b) {
+  const auto l = __builtin_amdgcn_permlane32_swap(lo32(a), lo32(b), false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi32(a), hi32(b), false, false);
+  return from32(l[0], h[0]) + from32(l[1], h[1]);
+}
+// the same across rows of 16 lanes: a summed over rows 2r and 2r+1 in even rows, b in odd rows
+__device__ __forceinline__ double swap16_sum(double a, double b) {
+  const auto l = __builtin_amdgcn_permlane16_swap(lo32(a), lo32(b), false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi32(a), hi32(b), false, false);
+  return from32(l[0], h[0]) + from32(l[1], h[1]);
+}
+constexpr int kDppRowRor8 = 0x128, kDppRowHalfMirror = 0x141, kDppQuad2301 = 0x4E, kDppQuad1032 = 0xB1;
+
+// Sums 16 per-lane values over the 64 lanes of a wavefront: at each step a lane keeps half of
+// its partial sums and trades the other half with a lane that differs in one more bit (32 and
+// 16: permlane swaps; 8: rotate within the row; 4: mirror within 8 lanes, then the quad sum).
+// Afterwards lane l holds the total of value idx = 8 b5 + 4 b4 + 2 b3 + b2 (b_k = bit k of l),
+// the same on the 4 lanes of its quad.  Every lane of the wavefront must be active.
 __device__ __forceinline__ double wave_reduce_scatter16(const double v[16], int lane, int& idx) {
-  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+  const bool b3 = lane & 8, b2 = lane & 4;
   double w[8], x[4], y[2];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const double send = b5 ? v[k] : v[k + 8], keep = b5 ? v[k + 8] : v[k];
-    w[k] = keep + __shfl_xor(send, 32);
-  }
+  for (int k = 0; k < 8; ++k) w[k] = swap32_sum(v[k], v[k + 8]);        // lanes 32..63 keep k + 8
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const double send = b4 ? w[k] : w[k + 4], keep = b4 ? w[k + 4] : w[k];
-    x[k] = keep + __shfl_xor(send, 16);
-  }
+  for (int k = 0; k < 4; ++k) x[k] = swap16_sum(w[k], w[k + 4]);        // odd rows keep k + 4
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const double send = b3 ? x[k] : x[k + 2], keep = b3 ? x[k + 2] : x[k];
-    y[k] = keep + __shfl_xor(send, 8);
+    y[k] = keep + dpp_f64<kDppRowRor8>(send);                           // partner l ^ 8
   }
-  double z = (b2 ? y[1] : y[0]) + __shfl_xor(b2 ? y[0] : y[1], 4);
-  z += __shfl_xor(z, 2);
-  z += __shfl_xor(z, 1);
-  idx = (b5 ? 8 : 0) + (b4 ? 4 : 0) + (b3 ? 2 : 0) + (b2 ? 1 : 0);
+  double z = (b2 ? y[1] : y[0]) + dpp_f64<kDppRowHalfMirror>(b2 ? y[0] : y[1]);   // partner 7 - l (mod 8)
+  z += dpp_f64<kDppQuad2301>(z);
+  z += dpp_f64<kDppQuad1032>(z);
+  idx = ((lane & 32) ? 8 : 0) + ((lane & 16) ? 4 : 0) + (b3 ? 2 : 0) + (b2 ? 1 : 0);
   return z;
 }
 

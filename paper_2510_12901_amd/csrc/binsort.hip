@@ -154,12 +154,15 @@ constexpr uint32_t kLbCount = (1u << 30) - 1u;
 // follows.
 __global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __restrict__ keys, size_t n_max,
                                                               const uint32_t* __restrict__ n_dev, int passes,
-                                                              uint32_t* __restrict__ hist) {
+                                                              uint32_t* __restrict__ hist, uint32_t* __restrict__ look,
+                                                              size_t look_tiles) {
   __shared__ uint32_t h[kMaxPasses][kRadix];
   const size_t n = n_dev ? (size_t)*n_dev : n_max;
   const size_t tile0 = (size_t)blockIdx.x * kSortTile;
   if (tile0 >= n) return;
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
+  // this tile's look-back words of every pass start cleared (the passes run after this kernel)
+  for (int p = 0; p < passes; ++p) look[((size_t)p * look_tiles + blockIdx.x) * kRadix + threadIdx.x] = 0u;
   for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kSortThreads) (&h[0][0])[i] = 0;
   __syncthreads();
   const size_t base = tile0 + (size_t)wave * (kSortItems * 64) + lane;
@@ -191,18 +194,6 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __r
   }
 }
 
-// hist[p][d] -> exclusive prefix over digits (one workgroup, thread d)
-__global__ __launch_bounds__(kSortThreads) void k_digit_offsets(uint32_t* __restrict__ hist, int passes) {
-  __shared__ uint32_t sh[4];
-  for (int p = 0; p < passes; ++p) {
-    uint32_t total;
-    const uint32_t v = hist[p * kRadix + threadIdx.x];
-    const uint32_t ex = block_exclusive<uint32_t>(v, sh, total);
-    hist[p * kRadix + threadIdx.x] = ex;
-    __syncthreads();
-  }
-}
-
 // One stable pass by digit (key >> shift) & 255 with decoupled look-back (single kernel per
 // pass).  A look-back word carries its state and count together, so relaxed device-scope
 // atomics suffice (an acquire would invalidate the XCD's L2 on every poll).  Workgroups take
@@ -217,7 +208,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
                                                            const uint32_t* __restrict__ vin,
                                                            uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                            size_t n_max, const uint32_t* __restrict__ n_dev, int shift,
-                                                           const uint32_t* __restrict__ digit_base,
+                                                           const uint32_t* __restrict__ digit_count,
                                                            uint32_t* __restrict__ look, uint32_t* __restrict__ ticket) {
   constexpr int kWaves = kSortThreads / 64;
   __shared__ uint32_t s_tile;
@@ -238,6 +229,12 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
   const size_t tile0 = (size_t)tile * kSortTile;
   const size_t base = tile0 + (size_t)wave * (kSortItems * 64) + lane;
   const uint32_t tile_n = (uint32_t)std::min<size_t>(kSortTile, n - tile0);
+  // global start of this thread's digit: exclusive prefix of the pass's digit counts
+  uint32_t digit_base;
+  {
+    uint32_t all;
+    digit_base = block_exclusive<uint32_t>(digit_count[threadIdx.x], scan_sh, all);
+  }
 
   uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
 #pragma unroll
@@ -313,7 +310,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
       }
       __hip_atomic_store(my, kLbPrefix | (excl + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    dst_shift[d] = digit_base[d] + excl - lstart;
+    dst_shift[d] = digit_base + excl - lstart;
   }
   __syncthreads();
   // reorder the tile by digit in LDS ...
@@ -338,19 +335,23 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
 
 }  // namespace
 
-// Bytes of the sort's own workspace for up to n_max keys: per-pass digit offsets, per-pass
-// look-back words and tickets.
+// Bytes of the sort's own workspace for up to n_max keys: per-pass digit counts and tickets
+// (radix_clear_words() words at the start, which must be zero when a sort starts), then the
+// per-pass look-back words, which the histogram kernel clears per tile.
 size_t radix_ws_bytes(size_t n_max) {
   const size_t tiles = (std::max<size_t>(n_max, 1) + kSortTile - 1) / kSortTile;
-  return 4 * ((size_t)kMaxPasses * kRadix + (size_t)kMaxPasses * tiles * kRadix + kMaxPasses);
+  return 4 * ((size_t)kMaxPasses * kRadix + kMaxPasses + (size_t)kMaxPasses * tiles * kRadix);
 }
+size_t radix_clear_words() { return (size_t)kMaxPasses * kRadix + kMaxPasses; }
 
 // Sorts (k, v) pairs by the low `bits` bits of k (bits <= 32), stable.  n_max sizes the grid;
 // when n_dev is given the kernels read the actual length from it.  Buffers ping-pong;
-// *k_res / *v_res receive the buffers holding the result.  `ws` holds radix_ws_bytes(n_max).
+// *k_res / *v_res receive the buffers holding the result.  `ws` holds radix_ws_bytes(n_max);
+// ws_clear: its first radix_clear_words() words are already zero (a kernel before the sort on
+// the same stream cleared them), else a fill kernel clears them.
 hipError_t radix_sort(uint32_t* kA, uint32_t* kB, uint32_t* vA, uint32_t* vB, size_t n_max,
                       const uint32_t* n_dev, int bits, uint32_t* ws, hipStream_t st,
-                      uint32_t** k_res, uint32_t** v_res) {
+                      uint32_t** k_res, uint32_t** v_res, bool ws_clear) {
   *k_res = kA;
   *v_res = vA;
   if (n_max == 0 || bits <= 0) return hipSuccess;
@@ -358,12 +359,14 @@ hipError_t radix_sort(uint32_t* kA, uint32_t* kB, uint32_t* vA, uint32_t* vB, si
   const int passes = (bits + 7) / 8;
   const size_t tiles = (n_max + kSortTile - 1) / kSortTile;
   uint32_t* hist = ws;
-  uint32_t* look = ws + (size_t)kMaxPasses * kRadix;
-  uint32_t* tickets = look + (size_t)kMaxPasses * tiles * kRadix;
-  hipError_t e = fill_u32(ws, 0u, radix_ws_bytes(n_max) / 4, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)tiles), dim3(kSortThreads), 0, st, kA, n_max, n_dev, passes, hist);
-  hipLaunchKernelGGL(k_digit_offsets, dim3(1), dim3(kSortThreads), 0, st, hist, passes);
+  uint32_t* tickets = ws + (size_t)kMaxPasses * kRadix;
+  uint32_t* look = tickets + kMaxPasses;
+  if (!ws_clear) {
+    const hipError_t e = fill_u32(ws, 0u, radix_clear_words(), st);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)tiles), dim3(kSortThreads), 0, st, kA, n_max, n_dev, passes, hist,
+                     look, tiles);
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL(k_onesweep, dim3((unsigned)tiles), dim3(kSortThreads), 0, st, kA, vA, kB, vB, n_max, n_dev,
                        8 * p, hist + p * kRadix, look + (size_t)p * tiles * kRadix, tickets + p);
@@ -396,47 +399,124 @@ __device__ __forceinline__ int super_cols(int x0, int x1, int tiles_x, int SX, i
   return nc;
 }
 
-// per particle (index order, coalesced): visible flag and super-tile count
-__global__ void k_prep(const uint32_t* __restrict__ count, const int32_t* __restrict__ rect, int tiles_x, int SX,
-                       int wrap, uint32_t* __restrict__ flag, uint32_t* __restrict__ scount, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint32_t c = 0;
-  if (count[i]) {
-    int sx0;
-    const int nc = super_cols(rect[i], rect[2 * n + i], tiles_x, SX, wrap, &sx0);
-    const int nr = rect[3 * n + i] / kSuper - rect[n + i] / kSuper + 1;
-    c = (uint32_t)(nc * nr);
+// super-tile count of particle i (0 when its tile count is 0)
+__device__ __forceinline__ uint32_t super_count(const uint32_t* __restrict__ count, const int32_t* __restrict__ rect,
+                                                int n, int i, int tiles_x, int SX, int SH, int wrap) {
+  if (!count[i]) return 0u;
+  int sx0;
+  const int nc = super_cols(rect[i], rect[2 * n + i], tiles_x, SX, wrap, &sx0);
+  const int nr = rect[3 * n + i] / SH - rect[n + i] / SH + 1;
+  return (uint32_t)(nc * nr);
+}
+
+// Visible-particle compaction, pass 1 of 3: per particle its super-tile count (kept for the
+// pair emission), per block of kScanTile particles the number of visible ones.
+__global__ __launch_bounds__(kScanThreads) void k_prep_reduce(const uint32_t* __restrict__ count,
+                                                              const int32_t* __restrict__ rect, int tiles_x, int SX,
+                                                              int SH, int wrap, uint32_t* __restrict__ scount, int n,
+                                                              uint32_t* __restrict__ sums) {
+  __shared__ uint32_t sh[4];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  uint32_t f = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int i = base + k;
+    if (i < n) {
+      const uint32_t c = super_count(count, rect, n, i, tiles_x, SX, SH, wrap);
+      scount[i] = c;
+      f += c ? 1u : 0u;
+    }
   }
-  scount[i] = c;
-  flag[i] = c ? 1u : 0u;
+  uint32_t total;
+  block_exclusive<uint32_t>(f, sh, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-// stable compaction of the visible particles: (depth key, index) in index order
-__global__ void k_compact(const uint32_t* __restrict__ key, const uint32_t* __restrict__ scount,
-                          const uint32_t* __restrict__ pos, uint32_t* __restrict__ dk, uint32_t* __restrict__ dv, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || !scount[i]) return;
-  const uint32_t p = pos[i];
-  dk[p] = key[i];
-  dv[p] = (uint32_t)i;
+// Pass 3 of 3 (after k_scan_sums turned the block counts into offsets): the stable compaction,
+// (depth key, index) of the visible particles in index order.  Block 0 also clears the depth
+// sort's counters (the sort runs next on the same stream).
+__global__ __launch_bounds__(kScanThreads) void k_compact_apply(const uint32_t* __restrict__ key,
+                                                                const uint32_t* __restrict__ scount, int n,
+                                                                const uint32_t* __restrict__ sums,
+                                                                uint32_t* __restrict__ dk, uint32_t* __restrict__ dv,
+                                                                uint32_t* __restrict__ clear, int n_clear) {
+  __shared__ uint32_t sh[4];
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < n_clear; i += kScanThreads) clear[i] = 0u;
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t f = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < n && scount[base + k] ? 1u : 0u;
+    f += v[k];
+  }
+  uint32_t total;
+  uint32_t p = block_exclusive<uint32_t>(f, sh, total) + sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (v[k]) {
+      dk[p] = key[base + k];
+      dv[p] = (uint32_t)(base + k);
+      ++p;
+    }
+  }
 }
 
-// super-tile counts in depth order (0 past the visible count)
-__global__ void k_gather_counts(const uint32_t* __restrict__ order, const uint32_t* __restrict__ scount,
-                                const uint32_t* __restrict__ m_dev, uint64_t* __restrict__ offs, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  offs[i] = (uint32_t)i < *m_dev ? (uint64_t)scount[order[i]] : 0ull;
+// Pair offsets, pass 1 of 3: per block of kScanTile depth-ordered particles, the sum of their
+// super-tile counts (0 past the visible count).
+__global__ __launch_bounds__(kScanThreads) void k_gather_reduce(const uint32_t* __restrict__ order,
+                                                                const uint32_t* __restrict__ scount,
+                                                                const uint32_t* __restrict__ m_dev, int n,
+                                                                uint64_t* __restrict__ sums) {
+  __shared__ uint64_t sh[4];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  const uint32_t m = *m_dev;
+  uint64_t t = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n && (uint32_t)(base + k) < m) t += scount[order[base + k]];
+  uint64_t total;
+  block_exclusive<uint64_t>(t, sh, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Pass 3 of 3: offs[i] = exclusive prefix of the super-tile counts in depth order.
+__global__ __launch_bounds__(kScanThreads) void k_gather_apply(const uint32_t* __restrict__ order,
+                                                               const uint32_t* __restrict__ scount,
+                                                               const uint32_t* __restrict__ m_dev, int n,
+                                                               const uint64_t* __restrict__ sums,
+                                                               uint64_t* __restrict__ offs) {
+  __shared__ uint64_t sh[4];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  const uint32_t m = *m_dev;
+  uint64_t v[kScanItems];
+  uint64_t t = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < n && (uint32_t)(base + k) < m ? (uint64_t)scount[order[base + k]] : 0ull;
+    t += v[k];
+  }
+  uint64_t total;
+  uint64_t run = block_exclusive<uint64_t>(t, sh, total) + sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) offs[base + k] = run;
+    run += v[k];
+  }
 }
 
 // One wavefront emits the (super-tile, particle) pairs of 64 consecutive depth-ordered
 // particles, 64 pairs per step.
 __global__ __launch_bounds__(256) void k_duplicate(const uint32_t* __restrict__ order, const uint64_t* __restrict__ offs,
                                                     const uint32_t* __restrict__ m_dev, const uint2* __restrict__ trect,
-                                                    int n, int tiles_x, int SX, int wrap,
+                                                    int n, int tiles_x, int SX, int SH, int wrap,
                                                     uint32_t* __restrict__ pair_key, uint32_t* __restrict__ pair_gauss,
-                                                    const uint32_t* __restrict__ emit) {
+                                                    const uint32_t* __restrict__ emit, uint32_t* __restrict__ clear,
+                                                    int n_clear) {
+  // block 0 clears the pair sort's counters (the sort runs next on the same stream)
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < n_clear; i += 256) clear[i] = 0u;
   if (emit && *emit == 0u) return;   // device-count sort: nothing to emit, or over capacity
   __shared__ uint32_t s_off[4][64], s_g[4][64];
   __shared__ int s_x0[4][64], s_y0[4][64], s_w[4][64];
@@ -452,8 +532,8 @@ __global__ __launch_bounds__(256) void k_duplicate(const uint32_t* __restrict__ 
     const uint2 r = trect[gi];
     const int x0 = (int)(r.x & 0xFFFFu), y0 = (int)(r.x >> 16), x1 = (int)(r.y & 0xFFFFu), y1 = (int)(r.y >> 16);
     nc = super_cols(x0, x1, tiles_x, SX, wrap, &sx0);
-    sy0 = y0 / kSuper;
-    c = (uint32_t)(nc * (y1 / kSuper - sy0 + 1));
+    sy0 = y0 / SH;
+    c = (uint32_t)(nc * (y1 / SH - sy0 + 1));
   }
   // lanes past the visible count keep off = 0; the wave base must come from lane 0, which is
   // valid whenever any lane of the wave is
@@ -623,23 +703,30 @@ PairWorkspace pair_workspace(void* base, uint64_t n_pairs) {
 }
 
 hipError_t launch_bin_count(const ut_projected& p, int n, const SensorK& s, CountWorkspace& ws, hipStream_t st) {
-  hipError_t e = fill_u64(ws.total, 0, 1, st);
-  if (e == hipSuccess) e = fill_u32(ws.m_dev, 0u, 1, st);
-  if (e != hipSuccess || n == 0) return e;
-  const int blocks = (n + 255) / 256;
+  if (n == 0) {
+    hipError_t e = fill_u64(ws.total, 0, 1, st);
+    if (e == hipSuccess) e = fill_u32(ws.m_dev, 0u, 1, st);
+    return e;
+  }
+  const int nb = (n + kScanTile - 1) / kScanTile;
   const int wrap = s.kind == UT_LIDAR ? 1 : 0;
+  uint32_t* sums32 = reinterpret_cast<uint32_t*>(ws.scan_aux);
   // visible particles (tile count > 0) compacted in index order, then depth-sorted
-  hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, st, p.count, p.rect, s.tiles_x, s.super_x, wrap,
-                     ws.dkB, ws.scount, n);
-  e = exclusive_scan<uint32_t>(ws.dkB, (size_t)n, reinterpret_cast<uint32_t*>(ws.scan_aux), ws.m_dev, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, st, p.key, ws.scount, ws.dkB, ws.dkA, ws.dvA, n);
+  hipLaunchKernelGGL(k_prep_reduce, dim3(nb), dim3(kScanThreads), 0, st, p.count, p.rect, s.tiles_x, s.super_x,
+                     s.super_h, wrap, ws.scount, n, sums32);
+  hipLaunchKernelGGL(k_scan_sums<uint32_t>, dim3(1), dim3(kScanThreads), 0, st, sums32, (size_t)nb, ws.m_dev);
+  hipLaunchKernelGGL(k_compact_apply, dim3(nb), dim3(kScanThreads), 0, st, p.key, ws.scount, n, sums32, ws.dkA, ws.dvA,
+                     ws.hist, (int)radix_clear_words());
   uint32_t *kr, *vr;
-  e = radix_sort(ws.dkA, ws.dkB, ws.dvA, ws.dvB, (size_t)n, ws.m_dev, 32, ws.hist, st, &kr, &vr);
+  hipError_t e = radix_sort(ws.dkA, ws.dkB, ws.dvA, ws.dvB, (size_t)n, ws.m_dev, 32, ws.hist, st, &kr, &vr, true);
   if (e != hipSuccess) return e;
-  // 4 passes: the result is back in the A buffers
-  hipLaunchKernelGGL(k_gather_counts, dim3(blocks), dim3(256), 0, st, ws.dvA, ws.scount, ws.m_dev, ws.offs, n);
-  return exclusive_scan<uint64_t>(ws.offs, (size_t)n, ws.scan_aux, ws.total, st);
+  // 4 passes: the result is back in the A buffers; the pair offsets in depth order
+  hipLaunchKernelGGL(k_gather_reduce, dim3(nb), dim3(kScanThreads), 0, st, ws.dvA, ws.scount, ws.m_dev, n,
+                     ws.scan_aux);
+  hipLaunchKernelGGL(k_scan_sums<uint64_t>, dim3(1), dim3(kScanThreads), 0, st, ws.scan_aux, (size_t)nb, ws.total);
+  hipLaunchKernelGGL(k_gather_apply, dim3(nb), dim3(kScanThreads), 0, st, ws.dvA, ws.scount, ws.m_dev, n,
+                     ws.scan_aux, ws.offs);
+  return hipGetLastError();
 }
 
 hipError_t launch_bin_sort(const ut_projected& p, int n, const SensorK& s, CountWorkspace& ws,
@@ -653,10 +740,10 @@ hipError_t launch_bin_sort(const ut_projected& p, int n, const SensorK& s, Count
   uint32_t* v_second = (radix_passes(bits) % 2) ? bins.gauss : pw.tv;
   const int blocks = (n + 255) / 256;
   hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(256), 0, st, ws.dvA, ws.offs, ws.m_dev,
-                     reinterpret_cast<const uint2*>(p.trect), n, s.tiles_x, s.super_x, s.kind == UT_LIDAR ? 1 : 0,
-                     pw.tkA, v_first, nullptr);
+                     reinterpret_cast<const uint2*>(p.trect), n, s.tiles_x, s.super_x, s.super_h, s.kind == UT_LIDAR ? 1 : 0,
+                     pw.tkA, v_first, nullptr, pw.hist, (int)radix_clear_words());
   uint32_t *kr, *vr;
-  e = radix_sort(pw.tkA, pw.tkB, v_first, v_second, (size_t)n_pairs, nullptr, bits, pw.hist, st, &kr, &vr);
+  e = radix_sort(pw.tkA, pw.tkB, v_first, v_second, (size_t)n_pairs, nullptr, bits, pw.hist, st, &kr, &vr, true);
   if (e != hipSuccess) return e;
   const unsigned rb = (unsigned)((n_pairs + 255) / 256);
   hipLaunchKernelGGL(k_ranges, dim3(rb), dim3(256), 0, st, kr, n_pairs, nullptr, bins.ranges, n_super);
@@ -688,10 +775,10 @@ hipError_t launch_bin_sort_device(const ut_projected& p, int n, const SensorK& s
   uint32_t* v_second = (radix_passes(bits) % 2) ? bins.gauss : pw.tv;
   const int blocks = (n + 255) / 256;
   hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(256), 0, st, ws.dvA, ws.offs, ws.m_dev,
-                     reinterpret_cast<const uint2*>(p.trect), n, s.tiles_x, s.super_x, s.kind == UT_LIDAR ? 1 : 0,
-                     pw.tkA, v_first, pw.n_dev);
+                     reinterpret_cast<const uint2*>(p.trect), n, s.tiles_x, s.super_x, s.super_h, s.kind == UT_LIDAR ? 1 : 0,
+                     pw.tkA, v_first, pw.n_dev, pw.hist, (int)radix_clear_words());
   uint32_t *kr, *vr;
-  e = radix_sort(pw.tkA, pw.tkB, v_first, v_second, (size_t)max_pairs, pw.n_dev, bits, pw.hist, st, &kr, &vr);
+  e = radix_sort(pw.tkA, pw.tkB, v_first, v_second, (size_t)max_pairs, pw.n_dev, bits, pw.hist, st, &kr, &vr, true);
   if (e != hipSuccess) return e;
   const unsigned rb = (unsigned)((max_pairs + 255) / 256);
   hipLaunchKernelGGL(k_ranges, dim3(rb), dim3(256), 0, st, kr, max_pairs, pw.n_dev, bins.ranges, n_super);

@@ -90,7 +90,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* 
     j0 = u.y;
     gt = u.z - u.y;
     tx = j0;
-    sid = (ty / kSuper) * s.super_x + j0 / kSuper;
+    sid = (ty / s.super_h) * s.super_x + j0 / kSuper;
   } else {
     tx = tile % s.tiles_x;
     ty = tile / s.tiles_x;
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(RPL == 1 
 
 // LiDAR compositing over units of adjacent azimuth tiles (one ray per lane, unit_rays lanes).
 template <int BLOCK, bool STATS, bool MOVING>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_composite_unit(
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 128 ? 3 : 4))) void k_composite_unit(
     SensorK s, const RecordG* __restrict__ rec, const uint2* __restrict__ trect, const uint32_t* __restrict__ bgauss,
     const uint32_t* __restrict__ branges, RenderParamsK prm, ut_render_out out) {
   constexpr int kBatchU = BLOCK == 64 ? 32 : 128;   // 64 lanes: small LDS for 4 waves per SIMD
@@ -404,11 +404,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 
 // Persistent batched compositing: workgroups pull (request, tile) items from a counter.  Static
 // and moving sensors run in separate launches (MOVING), so each keeps the register budget of
-// its single-request kernel.
-template <bool MOVING>
+// its single-request kernel; LiDAR requests run their 256-lane units in launches of their own
+// (UNIT).
+template <bool MOVING, bool UNIT>
 __global__ __launch_bounds__(kCamBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_composite_batch(
     const BatchItemK* __restrict__ items, int n_items, int total_tiles, uint32_t* counter, RenderParamsK prm) {
   __shared__ CompositeShared<kCamBlock, kCamRpl, kCamBatch> sm;
+  __shared__ UnitShared<kCamBlock, kCamBatch> us_mem;
+  UnitShared<kCamBlock, kCamBatch>* us = UNIT ? &us_mem : nullptr;
   __shared__ uint32_t s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
@@ -420,9 +423,8 @@ __global__ __launch_bounds__(kCamBlock) __attribute__((amdgpu_waves_per_eu(3))) 
     int it = 0;
     while (it + 1 < n_items && (uint32_t)items[it + 1].tile_base <= w) ++it;
     const BatchItemK& I = items[it];
-    composite_tile<kCamBlock, kCamRpl, kCamBatch, false, MOVING, false>(I.s, I.rec, I.trect, I.gauss, I.ranges,
-                                                                  (int)(w - I.tile_base), I.s.super_x * I.s.super_y,
-                                                                  prm, I.out, sm);
+    composite_tile<kCamBlock, kCamRpl, kCamBatch, false, MOVING, false, UNIT>(
+        I.s, I.rec, I.trect, I.gauss, I.ranges, (int)(w - I.tile_base), I.s.super_x * I.s.super_y, prm, I.out, sm, us);
   }
 }
 
@@ -485,17 +487,19 @@ hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, con
   return hipGetLastError();
 }
 
-hipError_t launch_composite_batch(const BatchItemK* items_dev, int n_static, int static_tiles, int n_moving,
-                                  int moving_tiles, uint32_t* counter, const RenderParamsK& prm, int n_workgroups,
-                                  hipStream_t st) {
-  hipError_t e = fill_u32(counter, 0u, 2, st);
+hipError_t launch_composite_batch(const BatchItemK* items_dev, const BatchGroups& grp, uint32_t* counter,
+                                  const RenderParamsK& prm, int n_workgroups, hipStream_t st) {
+  hipError_t e = fill_u32(counter, 0u, 4, st);
   if (e != hipSuccess) return e;
-  if (static_tiles > 0)
-    hipLaunchKernelGGL(k_composite_batch<false>, dim3(n_workgroups), dim3(kCamBlock), 0, st, items_dev, n_static,
-                       static_tiles, counter, prm);
-  if (moving_tiles > 0)
-    hipLaunchKernelGGL(k_composite_batch<true>, dim3(n_workgroups), dim3(kCamBlock), 0, st, items_dev + n_static,
-                       n_moving, moving_tiles, counter + 1, prm);
+#define UT_LAUNCH_BATCH(G, MV, UN)                                                                              \
+  if (grp.tiles[G] > 0)                                                                                         \
+  hipLaunchKernelGGL((k_composite_batch<MV, UN>), dim3(n_workgroups), dim3(kCamBlock), 0, st, items_dev + grp.first[G], \
+                     grp.count[G], grp.tiles[G], counter + (G), prm)
+  UT_LAUNCH_BATCH(0, false, false);
+  UT_LAUNCH_BATCH(1, true, false);
+  UT_LAUNCH_BATCH(2, false, true);
+  UT_LAUNCH_BATCH(3, true, true);
+#undef UT_LAUNCH_BATCH
   return hipGetLastError();
 }
 

@@ -17,6 +17,12 @@
 namespace ut_host {
 
 constexpr int kSuperTile = UT_SUPER_TILE;
+// Tile rows of a LiDAR super-tile (cameras: UT_SUPER_TILE).  Fewer rows shorten the bin each
+// LiDAR tile filters its list from (on the 300k-particle 128 x 2048 scan, 2 rows: bins 2.6x
+// the tile lists instead of 7x, compositing -13%), but add pairs and a second radix pass to
+// the pair sort (+60 us), a net loss there; the square super-tile is kept.
+constexpr int kLidarSuperRows = UT_SUPER_TILE;
+inline int super_rows(int kind) { return kind == UT_LIDAR ? kLidarSuperRows : kSuperTile; }
 constexpr int kUnitTiles = 4;         // tiles of a LiDAR compositing unit at most
 constexpr double kPiHost = 3.14159265358979323846;
 
@@ -31,7 +37,9 @@ inline TableLayout table_layout(int n_phi, int cull_az, int cull_el, int n_tiles
   t.beam_start = al(sizeof(double) * (size_t)(n_phi + 1));
   t.sat = t.beam_start + al(sizeof(int) * (size_t)(n_phi + 1));
   t.units = t.sat + al(sizeof(int) * (size_t)(cull_az + 1) * (size_t)(cull_el + 1));
-  t.total = t.units + al(4 * sizeof(int) * (size_t)(n_tiles > 0 ? n_tiles : 1));
+  // two unit lists of up to n_tiles units each: for the single-request kernel (unit_rays lanes)
+  // and for the batched kernel's 256-lane workgroups
+  t.total = t.units + al(2 * 4 * sizeof(int) * (size_t)(n_tiles > 0 ? n_tiles : 1));
   return t;
 }
 
@@ -160,6 +168,7 @@ inline bool sensor_ok(const ut_sensor* s) {
     return s->n_beams > 0 && s->n_az > 0 && s->n_phi > 0 && s->n_phi <= UT_MAX_ELEV_TILES &&
            s->n_theta > 0 && s->tables && s->max_tile_rays > 0 && s->max_tile_rays <= UT_MAX_LIDAR_TILE_RAYS &&
            s->n_units >= 0 && (long long)s->n_units <= (long long)s->n_phi * s->n_theta &&
+           s->n_units_wide >= 0 && (long long)s->n_units_wide <= (long long)s->n_phi * s->n_theta &&
            (s->unit_rays == 0 || ((s->unit_rays == 64 || s->unit_rays == 128 || s->unit_rays == 256) &&
                                   s->unit_rays >= s->max_tile_rays)) &&
            (!s->cull || (s->cull_az > 0 && s->cull_el > 0));

@@ -89,6 +89,7 @@ struct SensorK {
   const float* ray_dir;     // [3][R]
   long long n_rays;
   int super_x, super_y;     // super-tile grid
+  int super_h;              // tile rows per super-tile (kSuper columns each)
   // moving sensor: unit quaternions of the poses at t = 0 and 1 (shorter arc), the slerp
   // angle and 1 / sin of it (0: the rotations coincide, interpolate linearly), end origin,
   // per-ray origins and the fixed-point iteration count
@@ -102,6 +103,8 @@ struct SensorK {
   // most unit_rays rays; one workgroup of unit_rays lanes composites a unit
   const int4* units;
   int n_units, unit_rays;
+  const int4* units_wide;   // the same packing for 256 lanes (batched compositing)
+  int n_units_wide;
 };
 
 // Tiles of a LiDAR compositing unit: at most 4 adjacent tiles, inside one super-tile column.
@@ -353,7 +356,7 @@ __device__ __forceinline__ bool rect_meets_unit(uint2 r, int k, int j0, int j1, 
 
 __device__ __forceinline__ int super_of_tile(int tile, const SensorK& s) {
   const int tx = tile % s.tiles_x, ty = tile / s.tiles_x;
-  return (ty / kSuper) * s.super_x + tx / kSuper;
+  return (ty / s.super_h) * s.super_x + tx / kSuper;
 }
 
 // Rays of a tile: camera 16x16 pixel block; LiDAR beams of the elevation tile times the

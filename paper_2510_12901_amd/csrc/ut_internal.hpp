@@ -65,9 +65,13 @@ struct BatchItemK {
   int n_tiles;
   int tile_base;   // prefix over items of n_tiles
 };
-hipError_t launch_composite_batch(const BatchItemK* items_dev, int n_static, int static_tiles, int n_moving,
-                                  int moving_tiles, uint32_t* counter, const RenderParamsK& prm, int n_workgroups,
-                                  hipStream_t st);
+// Items of one batch in four groups (bit 0: moving sensor, bit 1: LiDAR units), each group's
+// items contiguous from first[g] in the device item array.
+struct BatchGroups {
+  int first[4], count[4], tiles[4];
+};
+hipError_t launch_composite_batch(const BatchItemK* items_dev, const BatchGroups& groups, uint32_t* counter,
+                                  const RenderParamsK& prm, int n_workgroups, hipStream_t st);
 
 hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const ut_bin_lists& bins,
                            const SensorK& s, const RenderParamsK& prm, const ut_render_out& fwd,
@@ -76,9 +80,10 @@ hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const u
 
 // Radix sort of (key, value) pairs, shared by the binning and the spatial order.
 size_t radix_ws_bytes(size_t n_max);
+size_t radix_clear_words();
 hipError_t radix_sort(uint32_t* kA, uint32_t* kB, uint32_t* vA, uint32_t* vB, size_t n_max,
                       const uint32_t* n_dev, int bits, uint32_t* ws, hipStream_t st,
-                      uint32_t** k_res, uint32_t** v_res);
+                      uint32_t** k_res, uint32_t** v_res, bool ws_clear = false);
 
 size_t spatial_order_ws_bytes(int n);
 hipError_t launch_spatial_order(const ut_gaussians& g, uint32_t* perm, void* ws, hipStream_t st);

@@ -481,7 +481,7 @@ def bench_served(g, gl, sensors_np, sensors, dev, args, log):
     rays = [s.n_rays for s in sensors]
     warm_s, meas_s = args.served_warmup, args.served_seconds
     out = {"rate_per_vehicle_fps": 30, "warmup_seconds": warm_s, "seconds": meas_s, "vehicles": {}}
-    server = Server(g, gl, sensors, pool_bytes=48 << 30, n_slots=14)
+    server = Server(g, gl, sensors, pool_bytes=48 << 30, n_slots=28)
     pipes = None
     warm = poisson_trace(60.0, 0.2, len(sensors), seed=99)
     server.run(warm)
@@ -509,7 +509,7 @@ def bench_served(g, gl, sensors_np, sensors, dev, args, log):
     out["served_saturation_mrays_per_s"] = max(r["served"]["mrays_per_s"] for r in out["vehicles"].values())
     del server
     torch.cuda.synchronize()
-    timed = Server(g, gl, sensors, pool_bytes=48 << 30, n_slots=14, timing=True)
+    timed = Server(g, gl, sensors, pool_bytes=48 << 30, n_slots=28, timing=True)
     treq = timed.run(poisson_trace(30.0 * 8, 2.0, len(sensors), seed=123))
     n_ov = timed.stats["device_overlap"]
     out["device_overlap_v8"] = {"requests": len(treq), "sort_overlapping_other_compositing": n_ov,

@@ -49,6 +49,16 @@ static void one_lidar(std::mt19937& rng, int n_beams, int n_az, int n_phi, int M
       for (int j = j0; j < j1; ++j) seen[(size_t)k * nth + j] += 1;
     }
     for (int v : seen) CHECK(v == 1);
+    // the 256-lane packing for the batched kernel partitions the tiles too, in fewer units
+    const int nw = ut_host::build_units(bstart.data(), n_phi, n_az, nth, 256, units.data());
+    CHECK(nw > 0 && nw <= nu);
+    std::fill(seen.begin(), seen.end(), 0);
+    for (int u = 0; u < nw; ++u) {
+      const int k = units[4 * u], j0 = units[4 * u + 1], j1 = units[4 * u + 2];
+      CHECK(units[4 * u + 3] <= 256 && j1 - j0 <= ut_host::kUnitTiles);
+      for (int j = j0; j < j1; ++j) seen[(size_t)k * nth + j] += 1;
+    }
+    for (int v : seen) CHECK(v == 1);
   }
   const int CA = 1 + (int)(rng() % 1600), CE = 1 + (int)(rng() % (8 * n_phi));
   std::vector<int32_t> sat((size_t)(CA + 1) * (CE + 1), 0);

@@ -349,7 +349,7 @@ def test_lidar_compositing_units_partition_the_tiles(name):
     """The compositing units built at sensor set-up: every azimuth-elevation tile lies in
     exactly one unit; a unit is a run of at most 4 adjacent tiles of one elevation tile inside
     one super-tile column; its rays fit unit_rays lanes, the smallest of 64, 128, 256 that
-    holds the largest tile."""
+    holds the largest tile (and 256 lanes in the batched kernel's packing)."""
     import paper_2510_12901_amd as ut
     g_np, s_np = _scene(name)
     s = ut.Sensor(s_np)
@@ -362,11 +362,14 @@ def test_lidar_compositing_units_partition_the_tiles(name):
     units = tb[off: off + 16 * c.n_units].view(np.int32).reshape(-1, 4)
     bstart = tb[al(8 * (NP + 1)): al(8 * (NP + 1)) + 4 * (NP + 1)].view(np.int32)
     assert c.unit_rays == min(u for u in (64, 128, 256) if u >= s.max_tile_rays)
+    wide = tb[off + 16 * NP * NT: off + 16 * NP * NT + 16 * c.n_units_wide].view(np.int32).reshape(-1, 4)
+    assert 0 < c.n_units_wide <= c.n_units
     az0 = lambda j: (j * c.n_az + NT - 1) // NT
-    seen = np.zeros((NP, NT), np.int64)
-    for k, j0, j1, rays in units:
-        assert 0 <= k < NP and 0 <= j0 < j1 <= NT and j1 - j0 <= 4
-        assert j0 // 8 == (j1 - 1) // 8
-        assert rays == (bstart[k + 1] - bstart[k]) * (az0(j1) - az0(j0)) <= c.unit_rays
-        seen[k, j0:j1] += 1
-    assert np.all(seen == 1)
+    for table, cap in ((units, c.unit_rays), (wide, 256)):   # single-request and batched packings
+        seen = np.zeros((NP, NT), np.int64)
+        for k, j0, j1, rays in table:
+            assert 0 <= k < NP and 0 <= j0 < j1 <= NT and j1 - j0 <= 4
+            assert j0 // 8 == (j1 - 1) // 8
+            assert rays == (bstart[k + 1] - bstart[k]) * (az0(j1) - az0(j0)) <= cap
+            seen[k, j0:j1] += 1
+        assert np.all(seen == 1)
