@@ -4,7 +4,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libutrast.so")
+# UTRAST_LIB: load another build of the library (the same ABI) instead of the in-tree one
+LIB_PATH = os.environ.get("UTRAST_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libutrast.so")
 
 P = C.c_void_p
 i32 = C.c_int32

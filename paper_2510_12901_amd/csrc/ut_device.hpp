@@ -243,7 +243,8 @@ __device__ __forceinline__ Centre pair_centre(const Rec& c, double ex, double ey
   return q;
 }
 
-__device__ __forceinline__ PairGeom pair_geometry(const Record& c, const Centre& v, const RayQ& d) {
+template <class Rec>
+__device__ __forceinline__ PairGeom pair_geometry(const Rec& c, const Centre& v, const RayQ& d) {
   PairGeom p;
   p.dbd = __builtin_fma(c.b[0], d.xx, __builtin_fma(c.b[3], d.yy, __builtin_fma(c.b[5], d.zz,
           __builtin_fma(c.b[1], d.xy, __builtin_fma(c.b[2], d.xz, c.b[4] * d.yz)))));
@@ -290,7 +291,8 @@ __device__ __forceinline__ bool record_thin(const Rec& c) { return c.vbv > kThin
 // compositing and the adjoint both evaluate pairs here, so their alphas are bit-identical.
 // Every active lane of a wavefront evaluates the same record, so the thin test is taken from
 // the first active lane as a scalar branch.
-__device__ __forceinline__ bool pair_eval(const Record& c, const Centre& cv, const RayQ& d, double ex, double ey,
+template <class Rec>
+__device__ __forceinline__ bool pair_eval(const Rec& c, const Centre& cv, const RayQ& d, double ex, double ey,
                                           double ez, double cut, PairResp& pr) {
   const PairGeom q = pair_geometry(c, cv, d);
   if (__builtin_expect(__builtin_amdgcn_readfirstlane((int)record_thin(c)), 0)) {
@@ -310,7 +312,8 @@ __device__ __forceinline__ bool pair_eval(const Record& c, const Centre& cv, con
 }
 
 // Unclamped opacity of the pair, sigma * exp(-D^2 / 2), evaluated as exp(ln sigma - D^2 / 2).
-__device__ __forceinline__ double pair_alpha(const Record& c, const PairResp& r, const double* tab) {
+template <class Rec>
+__device__ __forceinline__ double pair_alpha(const Rec& c, const PairResp& r, const double* tab) {
   return exp_neg(__builtin_fma(-0.5, r.D2, c.log_sigma), tab);
 }
 
