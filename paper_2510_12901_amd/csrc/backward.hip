@@ -453,14 +453,15 @@ hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const u
   const RecordG* rec = reinterpret_cast<const RecordG*>(p.records);
   const uint2* tr = reinterpret_cast<const uint2*>(p.trect);
   const int n_super = s.super_x * s.super_y;
+  const int grid = n_tiles;
   if (n_tiles > 0) {
 #define UT_LAUNCH_BACKWARD(B)                                                                              \
   do {                                                                                                     \
     if (s.moving)                                                                                          \
-      hipLaunchKernelGGL((k_backward<B, true>), dim3(n_tiles), dim3(B), 0, st, s, rec, tr, bins.gauss,     \
+      hipLaunchKernelGGL((k_backward<B, true>), dim3(grid), dim3(B), 0, st, s, rec, tr, bins.gauss,     \
                          bins.ranges, n_super, prm, fwd, up, acc, g.n);                             \
     else                                                                                                   \
-      hipLaunchKernelGGL((k_backward<B, false>), dim3(n_tiles), dim3(B), 0, st, s, rec, tr, bins.gauss,    \
+      hipLaunchKernelGGL((k_backward<B, false>), dim3(grid), dim3(B), 0, st, s, rec, tr, bins.gauss,    \
                          bins.ranges, n_super, prm, fwd, up, acc, g.n);                             \
   } while (0)
     if (s.kind != UT_LIDAR || max_tile_rays > 128)

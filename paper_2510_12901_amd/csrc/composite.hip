@@ -383,7 +383,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(RPL == 1 
                                                       const uint32_t* __restrict__ branges, int n_tiles,
                                                       RenderParamsK prm, ut_render_out out) {
   __shared__ CompositeShared<BLOCK, RPL, BATCH> sm;
-  const int tile = xcd_tile(blockIdx.x, n_tiles);
+  const int tile = xcd_super_tile(blockIdx.x, s);
   if (tile < 0) return;
   composite_tile<BLOCK, RPL, BATCH, STATS, MOVING>(s, rec, trect, bgauss, branges, tile, s.super_x * s.super_y, prm, out, sm);
 }
@@ -435,7 +435,7 @@ hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, con
                             hipStream_t st) {
   const int n_tiles = s.tiles_x * s.tiles_y;
   if (n_tiles == 0) return hipSuccess;
-  const int grid = 8 * ((n_tiles + 7) / 8);
+  const int grid = super_tile_slots(s.super_x, s.super_y, s.super_h);
   const RecordG* rec = reinterpret_cast<const RecordG*>(p.records);
   const uint2* tr = reinterpret_cast<const uint2*>(p.trect);
   const bool stats = out.n_visit != nullptr || out.n_pass != nullptr;
