@@ -644,7 +644,8 @@ def bench_actors(ut, synth, dev, args, n_particles, log):
 
 def bench_configs(ut, synth, dev, args):
     """Each single-sensor workload on its own (plain path, one stream): frame time (median of K
-    renders, host-count path) and per-stage GPU time from HIP events around projection,
+    renders, host-count path; and with the pair total kept on the GPU, as the multi-sensor
+    frame renders) and per-stage GPU time from HIP events around projection,
     depth sort + pair count, pair emission + super-tile sort, and compositing (median of K,
     pair totals kept on the GPU so the stages run back to back).  Projection and binning are
     priced against HBM with their algorithmic bytes:
@@ -697,6 +698,15 @@ def bench_configs(ut, synth, dev, args):
             torch.cuda.synchronize()
             for i, k in enumerate(st_ms):
                 st_ms[k].append(ev[i].elapsed_time(ev[i + 1]))
+        # the whole render with the pair total kept on the GPU (no host round trip inside the
+        # frame, as in the multi-sensor benchmark): wall time per frame, median of K
+        dtimes = []
+        for _ in range(K):
+            t0 = time.perf_counter()
+            pipe.run_device(stream)
+            torch.cuda.synchronize()
+            dtimes.append(time.perf_counter() - t0)
+        frame_dev_ms = float(np.median(dtimes)) * 1e3
         if pipe.overflowed():
             raise RuntimeError(f"{name}: pair capacity exceeded")
         med = {k: float(np.median(v)) for k, v in st_ms.items()}
@@ -709,7 +719,9 @@ def bench_configs(ut, synth, dev, args):
         gbps = lambda b, ms: b / (ms * 1e-3) / 1e9
         rows[name] = {
             "rays": s.n_rays, "frame_ms": round(frame_ms, 4), "mrays_per_s": round(s.n_rays / frame_ms / 1e3, 2),
-            "frames_per_s": round(1e3 / frame_ms, 1), "visible": V, "bin_pairs": P,
+            "frames_per_s": round(1e3 / frame_ms, 1),
+            "frame_ms_device_count": round(frame_dev_ms, 4),
+            "mrays_per_s_device_count": round(s.n_rays / frame_dev_ms / 1e3, 2), "visible": V, "bin_pairs": P,
             "stage_ms": {k: round(v, 4) for k, v in med.items()},
             "hbm_frac": {"project": round(gbps(b_proj, med["project"]) / PEAK_HBM_GBS, 3),
                          "depth_sort": round(gbps(b_depth, med["depth_sort"]) / PEAK_HBM_GBS, 3),

@@ -378,8 +378,12 @@ ut_status ut_composite_backward(const ut_gaussians* g, const ut_projected* p,
  * items from a device counter until the queue is exhausted.  Per-ray arithmetic is the
  * same as ut_composite_camera / ut_composite_lidar, so every ray's output is bit-identical
  * to the single-request call.  items: host array [n_items]; queue_ws: device workspace of
- * ut_batch_workspace_bytes(n_items) bytes.  Sensors whose tiles hold more than 256 rays
- * return UT_ERR_UNSUPPORTED (n_visit, n_pass and tile_end are not written on this path). */
+ * ut_batch_workspace_bytes(n_items) bytes.  n_workgroups > 0: that many persistent workgroups
+ * loop over the items; n_workgroups == 0: one workgroup per (request, tile) item, the
+ * hardware dispatcher handing them out in item order (no loop, so the kernel keeps the
+ * single-request kernel's register budget; the faster mode on MI355X).  Sensors whose tiles
+ * hold more than 256 rays return UT_ERR_UNSUPPORTED (n_visit, n_pass and tile_end are not
+ * written on this path). */
 typedef struct {
   const ut_projected* proj;
   const ut_bin_lists* bins;

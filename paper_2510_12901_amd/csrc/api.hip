@@ -449,14 +449,14 @@ size_t ut_batch_workspace_bytes(int32_t n_items) {
 
 ut_status ut_composite_batch(const ut_batch_item* items, int32_t n_items, const ut_render_params* prm,
                              void* queue_ws, size_t ws_bytes, int32_t n_workgroups, ut_stream stream) {
-  if (!items || n_items <= 0 || !params_ok(prm) || !queue_ws || n_workgroups <= 0) return UT_ERR_ARG;
+  if (!items || n_items <= 0 || !params_ok(prm) || !queue_ws || n_workgroups < 0) return UT_ERR_ARG;
   if (ws_bytes < ut_batch_workspace_bytes(n_items)) return UT_ERR_CAPACITY;
   return enqueue_batch(items, n_items, prm, queue_ws, n_workgroups, as_stream(stream));
 }
 
 ut_status ut_composite_batch_noalloc(const ut_batch_item* items, int32_t n_items, const ut_render_params* prm,
                                      int32_t n_workgroups, ut_stream stream) {
-  if (!items || n_items <= 0 || !params_ok(prm) || n_workgroups <= 0) return UT_ERR_ARG;
+  if (!items || n_items <= 0 || !params_ok(prm) || n_workgroups < 0) return UT_ERR_ARG;
   if (n_items > UT_BATCH_NOALLOC_MAX_ITEMS) return UT_ERR_CAPACITY;
   void* ws = nullptr;
   const ut_status st = batch_scratch_ptr(&ws);

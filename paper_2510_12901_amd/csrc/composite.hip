@@ -428,6 +428,24 @@ __global__ __launch_bounds__(kCamBlock) __attribute__((amdgpu_waves_per_eu(3))) 
   }
 }
 
+// The same items with one workgroup per (request, tile) item and no loop: the grid is the
+// batch's item count and the hardware dispatcher is the queue.  Without the persistent loop the
+// kernel keeps the single-request kernel's register budget (4 waves per SIMD, no spill), where
+// the looping kernel needs 168 VGPRs (3 waves).
+template <bool MOVING, bool UNIT>
+__global__ __launch_bounds__(kCamBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_composite_batch_direct(
+    const BatchItemK* __restrict__ items, int n_items, RenderParamsK prm) {
+  __shared__ CompositeShared<kCamBlock, kCamRpl, kCamBatch> sm;
+  __shared__ UnitShared<kCamBlock, kCamBatch> us_mem;
+  UnitShared<kCamBlock, kCamBatch>* us = UNIT ? &us_mem : nullptr;
+  const uint32_t w = blockIdx.x;
+  int it = 0;
+  while (it + 1 < n_items && (uint32_t)items[it + 1].tile_base <= w) ++it;
+  const BatchItemK& I = items[it];
+  composite_tile<kCamBlock, kCamRpl, kCamBatch, false, MOVING, false, UNIT>(
+      I.s, I.rec, I.trect, I.gauss, I.ranges, (int)(w - I.tile_base), I.s.super_x * I.s.super_y, prm, I.out, sm, us);
+}
+
 }  // namespace
 
 hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, const SensorK& s,
@@ -489,6 +507,19 @@ hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, con
 
 hipError_t launch_composite_batch(const BatchItemK* items_dev, const BatchGroups& grp, uint32_t* counter,
                                   const RenderParamsK& prm, int n_workgroups, hipStream_t st) {
+  if (n_workgroups <= 0) {
+    // one workgroup per (request, tile) item: the hardware dispatcher hands them out in order
+#define UT_LAUNCH_DIRECT(G, MV, UN)                                                                             \
+  if (grp.tiles[G] > 0)                                                                                         \
+  hipLaunchKernelGGL((k_composite_batch_direct<MV, UN>), dim3(grp.tiles[G]), dim3(kCamBlock), 0, st,             \
+                     items_dev + grp.first[G], grp.count[G], prm)
+    UT_LAUNCH_DIRECT(0, false, false);
+    UT_LAUNCH_DIRECT(1, true, false);
+    UT_LAUNCH_DIRECT(2, false, true);
+    UT_LAUNCH_DIRECT(3, true, true);
+#undef UT_LAUNCH_DIRECT
+    return hipGetLastError();
+  }
   hipError_t e = fill_u32(counter, 0u, 4, st);
   if (e != hipSuccess) return e;
 #define UT_LAUNCH_BATCH(G, MV, UN)                                                                              \

@@ -353,7 +353,8 @@ def backward(g: GaussianSet, p: Projection, bins: BinLists, sensor: Sensor, fwd:
 
 
 def composite_batch(items, params=None, n_workgroups=None, ws: torch.Tensor | None = None, stream=None):
-    """One persistent launch compositing several (projection, lists, sensor, out) requests."""
+    """One launch compositing several (projection, lists, sensor, out) requests: n_workgroups
+    persistent workgroups (default 1024), or 0 for one workgroup per (request, tile) item."""
     n = len(items)
     prm = params or render_params()
     arr = (A.UtBatchItem * n)()
@@ -384,8 +385,9 @@ def composite_batch_noalloc(items, params=None, n_workgroups=None, stream=None):
         pc, lc, oc = p.c(), bins.c(), out.c()
         keep += [pc, lc, oc]
         arr[i] = A.UtBatchItem(ref(pc), ref(lc), ref(sensor.c), ref(oc))
-    check(lib().ut_composite_batch_noalloc(C.cast(arr, C.c_void_p), n, ref(prm), n_workgroups or 256 * 4,
-                                           _stream(stream)), "ut_composite_batch_noalloc")
+    check(lib().ut_composite_batch_noalloc(C.cast(arr, C.c_void_p), n, ref(prm),
+                                           256 * 4 if n_workgroups is None else n_workgroups, _stream(stream)),
+          "ut_composite_batch_noalloc")
 
 
 class SensorPipeline:

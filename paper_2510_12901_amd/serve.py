@@ -9,7 +9,7 @@ moves through:
   enqueued   projection, depth sort + pair count and the pair sort are enqueued at once on
              the slot's stream; the pair total stays on the device (ut_bin_sort_device with
              the bound as capacity), so no host round trip sits between the stages
-  batched    composited together with every other enqueued request in one persistent launch
+  batched    composited together with every other enqueued request in one launch
              (ut_composite_batch) on one of two compositing streams, which waits on the
              requests' sorts on the device
   done       a waiter thread blocks on the launch's completion event and wakes the host loop;
@@ -155,10 +155,12 @@ class Batch:
 
 class Server:
     """timing=True records device timestamps of every request's pair sort and every batch's
-    compositing (stats["device"]), which show whether requests overlapped on the GPU."""
+    compositing (stats["device"]), which show whether requests overlapped on the GPU.
+    n_workgroups: 0 (default) composites a batch with one workgroup per (request, tile) item;
+    > 0 runs that many persistent workgroups over the items (ut_composite_batch)."""
 
     def __init__(self, g_cam: GaussianSet, g_lidar: GaussianSet, sensors: list, pool_bytes: int,
-                 n_slots: int = 12, n_workgroups: int = 1024, params=None, abk=(1.0, 2.0, 0.0),
+                 n_slots: int = 12, n_workgroups: int = 0, params=None, abk=(1.0, 2.0, 0.0),
                  timing: bool = False, bound_margin: float = 1.25):
         self.g_cam, self.g_lidar, self.sensors = g_cam, g_lidar, sensors
         dev = g_cam.mean.device
@@ -507,7 +509,16 @@ def bench_served(g, gl, sensors_np, sensors, dev, args, log):
             f"{pl['mrays_per_s']} Mrays/s")
     out["knee_vehicles"] = knee
     out["served_saturation_mrays_per_s"] = max(r["served"]["mrays_per_s"] for r in out["vehicles"].values())
+    out["batch_launch"] = "one workgroup per (request, tile) item"
     del server
+    torch.cuda.synchronize()
+    # the persistent mode of the same batched launch (1024 workgroups looping over the items)
+    pers = Server(g, gl, sensors, pool_bytes=48 << 30, n_slots=28, n_workgroups=1024)
+    preq8 = pers.run(poisson_trace(30.0 * 8, warm_s + 2.0, len(sensors), seed=8))
+    p8 = summarize(preq8, rays, t_from=warm_s)
+    out["persistent_workgroups_v8"] = {k: p8[k] for k in ("p50_frame_ms", "p99_frame_ms", "mrays_per_s")}
+    log(f"persistent batch launch at V=8: {json.dumps(out['persistent_workgroups_v8'])}")
+    del pers
     torch.cuda.synchronize()
     timed = Server(g, gl, sensors, pool_bytes=48 << 30, n_slots=28, timing=True)
     treq = timed.run(poisson_trace(30.0 * 8, 2.0, len(sensors), seed=123))

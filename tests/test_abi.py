@@ -86,6 +86,9 @@ def test_argument_errors_of_the_later_entry_points(L):
     assert L.ut_bin_sort_device(None, 0, None, None, 0, None, 0, 0, None, None, None) == A.UT_ERR_ARG
     assert L.ut_composite_backward(None, None, None, None, None, None, None, None, 0, None, None) == A.UT_ERR_ARG
     assert L.ut_composite_batch(None, 0, None, None, 0, 1, None) == A.UT_ERR_ARG
+    arr = (A.UtBatchItem * 1)()
+    prm = A.UtRenderParams(1 / 255, 0.99, 1e-4)
+    assert L.ut_composite_batch(C.cast(arr, C.c_void_p), 1, A.ref(prm), C.c_void_p(8), 1 << 20, -1, None) == A.UT_ERR_ARG
     g = A.UtGaussians(None, None, None, None, None, 0, 0, 0)
     assert L.ut_actor_transform(None, None, None, 0, None, None, None) == A.UT_ERR_ARG
     assert L.ut_actor_transform(A.ref(g), None, None, -1, None, None, None) == A.UT_ERR_ARG

@@ -264,13 +264,15 @@ def test_large_lidar_tiles_rejected_by_batch_and_adjoint():
         ut.composite_batch([(p, bins, s, out)])
 
 
-def test_batched_composite_with_moving_and_static_sensors():
-    """The batched persistent composite handles a moving sensor's per-ray origins: every output
-    is bit-identical to the plain single-request call."""
+@pytest.mark.parametrize("n_workgroups", [1024, 0])
+def test_batched_composite_with_moving_and_static_sensors(n_workgroups):
+    """The batched composite (persistent workgroups, or one workgroup per item) handles a
+    moving sensor's per-ray origins and LiDAR units: every output is bit-identical to the
+    plain single-request call."""
     import torch
     import paper_2510_12901_amd as ut
     items, plain = [], []
-    for name in ("pinhole_rolling_shutter", "pinhole_ragged", "lidar_moving"):
+    for name in ("pinhole_rolling_shutter", "pinhole_ragged", "lidar_moving", "lidar_small"):
         g_np, s_np = _scene(name)
         g = ut.GaussianSet.from_numpy(g_np)
         s = ut.Sensor(s_np)
@@ -278,7 +280,7 @@ def test_batched_composite_with_moving_and_static_sensors():
         b = ut.alloc_out(s, g.mean.device, state=True)
         items.append((p, bins, s, b))
         plain.append(a)
-    ut.composite_batch(items)
+    ut.composite_batch(items, n_workgroups=n_workgroups)
     torch.cuda.synchronize()
     for (p, bins, s, b), a in zip(items, plain):
         for k in ("feat", "depth", "alpha", "t_final", "n_proc"):

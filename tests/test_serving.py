@@ -118,7 +118,7 @@ def test_served_results_match_plain_and_oracle_under_memory_pressure():
     probe = serve.Server(g, gl, sensors, pool_bytes=1 << 20, n_slots=1)
     need = max(sum(probe._need(s, probe.bound[i])) for i, s in enumerate(sensors))
     del probe
-    server = serve.Server(g, gl, sensors, pool_bytes=need + 4096, n_slots=4, n_workgroups=512)
+    server = serve.Server(g, gl, sensors, pool_bytes=need + 4096, n_slots=4)
     trace = serve.poisson_trace(2000.0, 0.05, len(sensors), seed=1)
     assert len(trace) >= 40
     seen = []
@@ -151,7 +151,7 @@ def test_served_requests_share_launches_and_overlap_on_the_device():
     compositing launch that does not hold it runs (device timestamps).  Every result still
     equals its plain render."""
     g_np, gl_np, sensors_np, g, gl, sensors, ref = _served_scene()
-    server = serve.Server(g, gl, sensors, pool_bytes=256 << 20, n_slots=8, n_workgroups=512, timing=True)
+    server = serve.Server(g, gl, sensors, pool_bytes=256 << 20, n_slots=8, timing=True)
     trace = serve.poisson_trace(3000.0, 0.1, len(sensors), seed=4)
 
     def check(r):
