@@ -506,6 +506,183 @@ __global__ __launch_bounds__(kScanThreads) void k_gather_apply(const uint32_t* _
   }
 }
 
+// ---------------------------------------------------------------------------------- small sets
+// Up to kSmallMax particles the whole count stage, and up to kSmallMax pairs the whole pair
+// sort, run in one workgroup out of LDS: one launch instead of a chain of short launches that
+// each cost more than the work.  The orders are the same: a stable sort by key equals an
+// ascending sort of (key, position) words, which a bitonic network gives exactly.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallItems = 4;
+constexpr int kSmallMax = kSmallThreads * kSmallItems;
+
+// exclusive scan of one value per thread across a kSmallThreads block; returns the total
+template <typename T>
+__device__ __forceinline__ T small_exclusive(T v, T* sh /*[kSmallThreads / 64]*/, T& total) {
+  const int lane = __lane_id(), wave = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T y = shfl_up_t(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  T before = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kSmallThreads / 64; ++w) {
+    const T s = sh[w];
+    if (w < wave) before += s;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return before + x - v;
+}
+
+// Ascending bitonic sort of the 64-bit words s[0, len), len a power of two <= kSmallMax.
+__device__ void small_bitonic(uint64_t* s, int len) {
+  for (int k = 2; k <= len; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < len / 2; t += kSmallThreads) {
+        const int i = 2 * t - (t & (j - 1));   // lower element of pair t at distance j
+        const uint64_t a = s[i], b = s[i + j];
+        if ((a > b) == ((i & k) == 0)) {
+          s[i] = b;
+          s[i + j] = a;
+        }
+      }
+      __syncthreads();
+    }
+}
+
+__device__ __forceinline__ int pow2_at_least(int m) {
+  int len = 1;
+  while (len < m) len <<= 1;
+  return len;
+}
+
+// The count stage of up to kSmallMax particles in one workgroup: super-tile counts, the
+// visible particles in (depth key, index) order (dk / dv, *m_dev of them), the exclusive
+// prefix of their super-tile counts in that order (offs[j], the total past the visible ones)
+// and the total pair count.  Same results as the multi-kernel chain.
+__global__ __launch_bounds__(kSmallThreads) void k_count_small(const uint32_t* __restrict__ count,
+                                                               const int32_t* __restrict__ rect,
+                                                               const uint32_t* __restrict__ key, int n, int tiles_x,
+                                                               int SX, int SH, int wrap, uint32_t* __restrict__ scount,
+                                                               uint32_t* __restrict__ dk, uint32_t* __restrict__ dv,
+                                                               uint32_t* __restrict__ m_dev, uint64_t* __restrict__ offs,
+                                                               uint64_t* __restrict__ total) {
+  __shared__ uint64_t s_kv[kSmallMax];
+  __shared__ uint32_t s_cnt[kSmallMax];
+  __shared__ uint64_t s_sum[kSmallThreads / 64];
+  const int t = threadIdx.x;
+  const int base = t * kSmallItems;
+  uint32_t c[kSmallItems];
+  uint32_t f = 0;
+#pragma unroll
+  for (int k = 0; k < kSmallItems; ++k) {
+    const int i = base + k;
+    c[k] = i < n ? super_count(count, rect, n, i, tiles_x, SX, SH, wrap) : 0u;
+    if (i < n) {
+      scount[i] = c[k];
+      s_cnt[i] = c[k];
+    }
+    f += c[k] ? 1u : 0u;
+  }
+  uint64_t m64;
+  uint32_t p = (uint32_t)small_exclusive<uint64_t>(f, s_sum, m64);
+  const int m = (int)m64;
+#pragma unroll
+  for (int k = 0; k < kSmallItems; ++k)
+    if (c[k]) s_kv[p++] = ((uint64_t)key[base + k] << 32) | (uint32_t)(base + k);
+  const int len = pow2_at_least(m);
+  for (int i = m + t; i < len; i += kSmallThreads) s_kv[i] = ~0ull;
+  __syncthreads();
+  small_bitonic(s_kv, len);
+  uint64_t v[kSmallItems];
+  uint64_t run = 0;
+#pragma unroll
+  for (int k = 0; k < kSmallItems; ++k) {
+    const int j = base + k;
+    v[k] = 0;
+    if (j < m) {
+      const uint64_t w = s_kv[j];
+      dk[j] = (uint32_t)(w >> 32);
+      dv[j] = (uint32_t)w;
+      v[k] = s_cnt[(uint32_t)w];
+    }
+    run += v[k];
+  }
+  uint64_t tot;
+  run = small_exclusive<uint64_t>(run, s_sum, tot);
+#pragma unroll
+  for (int k = 0; k < kSmallItems; ++k) {
+    if (base + k < n) offs[base + k] = run;
+    run += v[k];
+  }
+  if (t == 0) {
+    *m_dev = (uint32_t)m;
+    *total = tot;
+  }
+}
+
+// The pair emission and super-tile sort of up to kSmallMax pairs in one workgroup, for up to
+// kSmallMax super-tiles: pairs of the depth-ordered particles ordered by (super-tile, pair
+// position), bins.gauss and the per-super-tile [start, end) ranges (0, 0 when empty).  With
+// total_dev (device count) the pair count is read there and checked against max_pairs: over
+// it nothing is emitted and *overflow is raised.
+__global__ __launch_bounds__(kSmallThreads) void k_pairs_small(const uint32_t* __restrict__ order,
+                                                               const uint64_t* __restrict__ offs,
+                                                               const uint32_t* __restrict__ m_dev,
+                                                               const uint2* __restrict__ trect, int n, int tiles_x,
+                                                               int SX, int SH, int wrap, uint32_t P_host,
+                                                               const uint64_t* __restrict__ total_dev,
+                                                               uint64_t max_pairs, uint32_t* __restrict__ overflow,
+                                                               uint32_t* __restrict__ gauss, uint32_t* __restrict__ ranges,
+                                                               int n_super) {
+  __shared__ uint64_t s_kv[kSmallMax];
+  __shared__ uint32_t s_g[kSmallMax];
+  const int t = threadIdx.x;
+  for (int i = t; i < 2 * n_super; i += kSmallThreads) ranges[i] = 0u;
+  uint32_t P = P_host;
+  if (total_dev) {
+    const uint64_t T = *total_dev;
+    const bool fits = T <= max_pairs && T <= (uint64_t)kSmallMax;   // the second holds by the launch bound
+    P = fits ? (uint32_t)T : 0u;
+    if (!fits && overflow && t == 0) overflow[0] = 1u;
+  }
+  const int m = (int)min((uint32_t)n, *m_dev);
+  // every visible particle writes its pairs (super-tile id << 32 | pair position) in depth order
+  for (int j = t; j < m; j += kSmallThreads) {
+    const uint2 r = trect[order[j]];
+    const int x0 = (int)(r.x & 0xFFFFu), y0 = (int)(r.x >> 16), x1 = (int)(r.y & 0xFFFFu), y1 = (int)(r.y >> 16);
+    int sx0;
+    const int nc = super_cols(x0, x1, tiles_x, SX, wrap, &sx0);
+    const int sy0 = y0 / SH, nr = y1 / SH - sy0 + 1;
+    uint32_t o = (uint32_t)offs[j];
+    for (int yy = 0; yy < nr; ++yy)
+      for (int xx = 0; xx < nc; ++xx, ++o) {
+        int x = sx0 + xx;
+        if (x >= SX) x -= SX;
+        if (o < P) {
+          s_kv[o] = ((uint64_t)(uint32_t)((sy0 + yy) * SX + x) << 32) | o;
+          s_g[o] = order[j];
+        }
+      }
+  }
+  const int len = pow2_at_least((int)P);
+  for (int i = (int)P + t; i < len; i += kSmallThreads) s_kv[i] = ~0ull;
+  __syncthreads();
+  small_bitonic(s_kv, len);
+  for (int i = t; i < (int)P; i += kSmallThreads) {
+    const uint64_t w = s_kv[i];
+    const uint32_t st = (uint32_t)(w >> 32);
+    gauss[i] = s_g[(uint32_t)w];
+    if (i == 0 || (uint32_t)(s_kv[i - 1] >> 32) != st) ranges[st] = (uint32_t)i;
+    if (i == (int)P - 1 || (uint32_t)(s_kv[i + 1] >> 32) != st) ranges[n_super + st] = (uint32_t)(i + 1);
+  }
+}
+
 // One wavefront emits the (super-tile, particle) pairs of 64 consecutive depth-ordered
 // particles, 64 pairs per step.
 __global__ __launch_bounds__(256) void k_duplicate(const uint32_t* __restrict__ order, const uint64_t* __restrict__ offs,
@@ -710,6 +887,11 @@ hipError_t launch_bin_count(const ut_projected& p, int n, const SensorK& s, Coun
   }
   const int nb = (n + kScanTile - 1) / kScanTile;
   const int wrap = s.kind == UT_LIDAR ? 1 : 0;
+  if (n <= kSmallMax) {
+    hipLaunchKernelGGL(k_count_small, dim3(1), dim3(kSmallThreads), 0, st, p.count, p.rect, p.key, n, s.tiles_x,
+                       s.super_x, s.super_h, wrap, ws.scount, ws.dkA, ws.dvA, ws.m_dev, ws.offs, ws.total);
+    return hipGetLastError();
+  }
   uint32_t* sums32 = reinterpret_cast<uint32_t*>(ws.scan_aux);
   // visible particles (tile count > 0) compacted in index order, then depth-sorted
   hipLaunchKernelGGL(k_prep_reduce, dim3(nb), dim3(kScanThreads), 0, st, p.count, p.rect, s.tiles_x, s.super_x,
@@ -734,6 +916,13 @@ hipError_t launch_bin_sort(const ut_projected& p, int n, const SensorK& s, Count
   const int n_super = s.super_x * s.super_y;
   hipError_t e = fill_u32(bins.ranges, 0u, 2 * (size_t)n_super, st);
   if (e != hipSuccess || n_pairs == 0 || n == 0) return e;
+  if (n_pairs <= (uint64_t)kSmallMax) {
+    hipLaunchKernelGGL(k_pairs_small, dim3(1), dim3(kSmallThreads), 0, st, ws.dvA, ws.offs, ws.m_dev,
+                       reinterpret_cast<const uint2*>(p.trect), n, s.tiles_x, s.super_x, s.super_h,
+                       s.kind == UT_LIDAR ? 1 : 0, (uint32_t)n_pairs, nullptr, 0ull, nullptr, bins.gauss, bins.ranges,
+                       n_super);
+    return hipGetLastError();
+  }
   const int bits = tile_bits(n_super);
   // place the emitted pair values so that the last radix pass writes into bins.gauss
   uint32_t* v_first = (radix_passes(bits) % 2) ? pw.tv : bins.gauss;
@@ -767,6 +956,16 @@ hipError_t launch_bin_sort_device(const ut_projected& p, int n, const SensorK& s
                                   PairWorkspace& pw, uint64_t max_pairs, const ut_bin_lists& bins,
                                   uint32_t* overflow, hipStream_t st) {
   const int n_super = s.super_x * s.super_y;
+  // the pair total is not known here: the one-workgroup sort runs when the capacity, or every
+  // particle touching every super-tile, bounds it by kSmallMax
+  const uint64_t bound = std::min<uint64_t>(max_pairs, (uint64_t)n * (uint64_t)n_super);
+  if (max_pairs > 0 && n > 0 && bound <= (uint64_t)kSmallMax) {
+    hipLaunchKernelGGL(k_pairs_small, dim3(1), dim3(kSmallThreads), 0, st, ws.dvA, ws.offs, ws.m_dev,
+                       reinterpret_cast<const uint2*>(p.trect), n, s.tiles_x, s.super_x, s.super_h,
+                       s.kind == UT_LIDAR ? 1 : 0, 0u, ws.total, max_pairs, overflow, bins.gauss, bins.ranges,
+                       n_super);
+    return hipGetLastError();
+  }
   hipError_t e = fill_u32(bins.ranges, 0u, 2 * (size_t)n_super, st);
   if (e != hipSuccess || max_pairs == 0 || n == 0) return e;
   hipLaunchKernelGGL(k_pair_guard, dim3(1), dim3(64), 0, st, ws.total, max_pairs, pw.n_dev, overflow);
