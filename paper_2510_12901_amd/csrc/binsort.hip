@@ -539,26 +539,82 @@ __device__ __forceinline__ T small_exclusive(T v, T* sh /*[kSmallThreads / 64]*/
   return before + x - v;
 }
 
-// Ascending bitonic sort of the 64-bit words s[0, len), len a power of two <= kSmallMax.
-__device__ void small_bitonic(uint64_t* s, int len) {
-  for (int k = 2; k <= len; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = threadIdx.x; t < len / 2; t += kSmallThreads) {
-        const int i = 2 * t - (t & (j - 1));   // lower element of pair t at distance j
-        const uint64_t a = s[i], b = s[i + j];
-        if ((a > b) == ((i & k) == 0)) {
-          s[i] = b;
-          s[i + j] = a;
-        }
-      }
-      __syncthreads();
-    }
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
+  return (uint64_t)__shfl_xor((unsigned long long)x, m);
 }
 
-__device__ __forceinline__ int pow2_at_least(int m) {
-  int len = 1;
+// One compare-exchange step of a bitonic network for element e holding a, partner e ^ j
+// holding b, in a block of k elements: the lower element keeps the smaller word when the
+// block ascends ((e & k) == 0), the larger one otherwise.
+__device__ __forceinline__ uint64_t bitonic_keep(uint64_t a, uint64_t b, int e, int j, int k) {
+  const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
+  return keep_min ? (a < b ? a : b) : (a < b ? b : a);
+}
+
+// Bitonic network over the elements e = r * kSmallThreads + threadIdx.x held in v[r]: sorts
+// every aligned block of len elements ascending (len a power of two, 64 <= len <= R *
+// kSmallThreads).  Partners within a wavefront (distance < 64) are exchanged by lane shuffles,
+// across wavefronts through the LDS buffer x (R * kSmallThreads words), within a thread
+// between registers.
+template <int R>
+__device__ void small_bitonic_regs(uint64_t (&v)[R], int len, uint64_t* x) {
+  const int t = threadIdx.x;
+  for (int k = 2; k <= len; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j < 64) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = bitonic_keep(v[r], shfl_xor_u64(v[r], j), r * kSmallThreads + t, j, k);
+      } else if (j < kSmallThreads) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r * kSmallThreads + t] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int e = r * kSmallThreads + t;
+          v[r] = bitonic_keep(v[r], x[e ^ j], e, j, k);
+        }
+        __syncthreads();
+      } else {
+#pragma unroll
+        for (int sr = 1; sr < R; sr <<= 1) {
+          if (j != sr * kSmallThreads) continue;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (r & sr) continue;
+            const int e = r * kSmallThreads + t;
+            const uint64_t lo = v[r], hi = v[r + sr];
+            v[r] = bitonic_keep(lo, hi, e, j, k);
+            v[r + sr] = bitonic_keep(hi, lo, e + j, j, k);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int R>
+__device__ void small_sort_lds_r(uint64_t* s, int m, int len) {
+  uint64_t v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = r * kSmallThreads + (int)threadIdx.x;
+    v[r] = e < m ? s[e] : ~0ull;
+  }
+  __syncthreads();
+  small_bitonic_regs<R>(v, len, s);
+#pragma unroll
+  for (int r = 0; r < R; ++r) s[r * kSmallThreads + threadIdx.x] = v[r];
+  __syncthreads();
+}
+
+// Ascending sort of the m <= kSmallMax words s[0, m) in LDS (all threads call it after a
+// barrier that follows the writes to s; s holds kSmallMax words).
+__device__ void small_sort_lds(uint64_t* s, int m) {
+  int len = 64;
   while (len < m) len <<= 1;
-  return len;
+  if (len <= kSmallThreads) small_sort_lds_r<1>(s, m, len);
+  else if (len <= 2 * kSmallThreads) small_sort_lds_r<2>(s, m, len);
+  else small_sort_lds_r<4>(s, m, len);
 }
 
 // The count stage of up to kSmallMax particles in one workgroup: super-tile counts, the
@@ -595,10 +651,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_count_small(const uint32_t* _
 #pragma unroll
   for (int k = 0; k < kSmallItems; ++k)
     if (c[k]) s_kv[p++] = ((uint64_t)key[base + k] << 32) | (uint32_t)(base + k);
-  const int len = pow2_at_least(m);
-  for (int i = m + t; i < len; i += kSmallThreads) s_kv[i] = ~0ull;
   __syncthreads();
-  small_bitonic(s_kv, len);
+  small_sort_lds(s_kv, m);
   uint64_t v[kSmallItems];
   uint64_t run = 0;
 #pragma unroll
@@ -670,10 +724,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_pairs_small(const uint32_t* _
         }
       }
   }
-  const int len = pow2_at_least((int)P);
-  for (int i = (int)P + t; i < len; i += kSmallThreads) s_kv[i] = ~0ull;
   __syncthreads();
-  small_bitonic(s_kv, len);
+  small_sort_lds(s_kv, (int)P);
   for (int i = t; i < (int)P; i += kSmallThreads) {
     const uint64_t w = s_kv[i];
     const uint32_t st = (uint32_t)(w >> 32);
