@@ -4,9 +4,9 @@
 //   1. stable LSD radix sort of the particles by their float32 depth key (4 x 8-bit passes);
 //   2. super-tile counts (8 x 8-tile blocks touched by the particle's tile rect) gathered in
 //      depth order, exclusive scan (uint64) -> pair offsets, total P;
-//   3. (super-tile, particle) pairs emitted in depth order by whole wavefronts (prefix
-//      offsets + binary search, so a particle touching many super-tiles is spread over 64
-//      lanes and writes coalesce);
+//   3. (super-tile, particle) pairs emitted in depth order, a fixed run of pairs per
+//      workgroup (prefix offsets + binary search, so a particle touching many super-tiles is
+//      spread over many lanes and the work is even however the pairs cluster);
 //   4. stable LSD radix sort of the pairs by super-tile id (one 8-bit pass up to 256
 //      super-tiles).
 // Sorting by depth first and then stably by super-tile gives (super-tile, depth, index)
@@ -141,39 +141,50 @@ constexpr int kSortThreads = 256;   // one thread per digit in the look-back
 constexpr int kSortItems = 16;      // keys per lane
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kMaxPasses = 4;
+constexpr int kHistItems = 4;                          // keys per lane in the histogram kernel
+constexpr int kHistTile = kSortThreads * kHistItems;   // keys per histogram workgroup
+static_assert(kSortTile % kHistTile == 0, "a sort tile is a whole number of histogram tiles");
+// The digit histograms are kept as kHistParts partial copies, workgroup b adding into copy
+// b % kHistParts: device-scope atomics from every workgroup on the same 256 words serialise,
+// spread over 16 copies they do not.  A pass reads the sum of the copies.
+constexpr int kHistParts = 16;
 
 // Look-back words: bits 30..31 hold the state, bits 0..29 the count.
 constexpr uint32_t kLbAggregate = 1u << 30;   // the tile's own digit count is published
 constexpr uint32_t kLbPrefix = 2u << 30;      // the inclusive prefix over tiles 0..t is published
 constexpr uint32_t kLbCount = (1u << 30) - 1u;
 
-// Digit histograms of every pass in one read of the keys: one workgroup per tile of
-// kSortTile keys, every lane's loads issued up front.  Depth keys concentrate in a few
-// high-byte values, so lanes are first grouped by equal digit (8 ballots) and only one lane
-// per group adds the group's size to the LDS counter; one global atomic per digit present
-// follows.
+// Digit histograms of every pass in one read of the keys: one workgroup per kHistTile keys
+// (a quarter of a sort tile, so four times the workgroups of a pass share the latency), every
+// lane's loads issued up front.  Depth keys concentrate in a few high-byte values, so lanes
+// are first grouped by equal digit (8 ballots) and only one lane per group adds the group's
+// size to the LDS counter; one global atomic per digit present follows.
 __global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __restrict__ keys, size_t n_max,
                                                               const uint32_t* __restrict__ n_dev, int passes,
                                                               uint32_t* __restrict__ hist, uint32_t* __restrict__ look,
                                                               size_t look_tiles) {
   __shared__ uint32_t h[kMaxPasses][kRadix];
   const size_t n = n_dev ? (size_t)*n_dev : n_max;
-  const size_t tile0 = (size_t)blockIdx.x * kSortTile;
-  if (tile0 >= n) return;
+  const size_t start = (size_t)blockIdx.x * kHistTile;
+  if (start >= n) return;
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
-  // this tile's look-back words of every pass start cleared (the passes run after this kernel)
-  for (int p = 0; p < passes; ++p) look[((size_t)p * look_tiles + blockIdx.x) * kRadix + threadIdx.x] = 0u;
+  // the first workgroup of a sort tile clears the tile's look-back words of every pass (the
+  // passes run after this kernel)
+  constexpr int kPerTile = kSortTile / kHistTile;
+  if (blockIdx.x % kPerTile == 0)
+    for (int p = 0; p < passes; ++p)
+      look[((size_t)p * look_tiles + blockIdx.x / kPerTile) * kRadix + threadIdx.x] = 0u;
   for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kSortThreads) (&h[0][0])[i] = 0;
   __syncthreads();
-  const size_t base = tile0 + (size_t)wave * (kSortItems * 64) + lane;
-  uint32_t key[kSortItems];
+  const size_t base = start + (size_t)wave * (kHistItems * 64) + lane;
+  uint32_t key[kHistItems];
 #pragma unroll
-  for (int k = 0; k < kSortItems; ++k) {
+  for (int k = 0; k < kHistItems; ++k) {
     const size_t i = base + (size_t)k * 64;
     key[k] = i < n ? keys[i] : 0u;
   }
 #pragma unroll
-  for (int k = 0; k < kSortItems; ++k) {
+  for (int k = 0; k < kHistItems; ++k) {
     const bool valid = base + (size_t)k * 64 < n;
     for (int p = 0; p < passes; ++p) {
       const uint32_t d = (key[k] >> (8 * p)) & (kRadix - 1);
@@ -188,9 +199,10 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __r
     }
   }
   __syncthreads();
+  uint32_t* part = hist + (size_t)(blockIdx.x % kHistParts) * kMaxPasses * kRadix;
   for (int i = threadIdx.x; i < passes * kRadix; i += kSortThreads) {
     const uint32_t c = (&h[0][0])[i];
-    if (c) atomicAdd(&hist[i], c);
+    if (c) atomicAdd(&part[i], c);
   }
 }
 
@@ -233,7 +245,10 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
   uint32_t digit_base;
   {
     uint32_t all;
-    digit_base = block_exclusive<uint32_t>(digit_count[threadIdx.x], scan_sh, all);
+    uint32_t c = 0;
+#pragma unroll
+    for (int g = 0; g < kHistParts; ++g) c += digit_count[(size_t)g * kMaxPasses * kRadix + threadIdx.x];
+    digit_base = block_exclusive<uint32_t>(c, scan_sh, all);
   }
 
   uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
@@ -338,11 +353,11 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
 // Bytes of the sort's own workspace for up to n_max keys: per-pass digit counts and tickets
 // (radix_clear_words() words at the start, which must be zero when a sort starts), then the
 // per-pass look-back words, which the histogram kernel clears per tile.
+size_t radix_tiles(size_t n_max) { return (std::max<size_t>(n_max, 1) + kSortTile - 1) / kSortTile; }
 size_t radix_ws_bytes(size_t n_max) {
-  const size_t tiles = (std::max<size_t>(n_max, 1) + kSortTile - 1) / kSortTile;
-  return 4 * ((size_t)kMaxPasses * kRadix + kMaxPasses + (size_t)kMaxPasses * tiles * kRadix);
+  return 4 * (radix_clear_words() + (size_t)kMaxPasses * radix_tiles(n_max) * kRadix);
 }
-size_t radix_clear_words() { return (size_t)kMaxPasses * kRadix + kMaxPasses; }
+size_t radix_clear_words() { return (size_t)kHistParts * kMaxPasses * kRadix + kMaxPasses; }
 
 // Sorts (k, v) pairs by the low `bits` bits of k (bits <= 32), stable.  n_max sizes the grid;
 // when n_dev is given the kernels read the actual length from it.  Buffers ping-pong;
@@ -357,16 +372,16 @@ hipError_t radix_sort(uint32_t* kA, uint32_t* kB, uint32_t* vA, uint32_t* vB, si
   if (n_max == 0 || bits <= 0) return hipSuccess;
   if (n_max > kLbCount || bits > 8 * kMaxPasses) return hipErrorInvalidValue;   // look-back counts are 30-bit
   const int passes = (bits + 7) / 8;
-  const size_t tiles = (n_max + kSortTile - 1) / kSortTile;
+  const size_t tiles = radix_tiles(n_max);
   uint32_t* hist = ws;
-  uint32_t* tickets = ws + (size_t)kMaxPasses * kRadix;
+  uint32_t* tickets = ws + (size_t)kHistParts * kMaxPasses * kRadix;
   uint32_t* look = tickets + kMaxPasses;
   if (!ws_clear) {
     const hipError_t e = fill_u32(ws, 0u, radix_clear_words(), st);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)tiles), dim3(kSortThreads), 0, st, kA, n_max, n_dev, passes, hist,
-                     look, tiles);
+  hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)((n_max + kHistTile - 1) / kHistTile)), dim3(kSortThreads), 0, st,
+                     kA, n_max, n_dev, passes, hist, look, tiles);
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL(k_onesweep, dim3((unsigned)tiles), dim3(kSortThreads), 0, st, kA, vA, kB, vB, n_max, n_dev,
                        8 * p, hist + p * kRadix, look + (size_t)p * tiles * kRadix, tickets + p);
@@ -409,13 +424,30 @@ __device__ __forceinline__ uint32_t super_count(const uint32_t* __restrict__ cou
   return (uint32_t)(nc * nr);
 }
 
-// Visible-particle compaction, pass 1 of 3: per particle its super-tile count (kept for the
-// pair emission), per block of kScanTile particles the number of visible ones.
+// Offset of block b from the per-block sums of a first pass: every block adds up its
+// predecessors' sums itself (a few thousand words at most, from L2), so no scan kernel runs
+// between the two passes.  For block 0, *all receives the sum over all nb blocks.
+template <typename T>
+__device__ __forceinline__ T block_offset(const T* __restrict__ sums, int b, int nb, T* sh /*[4]*/, T& all) {
+  const int upto = b == 0 ? nb : b;   // block 0 adds up everything (its own offset is 0)
+  T acc = 0;
+  for (int i = threadIdx.x; i < upto; i += kScanThreads) acc += sums[i];
+  T sum;
+  block_exclusive<T>(acc, sh, sum);
+  all = sum;
+  return b == 0 ? (T)0 : sum;
+}
+
+// Visible-particle compaction, pass 1 of 2: per particle its super-tile count (kept for the
+// pair emission), per block of kScanTile particles the number of visible ones.  The blocks
+// also clear the depth sort's counters (the sort runs after pass 2 on the same stream).
 __global__ __launch_bounds__(kScanThreads) void k_prep_reduce(const uint32_t* __restrict__ count,
                                                               const int32_t* __restrict__ rect, int tiles_x, int SX,
                                                               int SH, int wrap, uint32_t* __restrict__ scount, int n,
-                                                              uint32_t* __restrict__ sums) {
+                                                              uint32_t* __restrict__ sums, uint32_t* __restrict__ clear,
+                                                              int n_clear) {
   __shared__ uint32_t sh[4];
+  for (int i = blockIdx.x * kScanThreads + threadIdx.x; i < n_clear; i += gridDim.x * kScanThreads) clear[i] = 0u;
   const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   uint32_t f = 0;
 #pragma unroll
@@ -432,17 +464,14 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_reduce(const uint32_t* __
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-// Pass 3 of 3 (after k_scan_sums turned the block counts into offsets): the stable compaction,
-// (depth key, index) of the visible particles in index order.  Block 0 also clears the depth
-// sort's counters (the sort runs next on the same stream).
+// Pass 2 of 2: the stable compaction, (depth key, index) of the visible particles in index
+// order, and *m_dev = their number (block 0).
 __global__ __launch_bounds__(kScanThreads) void k_compact_apply(const uint32_t* __restrict__ key,
                                                                 const uint32_t* __restrict__ scount, int n,
-                                                                const uint32_t* __restrict__ sums,
+                                                                const uint32_t* __restrict__ sums, int nb,
                                                                 uint32_t* __restrict__ dk, uint32_t* __restrict__ dv,
-                                                                uint32_t* __restrict__ clear, int n_clear) {
+                                                                uint32_t* __restrict__ m_dev) {
   __shared__ uint32_t sh[4];
-  if (blockIdx.x == 0)
-    for (int i = threadIdx.x; i < n_clear; i += kScanThreads) clear[i] = 0u;
   const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   uint32_t f = 0;
@@ -451,8 +480,11 @@ __global__ __launch_bounds__(kScanThreads) void k_compact_apply(const uint32_t* 
     v[k] = base + k < n && scount[base + k] ? 1u : 0u;
     f += v[k];
   }
+  uint32_t all;
+  const uint32_t off = block_offset<uint32_t>(sums, blockIdx.x, nb, sh, all);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *m_dev = all;
   uint32_t total;
-  uint32_t p = block_exclusive<uint32_t>(f, sh, total) + sums[blockIdx.x];
+  uint32_t p = block_exclusive<uint32_t>(f, sh, total) + off;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     if (v[k]) {
@@ -463,7 +495,7 @@ __global__ __launch_bounds__(kScanThreads) void k_compact_apply(const uint32_t* 
   }
 }
 
-// Pair offsets, pass 1 of 3: per block of kScanTile depth-ordered particles, the sum of their
+// Pair offsets, pass 1 of 2: per block of kScanTile depth-ordered particles, the sum of their
 // super-tile counts (0 past the visible count).
 __global__ __launch_bounds__(kScanThreads) void k_gather_reduce(const uint32_t* __restrict__ order,
                                                                 const uint32_t* __restrict__ scount,
@@ -481,12 +513,14 @@ __global__ __launch_bounds__(kScanThreads) void k_gather_reduce(const uint32_t* 
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-// Pass 3 of 3: offs[i] = exclusive prefix of the super-tile counts in depth order.
+// Pass 2 of 2: offs[i] = exclusive prefix of the super-tile counts in depth order, *total the
+// pair total (block 0).
 __global__ __launch_bounds__(kScanThreads) void k_gather_apply(const uint32_t* __restrict__ order,
                                                                const uint32_t* __restrict__ scount,
                                                                const uint32_t* __restrict__ m_dev, int n,
-                                                               const uint64_t* __restrict__ sums,
-                                                               uint64_t* __restrict__ offs) {
+                                                               const uint64_t* __restrict__ sums, int nb,
+                                                               uint64_t* __restrict__ offs,
+                                                               uint64_t* __restrict__ total_out) {
   __shared__ uint64_t sh[4];
   const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   const uint32_t m = *m_dev;
@@ -497,8 +531,11 @@ __global__ __launch_bounds__(kScanThreads) void k_gather_apply(const uint32_t* _
     v[k] = base + k < n && (uint32_t)(base + k) < m ? (uint64_t)scount[order[base + k]] : 0ull;
     t += v[k];
   }
+  uint64_t all;
+  const uint64_t off = block_offset<uint64_t>(sums, blockIdx.x, nb, sh, all);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *total_out = all;
   uint64_t total;
-  uint64_t run = block_exclusive<uint64_t>(t, sh, total) + sums[blockIdx.x];
+  uint64_t run = block_exclusive<uint64_t>(t, sh, total) + off;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     if (base + k < n) offs[base + k] = run;
@@ -735,62 +772,84 @@ __global__ __launch_bounds__(kSmallThreads) void k_pairs_small(const uint32_t* _
   }
 }
 
-// One wavefront emits the (super-tile, particle) pairs of 64 consecutive depth-ordered
-// particles, 64 pairs per step.
-__global__ __launch_bounds__(256) void k_duplicate(const uint32_t* __restrict__ order, const uint64_t* __restrict__ offs,
-                                                    const uint32_t* __restrict__ m_dev, const uint2* __restrict__ trect,
-                                                    int n, int tiles_x, int SX, int SH, int wrap,
-                                                    uint32_t* __restrict__ pair_key, uint32_t* __restrict__ pair_gauss,
-                                                    const uint32_t* __restrict__ emit, uint32_t* __restrict__ clear,
-                                                    int n_clear) {
-  // block 0 clears the pair sort's counters (the sort runs next on the same stream)
-  if (blockIdx.x == 0)
-    for (int i = threadIdx.x; i < n_clear; i += 256) clear[i] = 0u;
-  if (emit && *emit == 0u) return;   // device-count sort: nothing to emit, or over capacity
-  __shared__ uint32_t s_off[4][64], s_g[4][64];
-  __shared__ int s_x0[4][64], s_y0[4][64], s_w[4][64];
-  const int lane = __lane_id(), wave = threadIdx.x >> 6;
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  const bool valid = j < n && (uint32_t)j < *m_dev;
-  uint32_t gi = 0, c = 0;
-  uint64_t off = 0;
-  int sx0 = 0, sy0 = 0, nc = 1;
-  if (valid) {
-    gi = order[j];
-    off = offs[j];
-    const uint2 r = trect[gi];
-    const int x0 = (int)(r.x & 0xFFFFu), y0 = (int)(r.x >> 16), x1 = (int)(r.y & 0xFFFFu), y1 = (int)(r.y >> 16);
-    nc = super_cols(x0, x1, tiles_x, SX, wrap, &sx0);
-    sy0 = y0 / SH;
-    c = (uint32_t)(nc * (y1 / SH - sy0 + 1));
+// Pair emission balanced over the pairs rather than the particles: near particles touch the
+// most super-tiles and sit together in depth order, so emitting per particle leaves a few
+// wavefronts with most of the pairs.  Block b writes the kEmitChunk pairs [b C, (b + 1) C):
+// two wavefronts find the particles holding its first and last pair (64-way searches of the
+// strictly increasing offsets), the block stages those particles' offsets and super-tile
+// rects in LDS, and every thread places its pairs by a binary search there.
+constexpr int kEmitThreads = 256;
+constexpr int kEmitChunk = 1024;
+
+// Largest j in [0, m) with offs[j] <= q, for offs strictly increasing with offs[0] = 0 <= q;
+// one wavefront, every lane returns the same j.
+__device__ int find_particle(const uint64_t* __restrict__ offs, int m, uint64_t q) {
+  const int lane = __lane_id();
+  int lo = 0, hi = m;
+  while (hi - lo > 1) {
+    const int stride = (hi - lo + 63) / 64;
+    const int idx = lo + lane * stride;
+    const unsigned long long b = __ballot(idx < hi && offs[idx] <= q);
+    lo += (63 - __clzll(b)) * stride;   // lane 0 always holds: offs[lo] <= q
+    hi = min(hi, lo + stride);
   }
-  // lanes past the visible count keep off = 0; the wave base must come from lane 0, which is
-  // valid whenever any lane of the wave is
-  if (!valid) off = 0;
-  const uint64_t wbase = (uint64_t)__shfl((unsigned long long)off, 0);
-  const uint32_t local = (uint32_t)(off - wbase);
-  uint32_t end = valid ? local + c : 0u;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) end = max(end, (uint32_t)__shfl_xor(end, o));
-  const uint32_t wave_total = end;
-  s_off[wave][lane] = valid ? local : wave_total;
-  s_g[wave][lane] = gi;
-  s_x0[wave][lane] = sx0;
-  s_y0[wave][lane] = sy0;
-  s_w[wave][lane] = nc;
+  return lo;
+}
+
+__global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(const uint32_t* __restrict__ order,
+                                                              const uint64_t* __restrict__ offs,
+                                                              const uint32_t* __restrict__ m_dev,
+                                                              const uint2* __restrict__ trect, int n, int tiles_x, int SX,
+                                                              int SH, int wrap, uint64_t P_host,
+                                                              const uint32_t* __restrict__ P_dev,
+                                                              uint32_t* __restrict__ pair_key,
+                                                              uint32_t* __restrict__ pair_gauss,
+                                                              uint32_t* __restrict__ clear, int n_clear) {
+  // the blocks clear the pair sort's counters (the sort runs next on the same stream)
+  for (int i = blockIdx.x * kEmitThreads + threadIdx.x; i < n_clear; i += gridDim.x * kEmitThreads) clear[i] = 0u;
+  const uint64_t P = P_dev ? (uint64_t)*P_dev : P_host;   // device count: 0 = nothing to emit
+  const uint64_t q0 = (uint64_t)blockIdx.x * kEmitChunk;
+  if (q0 >= P) return;
+  const uint32_t len = (uint32_t)min((uint64_t)kEmitChunk, P - q0);
+  const int m = min(n, (int)*m_dev);
+  __shared__ int s_j[2];
+  __shared__ uint32_t s_start[kEmitChunk], s_g[kEmitChunk];
+  __shared__ int s_x0[kEmitChunk], s_y0[kEmitChunk], s_w[kEmitChunk];
+  __shared__ uint32_t s_skip;
+  const int wave = threadIdx.x >> 6;
+  if (wave < 2) {
+    const int j = find_particle(offs, m, wave == 0 ? q0 : q0 + len - 1);
+    if (__lane_id() == 0) s_j[wave] = j;
+  }
   __syncthreads();
-  for (uint32_t p = lane; p < wave_total; p += 64) {
-    int lo = 0;
-#pragma unroll
-    for (int step = 32; step > 0; step >>= 1)
-      if (s_off[wave][lo + step] <= p) lo += step;
-    const uint32_t q = p - s_off[wave][lo];
-    const int w = s_w[wave][lo];
-    const int y = s_y0[wave][lo] + (int)(q / (uint32_t)w);
-    int x = s_x0[wave][lo] + (int)(q % (uint32_t)w);
+  const int j0 = s_j[0], cnt = s_j[1] - j0 + 1;   // every particle after j0 starts inside the chunk: cnt <= C
+  for (int k = threadIdx.x; k < cnt; k += kEmitThreads) {
+    const uint64_t o = offs[j0 + k];
+    s_start[k] = o > q0 ? (uint32_t)(o - q0) : 0u;
+    if (k == 0) s_skip = (uint32_t)(q0 - o);   // pairs of the first particle before the chunk
+    const uint32_t gi = order[j0 + k];
+    const uint2 r = trect[gi];
+    const int x0 = (int)(r.x & 0xFFFFu), y0 = (int)(r.x >> 16), x1 = (int)(r.y & 0xFFFFu);
+    int sx0;
+    s_w[k] = super_cols(x0, x1, tiles_x, SX, wrap, &sx0);
+    s_x0[k] = sx0;
+    s_y0[k] = y0 / SH;
+    s_g[k] = gi;
+  }
+  __syncthreads();
+  int top = 1;
+  while (2 * top <= cnt) top <<= 1;
+  for (uint32_t l = threadIdx.x; l < len; l += kEmitThreads) {
+    int k = 0;
+    for (int step = top; step > 0; step >>= 1)
+      if (k + step < cnt && s_start[k + step] <= l) k += step;
+    const uint32_t q = l - s_start[k] + (k == 0 ? s_skip : 0u);
+    const int w = s_w[k];
+    const int y = s_y0[k] + (int)(q / (uint32_t)w);
+    int x = s_x0[k] + (int)(q % (uint32_t)w);
     if (x >= SX) x -= SX;
-    pair_key[wbase + p] = (uint32_t)(y * SX + x);
-    pair_gauss[wbase + p] = s_g[wave][lo];
+    pair_key[q0 + l] = (uint32_t)(y * SX + x);
+    pair_gauss[q0 + l] = s_g[k];
   }
 }
 
@@ -947,19 +1006,17 @@ hipError_t launch_bin_count(const ut_projected& p, int n, const SensorK& s, Coun
   uint32_t* sums32 = reinterpret_cast<uint32_t*>(ws.scan_aux);
   // visible particles (tile count > 0) compacted in index order, then depth-sorted
   hipLaunchKernelGGL(k_prep_reduce, dim3(nb), dim3(kScanThreads), 0, st, p.count, p.rect, s.tiles_x, s.super_x,
-                     s.super_h, wrap, ws.scount, n, sums32);
-  hipLaunchKernelGGL(k_scan_sums<uint32_t>, dim3(1), dim3(kScanThreads), 0, st, sums32, (size_t)nb, ws.m_dev);
-  hipLaunchKernelGGL(k_compact_apply, dim3(nb), dim3(kScanThreads), 0, st, p.key, ws.scount, n, sums32, ws.dkA, ws.dvA,
-                     ws.hist, (int)radix_clear_words());
+                     s.super_h, wrap, ws.scount, n, sums32, ws.hist, (int)radix_clear_words());
+  hipLaunchKernelGGL(k_compact_apply, dim3(nb), dim3(kScanThreads), 0, st, p.key, ws.scount, n, sums32, nb, ws.dkA,
+                     ws.dvA, ws.m_dev);
   uint32_t *kr, *vr;
   hipError_t e = radix_sort(ws.dkA, ws.dkB, ws.dvA, ws.dvB, (size_t)n, ws.m_dev, 32, ws.hist, st, &kr, &vr, true);
   if (e != hipSuccess) return e;
   // 4 passes: the result is back in the A buffers; the pair offsets in depth order
   hipLaunchKernelGGL(k_gather_reduce, dim3(nb), dim3(kScanThreads), 0, st, ws.dvA, ws.scount, ws.m_dev, n,
                      ws.scan_aux);
-  hipLaunchKernelGGL(k_scan_sums<uint64_t>, dim3(1), dim3(kScanThreads), 0, st, ws.scan_aux, (size_t)nb, ws.total);
   hipLaunchKernelGGL(k_gather_apply, dim3(nb), dim3(kScanThreads), 0, st, ws.dvA, ws.scount, ws.m_dev, n,
-                     ws.scan_aux, ws.offs);
+                     ws.scan_aux, nb, ws.offs, ws.total);
   return hipGetLastError();
 }
 
@@ -979,10 +1036,10 @@ hipError_t launch_bin_sort(const ut_projected& p, int n, const SensorK& s, Count
   // place the emitted pair values so that the last radix pass writes into bins.gauss
   uint32_t* v_first = (radix_passes(bits) % 2) ? pw.tv : bins.gauss;
   uint32_t* v_second = (radix_passes(bits) % 2) ? bins.gauss : pw.tv;
-  const int blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(256), 0, st, ws.dvA, ws.offs, ws.m_dev,
-                     reinterpret_cast<const uint2*>(p.trect), n, s.tiles_x, s.super_x, s.super_h, s.kind == UT_LIDAR ? 1 : 0,
-                     pw.tkA, v_first, nullptr, pw.hist, (int)radix_clear_words());
+  const unsigned blocks = (unsigned)((n_pairs + kEmitChunk - 1) / kEmitChunk);
+  hipLaunchKernelGGL(k_emit_pairs, dim3(blocks), dim3(kEmitThreads), 0, st, ws.dvA, ws.offs, ws.m_dev,
+                     reinterpret_cast<const uint2*>(p.trect), n, s.tiles_x, s.super_x, s.super_h,
+                     s.kind == UT_LIDAR ? 1 : 0, n_pairs, nullptr, pw.tkA, v_first, pw.hist, (int)radix_clear_words());
   uint32_t *kr, *vr;
   e = radix_sort(pw.tkA, pw.tkB, v_first, v_second, (size_t)n_pairs, nullptr, bits, pw.hist, st, &kr, &vr, true);
   if (e != hipSuccess) return e;
@@ -1024,10 +1081,11 @@ hipError_t launch_bin_sort_device(const ut_projected& p, int n, const SensorK& s
   const int bits = tile_bits(n_super);
   uint32_t* v_first = (radix_passes(bits) % 2) ? pw.tv : bins.gauss;
   uint32_t* v_second = (radix_passes(bits) % 2) ? bins.gauss : pw.tv;
-  const int blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(256), 0, st, ws.dvA, ws.offs, ws.m_dev,
-                     reinterpret_cast<const uint2*>(p.trect), n, s.tiles_x, s.super_x, s.super_h, s.kind == UT_LIDAR ? 1 : 0,
-                     pw.tkA, v_first, pw.n_dev, pw.hist, (int)radix_clear_words());
+  const unsigned blocks = (unsigned)((max_pairs + kEmitChunk - 1) / kEmitChunk);
+  hipLaunchKernelGGL(k_emit_pairs, dim3(blocks), dim3(kEmitThreads), 0, st, ws.dvA, ws.offs, ws.m_dev,
+                     reinterpret_cast<const uint2*>(p.trect), n, s.tiles_x, s.super_x, s.super_h,
+                     s.kind == UT_LIDAR ? 1 : 0, max_pairs, pw.n_dev, pw.tkA, v_first, pw.hist,
+                     (int)radix_clear_words());
   uint32_t *kr, *vr;
   e = radix_sort(pw.tkA, pw.tkB, v_first, v_second, (size_t)max_pairs, pw.n_dev, bits, pw.hist, st, &kr, &vr, true);
   if (e != hipSuccess) return e;

@@ -80,6 +80,7 @@ hipError_t launch_backward(const ut_gaussians& g, const ut_projected& p, const u
 
 // Radix sort of (key, value) pairs, shared by the binning and the spatial order.
 size_t radix_ws_bytes(size_t n_max);
+size_t radix_tiles(size_t n_max);
 size_t radix_clear_words();
 hipError_t radix_sort(uint32_t* kA, uint32_t* kB, uint32_t* vA, uint32_t* vB, size_t n_max,
                       const uint32_t* n_dev, int bits, uint32_t* ws, hipStream_t st,
