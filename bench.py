@@ -85,6 +85,10 @@ def parse():
     ap.add_argument("--lidar-sweep", action="store_true",
                     help="instead of the frame benchmark: LiDAR tiling sweep (N_phi x M) and culling ablation "
                          "on the 300,000-particle 128x2048 LiDAR workload")
+    ap.add_argument("--config-only", type=int, choices=(0, 1, 2, 3), default=None,
+                    help="instead of the frame benchmark: render one single-sensor workload (0: pinhole "
+                         "128x96, 1: fisheye 1920x1280, 2: LiDAR 128x2048, 3: pinhole 1920x1080) K times with the "
+                         "pair total kept on the GPU, for a kernel profile of that workload alone")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/ summaries from rocprofv3 CSV output (kernel stats, FETCH_SIZE "
                          "and WRITE_SIZE counter collections) instead of benchmarking")
@@ -173,6 +177,41 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+CONFIG_SCENES = ("scene_pinhole_small", "scene_fisheye", "scene_lidar", "scene_pinhole_large")
+
+
+def config_only(args):
+    """One single-sensor workload alone: W warm-up renders, then K renders with the pair total
+    kept on the GPU (each synchronised); prints the median frame time."""
+    import torch
+
+    import paper_2510_12901_amd as ut
+    import synth
+
+    dev = torch.device("cuda:0")
+    g_np, s_np = getattr(synth, CONFIG_SCENES[args.config_only])(args.seed)
+    g = ut.GaussianSet.from_numpy(g_np, dev)
+    s = ut.Sensor(s_np, dev)
+    pipe = ut.SensorPipeline(g, s)
+    stream = torch.cuda.current_stream()
+    for _ in range(SETUP_FRAMES + args.warmup):
+        pipe.run(stream)
+    torch.cuda.synchronize()
+    pipe.set_capacity(int(pipe.n_pairs * 1.25) + 4096)
+    pipe.run_device(stream)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        pipe.run_device(stream)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    if pipe.overflowed():
+        raise RuntimeError("pair capacity exceeded")
+    print(json.dumps({"workload": CONFIG_SCENES[args.config_only], "rays": s.n_rays, "bin_pairs": pipe.n_pairs,
+                      "frame_ms_device_count": round(float(np.median(times)) * 1e3, 4)}))
+
+
 def lidar_sweep(args):
     """Tiling sweep and culling ablation on the LiDAR workload (300,000 particles, 128 beams x
     2048 azimuth steps): for every (N_phi, M) the whole LiDAR render (projection with culling,
@@ -232,6 +271,9 @@ def main():
         return
     if args.lidar_sweep:
         lidar_sweep(args)
+        return
+    if args.config_only is not None:
+        config_only(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -655,6 +697,8 @@ def bench_configs(ut, synth, dev, args):
       depth sort: per visible particle 4 radix passes of 16 B (key and value in and out) plus
                   4 B for the digit histogram, and 16 B per particle for the compaction;
       pair sort:  per super-tile pair 8 B emitted, 16 B per radix pass, 4 B for the ranges.
+    Compositing is priced against the VALU roof (65 lane-ops per evaluated pair, counted by a
+    counting launch, over the average of back-to-back launches).
     The same workloads drawn with the next two seeds are timed as whole frames."""
     import torch
     stream = torch.cuda.current_stream()
@@ -709,6 +753,14 @@ def bench_configs(ut, synth, dev, args):
         frame_dev_ms = float(np.median(dtimes)) * 1e3
         if pipe.overflowed():
             raise RuntimeError(f"{name}: pair capacity exceeded")
+        # the compositing kernel against the VALU roof: lane-ops of the pairs it evaluates (a
+        # counting launch) over the average of back-to-back launches
+        oc = ut.alloc_out(s, dev, state=True, counters=True)
+        pipe.composite_only(stream, oc)
+        c_ms = _launch_ms(stream, lambda: pipe.composite_only(stream))
+        c_vis = int(oc.n_visit.to(torch.int64).sum().item())
+        del oc
+        c_ach = LANE_OPS_PER_PAIR * c_vis / (c_ms * 1e-3) / 1e12
         med = {k: float(np.median(v)) for k, v in st_ms.items()}
         n, Kc = g.n, (g.sh_degree + 1) ** 2
         n_super = int(s.n_super)
@@ -723,6 +775,9 @@ def bench_configs(ut, synth, dev, args):
             "frame_ms_device_count": round(frame_dev_ms, 4),
             "mrays_per_s_device_count": round(s.n_rays / frame_dev_ms / 1e3, 2), "visible": V, "bin_pairs": P,
             "stage_ms": {k: round(v, 4) for k, v in med.items()},
+            "composite_roofline": {"bound": "alu", "achieved": round(c_ach, 3), "peak": round(PEAK_VALU_TOPS, 2),
+                                   "unit": "T VALU lane-ops/s", "frac": round(c_ach / PEAK_VALU_TOPS, 4),
+                                   "evaluated_pairs_per_launch": c_vis, "avg_launch_ms": round(c_ms, 4)},
             "hbm_frac": {"project": round(gbps(b_proj, med["project"]) / PEAK_HBM_GBS, 3),
                          "depth_sort": round(gbps(b_depth, med["depth_sort"]) / PEAK_HBM_GBS, 3),
                          "pair_sort": round(gbps(b_pair, med["pair_sort"]) / PEAK_HBM_GBS, 3)}}
