@@ -4,7 +4,7 @@
 // is replayed from the largest n_proc of the workgroup down to 0, in LDS batches.  Each
 // lane recomputes its pair exactly as the forward did (same expressions), recovers
 // T_i = T_{i+1} / (1 - alpha_i) from the stored final transmittance, and keeps the suffix
-// sum S = sum_{j>i} w_j a_j.  Per pair it forms 13 partials (colour 3, opacity, mean 3,
+// sum S = sum_{j>i} w_j a_j.  Per pair it forms 13 partials (colour 3, ln opacity, mean 3,
 // the 6 unique entries of B = Sigma^{-1}); wavefronts whose lanes touched the particle
 // reduce all 13 across 64 lanes in one reduce-scatter (17 exchanges) and 13 lanes add them
 // into the step's LDS sums (float64 LDS atomics), which reach the SoA accumulators acc[13][n]
@@ -117,6 +117,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MOVING ? 
     }
   }
   const double Tf = T;
+  const double gomTf = gom * Tf;   // the alpha output's upstream term, the same for every pair of the ray
   const RayQ rq = ray_q(dx, dy, dz);
   double S = 0.0;
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
@@ -223,8 +224,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MOVING ? 
             const double ioma = rcp_f64(1.0 - alpha);
             const double Ti = T * ioma;
             const double w = alpha * Ti;
-            const double ai = gf0 * r.feat[0] + gf1 * r.feat[1] + gf2 * r.feat[2] + gdep * tau;
-            const double dalpha = Ti * ai - S * ioma + gom * Tf * ioma;
+            const double ai = __builtin_fma(gf0, r.feat[0], __builtin_fma(gf1, r.feat[1],
+                                            __builtin_fma(gf2, r.feat[2], gdep * tau)));
+            const double dalpha = __builtin_fma(Ti, ai, (gomTf - S) * ioma);
             S = __builtin_fma(w, ai, S);
             T = Ti;
             g[0] = gf0 * w;
@@ -233,8 +235,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MOVING ? 
             const double dtau = gdep * w;
             double dD2 = 0.0;
             if (!clamped) {
-              g[3] = dalpha * (a / exp_neg(r.log_sigma, kExp2Frac));   // dL/dsigma = dL/dalpha * rho
-              dD2 = -0.5 * dalpha * a;
+              g[3] = dalpha * a;   // dL/d ln sigma: alpha = sigma rho, so d alpha / d ln sigma = alpha
+              dD2 = -0.5 * g[3];
             }
             // B d from the record's quadric and B u = B v - t* B d, u = mu - o - t* d (for thin
             // records B u from u itself: the difference cancels like the forward's num)
@@ -256,16 +258,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MOVING ? 
               buy = __builtin_fma(-tau, bdy, cv.bv[1]);
               buz = __builtin_fma(-tau, bdz, cv.bv[2]);
             }
+            // dL/dmu = 2 dD2 B u + (dtau / d^T B d) B d; dL/dB_kl from u u^T and the tau term
+            // (d u^T + u d^T) / 2, factored so each partial is one or two FMAs
             const double t2 = 2.0 * dD2, ti = dtau * pr.idbd;
-            g[4] = t2 * bux + ti * bdx;
-            g[5] = t2 * buy + ti * bdy;
-            g[6] = t2 * buz + ti * bdz;
-            g[7] = dD2 * ux * ux + ti * dx * ux;
-            g[8] = dD2 * uy * uy + ti * dy * uy;
-            g[9] = dD2 * uz * uz + ti * dz * uz;
-            g[10] = t2 * ux * uy + ti * (dx * uy + dy * ux);
-            g[11] = t2 * ux * uz + ti * (dx * uz + dz * ux);
-            g[12] = t2 * uy * uz + ti * (dy * uz + dz * uy);
+            const double tdx = ti * dx, tdy = ti * dy, tdz = ti * dz;
+            g[4] = __builtin_fma(t2, bux, ti * bdx);
+            g[5] = __builtin_fma(t2, buy, ti * bdy);
+            g[6] = __builtin_fma(t2, buz, ti * bdz);
+            g[7] = ux * __builtin_fma(dD2, ux, tdx);
+            g[8] = uy * __builtin_fma(dD2, uy, tdy);
+            g[9] = uz * __builtin_fma(dD2, uz, tdz);
+            g[10] = __builtin_fma(ux, __builtin_fma(t2, uy, tdy), uy * tdx);
+            g[11] = __builtin_fma(ux, __builtin_fma(t2, uz, tdz), uz * tdx);
+            g[12] = __builtin_fma(uy, __builtin_fma(t2, uz, tdz), uz * tdy);
           }
         }
       }
@@ -334,7 +339,7 @@ __global__ __launch_bounds__(256) void k_chain(ut_gaussians g, SensorK s, const 
                          2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
     const double sc[3] = {exp((double)l0), exp((double)l1), exp((double)l2)};
     const double sigma = 1.0 / (1.0 + exp(-(double)lg));
-    dlogit = a[3] * sigma * (1.0 - sigma);
+    dlogit = a[3] * (1.0 - sigma);   // a[3] = dL/d ln sigma; d ln sigma / d logit = 1 - sigma
     // unique-entry gradient of B -> full symmetric G
     const double G[9] = {a[7], 0.5 * a[10], 0.5 * a[11], 0.5 * a[10], a[8], 0.5 * a[12], 0.5 * a[11], 0.5 * a[12], a[9]};
     const double vx = mx - s.o[0], vy = my - s.o[1], vz = mz - s.o[2];
