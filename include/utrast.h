@@ -15,7 +15,7 @@
  *                         (walking the super-tile bins backwards)
  *
  * plus host set-up (ut_lidar_tiling = Alg. 1, ut_sensor_build = ray mask / summed-area
- * table of Appendix B), a batched, persistent composite for serving, and the scene graph's
+ * table of Appendix B), a batched composite for serving, and the scene graph's
  * rigid actor transforms (ut_actor_transform and its adjoint) that bring dynamic objects'
  * particles to the world frame before projection.
  *
@@ -372,10 +372,9 @@ ut_status ut_composite_backward(const ut_gaussians* g, const ut_projected* p,
                                 const ut_upstream* up, void* acc_ws, size_t acc_ws_bytes,
                                 ut_gaussian_grads* grads, ut_stream stream);
 
-/* Batched persistent compositing for serving.  One launch composites the tiles of several
- * independent render requests (any mix of camera and LiDAR sensors, each with its own
- * projection, lists and outputs): a fixed grid of workgroups pulls (request, tile) work
- * items from a device counter until the queue is exhausted.  Per-ray arithmetic is the
+/* Batched compositing for serving.  One launch composites the tiles of several independent
+ * render requests (any mix of camera and LiDAR sensors, each with its own projection, lists
+ * and outputs) as (request, tile) work items.  Per-ray arithmetic is the
  * same as ut_composite_camera / ut_composite_lidar, so every ray's output is bit-identical
  * to the single-request call.  items: host array [n_items]; queue_ws: device workspace of
  * ut_batch_workspace_bytes(n_items) bytes.  n_workgroups > 0: that many persistent workgroups

@@ -372,7 +372,7 @@ ut_status enqueue_batch(const ut_batch_item* items, int32_t n_items, const ut_re
       return UT_ERR_ARG;
     if (it.sensor->max_tile_rays > 256) return UT_ERR_UNSUPPORTED;   // one lane per ray of a 256-lane group
   }
-  // items in four groups, each its own persistent launch: static or moving sensor (the per-ray
+  // items in four groups, each its own launch: static or moving sensor (the per-ray
   // origins of a moving sensor would otherwise cost every static pair registers), tiles or LiDAR
   // units (several azimuth tiles per 256-lane workgroup)
   BatchGroups grp;

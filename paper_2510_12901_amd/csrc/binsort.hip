@@ -74,67 +74,6 @@ __device__ __forceinline__ T block_exclusive(T v, T* sh /*[4]*/, T& total) {
   return before + x - v;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T* __restrict__ in, size_t n, T* __restrict__ sums) {
-  __shared__ T sh[4];
-  const size_t base = (size_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  T s = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < n) s += in[base + k];
-  T total;
-  block_exclusive<T>(s, sh, total);
-  if (threadIdx.x == 0) sums[blockIdx.x] = total;
-}
-
-// single-block exclusive scan of the block sums, chunk by chunk with a running carry
-template <typename T>
-__global__ __launch_bounds__(kScanThreads) void k_scan_sums(T* sums, size_t nb, T* total_out) {
-  __shared__ T sh[4];
-  T carry = 0;
-  for (size_t base = 0; base < nb; base += kScanThreads) {
-    const size_t i = base + threadIdx.x;
-    const T v = i < nb ? sums[i] : 0;
-    T tot;
-    const T ex = block_exclusive<T>(v, sh, tot);
-    if (i < nb) sums[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0 && total_out) *total_out = carry;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const T* __restrict__ in, T* __restrict__ out, size_t n,
-                                                               const T* __restrict__ sums) {
-  __shared__ T sh[4];
-  const size_t base = (size_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  T v[kScanItems];
-  T s = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    v[k] = base + k < n ? in[base + k] : 0;
-    s += v[k];
-  }
-  T total;
-  T run = block_exclusive<T>(s, sh, total) + sums[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < n) out[base + k] = run;
-    run += v[k];
-  }
-}
-
-// in-place exclusive scan of n elements; aux needs ceil(n/1024) elements; *total_out = sum
-template <typename T>
-hipError_t exclusive_scan(T* data, size_t n, T* aux, T* total_out, hipStream_t st) {
-  const size_t nb = (n + kScanTile - 1) / kScanTile;
-  if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, st, data, n, aux);
-  hipLaunchKernelGGL(k_scan_sums<T>, dim3(1), dim3(kScanThreads), 0, st, aux, nb, total_out);
-  hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, st, data, data, n, aux);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------------- radix
 constexpr int kRadix = 256;
 constexpr int kSortThreads = 256;   // one thread per digit in the look-back

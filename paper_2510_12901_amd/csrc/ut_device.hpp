@@ -287,7 +287,7 @@ __device__ __forceinline__ bool record_thin(const Rec& c) { return c.vbv > kThin
 
 // Response of one (ray, record) pair for a ray whose origin lies e from the record's sensor
 // origin (cv = pair_centre(c, e), or record_centre(c) with e = 0).  Returns false when the
-// pair cannot reach alpha_min (D^2 > cut); otherwise pr holds 1/d^T B d, t* and D^2.  The
+// pair cannot reach alpha_min (D^2 > cut); pr holds 1/d^T B d, t* and D^2 either way.  The
 // compositing and the adjoint both evaluate pairs here, so their alphas are bit-identical.
 // Every active lane of a wavefront evaluates the same record, so the thin test is taken from
 // the first active lane as a scalar branch.
@@ -306,9 +306,8 @@ __device__ __forceinline__ bool pair_eval(const Rec& c, const Centre& cv, const 
     pr.D2 = __builtin_fmax(__builtin_fma(2.0, cross, diag), 0.0);
     return !(pr.D2 > cut);
   }
-  if (pair_cut(q, cut)) return false;
-  pr = pair_response(q);
-  return true;
+  pr = pair_response(q);   // formed before the test, so a caller can select on the result
+  return !pair_cut(q, cut);
 }
 
 // Unclamped opacity of the pair, sigma * exp(-D^2 / 2), evaluated as exp(ln sigma - D^2 / 2).

@@ -54,7 +54,7 @@ hipError_t launch_composite(const ut_projected& p, const ut_bin_lists& bins, con
                             const RenderParamsK& prm, const ut_render_out& out, int max_tile_rays,
                             hipStream_t st);
 
-// Batched persistent compositing over several requests.
+// Batched compositing over several requests.
 struct BatchItemK {
   SensorK s;
   const RecordG* rec;

@@ -352,9 +352,10 @@ def backward(g: GaussianSet, p: Projection, bins: BinLists, sensor: Sensor, fwd:
     return grads
 
 
-def composite_batch(items, params=None, n_workgroups=None, ws: torch.Tensor | None = None, stream=None):
-    """One launch compositing several (projection, lists, sensor, out) requests: n_workgroups
-    persistent workgroups (default 1024), or 0 for one workgroup per (request, tile) item."""
+def composite_batch(items, params=None, n_workgroups=0, ws: torch.Tensor | None = None, stream=None):
+    """One launch compositing several (projection, lists, sensor, out) requests: one workgroup
+    per (request, tile) item (n_workgroups = 0, the default), or that many persistent
+    workgroups looping over the items."""
     n = len(items)
     prm = params or render_params()
     arr = (A.UtBatchItem * n)()
@@ -367,8 +368,6 @@ def composite_batch(items, params=None, n_workgroups=None, ws: torch.Tensor | No
     dev = items[0][0].records.device
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
-    if n_workgroups is None:
-        n_workgroups = 256 * 4
     check(lib().ut_composite_batch(C.cast(arr, C.c_void_p), n, ref(prm), ws.data_ptr(), ws.numel(), n_workgroups, _stream(stream)),
           "ut_composite_batch")
     return ws
