@@ -179,12 +179,22 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     int invalid = 0, raycull = 0;
     const float mx = g.mean[i], my = g.mean[n + i], mz = g.mean[2 * n + i];
-    const float q0 = g.quat[i], q1 = g.quat[n + i], q2 = g.quat[2 * n + i], q3 = g.quat[3 * n + i];
-    const float l0 = g.log_scale[i], l1 = g.log_scale[n + i], l2 = g.log_scale[2 * n + i];
-    const float lg = g.opacity_logit[i];
+    // The UT's first sigma point is the mean: where its projection is invalid (behind a
+    // pinhole, outside a fisheye's field of view) the particle is culled as invalid whatever its
+    // other parameters, so those are neither loaded nor set up (about half of the particles
+    // around a camera).  Outputs are exactly those of the full path.
+    double gu0 = 0, gv0 = 0;
+    const double mu[3] = {(double)mx, (double)my, (double)mz};
+    const bool mean_ok =
+        isfinite(mx) && isfinite(my) && isfinite(mz) && project_point<KIND, MOVING>(s, mu, gu0, gv0);
+    float q0 = 1.0f, q1 = 0.0f, q2 = 0.0f, q3 = 0.0f, l0 = 0.0f, l1 = 0.0f, l2 = 0.0f, lg = 0.0f;
+    if (mean_ok) {
+      q0 = g.quat[i]; q1 = g.quat[n + i]; q2 = g.quat[2 * n + i]; q3 = g.quat[3 * n + i];
+      l0 = g.log_scale[i]; l1 = g.log_scale[n + i]; l2 = g.log_scale[2 * n + i];
+      lg = g.opacity_logit[i];
+    }
     const double qq = (double)q0 * q0 + (double)q1 * q1 + (double)q2 * q2 + (double)q3 * q3;
-    bool ok = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(l0) && isfinite(l1) &&
-              isfinite(l2) && isfinite(lg) && isfinite(qq) && qq > 0;
+    bool ok = mean_ok && isfinite(l0) && isfinite(l1) && isfinite(l2) && isfinite(lg) && isfinite(qq) && qq > 0;
     RecordG r;
     double M[9], A[3];   // M with M^T M = Sigma^{-1}, and A = M (mu - o)
     double Rm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, sc[3] = {1, 1, 1};
@@ -265,8 +275,8 @@ __device__ __forceinline__ void project_all(const ut_gaussians& g, const SensorK
       if (ok) {
         const double gam = sqrt(cpl);
         double gu[7], gv[7];
-        const double mu[3] = {(double)mx, (double)my, (double)mz};
-        ok = project_point<KIND, MOVING>(s, mu, gu[0], gv[0]);
+        gu[0] = gu0;   // the mean, projected above
+        gv[0] = gv0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
           if (!ok) break;
