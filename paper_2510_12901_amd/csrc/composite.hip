@@ -59,8 +59,8 @@ struct UnitShared {
   uint32_t cposT[kRing][kUnitTilesMax];
   uint32_t rposT[BATCH][kUnitTilesMax];
   uint8_t cmask[kRing];
-  uint8_t rmask[BATCH];
   uint32_t wcntT[BLOCK / 64][kUnitTilesMax];
+  uint8_t tlist[kUnitTilesMax][BATCH];   // per tile: the staged slots of its list entries, in order
   uint32_t nhT[kUnitTilesMax];
   uint32_t tendT[kUnitTilesMax];
 };
@@ -266,21 +266,88 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* 
       if constexpr (TILE_END) sm.rbin[j] = sm.cbin[slot];
       if constexpr (UNIT) {
         const uint32_t m = us->cmask[slot];
-        us->rmask[j] = (uint8_t)m;
         for (int t = 0; t < gt; ++t)
           if ((m >> t) & 1u) us->rposT[j][t] = us->cposT[slot][t];
       }
     }
+    if constexpr (UNIT) {
+      // per tile of the unit, the staged slots of its entries in list order (slot j is thread
+      // j's: a batch never exceeds the workgroup), so each ray walks only its own tile's entries
+      const uint32_t jt = threadIdx.x;
+      const uint32_t mt = jt < cnt ? (uint32_t)us->cmask[(head + jt) & kRing] : 0u;
+      unsigned long long bt[kUnitTilesMax];
+#pragma unroll
+      for (int t = 0; t < kUnitTilesMax; ++t) {
+        bt[t] = __ballot(t < gt && ((mt >> t) & 1u));
+        if (lane == 0) us->wcntT[wave][t] = (uint32_t)__popcll(bt[t]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < kUnitTilesMax; ++t) {
+        if (t < gt && ((mt >> t) & 1u)) {
+          uint32_t p = (uint32_t)__popcll(bt[t] & lt);
+          for (int w = 0; w < wave; ++w) p += us->wcntT[w][t];
+          us->tlist[t][p] = (uint8_t)jt;
+        }
+      }
+    }
     __syncthreads();
-    if (!done) {
+    if constexpr (UNIT) {
+      if (!done) {
+        // LiDAR units: the longest units set the launch time and run alone at the end, so each
+        // ray takes two of its tile's entries per step (two independent float64 chains), then
+        // composites them in list order; the second is evaluated even when the first ends the ray
+        const int t = tl[0];
+        uint32_t n_t = 0;
+        for (int w = 0; w < BLOCK / 64; ++w) n_t += us->wcntT[w][t];
+        auto resp = [&](const Record& r, double& tau, double& alpha, bool& pass) -> bool {
+          Centre cv;
+          if constexpr (MOVING) cv = pair_centre(r, ex[0], ey[0], ez[0]);
+          else cv = record_centre(r);
+          PairResp pr;
+          pass = pair_eval<Record, false>(r, cv, rq[0], MOVING ? ex[0] : 0.0, MOVING ? ey[0] : 0.0,
+                                          MOVING ? ez[0] : 0.0, cut_threshold(r.log_sigma, prm.log_alpha_min), pr);
+          tau = pr.tau;
+          alpha = __builtin_fmin(pair_alpha(r, pr, sm.etab), prm.alpha_max);
+          return pass && tau >= s.near_ && alpha >= prm.alpha_min;
+        };
+        auto add = [&](const Record& r, double tau, double alpha, uint32_t j) {
+          const double w = alpha * T[0];
+          f0[0] = __builtin_fma(w, r.feat[0], f0[0]);
+          f1[0] = __builtin_fma(w, r.feat[1], f1[0]);
+          f2[0] = __builtin_fma(w, r.feat[2], f2[0]);
+          dep[0] = __builtin_fma(w, tau, dep[0]);
+          T[0] = T[0] * (1.0 - alpha);
+          if (T[0] < prm.t_min) {
+            rdone[0] = true;
+            nproc[0] = us->rposT[j][t] + 1;
+            if constexpr (TILE_END) nbin[0] = sm.rbin[j] + 1;
+          }
+        };
+        for (uint32_t p = 0; p < n_t; p += 2) {
+          const bool two = p + 1 < n_t;
+          const uint32_t ja = us->tlist[t][p], jb = two ? us->tlist[t][p + 1] : ja;
+          const Record& ra = sm.rec[ja];
+          const Record& rb = sm.rec[jb];
+          double taua, alpa, taub, alpb;
+          bool passa, passb;
+          const bool hita = resp(ra, taua, alpa, passa);
+          const bool hitb = resp(rb, taub, alpb, passb);
+          if constexpr (STATS) ++nvisit[0], npass[0] += passa ? 1u : 0u;
+          if (hita) add(ra, taua, alpa, ja);
+          if (rdone[0] || !two) break;
+          if constexpr (STATS) ++nvisit[0], npass[0] += passb ? 1u : 0u;
+          if (hitb) add(rb, taub, alpb, jb);
+          if (rdone[0]) break;
+        }
+        done = rdone[0];
+      }
+    } else if (!done) {
       for (uint32_t j = 0; j < cnt; ++j) {
         const Record& r = sm.rec[j];
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
           if (rdone[k]) continue;
-          if constexpr (UNIT) {
-            if (!((us->rmask[j] >> tl[k]) & 1u)) continue;   // not in this ray's tile's list
-          }
           Centre cv;
           if constexpr (MOVING) cv = pair_centre(r, ex[k], ey[k], ez[k]);
           else cv = record_centre(r);
@@ -303,8 +370,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* 
           if (T[k] < prm.t_min) {
             rdone[k] = true;
             // list entries up to and including the terminating one
-            if constexpr (UNIT) nproc[k] = us->rposT[j][tl[k]] + 1;
-            else nproc[k] = sm.rpos[j] + 1;
+            nproc[k] = sm.rpos[j] + 1;
             if constexpr (TILE_END) nbin[k] = sm.rbin[j] + 1;   // bin entries up to and including it
           }
         }
@@ -390,7 +456,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(RPL == 1 
 
 // LiDAR compositing over units of adjacent azimuth tiles (one ray per lane, unit_rays lanes).
 template <int BLOCK, bool STATS, bool MOVING>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 128 ? 3 : 4))) void k_composite_unit(
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 128 || MOVING ? 3 : 4))) void k_composite_unit(
     SensorK s, const RecordG* __restrict__ rec, const uint2* __restrict__ trect, const uint32_t* __restrict__ bgauss,
     const uint32_t* __restrict__ branges, RenderParamsK prm, ut_render_out out) {
   constexpr int kBatchU = BLOCK == 64 ? 32 : 128;   // 64 lanes: small LDS for 4 waves per SIMD
@@ -430,10 +496,11 @@ __global__ __launch_bounds__(kCamBlock) __attribute__((amdgpu_waves_per_eu(3))) 
 
 // The same items with one workgroup per (request, tile) item and no loop: the grid is the
 // batch's item count and the hardware dispatcher is the queue.  Without the persistent loop the
-// kernel keeps the single-request kernel's register budget (4 waves per SIMD, no spill), where
-// the looping kernel needs 168 VGPRs (3 waves).
+// kernel keeps the single-request kernel's register budget (4 waves per SIMD, no spill; 3 for
+// LiDAR units, whose two-entry walk needs a few more registers), where the looping kernel needs
+// 168 VGPRs (3 waves).
 template <bool MOVING, bool UNIT>
-__global__ __launch_bounds__(kCamBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_composite_batch_direct(
+__global__ __launch_bounds__(kCamBlock) __attribute__((amdgpu_waves_per_eu(UNIT ? 3 : 4))) void k_composite_batch_direct(
     const BatchItemK* __restrict__ items, int n_items, RenderParamsK prm) {
   __shared__ CompositeShared<kCamBlock, kCamRpl, kCamBatch> sm;
   __shared__ UnitShared<kCamBlock, kCamBatch> us_mem;

@@ -291,11 +291,13 @@ __device__ __forceinline__ bool record_thin(const Rec& c) { return c.vbv > kThin
 // compositing and the adjoint both evaluate pairs here, so their alphas are bit-identical.
 // Every active lane of a wavefront evaluates the same record, so the thin test is taken from
 // the first active lane as a scalar branch.
-template <class Rec>
+// UNIFORM = false: the lanes may hold different records, so the thin test is taken per lane.
+template <class Rec, bool UNIFORM = true>
 __device__ __forceinline__ bool pair_eval(const Rec& c, const Centre& cv, const RayQ& d, double ex, double ey,
                                           double ez, double cut, PairResp& pr) {
   const PairGeom q = pair_geometry(c, cv, d);
-  if (__builtin_expect(__builtin_amdgcn_readfirstlane((int)record_thin(c)), 0)) {
+  const bool thin = UNIFORM ? __builtin_amdgcn_readfirstlane((int)record_thin(c)) != 0 : record_thin(c);
+  if (__builtin_expect(thin, 0)) {
     pr.idbd = rcp_f64(q.dbd);
     pr.tau = q.dbv * pr.idbd;
     const double ux = __builtin_fma(-pr.tau, d.x, c.v[0] - ex);
