@@ -81,6 +81,7 @@ __device__ __forceinline__ void composite_tile(const SensorK& s, const RecordG* 
                                                CompositeShared<BLOCK, RPL, BATCH>& sm,
                                                UnitShared<BLOCK, BATCH>* us = nullptr) {
   static_assert(!UNIT || RPL == 1, "a unit runs one ray per lane");
+  static_assert(!UNIT || BATCH <= BLOCK, "a unit's per-tile lists give each staged slot its own thread");
   constexpr int kBatch = BATCH;
   constexpr uint32_t kRing = CompositeShared<BLOCK, RPL, BATCH>::kRing - 1;
   int tx, ty, sid, j0 = 0, gt = 1;
