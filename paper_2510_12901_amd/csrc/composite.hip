@@ -7,7 +7,9 @@
 // the tile (the tile-cone test below), stages batches of their 128-byte records in LDS
 // (gathered cooperatively as 16-byte chunks), and every lane walks the batch for its own ray.
 // A lane that reaches T < t_min stops (its wavefront stops when all 64 lanes have), and the
-// workgroup stops once every lane is done.
+// workgroup stops once every lane is done.  LiDAR tiles are composited in units of a few
+// adjacent azimuth tiles per workgroup: the unit keeps the bin entries that meet any of its
+// tiles, with per-tile list positions, and each ray walks only its own tile's entries.
 //
 // Per (ray, particle), from the record's response quadric B = Sigma^{-1}, B v and v^T B v
 // (v = mu - o): d^T B d from the ray's six quadratic monomials, d^T B v, and
@@ -50,9 +52,10 @@ struct CompositeShared {
   TileCone cone;
 };
 
-// What a LiDAR unit (several azimuth tiles in one workgroup) adds: per candidate and staged
-// record the tiles of the unit its rect covers (bit t = tile j0 + t) and its position in
-// each of those tiles' lists, per tile the list entries seen so far and the adjoint's bin end.
+// What a LiDAR unit (several azimuth tiles in one workgroup) adds: per candidate the tiles of
+// the unit its rect covers (bit t = tile j0 + t), per candidate and staged record its position
+// in each of those tiles' lists, per tile the staged slots of its entries, the list entries
+// seen so far and the adjoint's bin end.
 template <int BLOCK, int BATCH>
 struct UnitShared {
   static constexpr uint32_t kRing = CompositeShared<BLOCK, 1, BATCH>::kRing;
