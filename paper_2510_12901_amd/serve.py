@@ -137,6 +137,7 @@ class Slot:
         self.drop = torch.empty(max_rays, dtype=torch.float32, device=device)
         self.ev_sorted = torch.cuda.Event(enable_timing=timing)
         self.ev_sort0 = torch.cuda.Event(enable_timing=True) if timing else None
+        self.ev_proj0 = torch.cuda.Event(enable_timing=True) if timing else None   # before projection
 
     def out_for(self, sensor: Sensor) -> RenderOut:
         R = sensor.n_rays
@@ -225,6 +226,8 @@ class Server:
         gauss = self.pool.view(r.mem, pw, lb).view(torch.int32)
         ranges = self.pool.view(r.mem, pw + lb, rb)[: 8 * sensor.n_super].view(torch.int32).view(2, sensor.n_super)
         r.bins = BinLists(gauss, ranges, r.capacity)
+        if s.ev_proj0 is not None:
+            s.ev_proj0.record(s.stream)
         self._project_count(s, sensor)
         with torch.cuda.stream(s.stream):
             s.overflow.zero_()
@@ -299,6 +302,7 @@ class Server:
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
         sort_times = {}
+        stage_dev = []   # per request: device ms of projection + count, and of the pair sort
         try:
             while n_done < len(reqs):
                 wake.clear()
@@ -319,6 +323,8 @@ class Server:
                         self._raise_bound(r.sensor, P)
                         if self.timing:
                             sort_times[r.rid] = (t_ev0.elapsed_time(r.slot.ev_sort0), t_ev0.elapsed_time(r.slot.ev_sorted))
+                            stage_dev.append((r.slot.ev_proj0.elapsed_time(r.slot.ev_sort0),
+                                              r.slot.ev_sort0.elapsed_time(r.slot.ev_sorted)))
                         if int(r.slot.overflow_host.item()) != 0:
                             # the pair total exceeded the bound: nothing was rendered; again with
                             # the bound raised to the now known total
@@ -393,6 +399,9 @@ class Server:
         if self.timing:
             self.stats["device"] = {"sort_ms": sort_times, "batches_ms": dev_batches}
             self.stats["device_overlap"] = overlap_count(sort_times, dev_batches)
+            if stage_dev:
+                self.stats["device_stage_ms"] = {"project_count": round(float(np.mean([a for a, _ in stage_dev])), 3),
+                                                 "pair_sort": round(float(np.mean([b for _, b in stage_dev])), 3)}
         return reqs
 
 
@@ -524,6 +533,11 @@ def bench_served(g, gl, sensors_np, sensors, dev, args, log):
     treq = timed.run(poisson_trace(30.0 * 8, 2.0, len(sensors), seed=123))
     n_ov = timed.stats["device_overlap"]
     out["device_overlap_v8"] = {"requests": len(treq), "sort_overlapping_other_compositing": n_ov,
-                                "frac": round(n_ov / len(treq), 3), "mean_batch": round(timed.stats["mean_batch"], 2)}
-    log(f"device overlap at V=8: {json.dumps(out['device_overlap_v8'])}")
+                                "frac": round(n_ov / len(treq), 3), "mean_batch": round(timed.stats["mean_batch"], 2),
+                                "device_stage_ms": timed.stats.get("device_stage_ms")}
+    # the same device stages of a request when requests arrive one vehicle at a time
+    t1 = timed.run(poisson_trace(30.0, 2.0, len(sensors), seed=124))
+    out["device_stage_ms_v1"] = timed.stats.get("device_stage_ms")
+    del t1
+    log(f"device overlap at V=8: {json.dumps(out['device_overlap_v8'])}; device stages at V=1: {json.dumps(out['device_stage_ms_v1'])}")
     return out
