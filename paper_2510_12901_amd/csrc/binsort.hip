@@ -50,9 +50,10 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
-// exclusive scan of one value per thread across a 256-thread block; returns the block total
-template <typename T>
-__device__ __forceinline__ T block_exclusive(T v, T* sh /*[4]*/, T& total) {
+// exclusive scan of one value per thread across a THREADS-thread block (sh: THREADS / 64
+// words); returns the block total
+template <typename T, int THREADS = kScanThreads>
+__device__ __forceinline__ T block_exclusive(T v, T* sh, T& total) {
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
   T x = v;
 #pragma unroll
@@ -64,7 +65,7 @@ __device__ __forceinline__ T block_exclusive(T v, T* sh /*[4]*/, T& total) {
   __syncthreads();
   T before = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < kScanThreads / 64; ++w) {
+  for (int w = 0; w < THREADS / 64; ++w) {
     const T s = sh[w];
     if (w < wave) before += s;
     tot += s;
@@ -76,12 +77,18 @@ __device__ __forceinline__ T block_exclusive(T v, T* sh /*[4]*/, T& total) {
 
 // ---------------------------------------------------------------------------------- radix
 constexpr int kRadix = 256;
-constexpr int kSortThreads = 256;   // one thread per digit in the look-back
+// A pass ranks its tile with 4 wavefronts of 16 keys per lane, one wavefront per SIMD: 512 or
+// 1,024 threads rank a tile faster (13.8 and 14.1 against 15.9 us per pass on 214k keys) but
+// need 2 or 4 free wavefront slots per SIMD at once, which a CU busy with another sensor's
+// compositing frees later, and the multi-sensor frame lost 1-4%.  The first kRadix threads
+// own one digit each in the look-back.
+constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;      // keys per lane
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kMaxPasses = 4;
+constexpr int kHistThreads = 256;
 constexpr int kHistItems = 4;                          // keys per lane in the histogram kernel
-constexpr int kHistTile = kSortThreads * kHistItems;   // keys per histogram workgroup
+constexpr int kHistTile = kHistThreads * kHistItems;   // keys per histogram workgroup
 static_assert(kSortTile % kHistTile == 0, "a sort tile is a whole number of histogram tiles");
 // The digit histograms are kept as kHistParts partial copies, workgroup b adding into copy
 // b % kHistParts: device-scope atomics from every workgroup on the same 256 words serialise,
@@ -98,7 +105,7 @@ constexpr uint32_t kLbCount = (1u << 30) - 1u;
 // lane's loads issued up front.  Depth keys concentrate in a few high-byte values, so lanes
 // are first grouped by equal digit (8 ballots) and only one lane per group adds the group's
 // size to the LDS counter; one global atomic per digit present follows.
-__global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __restrict__ keys, size_t n_max,
+__global__ __launch_bounds__(kHistThreads) void k_digit_hist(const uint32_t* __restrict__ keys, size_t n_max,
                                                               const uint32_t* __restrict__ n_dev, int passes,
                                                               uint32_t* __restrict__ hist, uint32_t* __restrict__ look,
                                                               size_t look_tiles) {
@@ -113,7 +120,7 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __r
   if (blockIdx.x % kPerTile == 0)
     for (int p = 0; p < passes; ++p)
       look[((size_t)p * look_tiles + blockIdx.x / kPerTile) * kRadix + threadIdx.x] = 0u;
-  for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kSortThreads) (&h[0][0])[i] = 0;
+  for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kHistThreads) (&h[0][0])[i] = 0;
   __syncthreads();
   const size_t base = start + (size_t)wave * (kHistItems * 64) + lane;
   uint32_t key[kHistItems];
@@ -139,7 +146,7 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __r
   }
   __syncthreads();
   uint32_t* part = hist + (size_t)(blockIdx.x % kHistParts) * kMaxPasses * kRadix;
-  for (int i = threadIdx.x; i < passes * kRadix; i += kSortThreads) {
+  for (int i = threadIdx.x; i < passes * kRadix; i += kHistThreads) {
     const uint32_t c = (&h[0][0])[i];
     if (c) atomicAdd(&part[i], c);
   }
@@ -167,12 +174,20 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
   __shared__ uint32_t local_start[kRadix];   // tile-local exclusive prefix over digits
   __shared__ uint32_t dst_shift[kRadix];     // global start of digit d minus its local start
   __shared__ uint32_t sk[kSortTile], sv[kSortTile];
-  __shared__ uint32_t scan_sh[4];
+  __shared__ uint32_t scan_sh[kWaves];
+  // The loads that do not depend on the tile (the key count, this thread's digit count) go
+  // out together with the ticket, and the tile's keys before the digit-count scan, so the
+  // pass waits on two memory round trips before ranking instead of four.
+  const size_t n = n_dev ? (size_t)*n_dev : n_max;
+  uint32_t c = 0;
+  if (threadIdx.x < kRadix) {
+#pragma unroll
+    for (int g = 0; g < kHistParts; ++g) c += digit_count[(size_t)g * kMaxPasses * kRadix + threadIdx.x];
+  }
   if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
   for (int i = threadIdx.x; i < kWaves * kRadix; i += kSortThreads) (&wcnt[0][0])[i] = 0;
   __syncthreads();
   const uint32_t tile = s_tile;
-  const size_t n = n_dev ? (size_t)*n_dev : n_max;
   const size_t n_tiles = (n + kSortTile - 1) / kSortTile;
   if (tile >= n_tiles) return;
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
@@ -180,22 +195,18 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
   const size_t tile0 = (size_t)tile * kSortTile;
   const size_t base = tile0 + (size_t)wave * (kSortItems * 64) + lane;
   const uint32_t tile_n = (uint32_t)std::min<size_t>(kSortTile, n - tile0);
-  // global start of this thread's digit: exclusive prefix of the pass's digit counts
-  uint32_t digit_base;
-  {
-    uint32_t all;
-    uint32_t c = 0;
-#pragma unroll
-    for (int g = 0; g < kHistParts; ++g) c += digit_count[(size_t)g * kMaxPasses * kRadix + threadIdx.x];
-    digit_base = block_exclusive<uint32_t>(c, scan_sh, all);
-  }
-
   uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
     const size_t i = base + (size_t)k * 64;
     key[k] = i < n ? kin[i] : 0u;
     val[k] = i < n ? vin[i] : 0u;
+  }
+  // global start of this thread's digit: exclusive prefix of the pass's digit counts
+  uint32_t digit_base;
+  {
+    uint32_t all;
+    digit_base = block_exclusive<uint32_t, kSortThreads>(c, scan_sh, all);
   }
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
@@ -217,54 +228,59 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
   }
   __syncthreads();
 
-  // thread d: the tile's count of digit d, each wave's offset, the tile-local digit start and
-  // the look-back for the digit's global start
+  // thread d < kRadix: the tile's count of digit d, each wave's offset, the tile-local digit
+  // start and the look-back for the digit's global start
   {
     const int d = threadIdx.x;
+    const bool own = d < kRadix;
     uint32_t total = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      const uint32_t c = wcnt[w][d];
-      wcnt[w][d] = total;
-      total += c;
-    }
     uint32_t* my = look + (size_t)tile * kRadix + d;
-    __hip_atomic_store(my, (tile == 0 ? kLbPrefix : kLbAggregate) | total, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t tile_total;
-    const uint32_t lstart = block_exclusive<uint32_t>(total, scan_sh, tile_total);
-    local_start[d] = lstart;
-    uint32_t excl = 0;
-    if (tile > 0) {
-      // walk back over the predecessors kLookWindow at a time (independent loads in flight),
-      // adding aggregates until a published inclusive prefix; tile 0 always publishes one
-      constexpr int kLookWindow = 8;
-      int64_t j = (int64_t)tile - 1;
-      for (;;) {
-        uint32_t v[kLookWindow];
+    if (own) {
 #pragma unroll
-        for (int q = 0; q < kLookWindow; ++q)
-          v[q] = j - q >= 0 ? __hip_atomic_load(look + (size_t)(j - q) * kRadix + d, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT)
-                            : kLbPrefix;
-        int used = 0;
-        bool found = false;
-#pragma unroll
-        for (int q = 0; q < kLookWindow; ++q) {
-          if (found || used < q) continue;   // stop at the first prefix or the first gap
-          const uint32_t st = v[q] & ~kLbCount;
-          if (st == 0u) continue;
-          excl += v[q] & kLbCount;
-          used = q + 1;
-          found = st == kLbPrefix;
-        }
-        if (found) break;
-        j -= used;
-        if (used == 0) __builtin_amdgcn_s_sleep(1);
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = wcnt[w][d];
+        wcnt[w][d] = total;
+        total += c;
       }
-      __hip_atomic_store(my, kLbPrefix | (excl + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(my, (tile == 0 ? kLbPrefix : kLbAggregate) | total, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
     }
-    dst_shift[d] = digit_base + excl - lstart;
+    uint32_t tile_total;
+    const uint32_t lstart = block_exclusive<uint32_t, kSortThreads>(total, scan_sh, tile_total);
+    if (own) {
+      local_start[d] = lstart;
+      uint32_t excl = 0;
+      if (tile > 0) {
+        // walk back over the predecessors kLookWindow at a time (independent loads in flight),
+        // adding aggregates until a published inclusive prefix; tile 0 always publishes one
+        constexpr int kLookWindow = 8;
+        int64_t j = (int64_t)tile - 1;
+        for (;;) {
+          uint32_t v[kLookWindow];
+#pragma unroll
+          for (int q = 0; q < kLookWindow; ++q)
+            v[q] = j - q >= 0 ? __hip_atomic_load(look + (size_t)(j - q) * kRadix + d, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT)
+                              : kLbPrefix;
+          int used = 0;
+          bool found = false;
+#pragma unroll
+          for (int q = 0; q < kLookWindow; ++q) {
+            if (found || used < q) continue;   // stop at the first prefix or the first gap
+            const uint32_t st = v[q] & ~kLbCount;
+            if (st == 0u) continue;
+            excl += v[q] & kLbCount;
+            used = q + 1;
+            found = st == kLbPrefix;
+          }
+          if (found) break;
+          j -= used;
+          if (used == 0) __builtin_amdgcn_s_sleep(1);
+        }
+        __hip_atomic_store(my, kLbPrefix | (excl + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      dst_shift[d] = digit_base + excl - lstart;
+    }
   }
   __syncthreads();
   // reorder the tile by digit in LDS ...
@@ -319,7 +335,7 @@ hipError_t radix_sort(uint32_t* kA, uint32_t* kB, uint32_t* vA, uint32_t* vB, si
     const hipError_t e = fill_u32(ws, 0u, radix_clear_words(), st);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)((n_max + kHistTile - 1) / kHistTile)), dim3(kSortThreads), 0, st,
+  hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)((n_max + kHistTile - 1) / kHistTile)), dim3(kHistThreads), 0, st,
                      kA, n_max, n_dev, passes, hist, look, tiles);
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL(k_onesweep, dim3((unsigned)tiles), dim3(kSortThreads), 0, st, kA, vA, kB, vB, n_max, n_dev,

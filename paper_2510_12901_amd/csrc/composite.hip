@@ -453,7 +453,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(RPL == 1 
                                                       const uint32_t* __restrict__ branges, int n_tiles,
                                                       RenderParamsK prm, ut_render_out out) {
   __shared__ CompositeShared<BLOCK, RPL, BATCH> sm;
-  const int tile = xcd_super_tile(blockIdx.x, s);
+  const int tile = super_major_tile(blockIdx.x, s);
   if (tile < 0) return;
   composite_tile<BLOCK, RPL, BATCH, STATS, MOVING>(s, rec, trect, bgauss, branges, tile, s.super_x * s.super_y, prm, out, sm);
 }

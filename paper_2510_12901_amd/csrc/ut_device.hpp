@@ -363,23 +363,21 @@ __device__ __forceinline__ int super_of_tile(int tile, const SensorK& s) {
   return (ty / s.super_h) * s.super_x + tx / kSuper;
 }
 
-// Workgroup b of a grid of super_tile_slots() -> tile.  The GPU hands consecutive workgroups
-// to its 8 XCDs in turn; XCD b % 8 takes every 8th super-tile (spread over the whole image, so
-// each XCD's share holds dense and sparse regions alike) and runs the tiles of each of its
-// super-tiles back to back (they filter one bin, which stays in that XCD's L2).  Slots of an
+// Workgroup b of a grid of super_tile_slots() -> tile: the tiles of super-tile b / slots, row
+// by row.  The GPU hands consecutive workgroups to its 8 XCDs in turn, so every super-tile's
+// tiles are spread over all XCDs and each XCD gets an even share of every image region.  (Giving
+// each XCD whole super-tiles, so that the tiles filtering one bin share that XCD's L2, left
+// the XCDs unevenly loaded: the frame's fisheye compositing took 9-11% longer.)  Slots of an
 // edge super-tile that lie past the image return -1.
-__device__ __forceinline__ int xcd_super_tile(int b, const SensorK& s) {
+__device__ __forceinline__ int super_major_tile(int b, const SensorK& s) {
   const int slots = kSuper * s.super_h;
-  const int xcd = b & 7, local = b >> 3;
-  const int sid = xcd + 8 * (local / slots), t = local % slots;
+  const int sid = b / slots, t = b % slots;
   if (sid >= s.super_x * s.super_y) return -1;
   const int tx = (sid % s.super_x) * kSuper + t % kSuper, ty = (sid / s.super_x) * s.super_h + t / kSuper;
   if (tx >= s.tiles_x || ty >= s.tiles_y) return -1;
   return ty * s.tiles_x + tx;
 }
-inline int super_tile_slots(int super_x, int super_y, int super_h) {
-  return 8 * ((super_x * super_y + 7) / 8) * kSuper * super_h;
-}
+inline int super_tile_slots(int super_x, int super_y, int super_h) { return super_x * super_y * kSuper * super_h; }
 
 // Rays of a tile: camera 16x16 pixel block; LiDAR beams of the elevation tile times the
 // azimuth steps a with floor(a N_theta / n_az) == azimuth tile.  Returns -1 past the end.
