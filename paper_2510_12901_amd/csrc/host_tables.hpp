@@ -18,9 +18,11 @@ namespace ut_host {
 
 constexpr int kSuperTile = UT_SUPER_TILE;
 // Tile rows of a LiDAR super-tile (cameras: UT_SUPER_TILE).  Fewer rows shorten the bin each
-// LiDAR tile filters its list from (on the 300k-particle 128 x 2048 scan, 2 rows: bins 2.6x
-// the tile lists instead of 7x, compositing -13%), but add pairs and a second radix pass to
-// the pair sort (+60 us), a net loss there; the square super-tile is kept.
+// LiDAR tile filters its list from, but add pairs, and past 256 super-tiles a second radix
+// pass of the pair sort.  On the 300k-particle 128 x 2048 scan: 2 rows, bins 2.6x the tile
+// lists instead of 7x, compositing -13%, pair sort +60 us; 4 rows, compositing 202 -> 177 us,
+// one more radix pass (+15 us), and the multi-sensor frame about 1% slower.  The square
+// super-tile is kept.
 constexpr int kLidarSuperRows = UT_SUPER_TILE;
 inline int super_rows(int kind) { return kind == UT_LIDAR ? kLidarSuperRows : kSuperTile; }
 constexpr int kUnitTiles = 4;         // tiles of a LiDAR compositing unit at most
